@@ -1,0 +1,195 @@
+"""Greedy recovery algorithms, step by step, in FP64.
+
+OMP follows Sec. II (steps 1-4) and Algorithm 1 (outer loop): exactly K
+iterations of correlation, argmax, support update, least squares, residual.
+SP (Dai and Milenkovic) and OMPR (Jain, Tewari and Dhillon) are the other two
+greedy algorithms run in Sec. IV; the paper names them but does not restate
+them, so they are written here from their original definitions with the
+readings below.
+
+Decision rules (the paper leaves ties unstated):
+* every selection ranks candidates by (key descending, index ascending); the
+  chosen set is the first k of that order;
+* OMP's argmax and SP's expansion step only consider indices outside the
+  current support (in exact arithmetic the correlation vanishes on the
+  support, Theorem 2's orthogonality, so this changes nothing there);
+* OMPR drops the element ranked last by the same order over I u {j}.
+
+SP reading: T = top-K of |A^T y|, x = LS(T), r = y - A x; then repeat
+  c = A^T r;  D = top-K of |c| outside T;  x~ = LS(T u D);
+  T' = top-K of |x~| over T u D;  x' = LS(T'), r' = y - A x';
+  stop with (T', x') if T' == T; stop with (T, x) if ||r'|| > ||r||;
+  otherwise continue with (T', x', r').  At most ``max_iter`` rounds.
+
+OMPR reading (replacement size l = 1, step eta = N/M so that eta * a_j^T r
+is on the scale of a coefficient, since ||a_j||^2 is M/N on average):
+  I = top-K of |A^T y|, x = LS(I), r = y - A x; then repeat
+  stop if ||r|| <= 1e-12 ||y||;  c = A^T r;  j = argmax |c| outside I;
+  z = x + eta c on I u {j} (x_j = 0);  keep = top-K of |z| over I u {j};
+  stop if j is not kept; otherwise I = keep, x = LS(I), r = y - A x.
+  At most ``max_iter`` swaps.
+
+Every decision is logged with its margin (FP64 key gap between the last
+chosen and the first rejected candidate).
+"""
+from __future__ import annotations
+
+import dataclasses
+import numpy as np
+
+from .operator import SRM
+from .lsq import LSContext
+
+
+def topk_order(keys: np.ndarray, idx: np.ndarray, k: int) -> np.ndarray:
+    """Positions of the first k candidates under (key desc, index asc)."""
+    order = np.lexsort((idx, -keys))
+    return order[:k]
+
+
+def _margin(keys: np.ndarray, idx: np.ndarray, k: int) -> float:
+    if keys.size <= k:
+        return float("inf")
+    order = np.lexsort((idx, -keys))
+    return float(keys[order[k - 1]] - keys[order[k]])
+
+
+def argmax_excluding(c: np.ndarray, excluded: np.ndarray):
+    """argmax_j |c_j| over j not excluded; ties go to the lowest j.
+
+    Returns (j, margin)."""
+    key = np.abs(c).astype(np.float64)
+    key[excluded] = -1.0
+    j = int(np.argmax(key))          # first occurrence = lowest index on ties
+    key2 = key.copy()
+    key2[j] = -1.0
+    second = key2.max()
+    return j, float(key[j] - second) if second >= 0 else float("inf")
+
+
+def topk_excluding(c: np.ndarray, excluded: np.ndarray | None, k: int):
+    """Top-k indices of |c| outside ``excluded`` under (|c| desc, j asc), sorted ascending."""
+    idx = np.arange(c.size) if excluded is None else np.flatnonzero(~excluded)
+    keys = np.abs(c[idx]).astype(np.float64)
+    pos = topk_order(keys, idx, k)
+    return np.sort(idx[pos]), _margin(keys, idx, k)
+
+
+@dataclasses.dataclass
+class Result:
+    s: np.ndarray                 # dense N-vector, zeros off the support
+    support: np.ndarray           # int64, ascending
+    iters: int                    # outer iterations (OMP: K; SP: rounds; OMPR: swaps)
+    resid_norm: float
+    trace: list                   # (step, kind, margin)
+    stop: str = ""
+    supports: list = dataclasses.field(default_factory=list)  # per-iteration support history
+
+
+def _dense(n, supp, vals):
+    s = np.zeros(n)
+    s[supp] = vals
+    return s
+
+
+def omp(op: SRM, y, K: int, ls_route: str = "auto") -> Result:
+    y = np.asarray(y, dtype=np.float64)
+    ctx = LSContext(op, y, ls_route)
+    r = y.copy()
+    S: list[int] = []
+    excluded = np.zeros(op.n, dtype=bool)
+    trace = []
+    vals = np.zeros(0)
+    for i in range(1, K + 1):
+        c = op.adjoint(r)
+        t, m = argmax_excluding(c, excluded)
+        trace.append((i, "argmax", m))
+        S.append(t)
+        excluded[t] = True
+        vals = ctx.solve(S)
+        r = y - op.apply_sparse(S, vals)
+    order = np.argsort(S)
+    supp = np.asarray(S, dtype=np.int64)[order]
+    return Result(_dense(op.n, supp, vals[order]), supp, K, float(np.linalg.norm(r)), trace, "K iterations")
+
+
+def sp(op: SRM, y, K: int, max_iter: int = 100, ls_route: str = "auto") -> Result:
+    y = np.asarray(y, dtype=np.float64)
+    ctx = LSContext(op, y, ls_route)
+    trace = []
+    T, m = topk_excluding(ctx.aty, None, K)
+    trace.append((0, "init_topk", m))
+    x = ctx.solve(T)
+    r = y - op.apply_sparse(T, x)
+    rn = float(np.linalg.norm(r))
+    supports = [T]
+    stop = "max_iter"
+    it = 0
+    for it in range(1, max_iter + 1):
+        c = op.adjoint(r)
+        excl = np.zeros(op.n, dtype=bool)
+        excl[T] = True
+        D, m = topk_excluding(c, excl, K)
+        trace.append((it, "expand_topk", m))
+        Tt = np.union1d(T, D)
+        xt = ctx.solve(Tt)
+        pos = topk_order(np.abs(xt), Tt, K)
+        trace.append((it, "prune_topk", _margin(np.abs(xt), Tt, K)))
+        Tn = np.sort(Tt[pos])
+        xn = ctx.solve(Tn)
+        rn_vec = y - op.apply_sparse(Tn, xn)
+        rnn = float(np.linalg.norm(rn_vec))
+        if np.array_equal(Tn, T):
+            x, r, rn = xn, rn_vec, rnn
+            supports.append(Tn)
+            stop = "support unchanged"
+            break
+        if rnn > rn:
+            stop = "residual increased"
+            break
+        T, x, r, rn = Tn, xn, rn_vec, rnn
+        supports.append(T)
+    return Result(_dense(op.n, T, x), np.asarray(T, dtype=np.int64), it, rn, trace, stop, supports)
+
+
+def ompr(op: SRM, y, K: int, eta: float | None = None, max_iter: int | None = None,
+         ls_route: str = "auto") -> Result:
+    y = np.asarray(y, dtype=np.float64)
+    if eta is None:
+        eta = op.n / op.m
+    if max_iter is None:
+        max_iter = 4 * K
+    ctx = LSContext(op, y, ls_route)
+    trace = []
+    I, m = topk_excluding(ctx.aty, None, K)
+    trace.append((0, "init_topk", m))
+    x = ctx.solve(I)
+    r = y - op.apply_sparse(I, x)
+    ynorm = float(np.linalg.norm(y))
+    stop = "max_iter"
+    t = 0
+    swaps = 0
+    for t in range(1, max_iter + 1):
+        if np.linalg.norm(r) <= 1e-12 * ynorm:
+            stop = "residual zero"
+            break
+        c = op.adjoint(r)
+        excl = np.zeros(op.n, dtype=bool)
+        excl[I] = True
+        j, m = argmax_excluding(c, excl)
+        trace.append((t, "argmax", m))
+        cand = np.append(I, j)
+        z = np.append(x + eta * c[I], eta * c[j])
+        keys = np.abs(z)
+        pos = topk_order(keys, cand, K)
+        trace.append((t, "drop", _margin(keys, cand, K)))
+        keep = np.sort(cand[pos])
+        if j not in set(keep.tolist()):
+            stop = "no replacement"
+            break
+        I = keep
+        x = ctx.solve(I)
+        r = y - op.apply_sparse(I, x)
+        swaps += 1
+    return Result(_dense(op.n, I, x), np.asarray(I, dtype=np.int64), swaps,
+                  float(np.linalg.norm(r)), trace, stop)

@@ -1,0 +1,89 @@
+"""Sensing operator of Sec. III-A, Eq. (7): Phi = D F R, with Psi = I so A = Phi.
+
+* D keeps the sampled rows ``rows`` (M of N, ascending) of an N-vector
+  (the "randomly choose M indices" operator of Sec. III-D).
+* F is the orthonormal N-point DCT-II,
+      (F x)_k = c_k sum_n x_n cos(pi (2n+1) k / (2N)),
+      c_0 = sqrt(1/N), c_k = sqrt(2/N) for k >= 1.
+  Its transpose (= inverse) is the orthonormal DCT-III.
+* R = diag(signs) with signs in {+1, -1}.
+
+So A x = (F (signs * x))[rows] and A^T u = signs * F^T (zero-fill_rows(u)).
+
+Two independent routes are provided: SciPy's FFT-based DCT (``apply``,
+``adjoint``) and the dense cosine formula (``columns``, ``dense``) with the
+angle reduced exactly in integers, for small problems and for pins.
+"""
+from __future__ import annotations
+
+import os
+import numpy as np
+import scipy.fft as sfft
+
+WORKERS = os.cpu_count() or 1
+
+
+def _dct_scale(k: np.ndarray, n: int) -> np.ndarray:
+    return np.where(k == 0, np.sqrt(1.0 / n), np.sqrt(2.0 / n))
+
+
+def _cos_table(k: np.ndarray, j: np.ndarray, n: int) -> np.ndarray:
+    """cos(pi (2j+1) k / (2n)) for broadcast integer arrays k, j.
+
+    The angle is pi * a / (2n) with a = (2j+1) k reduced modulo 4n in exact
+    integer arithmetic before the floating-point cosine."""
+    a = ((2 * j.astype(np.int64) + 1) * k.astype(np.int64)) % (4 * n)
+    return np.cos(np.pi * a.astype(np.float64) / (2.0 * n))
+
+
+def dct2_matrix(n: int) -> np.ndarray:
+    """Dense orthonormal DCT-II matrix F (n x n) from the cosine formula."""
+    k = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    return _dct_scale(k, n) * _cos_table(k, j, n)
+
+
+class SRM:
+    """A = D_rows . DCT-II . diag(signs), an M x N operator (FP64)."""
+
+    def __init__(self, n: int, rows, signs):
+        rows = np.asarray(rows, dtype=np.int64)
+        signs = np.asarray(signs)
+        if rows.ndim != 1 or signs.shape != (n,):
+            raise ValueError("rows must be 1-D and signs must have length n")
+        if rows.size and (rows[0] < 0 or rows[-1] >= n or np.any(np.diff(rows) <= 0)):
+            raise ValueError("rows must be strictly ascending in [0, n)")
+        if not np.all(np.abs(signs) == 1):
+            raise ValueError("signs must be +-1")
+        self.n = int(n)
+        self.m = int(rows.size)
+        self.rows = rows
+        self.signs = signs.astype(np.float64)
+
+    # ---------------------------------------------------------- FFT route
+    def apply(self, x: np.ndarray) -> np.ndarray:
+        """A x for a dense N-vector x."""
+        x = np.asarray(x, dtype=np.float64)
+        return sfft.dct(self.signs * x, type=2, norm="ortho", workers=WORKERS)[self.rows]
+
+    def apply_sparse(self, supp, vals) -> np.ndarray:
+        """A x where x is zero off ``supp`` and equals ``vals`` on it."""
+        x = np.zeros(self.n)
+        x[np.asarray(supp, dtype=np.int64)] = vals
+        return self.apply(x)
+
+    def adjoint(self, u: np.ndarray) -> np.ndarray:
+        """A^T u for an M-vector u: zero-fill, orthonormal DCT-III, sign flip."""
+        full = np.zeros(self.n)
+        full[self.rows] = np.asarray(u, dtype=np.float64)
+        return self.signs * sfft.idct(full, type=2, norm="ortho", workers=WORKERS)
+
+    # ---------------------------------------------------- formula route
+    def columns(self, supp) -> np.ndarray:
+        """Dense A_S (M x |S|) from the cosine formula."""
+        j = np.asarray(supp, dtype=np.int64)[None, :]
+        k = self.rows[:, None]
+        return _dct_scale(k, self.n) * _cos_table(k, j, self.n) * self.signs[j]
+
+    def dense(self) -> np.ndarray:
+        return self.columns(np.arange(self.n))

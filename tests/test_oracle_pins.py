@@ -1,0 +1,429 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics and the paper.
+
+Each pin checks the oracle against something other than itself: a textbook
+identity, a closed form, an invariant stated by the paper's theorems, a
+special case that reduces to a known answer, or exhaustive search.  The
+planted-mistake tests at the end make sure that plausible slips in the
+oracle (wrong DCT type, dropped sign flip, dropped Hankel term, transposed
+operand, wrong tie order) are caught by at least one pin.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import operator as oop
+import importlib
+ogram = importlib.import_module("oracle.gram")
+from oracle import greedy as ogreedy
+from tests.problems import problem
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ------------------------------------------------------------------ P1 DCT
+def pin_dct_formula(n=64, seed=0):
+    """SciPy route equals the dense cosine formula; F is orthonormal."""
+    rng = np.random.default_rng(seed)
+    F = oracle.dct2_matrix(n)
+    x = rng.standard_normal(n)
+    op = oracle.SRM(n, np.arange(n), np.ones(n, dtype=np.int8))
+    ok1 = np.allclose(op.apply(x), F @ x, atol=1e-13, rtol=0)
+    ok2 = np.allclose(F @ F.T, np.eye(n), atol=1e-13)
+    return ok1 and ok2
+
+
+def pin_dct_basis(n=128):
+    """Textbook cosine orthogonality: sum_n cos(pi(2n+1)k/2N) cos(pi(2n+1)k0/2N) = N/2 [k=k0>0],
+    so the DCT-II of that cosine is sqrt(N/2) at k0 and 0 elsewhere; the DCT-II of all-ones is sqrt(N) e_0."""
+    op = oracle.SRM(n, np.arange(n), np.ones(n, dtype=np.int8))
+    ok = True
+    nn = np.arange(n)
+    for k0 in (1, 5, n // 2, n - 1):
+        a = ((2 * nn + 1) * k0) % (4 * n)          # exact angle reduction
+        x = np.cos(np.pi * a / (2 * n))
+        e = np.zeros(n)
+        e[k0] = np.sqrt(n / 2)
+        ok &= np.allclose(op.apply(x), e, atol=1e-13 * np.sqrt(n))
+    e = np.zeros(n)
+    e[0] = np.sqrt(n)
+    ok &= np.allclose(op.apply(np.ones(n)), e, atol=1e-13 * np.sqrt(n))
+    return bool(ok)
+
+
+def test_p1_dct_formula():
+    for n in (8, 64, 256, 1000):
+        assert pin_dct_formula(n)
+
+
+def test_p1_dct_basis():
+    assert pin_dct_basis(128)
+    assert pin_dct_basis(4096)
+
+
+# ------------------------------------------------------------------ P2 A, A^T
+def pin_adjoint(n=256, m=77, seed=1):
+    """A A^T = I_M (rows of an orthonormal matrix) and <A x, u> = <x, A^T u>;
+    the FFT route agrees with the dense formula for A and A^T."""
+    rng = np.random.default_rng(seed)
+    rows, signs = synth.draw_operator(rng, n, m)
+    op = oracle.SRM(n, rows, signs)
+    x = rng.standard_normal(n)
+    u = rng.standard_normal(m)
+    A = op.dense()
+    ok = np.allclose(op.apply(op.adjoint(u)), u, atol=1e-13)
+    ok &= abs(op.apply(x) @ u - x @ op.adjoint(u)) < 1e-12
+    ok &= np.allclose(op.apply(x), A @ x, atol=1e-13)
+    ok &= np.allclose(op.adjoint(u), A.T @ u, atol=1e-13)
+    ok &= np.allclose(A @ A.T, np.eye(m), atol=1e-13)
+    return bool(ok)
+
+
+def test_p2_adjoint():
+    assert pin_adjoint()
+    assert pin_adjoint(1024, 300, 2)
+
+
+# ------------------------------------------------------------------ P3 Gram
+def pin_gram(n=256, m=90, k=20, seed=3):
+    rng = np.random.default_rng(seed)
+    rows, signs = synth.draw_operator(rng, n, m)
+    op = oracle.SRM(n, rows, signs)
+    S = np.sort(rng.choice(n, k, replace=False))
+    S[0] = 0            # include both ends: j = 0 and j = N-1
+    S[-1] = n - 1
+    As = op.columns(S)
+    return bool(np.allclose(oracle.gram_matrix(op, S), As.T @ As, atol=1e-13))
+
+
+def test_p3_gram():
+    assert pin_gram()
+    assert pin_gram(4096, 1024, 50, 4)
+
+
+def test_p3_gram_row0_dc():
+    # the DC row (k = 0) has a different scale c_0; make sure it is sampled
+    n = 64
+    rows = np.array([0, 1, 7, 20, 33, 63])
+    signs = np.ones(n, dtype=np.int8)
+    signs[::3] = -1
+    op = oracle.SRM(n, rows, signs)
+    S = np.array([0, 5, 31, 62, 63])
+    As = op.columns(S)
+    assert np.allclose(oracle.gram_matrix(op, S), As.T @ As, atol=1e-14)
+
+
+# ------------------------------------------------------------------ P4 LS
+def pin_ls_routes(seed=5, n=1024, m=256, k=40, snr=30.0):
+    d, op, y = problem(90, seed, n, m, k, "normal", snr)
+    S = np.sort(np.concatenate([d.supp[:30], np.setdiff1d(np.arange(n), d.supp)[:10]]))
+    a = oracle.ls_dense(op, S, y)
+    b = oracle.ls_gram(op, S, y)
+    c, _ = oracle.ls_cg(op, S, y, tol=1e-14)
+    ok = np.allclose(a, b, atol=1e-12, rtol=0) and np.allclose(a, c, atol=1e-11, rtol=0)
+    # Theorems 1-2: the residual is orthogonal to the selected columns
+    r = y - op.apply_sparse(S, a)
+    ok &= np.linalg.norm(op.columns(S).T @ r) <= 1e-12 * np.linalg.norm(y)
+    return bool(ok)
+
+
+def test_p4_ls_routes_agree_and_orthogonal():
+    assert pin_ls_routes()
+
+
+def test_p4_noiseless_true_support_exact():
+    d, op, y = problem(91, 0, 4096, 1024, 50, "normal_min0.1")
+    v = oracle.ls(op, d.supp, y)
+    assert np.allclose(v, d.vals, atol=1e-12)
+
+
+def test_p4_single_column_closed_form():
+    d, op, y = problem(92, 0, 512, 128, 5, "normal", 20.0)
+    t = np.array([37])
+    a = op.columns(t)[:, 0]
+    assert np.allclose(oracle.ls(op, t, y), [a @ y / (a @ a)], rtol=1e-13)
+
+
+# ------------------------------------------------------------------ P5 CG (Theorems 4-5)
+def test_p5_cg_iteration_bound():
+    """Theorem 5: at most |S| iterations (exact arithmetic); allow +2 for rounding."""
+    for k in (1, 4, 9, 16):
+        d, op, y = problem(93, k, 512, 160, k, "normal", 25.0)
+        S = d.supp
+        v, it = oracle.ls_cg(op, S, y, tol=1e-12)
+        assert it <= k + 2, (k, it)
+        assert np.allclose(v, oracle.ls_dense(op, S, y), atol=1e-10)
+
+
+def test_p5_cg_orthogonal_operator_one_step():
+    """M = N makes A orthogonal, A_S^T A_S = I has one eigenvalue: CG stops after 1 iteration (Theorem 4)."""
+    rng = np.random.default_rng(7)
+    n = 256
+    op = oracle.SRM(n, np.arange(n), synth.draw_operator(rng, n, n)[1])
+    y = rng.standard_normal(n)
+    S = np.sort(rng.choice(n, 30, replace=False))
+    v, it = oracle.ls_cg(op, S, y, tol=1e-13)
+    assert it == 1
+    assert np.allclose(v, op.adjoint(y)[S], atol=1e-13)
+
+
+# ------------------------------------------------------------------ P6 M = N
+def pin_orthogonal_special_case(seed=11, n=512, k=20):
+    """With M = N, A is orthogonal, LS on any S is (A^T y)_S and all three
+    algorithms return hard thresholding H_K(A^T y)."""
+    rng = np.random.default_rng(seed)
+    rows, signs = synth.draw_operator(rng, n, n)
+    op = oracle.SRM(n, rows, signs)
+    y = rng.standard_normal(n)
+    c = op.adjoint(y)
+    expect = np.sort(np.argsort(-np.abs(c), kind="stable")[:k])
+    ok = True
+    for f in (oracle.omp, oracle.sp, oracle.ompr):
+        kw = {"eta": 1.0} if f is oracle.ompr else {}
+        r = f(op, y, k, **kw)
+        ok &= np.array_equal(r.support, expect)
+        ok &= np.allclose(r.s[expect], c[expect], atol=1e-12)
+        if f is oracle.sp:
+            ok &= r.iters == 1
+        if f is oracle.ompr:
+            ok &= r.iters == 0
+    return bool(ok)
+
+
+def test_p6_orthogonal_special_case():
+    assert pin_orthogonal_special_case()
+
+
+def test_p6_omp_picks_in_decreasing_magnitude():
+    rng = np.random.default_rng(12)
+    n = 128
+    op = oracle.SRM(n, np.arange(n), synth.draw_operator(rng, n, n)[1])
+    y = rng.standard_normal(n)
+    c = np.abs(op.adjoint(y))
+    r = oracle.omp(op, y, 10)
+    picks = [t[2] for t in r.trace]
+    assert len(picks) == 10
+    # the picks follow |c| order: reconstruct from the support
+    assert np.array_equal(r.support, np.sort(np.argsort(-c, kind="stable")[:10]))
+
+
+# ------------------------------------------------------------------ P7 brute force
+def _erc(op, S):
+    """Tropp's exact recovery condition max_{j not in S} ||A_S^+ a_j||_1 < 1."""
+    A = op.dense()
+    pinv = np.linalg.pinv(A[:, S])
+    others = np.setdiff1d(np.arange(op.n), S)
+    return float(np.max(np.abs(pinv @ A[:, others]).sum(axis=0)))
+
+
+def test_p7_bruteforce_and_omp_under_erc():
+    certified = 0
+    for seed in range(40):
+        d, op, y = problem(94, seed, 16, 10, 2, "normal_min0.1")
+        supp, vals, rn = oracle.l0_bruteforce(op, y, 2)
+        # noiseless: the true support gives zero residual, so the minimiser does too
+        assert rn < 1e-10
+        if np.array_equal(supp, d.supp):
+            assert np.allclose(vals, d.vals, atol=1e-10)
+        if _erc(op, d.supp) < 1.0:
+            certified += 1
+            r = oracle.omp(op, y, 2)
+            assert np.array_equal(r.support, supp)
+            assert np.array_equal(r.support, d.supp)
+    assert certified >= 5
+
+
+def test_p7_bruteforce_is_optimal_for_greedy():
+    for seed in range(10):
+        d, op, y = problem(95, seed, 14, 8, 2, "normal", 15.0)
+        _, _, rn = oracle.l0_bruteforce(op, y, 2)
+        for f in (oracle.omp, oracle.sp, oracle.ompr):
+            assert f(op, y, 2).resid_norm >= rn - 1e-12
+
+
+def test_p7_sp_ompr_single_atom_certificate():
+    """K = 1, noiseless y = v a_t: A^T y = v A^T a_t, so whenever ||a_t||^2 exceeds
+    every |a_j^T a_t| (j != t) the top-1 of |A^T y| is t, the LS fit is exact and
+    SP and OMPR must both return {t} with value v (and equal the l0 minimiser)."""
+    certified = 0
+    for seed in range(30):
+        d, op, y = problem(96, seed, 16, 9, 1, "normal_min0.1")
+        A = op.dense()
+        t = int(d.supp[0])
+        gram_col = np.abs(A.T @ A[:, t])
+        if gram_col[t] > np.max(np.delete(gram_col, t)):
+            certified += 1
+            supp, vals, _ = oracle.l0_bruteforce(op, y, 1)
+            for f in (oracle.sp, oracle.ompr):
+                r = f(op, y, 1)
+                assert np.array_equal(r.support, d.supp) and np.array_equal(r.support, supp)
+                assert np.allclose(r.s[t], d.vals[0], atol=1e-12)
+    assert certified >= 5
+
+
+def test_p7_sp_ompr_fixed_points():
+    """The returned support satisfies the algorithm's own stopping rule: one more
+    SP round from it does not lower the residual, and OMPR finds no replacement."""
+    d, op, y = problem(100, 0, 1024, 256, 20, "normal", 15.0)
+    r = oracle.sp(op, y, 20)
+    T = r.support
+    c = op.adjoint(y - op.apply(r.s))
+    excl = np.zeros(op.n, dtype=bool)
+    excl[T] = True
+    D, _ = ogreedy.topk_excluding(c, excl, 20)
+    Tt = np.union1d(T, D)
+    xt = oracle.ls(op, Tt, y)
+    Tn = np.sort(Tt[ogreedy.topk_order(np.abs(xt), Tt, 20)])
+    rn = np.linalg.norm(y - op.apply_sparse(Tn, oracle.ls(op, Tn, y)))
+    assert np.array_equal(Tn, T) or rn >= r.resid_norm * (1 - 1e-12)
+    q = oracle.ompr(op, y, 20)
+    if q.stop == "no replacement":
+        I = q.support
+        c = op.adjoint(y - op.apply(q.s))
+        excl = np.zeros(op.n, dtype=bool)
+        excl[I] = True
+        j, _ = oracle.argmax_excluding(c, excl)
+        eta = op.n / op.m
+        z = np.append(q.s[I] + eta * c[I], eta * c[j])
+        cand = np.append(I, j)
+        assert j not in cand[ogreedy.topk_order(np.abs(z), cand, 20)]
+
+
+# ------------------------------------------------------------------ exact recovery (the benchmark spec)
+@pytest.mark.parametrize("algo", ["omp", "sp", "ompr"])
+def test_exact_recovery_well_separated(algo):
+    d, op, y = problem(97, 0, 4096, 1024, 50, "normal_min0.1")
+    r = getattr(oracle, algo)(op, y, 50)
+    assert np.array_equal(r.support, d.supp)
+    assert np.linalg.norm(r.s - d.s_dense()) <= 1e-12 * np.linalg.norm(d.vals)
+    # final residual orthogonal to A_S
+    res = y - op.apply(r.s)
+    assert np.linalg.norm(op.columns(r.support).T @ res) <= 1e-12 * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("algo", ["omp", "sp", "ompr"])
+def test_noisy_residual_orthogonal(algo):
+    d, op, y = problem(98, 0, 2048, 512, 30, "normal", 20.0)
+    r = getattr(oracle, algo)(op, y, 30)
+    res = y - op.apply(r.s)
+    assert len(r.support) == 30
+    assert np.linalg.norm(op.columns(r.support).T @ res) <= 1e-11 * np.linalg.norm(y)
+
+
+# ------------------------------------------------------------------ P8 selection
+def test_p8_selection_ties():
+    keys = np.array([3.0, 1.0, 3.0, 0.0, -0.0, 2.0, 3.0, 1.0, 2.0, 0.0])
+    idx = np.arange(keys.size)
+    ref = sorted(idx.tolist(), key=lambda j: (-abs(keys[j]), j))
+    for k in range(1, keys.size + 1):
+        pos = ogreedy.topk_order(np.abs(keys), idx, k)
+        assert idx[pos].tolist() == ref[:k]
+    excl = np.zeros(keys.size, dtype=bool)
+    excl[0] = True
+    j, m = oracle.argmax_excluding(keys, excl)
+    assert j == 2 and m == 0.0
+    allzero = np.zeros(7)
+    assert oracle.argmax_excluding(allzero, np.zeros(7, dtype=bool))[0] == 0
+    sel, _ = ogreedy.topk_excluding(allzero, np.array([True, False, True, False, False, False, False]), 3)
+    assert sel.tolist() == [1, 3, 4]
+
+
+# ------------------------------------------------------------------ P9 adjoint
+def test_p9_adjoint_matches_central_differences():
+    d, op, y = problem(99, 0, 1024, 256, 12, "normal", 30.0)
+    t = d.s_dense()
+    S = d.supp
+    g, _ = oracle.adjoint_gradient(op, S, y, t)
+
+    def loss(yy):
+        v = oracle.ls_dense(op, S, yy)
+        s = np.zeros(op.n)
+        s[S] = v
+        return float(np.sum((s - t) ** 2))
+
+    rng = np.random.default_rng(0)
+    for c in rng.choice(op.m, 16, replace=False):
+        h = 1e-3
+        e = np.zeros(op.m)
+        e[c] = h
+        fd = (loss(y + e) - loss(y - e)) / (2 * h)
+        assert abs(fd - g[c]) <= 1e-7 * max(1.0, abs(g[c])), (c, fd, g[c])
+
+
+# ------------------------------------------------------------------ planted mistakes
+def _mutants():
+    import scipy.fft as sfft
+
+    def apply_dct3(self, x):
+        return sfft.dct(self.signs * np.asarray(x, float), type=3, norm="ortho")[self.rows]
+
+    def adjoint_nosign(self, u):
+        full = np.zeros(self.n)
+        full[self.rows] = u
+        return sfft.idct(full, type=2, norm="ortho")
+
+    def gram_no_hankel(op, supp, g=None):
+        if g is None:
+            g = ogram.gram_generator(op)
+        s = np.asarray(supp, dtype=np.int64)
+        sg = op.signs[s]
+        return 0.5 * (sg[:, None] * sg[None, :]) * (g[np.abs(s[:, None] - s[None, :])] * 2)
+
+    def gram_minus(op, supp, g=None):
+        if g is None:
+            g = ogram.gram_generator(op)
+        s = np.asarray(supp, dtype=np.int64)
+        sg = op.signs[s]
+        return 0.5 * (sg[:, None] * sg[None, :]) * (g[np.abs(s[:, None] - s[None, :])] - g[s[:, None] + s[None, :] + 1])
+
+    def columns_transposed_angle(self, supp):
+        j = np.asarray(supp, dtype=np.int64)[None, :]
+        k = self.rows[:, None]
+        return oop._dct_scale(k, self.n) * oop._cos_table(j, k, self.n) * self.signs[j]
+
+    def topk_order_wrong_ties(keys, idx, k):
+        return np.lexsort((-idx, -keys))[:k]
+
+    return {
+        "dct type 3 instead of 2": (oop.SRM, "apply", apply_dct3),
+        "adjoint drops sign flip": (oop.SRM, "adjoint", adjoint_nosign),
+        "gram drops Hankel term": (ogram, "gram_matrix", gram_no_hankel),
+        "gram wrong sign": (ogram, "gram_matrix", gram_minus),
+        "columns transposed angle": (oop.SRM, "columns", columns_transposed_angle),
+        "ties to highest index": (ogreedy, "topk_order", topk_order_wrong_ties),
+    }
+
+
+ALL_PINS = [pin_dct_formula, pin_dct_basis, pin_adjoint, pin_gram, pin_ls_routes,
+            pin_orthogonal_special_case]
+
+
+def _pin_ties():
+    keys = np.array([2.0, 1.0, 2.0, 2.0])
+    idx = np.arange(4)
+    return ogreedy.topk_order(keys, idx, 2).tolist() == [0, 2]
+
+
+@pytest.mark.parametrize("name", list(_mutants().keys()))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    target, attr, repl = _mutants()[name]
+    monkeypatch.setattr(target, attr, repl)
+    # oracle/__init__ re-exports some names; patch those too
+    if target is ogram and attr == "gram_matrix":
+        monkeypatch.setattr(importlib.import_module("oracle.lsq"), "gram_matrix", repl)
+        monkeypatch.setattr(oracle, "gram_matrix", repl)
+    if target is ogreedy and attr == "topk_order":
+        monkeypatch.setattr(oracle, "topk_order", repl)
+    results = []
+    for pin in ALL_PINS + [_pin_ties]:
+        try:
+            results.append(bool(pin()))
+        except Exception:
+            results.append(False)
+    assert not all(results), f"no pin caught: {name}"
+
+
+def test_all_pins_pass_unmutated():
+    assert all(p() for p in ALL_PINS + [_pin_ties])
