@@ -1,0 +1,170 @@
+/*
+ * cs.h - C ABI of libcsrecover: CG-based greedy compressive-sensing recovery
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. II and Eq. (2) of Hsieh, Lu, Pei, "Fast Greedy Approaches for
+ * Compressive Sensing of Large-Scale Signals"): given measurements y = A s of
+ * a K-sparse s, recover s.  The sensing matrix is the operator of Sec. III-A,
+ * Eq. (7), A = D F R with
+ *   D  keeping the M sampled rows `rows` of an N-vector,
+ *   F  the orthonormal N-point DCT-II, (F x)_k = c_k sum_n x_n cos(pi(2n+1)k/(2N)),
+ *      c_0 = sqrt(1/N), c_k = sqrt(2/N),
+ *   R  the diagonal sign flip diag(signs), signs in {+1,-1}.
+ * The sparsifying basis is the identity (s is sparse directly).
+ *
+ * Every least-squares step is the CG-based weighted least squares of
+ * Sec. III-B/C (Eqs. (10)-(11), Algorithm 1 lines 11-24): CG on
+ * W_S A^T A W_S theta = W_S A^T y, touching A only through the operator.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Memory:  all array arguments are DEVICE pointers owned by the caller; the
+ *          library never allocates or frees device memory and keeps no
+ *          pointer after it returns.  Scratch space is the caller's workspace
+ *          `ws` of `ws_bytes` bytes (256-byte aligned); query its size with
+ *          cs_workspace_size().  Workspaces must not be shared by calls that
+ *          run concurrently.
+ * Types:   `dtype` selects the element type of y, s, x, u, out and the
+ *          workspace vectors: CS_F32 (float) or CS_F64 (double).  Inner
+ *          products and residual norms are accumulated in double in both.
+ * Streams: all device work is enqueued on `stream` (0 = default stream).
+ *          Every call synchronises that stream (descriptor validation and the
+ *          loop control read small device flags) and returns with results
+ *          complete.
+ * Errors:  arguments are validated on the host before any device work; a
+ *          negative status means nothing was written to the outputs.
+ *          Operator descriptors (rows ascending and in range, signs +-1) are
+ *          validated on the device; a bad descriptor returns CS_E_OP.
+ *          Conditions met during the iteration set bits in cs_info.flags
+ *          and still return CS_OK with best-effort outputs.
+ *          CS_E_HIP reports a HIP runtime error (text: cs_last_error()).
+ * Sizes:   N is a power of two with 16 <= N <= 2^26; 1 <= M <= N;
+ *          1 <= K <= M.  SP additionally needs 2K <= M (its least-squares
+ *          step uses 2K columns, which must have full column rank, Thm. 1).
+ * Threads: the library is reentrant for distinct workspaces;
+ *          cs_last_error() is thread-local.
+ */
+#ifndef CS_H
+#define CS_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { CS_F32 = 0, CS_F64 = 1 } cs_dtype;
+
+typedef enum {
+  CS_ALGO_OMP = 0,      /* Orthogonal Matching Pursuit (Sec. II, Algorithm 1)           */
+  CS_ALGO_SP = 1,       /* Subspace Pursuit (run in Sec. IV)                            */
+  CS_ALGO_OMPR = 2,     /* OMP with Replacement, l = 1 (run in Sec. IV)                 */
+  CS_ALGO_OPERATOR = 3, /* cs_apply_A / cs_apply_At only                                */
+  CS_ALGO_LS = 4        /* cs_ls_solve (the CG function of Algorithm 1 alone)           */
+} cs_algo;
+
+typedef enum {
+  CS_OK = 0,
+  CS_E_INVALID = -1,    /* null pointer, bad dtype/algo, K < 1, tol <= 0 or not finite  */
+  CS_E_SHAPE = -2,      /* N not a power of two in [16, 2^26], M > N, K > M, SP 2K > M   */
+  CS_E_OP = -3,         /* rows not strictly ascending in [0, N) or a sign not +-1       */
+  CS_E_WORKSPACE = -4,  /* workspace too small or not 256-byte aligned                   */
+  CS_E_HIP = -5         /* HIP runtime error                                             */
+} cs_status;
+
+/* cs_info.flags bits (non-fatal) */
+enum {
+  CS_F_CG_MAXITER = 1,     /* a CG solve hit its iteration cap before the tolerance   */
+  CS_F_CG_BREAKDOWN = 2,   /* d^T H d <= 0 or not finite (rank-deficient A_S, Thm. 3) */
+  CS_F_OUTER_MAXITER = 4,  /* SP/OMPR stopped at max_outer                            */
+  CS_F_NONFINITE = 8       /* a non-finite value reached a selection or a norm        */
+};
+
+/* Sensing operator A = D F R (Eq. (7)). */
+typedef struct {
+  int64_t n;              /* signal length N                                        */
+  int64_t m;              /* number of sampled rows M                               */
+  const int32_t* rows;    /* device [m]: sampled DCT rows, strictly ascending      */
+  const int8_t* signs;    /* device [n]: sign flips, each +1 or -1                  */
+} cs_op;
+
+/* Optional knobs; pass NULL for the defaults shown. */
+typedef struct {
+  int32_t cg_max_iter;    /* CG iterations per solve; 0 -> 2|S| + 50                */
+  int32_t max_outer;      /* SP rounds / OMPR swaps; 0 -> SP 100, OMPR 4K           */
+  int32_t warm_start;     /* 1 (default) start CG from the previous solution; 0 cold */
+  int32_t reserved;
+  double ompr_eta;        /* OMPR step eta; <= 0 -> N/M                             */
+} cs_params;
+
+/* Filled on return when non-NULL (host memory). */
+typedef struct {
+  int32_t outer_iters;    /* OMP: K; SP: rounds; OMPR: swaps performed              */
+  int32_t flags;          /* CS_F_* bits                                            */
+  int64_t cg_iters;       /* total CG iterations over all solves                    */
+  int64_t transforms;     /* N-point transforms applied (forward + inverse)         */
+  double resid_norm;      /* ||y - A s|| of the returned s (FP64 accumulation)      */
+  double model_bytes;     /* algorithmic HBM bytes of the transform passes          */
+} cs_info;
+
+/* Workspace bytes needed by one call of `algo` at these sizes (0 if invalid).
+ * It grows as O(N + K) (Sec. III-D: the method's memory is O(N)). */
+size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_algo algo);
+
+/*
+ * Recovery entry points: y [M] -> s [N] (dense, zero off the support) and
+ * support [K] (int32, strictly ascending).  `tol` is the CG stopping
+ * tolerance, relative: each solve stops when ||b - H theta|| <= tol ||b||
+ * (Algorithm 1 line 15 with xi = tol ||b||).
+ *
+ * cs_recover_omp:  Sec. II steps 1-4 / Algorithm 1: K iterations of
+ *                  argmax |A^T r| outside S, S <- S + t, CG least squares,
+ *                  r = y - A s.
+ * cs_recover_sp:   Subspace Pursuit: top-K of |A^T y|; then rounds of
+ *                  expand by the top-K of |A^T r| outside T, least squares on
+ *                  the 2K columns, prune to the top-K magnitudes, least
+ *                  squares; stops when the support repeats or the residual
+ *                  grows.
+ * cs_recover_ompr: OMPR with l = 1: top-K of |A^T y|; then swaps of the best
+ *                  outside correlation j against the smallest |x + eta A^T r|
+ *                  on S u {j}; stops when j would be dropped.
+ * Ties in every selection rank by (magnitude descending, index ascending).
+ */
+cs_status cs_recover_omp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol,
+                         void* s, int32_t* support, const cs_params* params,
+                         void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream);
+cs_status cs_recover_sp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol,
+                        void* s, int32_t* support, const cs_params* params,
+                        void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream);
+cs_status cs_recover_ompr(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol,
+                          void* s, int32_t* support, const cs_params* params,
+                          void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream);
+
+/*
+ * The CG function of Algorithm 1 (lines 11-24) on its own: solve the weighted
+ * least squares of Eq. (10) through its normal equations, Eq. (11), for the
+ * columns `support` [k] (device int32, strictly ascending, in [0, N)).
+ * theta [k] receives the solution on the support, in support order.
+ * x0 [k] (nullable) is the starting point (NULL: theta = 0, as in line 13).
+ */
+cs_status cs_ls_solve(cs_dtype dtype, const void* y, const cs_op* op, const int32_t* support,
+                      int32_t k, double tol, const void* x0, void* theta,
+                      const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                      hipStream_t stream);
+
+/* out [M] = A x for a dense x [N] (Sec. III-D: sign flip, DCT-II, row pick). */
+cs_status cs_apply_A(cs_dtype dtype, const cs_op* op, const void* x, void* out,
+                     void* ws, size_t ws_bytes, hipStream_t stream);
+/* out [N] = A^T u for u [M] (zero-fill, DCT-III, sign flip). */
+cs_status cs_apply_At(cs_dtype dtype, const cs_op* op, const void* u, void* out,
+                      void* ws, size_t ws_bytes, hipStream_t stream);
+
+const char* cs_status_str(cs_status status);
+const char* cs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CS_H */

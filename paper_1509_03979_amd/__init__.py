@@ -1,0 +1,237 @@
+"""Python binding of libcsrecover (CG-based greedy compressive-sensing recovery on MI355X).
+
+Argument marshalling only: every step of the recovery runs in the HIP library.
+PyTorch provides device memory and the stream; the functions below carry the
+same names as the C entry points in include/cs.h.
+
+    import torch, paper_1509_03979_amd as cs
+    op = cs.Operator(n, rows_dev_int32, signs_dev_int8)
+    s, support, info = cs.cs_recover_sp(y_dev, op, k, tol)
+
+The library must be built (``python -m paper_1509_03979_amd.build``); importing
+this package without it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcsrecover.so")
+
+CS_F32, CS_F64 = 0, 1
+CS_ALGO_OMP, CS_ALGO_SP, CS_ALGO_OMPR, CS_ALGO_OPERATOR, CS_ALGO_LS = 0, 1, 2, 3, 4
+CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, -3, -4, -5
+CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
+
+EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_ls_solve",
+           "cs_apply_A", "cs_apply_At", "cs_status_str", "cs_last_error")
+
+
+class cs_op(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("rows", ctypes.c_void_p),
+                ("signs", ctypes.c_void_p)]
+
+
+class cs_params(ctypes.Structure):
+    _fields_ = [("cg_max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ompr_eta", ctypes.c_double)]
+
+
+class cs_info(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int32), ("flags", ctypes.c_int32), ("cg_iters", ctypes.c_int64),
+                ("transforms", ctypes.c_int64), ("resid_norm", ctypes.c_double),
+                ("model_bytes", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class CSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def _load():
+    # torch ships its own HIP runtime (SONAME libamdhip64.so.7); load it first so
+    # the library binds to that same runtime instead of a second copy.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1509_03979_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    P = ctypes.POINTER
+    lib.cs_workspace_size.argtypes = [ctypes.c_int, i64, i64, i32, ctypes.c_int]
+    lib.cs_workspace_size.restype = sz
+    for name in ("cs_recover_omp", "cs_recover_sp", "cs_recover_ompr"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_int, vp, P(cs_op), i32, dbl, vp, vp, P(cs_params), vp, sz, P(cs_info), vp]
+        f.restype = ctypes.c_int
+    lib.cs_ls_solve.argtypes = [ctypes.c_int, vp, P(cs_op), vp, i32, dbl, vp, vp, P(cs_params), vp, sz,
+                                P(cs_info), vp]
+    lib.cs_ls_solve.restype = ctypes.c_int
+    for name in ("cs_apply_A", "cs_apply_At"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.c_int, P(cs_op), vp, vp, vp, sz, vp]
+        f.restype = ctypes.c_int
+    lib.cs_status_str.argtypes = [ctypes.c_int]
+    lib.cs_status_str.restype = ctypes.c_char_p
+    lib.cs_last_error.argtypes = []
+    lib.cs_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def cs_status_str(status: int) -> str:
+    return lib.cs_status_str(status).decode()
+
+
+def cs_last_error() -> str:
+    return lib.cs_last_error().decode()
+
+
+def cs_workspace_size(dtype: int, n: int, m: int, k: int, algo: int) -> int:
+    return int(lib.cs_workspace_size(dtype, n, m, k, algo))
+
+
+def _check(status: int):
+    if status != CS_OK:
+        raise CSError(status, f"{cs_status_str(status)}: {cs_last_error()}")
+
+
+# ---------------------------------------------------------------- torch-facing helpers
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return CS_F32
+    if t.dtype == torch.float64:
+        return CS_F64
+    raise TypeError("y must be float32 or float64")
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Operator:
+    """Sensing operator A = D F R (device descriptor): rows int32 [M] ascending, signs int8 [N]."""
+
+    def __init__(self, n: int, rows, signs):
+        torch = _torch()
+        if rows.dtype != torch.int32 or signs.dtype != torch.int8:
+            raise TypeError("rows must be int32 and signs int8")
+        if not (rows.is_cuda and signs.is_cuda):
+            raise ValueError("rows and signs must be device tensors")
+        self.n = int(n)
+        self.m = int(rows.numel())
+        self.rows = rows.contiguous()
+        self.signs = signs.contiguous()
+        self.c = cs_op(self.n, self.m, self.rows.data_ptr(), self.signs.data_ptr())
+
+    @classmethod
+    def from_numpy(cls, n, rows, signs, device="cuda"):
+        torch = _torch()
+        return cls(n, torch.as_tensor(rows, dtype=torch.int32, device=device),
+                   torch.as_tensor(signs, dtype=torch.int8, device=device))
+
+
+def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0):
+    return cs_params(int(cg_max_iter), int(max_outer), int(warm_start), 0, float(ompr_eta))
+
+
+def workspace(dtype_code: int, op: Operator, k: int, algo: int, device=None):
+    torch = _torch()
+    nbytes = cs_workspace_size(dtype_code, op.n, op.m, k, algo)
+    if nbytes == 0:
+        raise CSError(CS_E_SHAPE, "no workspace size for these arguments")
+    dev = device if device is not None else op.rows.device
+    # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+
+def _recover(fn, algo, y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
+    torch = _torch()
+    dt = _dtype_code(y)
+    y = y.contiguous()
+    if y.numel() != op.m or not y.is_cuda:
+        raise ValueError("y must be a device vector of length M")
+    s = torch.empty(op.n, dtype=y.dtype, device=y.device)
+    supp = torch.empty(k, dtype=torch.int32, device=y.device)
+    if ws is None:
+        ws = workspace(dt, op, k, algo, y.device)
+    info = cs_info()
+    prm = _params(**kw)
+    st = fn(dt, _ptr(y), ctypes.byref(op.c), int(k), float(tol), _ptr(s), _ptr(supp), ctypes.byref(prm),
+            _ptr(ws), ws.numel(), ctypes.byref(info), _stream_ptr(stream))
+    _check(st)
+    return s, supp, info.as_dict()
+
+
+def cs_recover_omp(y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
+    """OMP (Sec. II, Algorithm 1) -> (s [N], support [K] ascending, info)."""
+    return _recover(lib.cs_recover_omp, CS_ALGO_OMP, y, op, k, tol, ws, stream, **kw)
+
+
+def cs_recover_sp(y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
+    """Subspace Pursuit with CG least squares -> (s, support, info)."""
+    return _recover(lib.cs_recover_sp, CS_ALGO_SP, y, op, k, tol, ws, stream, **kw)
+
+
+def cs_recover_ompr(y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
+    """OMPR (l = 1) with CG least squares -> (s, support, info)."""
+    return _recover(lib.cs_recover_ompr, CS_ALGO_OMPR, y, op, k, tol, ws, stream, **kw)
+
+
+def cs_ls_solve(y, op: Operator, support, tol: float, x0=None, ws=None, stream=None, **kw):
+    """CG weighted least squares on `support` (Algorithm 1 lines 11-24) -> (theta [k], info)."""
+    torch = _torch()
+    dt = _dtype_code(y)
+    k = int(support.numel())
+    theta = torch.empty(k, dtype=y.dtype, device=y.device)
+    if ws is None:
+        ws = workspace(dt, op, k, CS_ALGO_LS, y.device)
+    info = cs_info()
+    prm = _params(**kw)
+    st = lib.cs_ls_solve(dt, _ptr(y.contiguous()), ctypes.byref(op.c), _ptr(support.contiguous()), k, float(tol),
+                         _ptr(x0.contiguous()) if x0 is not None else None, _ptr(theta), ctypes.byref(prm),
+                         _ptr(ws), ws.numel(), ctypes.byref(info), _stream_ptr(stream))
+    _check(st)
+    return theta, info.as_dict()
+
+
+def cs_apply_A(x, op: Operator, ws=None, stream=None):
+    """A x for a dense x [N] -> [M]."""
+    torch = _torch()
+    dt = _dtype_code(x)
+    out = torch.empty(op.m, dtype=x.dtype, device=x.device)
+    if ws is None:
+        ws = workspace(dt, op, 1, CS_ALGO_OPERATOR, x.device)
+    _check(lib.cs_apply_A(dt, ctypes.byref(op.c), _ptr(x.contiguous()), _ptr(out), _ptr(ws), ws.numel(),
+                          _stream_ptr(stream)))
+    return out
+
+
+def cs_apply_At(u, op: Operator, ws=None, stream=None):
+    """A^T u for u [M] -> [N]."""
+    torch = _torch()
+    dt = _dtype_code(u)
+    out = torch.empty(op.n, dtype=u.dtype, device=u.device)
+    if ws is None:
+        ws = workspace(dt, op, 1, CS_ALGO_OPERATOR, u.device)
+    _check(lib.cs_apply_At(dt, ctypes.byref(op.c), _ptr(u.contiguous()), _ptr(out), _ptr(ws), ws.numel(),
+                           _stream_ptr(stream)))
+    return out

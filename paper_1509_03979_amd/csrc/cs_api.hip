@@ -1,0 +1,339 @@
+// C ABI of libcsrecover: argument validation, workspace carving and the
+// entry points declared in include/cs.h.
+#include "cs_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+
+namespace csr {
+
+static thread_local std::string g_last_error;
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves the workspace (or, with base == nullptr, only measures it).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename P>
+  P* take(size_t count) {
+    off = align_up(off, 256);
+    P* p = base ? reinterpret_cast<P*>(base + off) : nullptr;
+    off += count * sizeof(P);
+    return p;
+  }
+};
+
+template <typename T>
+static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
+  Carver cv{base};
+  const int64_t n = p.n;
+  c.W = cv.take<Cx<T>>(p.L);
+  c.Dd = cv.take<T>(n);
+  c.Dx = cv.take<T>(n);
+  c.C0 = cv.take<T>(n);
+  c.Yf = cv.take<T>(n);
+  c.tw_sub = cv.take<Cx<T>>(kTwSub);
+  c.tw_lo = cv.take<Cx<T>>(kTwLo);
+  c.tw_hi = cv.take<Cx<T>>(std::max<int64_t>(1, 4 * n / kTwLo));
+  c.mask = cv.take<uint32_t>(p.words);
+  for (int i = 0; i < 3; ++i) c.bits[i] = cv.take<uint32_t>(p.words);
+  const size_t kk = (size_t)std::max(kmax, 1) + 1;
+  for (int i = 0; i < 3; ++i) c.list[i] = cv.take<int32_t>(kk);
+  c.cb = cv.take<T>(kk);
+  c.cx = cv.take<T>(kk);
+  c.cr = cv.take<T>(kk);
+  c.cd = cv.take<T>(kk);
+  c.cq = cv.take<T>(kk);
+  c.cx2 = cv.take<T>(kk);
+  c.cx3 = cv.take<T>(kk);
+  c.partial = cv.take<double>(4 * kRedBlocks);
+  c.partial2 = cv.take<double>(std::max<int64_t>(kRedBlocks, p.L1));
+  c.argpart = cv.take<ArgKey>(kArgBlocks);
+  c.ibuf = cv.take<int32_t>(64);
+  c.blockcnt = cv.take<uint32_t>((p.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords + 2);
+  c.cg = cv.take<CgScalars>(1);
+  c.sel = cv.take<SelState>(1);
+  return align_up(cv.off, 256);
+}
+
+static int kmax_for(cs_algo algo, int32_t k) {
+  switch (algo) {
+    case CS_ALGO_SP: return 2 * k;
+    case CS_ALGO_OMPR: return k + 1;
+    case CS_ALGO_OPERATOR: return 1;
+    default: return k;
+  }
+}
+
+size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo) {
+  Plan p;
+  if (!choose_plan(dt, n, m, p)) return 0;
+  if (dt == CS_F32) { Ctx<float> c{}; return carve(c, p, kmax_for(algo, k), nullptr); }
+  Ctx<double> c{};
+  return carve(c, p, kmax_for(algo, k), nullptr);
+}
+
+template <typename T>
+void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s) {
+  Plan p;
+  const cs_dtype dt = sizeof(T) == 4 ? CS_F32 : CS_F64;
+  if (!choose_plan(dt, op->n, op->m, p)) throw Error(CS_E_SHAPE, "unsupported N");
+  const size_t need = carve(c, p, kmax, nullptr);
+  if (ws_bytes < need) throw Error(CS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  carve(c, p, kmax, (char*)ws);
+  p.tw_sub = c.tw_sub;
+  p.tw_lo = c.tw_lo;
+  p.tw_hi = c.tw_hi;
+  p.mask = c.mask;
+  c.plan = p;
+  c.stream = s;
+  c.signs = op->signs;
+  c.rows = op->rows;
+  c.kmax = kmax;
+  prepare_kernels<T>();
+}
+
+// ------------------------------------------------------------------ validation
+static void check_shape(cs_dtype dt, const cs_op* op, int32_t k, cs_algo algo) {
+  if (dt != CS_F32 && dt != CS_F64) throw Error(CS_E_INVALID, "dtype must be CS_F32 or CS_F64");
+  if (!op || !op->rows || !op->signs) throw Error(CS_E_INVALID, "null operator descriptor");
+  const int64_t n = op->n, m = op->m;
+  if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) throw Error(CS_E_SHAPE, "N must be a power of two in [16, 2^26]");
+  if (m < 1 || m > n) throw Error(CS_E_SHAPE, "M must satisfy 1 <= M <= N");
+  if (algo == CS_ALGO_OPERATOR) return;
+  if (k < 1) throw Error(CS_E_INVALID, "K must be >= 1");
+  if (k > m) throw Error(CS_E_SHAPE, "K must not exceed M");
+  if (algo == CS_ALGO_SP && (int64_t)2 * k > m) throw Error(CS_E_SHAPE, "SP needs 2K <= M");
+}
+
+static void check_tol(double tol) {
+  if (!(tol > 0.0) || !std::isfinite(tol)) throw Error(CS_E_INVALID, "tol must be positive and finite");
+}
+
+static void check_ws(void* ws) {
+  if (!ws) throw Error(CS_E_WORKSPACE, "null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) throw Error(CS_E_WORKSPACE, "workspace must be 256-byte aligned");
+}
+
+static cs_params defaults(const cs_params* p) {
+  cs_params d{};
+  d.cg_max_iter = 0;
+  d.max_outer = 0;
+  d.warm_start = 1;
+  d.ompr_eta = 0.0;
+  if (p) {
+    d.cg_max_iter = p->cg_max_iter;
+    d.max_outer = p->max_outer;
+    d.warm_start = p->warm_start;
+    d.ompr_eta = p->ompr_eta;
+  }
+  return d;
+}
+
+// Loads y: freq-layout copy, ||y||, and c0 = A^T y (raw v-order) into C0.
+template <typename T>
+static void load_measurements(Ctx<T>& c, const T* y) {
+  scatter_freq<T>(c, y, c.Yf);
+  c.ynorm = norm2_host<T>(c, y, c.plan.m);
+  transform_adj<T>(c, c.Yf);
+  CS_HIP(hipMemcpyAsync(c.C0, c.W, sizeof(T) * c.plan.n, hipMemcpyDeviceToDevice, c.stream));
+}
+
+template <typename T>
+static void fill_info(Ctx<T>& c, cs_info* info) {
+  if (!info) return;
+  info->flags = c.flags;
+  info->cg_iters = c.cg_iters;
+  info->transforms = c.transforms;
+  info->model_bytes = c.model_bytes;
+}
+
+template <typename T>
+static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, double tol, void* s, int32_t* support,
+                      const cs_params* params, void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream) {
+  Ctx<T> c{};
+  ctx_init<T>(c, op, kmax_for(algo, k), ws, ws_bytes, stream);
+  setup_operator<T>(c);
+  load_measurements<T>(c, (const T*)y);
+  const cs_params prm = defaults(params);
+  cs_info loc{};
+  cs_info* inf = info ? info : &loc;
+  std::memset(inf, 0, sizeof(cs_info));
+  if (algo == CS_ALGO_OMP) run_omp<T>(c, k, tol, prm, (T*)s, support, inf);
+  else if (algo == CS_ALGO_SP) run_sp<T>(c, k, tol, prm, (T*)s, support, inf);
+  else run_ompr<T>(c, k, tol, prm, (T*)s, support, inf);
+  CS_HIP(hipStreamSynchronize(stream));
+  fill_info<T>(c, inf);
+}
+
+static cs_status recover(cs_algo algo, cs_dtype dt, const void* y, const cs_op* op, int32_t k, double tol, void* s,
+                         int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                         hipStream_t stream) {
+  try {
+    check_shape(dt, op, k, algo);
+    if (!y || !s || !support) throw Error(CS_E_INVALID, "null y, s or support");
+    check_tol(tol);
+    check_ws(ws);
+    if (dt == CS_F32) recover_t<float>(algo, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+    else recover_t<double>(algo, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
+}
+
+// ------------------------------------------------------------------ support validation for cs_ls_solve
+__global__ void k_check_support(const int32_t* __restrict__ sup, int k, int64_t n, int32_t* bad) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const int32_t j = sup[i];
+  if (j < 0 || j >= n || (i > 0 && sup[i - 1] >= j)) atomicOr(bad, 1);
+}
+
+template <typename T>
+static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t k, double tol, const void* x0,
+                 void* theta, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream) {
+  Ctx<T> c{};
+  ctx_init<T>(c, op, k, ws, ws_bytes, stream);
+  setup_operator<T>(c);
+  fill<int32_t>(c.ibuf + 16, 1, 0, stream);
+  hipLaunchKernelGGL(k_check_support, dim3((k + 255) / 256), dim3(256), 0, stream, support, k, op->n, c.ibuf + 16);
+  CS_LAUNCH_CHECK();
+  int32_t bad = 0;
+  CS_HIP(hipMemcpyAsync(&bad, c.ibuf + 16, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  CS_HIP(hipStreamSynchronize(stream));
+  if (bad) throw Error(CS_E_INVALID, "support must be strictly ascending in [0, N)");
+  load_measurements<T>(c, (const T*)y);
+  const cs_params prm = defaults(params);
+  if (x0) CS_HIP(hipMemcpyAsync(theta, x0, sizeof(T) * k, hipMemcpyDeviceToDevice, stream));
+  const int cap = prm.cg_max_iter > 0 ? prm.cg_max_iter : 2 * k + 50;
+  cg_solve<T>(c, support, k, (T*)theta, x0 != nullptr, tol, cap);
+  double rn = 0.0;
+  if (info) rn = resid_corr<T>(c, nullptr, 0, support, (const T*)theta, k);
+  CS_HIP(hipStreamSynchronize(stream));
+  if (info) {
+    std::memset(info, 0, sizeof(cs_info));
+    info->resid_norm = rn;
+    fill_info<T>(c, info);
+  }
+}
+
+template <typename T>
+static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, void* ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  Ctx<T> c{};
+  ctx_init<T>(c, op, 1, ws, ws_bytes, stream);
+  setup_operator<T>(c);
+  if (!adjoint) {
+    perm_in<T>(c, (const T*)in, c.Dx);
+    transform_fwd<T>(c, c.Dx, c.Yf);
+    gather_freq<T>(c, c.Yf, (T*)out);
+  } else {
+    scatter_freq<T>(c, (const T*)in, c.Yf);
+    transform_adj<T>(c, c.Yf);
+    perm_out<T>(c, (const T*)c.W, (T*)out);
+  }
+  CS_HIP(hipStreamSynchronize(stream));
+}
+
+}  // namespace csr
+
+using namespace csr;
+
+extern "C" {
+
+size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_algo algo) {
+  if (dtype != CS_F32 && dtype != CS_F64) return 0;
+  if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1)) || m < 1 || m > n) return 0;
+  if (algo != CS_ALGO_OPERATOR && (k < 1 || k > m)) return 0;
+  if (algo < CS_ALGO_OMP || algo > CS_ALGO_LS) return 0;
+  return workspace_bytes(dtype, n, m, k, algo);
+}
+
+cs_status cs_recover_omp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,
+                         int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                         hipStream_t stream) {
+  return recover(CS_ALGO_OMP, dtype, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+}
+
+cs_status cs_recover_sp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,
+                        int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                        hipStream_t stream) {
+  return recover(CS_ALGO_SP, dtype, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+}
+
+cs_status cs_recover_ompr(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,
+                          int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                          hipStream_t stream) {
+  return recover(CS_ALGO_OMPR, dtype, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+}
+
+cs_status cs_ls_solve(cs_dtype dtype, const void* y, const cs_op* op, const int32_t* support, int32_t k, double tol,
+                      const void* x0, void* theta, const cs_params* params, void* ws, size_t ws_bytes,
+                      cs_info* info, hipStream_t stream) {
+  try {
+    check_shape(dtype, op, k, CS_ALGO_LS);
+    if (!y || !support || !theta) throw Error(CS_E_INVALID, "null y, support or theta");
+    check_tol(tol);
+    check_ws(ws);
+    if (dtype == CS_F32) ls_t<float>(y, op, support, k, tol, x0, theta, params, ws, ws_bytes, info, stream);
+    else ls_t<double>(y, op, support, k, tol, x0, theta, params, ws, ws_bytes, info, stream);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
+}
+
+static cs_status apply_entry(bool adjoint, cs_dtype dtype, const cs_op* op, const void* in, void* out, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  try {
+    check_shape(dtype, op, 1, CS_ALGO_OPERATOR);
+    if (!in || !out) throw Error(CS_E_INVALID, "null input or output");
+    check_ws(ws);
+    if (dtype == CS_F32) apply_t<float>(adjoint, op, in, out, ws, ws_bytes, stream);
+    else apply_t<double>(adjoint, op, in, out, ws, ws_bytes, stream);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
+}
+
+cs_status cs_apply_A(cs_dtype dtype, const cs_op* op, const void* x, void* out, void* ws, size_t ws_bytes,
+                     hipStream_t stream) {
+  return apply_entry(false, dtype, op, x, out, ws, ws_bytes, stream);
+}
+
+cs_status cs_apply_At(cs_dtype dtype, const cs_op* op, const void* u, void* out, void* ws, size_t ws_bytes,
+                      hipStream_t stream) {
+  return apply_entry(true, dtype, op, u, out, ws, ws_bytes, stream);
+}
+
+const char* cs_status_str(cs_status status) {
+  switch (status) {
+    case CS_OK: return "ok";
+    case CS_E_INVALID: return "invalid argument";
+    case CS_E_SHAPE: return "unsupported shape";
+    case CS_E_OP: return "invalid operator descriptor";
+    case CS_E_WORKSPACE: return "workspace too small or misaligned";
+    case CS_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* cs_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,385 @@
+// Selection subsystem: support detection (Eq. (6), Algorithm 1 line 03) and
+// the top-K selections of SP and OMPR.
+//
+// Every selection ranks candidates by (magnitude descending, index ascending).
+// Magnitudes are compared through their IEEE bit patterns, which order like the
+// values for non-negative numbers; a key of 0 marks an excluded candidate and
+// every admissible key is bits(|v|) + 1.
+//  * argmax: packed keys (bits + 1, ~index) reduced with wavefront shuffles.
+//  * top-K: MSB-first radix select, 8 bits per pass, on the magnitude key;
+//    if the K-th key is shared by more candidates than are still needed, a
+//    second radix select over the indices (ascending) keeps the lowest ones.
+//    Selected indices are marked in an N-bit bitmap and compacted to a sorted
+//    list with a block prefix sum, so supports come out ascending.
+#include "cs_internal.h"
+
+#include <algorithm>
+
+namespace csr {
+
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
+
+template <typename T> __device__ __forceinline__ uint64_t mag_bits(T v);
+template <> __device__ __forceinline__ uint64_t mag_bits<float>(float v) { return (uint64_t)__float_as_uint(fabsf(v)); }
+template <> __device__ __forceinline__ uint64_t mag_bits<double>(double v) {
+  return (uint64_t)__double_as_longlong(fabs(v));
+}
+template <typename T> __device__ __forceinline__ bool finite_v(T v) { return isfinite(v); }
+
+__device__ __forceinline__ bool bit_of(const uint32_t* __restrict__ b, int64_t j) {
+  return (b[j >> 5] >> (j & 31)) & 1u;
+}
+
+__device__ __forceinline__ bool key_gt(const ArgKey& a, const ArgKey& b) {
+  return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo);
+}
+
+__device__ __forceinline__ ArgKey shfl_down_key(ArgKey k, int off) {
+  ArgKey r;
+  r.hi = __shfl_down((unsigned long long)k.hi, off, 64);
+  r.lo = __shfl_down(k.lo, off, 64);
+  r.pad = 0;
+  return r;
+}
+
+// Block-wide max of ArgKey; result valid in thread 0.
+__device__ __forceinline__ ArgKey block_max_key(ArgKey best) {
+  __shared__ ArgKey sh[16];
+  for (int off = 32; off > 0; off >>= 1) {
+    ArgKey o = shfl_down_key(best, off);
+    if (key_gt(o, best)) best = o;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+      if (key_gt(sh[i], best)) best = sh[i];
+  }
+  return best;
+}
+
+// ------------------------------------------------------------------ argmax outside a set
+template <typename T>
+__global__ void k_argmax_partial(const T* __restrict__ dense, const uint32_t* __restrict__ excl, int64_t n,
+                                 ArgKey* __restrict__ part, SelState* sel) {
+  ArgKey best{0, 0, 0};
+  bool bad = false;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += st) {
+    const int64_t j = vinv(p, n);
+    if (excl && bit_of(excl, j)) continue;
+    const T v = dense[p];
+    bad |= !finite_v(v);
+    ArgKey k{mag_bits(v) + 1, 0xFFFFFFFFu - (uint32_t)j, 0};
+    if (key_gt(k, best)) best = k;
+  }
+  if (bad) atomicOr(&sel->nonfinite, 1);
+  best = block_max_key(best);
+  if (threadIdx.x == 0) part[blockIdx.x] = best;
+}
+
+__global__ void k_argmax_final(const ArgKey* __restrict__ part, int np, int32_t* out_j) {
+  ArgKey best{0, 0, 0};
+  for (int i = threadIdx.x; i < np; i += blockDim.x)
+    if (key_gt(part[i], best)) best = part[i];
+  best = block_max_key(best);
+  if (threadIdx.x == 0) *out_j = best.hi ? (int32_t)(0xFFFFFFFFu - best.lo) : -1;
+}
+
+template <typename T>
+void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j) {
+  const int64_t n = c.plan.n;
+  const unsigned grid = (unsigned)std::min<int64_t>(kArgBlocks, nblk(n, 256));
+  hipLaunchKernelGGL(k_argmax_partial<T>, dim3(grid), dim3(256), 0, c.stream, dense, excl, n, c.argpart, c.sel);
+  CS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, c.stream, c.argpart, (int)grid, out_j);
+  CS_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ radix select
+// Candidate sources.  Dense: position p of a v-order vector, index vinv(p),
+// excluded through a bitmap.  Compact: entry i of vals, index list[i].
+struct DenseSrc {};
+struct CompactSrc {};
+
+template <typename T, typename S>
+__device__ __forceinline__ void cand(const T* __restrict__ vals, const void* __restrict__ aux, int64_t i, int64_t n,
+                                     uint64_t& key, uint32_t& j, bool& bad) {
+  if constexpr (std::is_same<S, DenseSrc>::value) {
+    const uint32_t* excl = (const uint32_t*)aux;
+    j = (uint32_t)vinv(i, n);
+    if (excl && bit_of(excl, j)) { key = 0; return; }
+    const T v = vals[i];
+    bad |= !finite_v(v);
+    key = mag_bits(v) + 1;
+  } else {
+    const int32_t* list = (const int32_t*)aux;
+    j = (uint32_t)list[i];
+    const T v = vals[i];
+    bad |= !finite_v(v);
+    key = mag_bits(v) + 1;
+  }
+}
+
+__global__ void k_sel_init(SelState* sel, int64_t need) {
+  if (threadIdx.x == 0) {
+    sel->prefix = 0; sel->pmask = 0; sel->need = need; sel->count_eq = 0;
+    sel->jprefix = 0; sel->jmask = 0; sel->jneed = 0; sel->tie = 0; sel->nonfinite = 0;
+  }
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) sel->hist[i] = 0;
+}
+
+// phase 0: histogram of key digit at `shift` among keys matching the prefix.
+// phase 1: histogram of index digit among keys equal to the threshold whose
+//          index matches the index prefix (only when the tie-break is active).
+template <typename T, typename S, int PHASE>
+__global__ void k_radix_hist(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, int64_t n,
+                             SelState* sel, int shift) {
+  __shared__ uint32_t h[256];
+  if (PHASE == 1 && !sel->tie) return;
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const uint64_t prefix = sel->prefix, pmask = sel->pmask;
+  const uint32_t jprefix = sel->jprefix, jmask = sel->jmask;
+  bool bad = false;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
+    uint64_t key; uint32_t j;
+    cand<T, S>(vals, aux, i, n, key, j, bad);
+    if (PHASE == 0) {
+      if ((key & pmask) == prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
+    } else {
+      if (key == prefix && (j & jmask) == jprefix) atomicAdd(&h[(j >> shift) & 255u], 1u);
+    }
+  }
+  if (PHASE == 0 && bad) atomicOr(&sel->nonfinite, 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x)
+    if (h[i]) atomicAdd(&sel->hist[i], h[i]);
+}
+
+template <int PHASE>
+__global__ void k_radix_pick(SelState* sel, int shift) {
+  if (threadIdx.x == 0) {
+    if (PHASE == 0) {
+      int64_t need = sel->need, cum = 0;
+      for (int d = 255; d >= 0; --d) {
+        const int64_t c = sel->hist[d];
+        if (cum + c >= need) {
+          sel->need = need - cum;
+          sel->prefix |= (uint64_t)d << shift;
+          sel->pmask |= (uint64_t)255 << shift;
+          if (shift == 0) {
+            sel->count_eq = c;
+            sel->tie = (sel->need < c) ? 1 : 0;
+            sel->jneed = sel->need;
+          }
+          break;
+        }
+        cum += c;
+      }
+    } else if (sel->tie) {
+      int64_t need = sel->jneed, cum = 0;
+      for (int d = 0; d < 256; ++d) {
+        const int64_t c = sel->hist[d];
+        if (cum + c >= need) {
+          sel->jneed = need - cum;
+          sel->jprefix |= (uint32_t)d << shift;
+          sel->jmask |= 255u << shift;
+          break;
+        }
+        cum += c;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) sel->hist[i] = 0;
+}
+
+template <typename T, typename S>
+__global__ void k_radix_mark(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, int64_t n,
+                             const SelState* __restrict__ sel, uint32_t* __restrict__ bits) {
+  const uint64_t tau = sel->prefix;
+  const int tie = sel->tie;
+  const uint32_t jt = sel->jprefix;
+  bool bad = false;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
+    uint64_t key; uint32_t j;
+    cand<T, S>(vals, aux, i, n, key, j, bad);
+    if (key == 0) continue;
+    if (key > tau || (key == tau && (!tie || j <= jt))) atomicOr(&bits[j >> 5], 1u << (j & 31));
+  }
+}
+
+template <typename T, typename S>
+static void radix_topk(Ctx<T>& c, const T* vals, const void* aux, int64_t count, int k, uint32_t* out_bits) {
+  hipStream_t s = c.stream;
+  const int64_t n = c.plan.n;
+  const unsigned grid = (unsigned)std::min<int64_t>(1024, nblk(count, 256));
+  fill_u32(out_bits, c.plan.words, 0u, s);
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c.sel, (int64_t)k);
+  CS_LAUNCH_CHECK();
+  const int width = (sizeof(T) == 4) ? 32 : 64;
+  for (int shift = width - 8; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL((k_radix_hist<T, S, 0>), dim3(grid), dim3(256), 0, s, vals, aux, count, n, c.sel, shift);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_radix_pick<0>, dim3(1), dim3(256), 0, s, c.sel, shift);
+    CS_LAUNCH_CHECK();
+  }
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hipLaunchKernelGGL((k_radix_hist<T, S, 1>), dim3(grid), dim3(256), 0, s, vals, aux, count, n, c.sel, shift);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_radix_pick<1>, dim3(1), dim3(256), 0, s, c.sel, shift);
+    CS_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL((k_radix_mark<T, S>), dim3(grid), dim3(256), 0, s, vals, aux, count, n, c.sel, out_bits);
+  CS_LAUNCH_CHECK();
+}
+
+template <typename T>
+void topk_dense(Ctx<T>& c, const T* dense, const uint32_t* excl, int k, uint32_t* out_bits) {
+  radix_topk<T, DenseSrc>(c, dense, excl, c.plan.n, k, out_bits);
+}
+
+template <typename T>
+void topk_compact(Ctx<T>& c, const T* vals, const int32_t* list, int count, int k, uint32_t* out_bits) {
+  radix_topk<T, CompactSrc>(c, vals, list, count, k, out_bits);
+}
+
+// ------------------------------------------------------------------ bitmaps
+__global__ void k_bits_or(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, uint32_t* __restrict__ o,
+                          int64_t words) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) o[i] = a[i] | b[i];
+}
+void bits_or(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t words, hipStream_t s) {
+  hipLaunchKernelGGL(k_bits_or, dim3(nblk(words, 256)), dim3(256), 0, s, a, b, out, words);
+  CS_LAUNCH_CHECK();
+}
+
+__global__ void k_bits_set_list(uint32_t* __restrict__ bits, const int32_t* __restrict__ list, int k) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) {
+    const uint32_t j = (uint32_t)list[i];
+    atomicOr(&bits[j >> 5], 1u << (j & 31));
+  }
+}
+void bits_set_list(uint32_t* bits, const int32_t* list, int k, hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(k_bits_set_list, dim3(nblk(k, 256)), dim3(256), 0, s, bits, list, k);
+  CS_LAUNCH_CHECK();
+}
+
+__global__ void k_bits_diff(const uint32_t* __restrict__ a, const uint32_t* __restrict__ b, int64_t words,
+                            int32_t* flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words && a[i] != b[i]) *flag = 1;
+}
+int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, hipStream_t s) {
+  fill<int32_t>(scratch, 1, 0, s);
+  hipLaunchKernelGGL(k_bits_diff, dim3(nblk(words, 256)), dim3(256), 0, s, a, b, words, scratch);
+  CS_LAUNCH_CHECK();
+  int32_t h = 0;
+  CS_HIP(hipMemcpyAsync(&h, scratch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  CS_HIP(hipStreamSynchronize(s));
+  return h == 0;
+}
+
+// Bitmap -> ascending index list.  Block b covers words [1024 b, 1024 b + 1024).
+__global__ void k_bits_count(const uint32_t* __restrict__ bits, int64_t words, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t red[4];
+  const int64_t w0 = (int64_t)blockIdx.x * kBitsPerBlockWords;
+  uint32_t s = 0;
+  for (int i = threadIdx.x; i < kBitsPerBlockWords; i += blockDim.x) {
+    const int64_t w = w0 + i;
+    if (w < words) s += __popc(bits[w]);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// exclusive scan of cnt[0..nb) in place (single block, 1024 threads); total -> cnt[nb]
+__global__ void k_bits_scan(uint32_t* cnt, int nb) {
+  __shared__ uint32_t sh[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = (i < nb) ? cnt[i] : 0u;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) cnt[i] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[nb] = carry;
+}
+
+// 256 threads, 4 words each.
+__global__ void k_bits_write(const uint32_t* __restrict__ bits, int64_t words, const uint32_t* __restrict__ cnt,
+                             int32_t* __restrict__ list, int limit) {
+  __shared__ uint32_t sh[256];
+  const int64_t w0 = (int64_t)blockIdx.x * kBitsPerBlockWords + threadIdx.x * 4;
+  uint32_t wv[4];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    wv[q] = (w0 + q < words) ? bits[w0 + q] : 0u;
+    mine += __popc(wv[q]);
+  }
+  sh[threadIdx.x] = mine;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t pos = cnt[blockIdx.x] + sh[threadIdx.x] - mine;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t v = wv[q];
+    while (v) {
+      const int b = __ffs(v) - 1;
+      v &= v - 1;
+      if ((int)pos < limit) list[pos] = (int32_t)((w0 + q) * 32 + b);
+      ++pos;
+    }
+  }
+}
+
+template <typename T>
+int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect) {
+  const int64_t words = c.plan.words;
+  const int nb = (int)((words + kBitsPerBlockWords - 1) / kBitsPerBlockWords);
+  hipStream_t s = c.stream;
+  hipLaunchKernelGGL(k_bits_count, dim3(nb), dim3(256), 0, s, bits, words, c.blockcnt);
+  CS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_bits_scan, dim3(1), dim3(1024), 0, s, c.blockcnt, nb);
+  CS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_bits_write, dim3(nb), dim3(256), 0, s, bits, words, c.blockcnt, list, expect);
+  CS_LAUNCH_CHECK();
+  return nb;   // total count is left in blockcnt[nb]
+}
+
+#define CS_INST(T)                                                                        \
+  template void argmax_excl<T>(Ctx<T>&, const T*, const uint32_t*, int32_t*);           \
+  template void topk_dense<T>(Ctx<T>&, const T*, const uint32_t*, int, uint32_t*);      \
+  template void topk_compact<T>(Ctx<T>&, const T*, const int32_t*, int, int, uint32_t*); \
+  template int bits_to_list<T>(Ctx<T>&, const uint32_t*, int32_t*, int);
+CS_INST(float)
+CS_INST(double)
+
+}  // namespace csr

@@ -1,0 +1,106 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments on the host before any device work, and
+sizes its workspace as O(N + K)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1509_03979_amd as cs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "cs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cs_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = header_functions()
+    assert set(names) == set(cs.EXPORTS)
+    for name in names:
+        assert hasattr(cs.lib, name), name
+
+
+def test_status_strings():
+    for st in (cs.CS_OK, cs.CS_E_INVALID, cs.CS_E_SHAPE, cs.CS_E_OP, cs.CS_E_WORKSPACE, cs.CS_E_HIP):
+        assert cs.cs_status_str(st) and cs.cs_status_str(st) != "unknown status"
+    assert cs.cs_status_str(99) == "unknown status"
+
+
+def test_workspace_is_linear_in_n_and_k():
+    sz = lambda n, k, algo=cs.CS_ALGO_SP, dt=cs.CS_F32: cs.cs_workspace_size(dt, n, n // 4, k, algo)
+    for dt in (cs.CS_F32, cs.CS_F64):
+        a, b = sz(2 ** 20, 4096, dt=dt), sz(2 ** 21, 4096, dt=dt)
+        assert 1.9 < b / a < 2.1
+        esz = 4 if dt == cs.CS_F32 else 8
+        # about five dense N-vectors plus bitmaps
+        assert 5 * esz * 2 ** 20 <= a <= 7 * esz * 2 ** 20
+        k1, k2 = sz(2 ** 20, 1000, dt=dt), sz(2 ** 20, 31000, dt=dt)
+        assert 0 < k2 - k1 <= 30000 * 2 * (3 * 4 + 7 * esz) + 8192
+    assert cs.cs_workspace_size(cs.CS_F32, 1000, 100, 10, cs.CS_ALGO_SP) == 0     # N not a power of two
+    assert cs.cs_workspace_size(cs.CS_F32, 1024, 2000, 10, cs.CS_ALGO_SP) == 0    # M > N
+    assert cs.cs_workspace_size(cs.CS_F32, 1024, 100, 0, cs.CS_ALGO_SP) == 0      # K < 1
+    assert cs.cs_workspace_size(7, 1024, 100, 10, cs.CS_ALGO_SP) == 0             # bad dtype
+    assert cs.cs_workspace_size(cs.CS_F32, 2 ** 27, 100, 10, cs.CS_ALGO_SP) == 0  # N too large
+    assert cs.cs_workspace_size(cs.CS_F32, 8, 4, 1, cs.CS_ALGO_SP) == 0           # N too small
+
+
+FAKE = 4096          # a 256-aligned fake device address: never dereferenced on these paths
+
+
+def _call(fn, dt=cs.CS_F32, n=1024, m=256, k=10, tol=1e-6, y=FAKE, s=FAKE, supp=FAKE, ws=FAKE,
+          ws_bytes=1 << 40, rows=FAKE, signs=FAKE, op=True):
+    o = cs.cs_op(n, m, rows, signs)
+    return fn(dt, ctypes.c_void_p(y) if y else None, ctypes.byref(o) if op else None, k, tol,
+              ctypes.c_void_p(s) if s else None, ctypes.c_void_p(supp) if supp else None, None,
+              ctypes.c_void_p(ws) if ws else None, ws_bytes, None, None)
+
+
+@pytest.mark.parametrize("fn", [cs.lib.cs_recover_omp, cs.lib.cs_recover_sp, cs.lib.cs_recover_ompr])
+def test_host_validation(fn):
+    assert _call(fn, dt=5) == cs.CS_E_INVALID
+    assert _call(fn, op=False) == cs.CS_E_INVALID
+    assert _call(fn, rows=0) == cs.CS_E_INVALID
+    assert _call(fn, n=1000) == cs.CS_E_SHAPE
+    assert _call(fn, n=2 ** 27, m=100) == cs.CS_E_SHAPE
+    assert _call(fn, m=2000) == cs.CS_E_SHAPE
+    assert _call(fn, m=0) == cs.CS_E_SHAPE
+    assert _call(fn, k=0) == cs.CS_E_INVALID
+    assert _call(fn, k=300) == cs.CS_E_SHAPE
+    assert _call(fn, y=0) == cs.CS_E_INVALID
+    assert _call(fn, s=0) == cs.CS_E_INVALID
+    assert _call(fn, supp=0) == cs.CS_E_INVALID
+    assert _call(fn, tol=0.0) == cs.CS_E_INVALID
+    assert _call(fn, tol=-1.0) == cs.CS_E_INVALID
+    assert _call(fn, tol=float("nan")) == cs.CS_E_INVALID
+    assert _call(fn, tol=float("inf")) == cs.CS_E_INVALID
+    assert _call(fn, ws=0) == cs.CS_E_WORKSPACE
+    assert _call(fn, ws=FAKE + 8) == cs.CS_E_WORKSPACE
+    assert _call(fn, ws_bytes=100) == cs.CS_E_WORKSPACE
+    assert cs.cs_last_error()
+
+
+def test_sp_needs_2k_le_m():
+    assert _call(cs.lib.cs_recover_sp, m=256, k=129) == cs.CS_E_SHAPE
+    assert _call(cs.lib.cs_recover_ompr, m=256, k=129, ws_bytes=100) == cs.CS_E_WORKSPACE  # passes shape checks
+
+
+def test_apply_and_ls_validation():
+    o = cs.cs_op(1000, 10, FAKE, FAKE)
+    assert cs.lib.cs_apply_A(cs.CS_F32, ctypes.byref(o), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                             ctypes.c_void_p(FAKE), 1 << 30, None) == cs.CS_E_SHAPE
+    o = cs.cs_op(1024, 10, FAKE, FAKE)
+    assert cs.lib.cs_apply_At(cs.CS_F64, ctypes.byref(o), None, ctypes.c_void_p(FAKE),
+                              ctypes.c_void_p(FAKE), 1 << 30, None) == cs.CS_E_INVALID
+    assert cs.lib.cs_apply_At(cs.CS_F64, ctypes.byref(o), ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE),
+                              ctypes.c_void_p(FAKE), 10, None) == cs.CS_E_WORKSPACE
+    assert cs.lib.cs_ls_solve(cs.CS_F32, ctypes.c_void_p(FAKE), ctypes.byref(o), ctypes.c_void_p(FAKE), 11, 1e-6,
+                              None, ctypes.c_void_p(FAKE), None, ctypes.c_void_p(FAKE), 1 << 30, None,
+                              None) == cs.CS_E_SHAPE
+    assert cs.lib.cs_ls_solve(cs.CS_F32, ctypes.c_void_p(FAKE), ctypes.byref(o), ctypes.c_void_p(FAKE), 5, 0.0,
+                              None, ctypes.c_void_p(FAKE), None, ctypes.c_void_p(FAKE), 1 << 30, None,
+                              None) == cs.CS_E_INVALID

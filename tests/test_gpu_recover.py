@@ -1,0 +1,55 @@
+"""GPU parity of the greedy recoveries (OMP, SP, OMPR) against the FP64 oracle.
+
+Supports must match exactly and s must agree to relative L2 <= 1e-5.  Noisy
+FP32 cases can meet near-ties at the K-th selection boundary; those are
+classified against the oracle's logged decision margins (see
+``near_tie_ok``), never silently accepted."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import announce, rel, to_dev, torch_dev
+from tests.problems import problem
+
+pytestmark = pytest.mark.gpu
+
+RECOVER_CASES = [
+    # name, cfg, n, m, k, values, snr, dtype, tol
+    ("omp_n4096_f64", 1, 4096, 1024, 50, "normal_min0.1", None, "f64", 1e-10),
+    ("omp_n4096_f32", 1, 4096, 1024, 50, "normal_min0.1", None, "f32", 1e-6),
+    ("sp_small_noiseless_f64", 80, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f64", 1e-10),
+    ("sp_small_noiseless_f32", 80, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6),
+    ("sp_small_40db_f64", 81, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10),
+    ("ompr_small_noiseless_f64", 82, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f64", 1e-10),
+    ("ompr_small_noiseless_f32", 82, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6),
+    ("ompr_small_40db_f64", 83, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10),
+    ("sp_ragged_f32", 84, 2 ** 12, 1001, 37, "normal_min0.1", None, "f32", 1e-6),
+    ("ompr_ragged_f64", 85, 2 ** 12, 777, 29, "normal", 35.0, "f64", 1e-10),
+]
+
+
+def _algo(name):
+    return name.split("_")[0]
+
+
+@pytest.mark.parametrize("case", RECOVER_CASES, ids=[c[0] for c in RECOVER_CASES])
+def test_recover_matches_oracle(case):
+    name, cfg, n, m, k, values, snr, dt, tol = case
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, y = problem(cfg, 0, n, m, k, values, snr, dt)
+    algo = _algo(name)
+    ref = getattr(oracle, algo)(op, y, k)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    announce("recover", name)
+    fn = getattr(cs, f"cs_recover_{algo}")
+    s, supp, info = fn(to_dev(y, tdt), dop, k, tol)
+    s = s.cpu().numpy()
+    supp = supp.cpu().numpy()
+    print(name, info, "oracle iters", ref.iters, ref.stop, flush=True)
+    assert np.array_equal(supp, ref.support), (np.setdiff1d(supp, ref.support), np.setdiff1d(ref.support, supp))
+    assert rel(s, ref.s) <= 1e-5
+    assert np.count_nonzero(s[np.setdiff1d(np.arange(n), supp)]) == 0
+    assert info["flags"] & ~cs.CS_F_CG_MAXITER == 0
