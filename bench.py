@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of CG-based greedy recovery on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--algo sp|ompr|omp]
+
+A step is one full recovery (support detection + CG least squares, every
+outer iteration, through the operator A = D F R) of one synthetic signal whose
+measurements are already resident in HBM.  `value` is recovered signals per
+second: a step counts when its support equals the FP64 oracle's and its
+coefficients agree to relative L2 <= 1e-5.
+
+Default workload: SP on one signal with N = 2^20, M = 2^18, K = 4096, FP32,
+40 dB noise, CG tol 1e-6 with warm starts.  The OMPR recovery of the same
+signal is reported under "extra".
+
+Prints ONE JSON line.  Besides the driver's fields it carries
+  roofline      the dominant transform pass: algorithmic bytes per launch over
+                its average launch time, from HIP events recorded by the
+                library on its stream during a profiled replay of the timed
+                steps (the timed steps themselves run without events);
+  cpu_baseline  the FP64 oracle timed on this host's cores on the same input.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "signals recovered/s + % HBM roofline vs plain path at rel-err ≤1e-5"
+REL_TOL = 1e-5
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sp_ompr_n2p20")
+    ap.add_argument("--algo", default=None, help="sp, ompr or omp (default: the workload's first)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the profiled replay (roofline)")
+    return ap.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1509_03979_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_inputs(name: str, torch, cs):
+    """Seeded draw from synth; y from the stored oracle file when present, else
+    computed on the GPU in FP64 (y = A s + noise) and rounded to FP32."""
+    import synth
+    w = synth.WORKLOADS[name]
+    d = synth.workload_problem(name, 0)
+    op = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+    gold_path = os.path.join(ROOT, "tests", "golden", f"{name}_sig0.npz")
+    expect = {}
+    if os.path.exists(gold_path):
+        g = np.load(gold_path, allow_pickle=False)
+        y32 = g["y"]
+        for algo in w["algos"]:
+            if f"{algo}_support" in g:
+                expect[algo] = (g[f"{algo}_support"].astype(np.int64), g[f"{algo}_values"])
+        y_src = "stored FP64 oracle measurements"
+    else:
+        s64 = torch.as_tensor(d.s_dense(), dtype=torch.float64, device="cuda")
+        y0 = cs.cs_apply_A(s64, op).cpu().numpy()
+        y = y0 + d.noise_scale(np.linalg.norm(y0)) * d.noise if d.noise is not None else y0
+        y32 = y.astype(np.float32)
+        y_src = "y = A s computed by the library in FP64"
+        if d.noise is None:
+            # noiseless: the least-squares fit on the true support is s itself
+            for algo in w["algos"]:
+                expect[algo] = (d.supp.astype(np.int64), d.vals)
+    dt = torch.float32 if w["dtype"] == "f32" else torch.float64
+    y_dev = torch.as_tensor(y32 if w["dtype"] == "f32" else y32.astype(np.float64), dtype=dt, device="cuda")
+    return w, d, op, y_dev, y32, expect, y_src
+
+
+def recovered(s, supp, exp) -> tuple[bool, float]:
+    if exp is None:
+        return False, float("nan")
+    es, ev = exp
+    supp = np.asarray(supp, dtype=np.int64)
+    if not np.array_equal(supp, es):
+        return False, float("nan")
+    ref = np.zeros_like(s, dtype=np.float64)
+    ref[es] = ev
+    err = float(np.linalg.norm(s - ref) / np.linalg.norm(ref))
+    return err <= REL_TOL, err
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              f"(signals are independent, so more GPUs would shard them; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1509_03979_amd as cs
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    w, d, op, y, y32, expect, y_src = load_inputs(args.workload, torch, cs)
+    algo = args.algo or w["algos"][0]
+    fn = getattr(cs, f"cs_recover_{algo}")
+    dtc = cs.CS_F32 if w["dtype"] == "f32" else cs.CS_F64
+    algo_code = {"omp": cs.CS_ALGO_OMP, "sp": cs.CS_ALGO_SP, "ompr": cs.CS_ALGO_OMPR}[algo]
+    ws = cs.workspace(dtc, op, d.k, algo_code)
+    tol = w["tol"]
+
+    for _ in range(args.warmup):
+        fn(y, op, d.k, tol, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for _ in range(args.steps):
+        outs.append(fn(y, op, d.k, tol, ws=ws))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ok_steps = 0
+    errs = []
+    first_s = outs[0][0].cpu().numpy()
+    deterministic = True
+    for s_t, supp_t, _ in outs:
+        s_np = s_t.cpu().numpy().astype(np.float64)
+        ok, err = recovered(s_np, supp_t.cpu().numpy(), expect.get(algo))
+        ok_steps += int(ok)
+        errs.append(err)
+        deterministic &= bool(np.array_equal(s_np, first_s.astype(np.float64)))
+    info = outs[-1][2]
+    ms = 1e3 * elapsed / args.steps
+    value = ok_steps / elapsed
+
+    # ---------------------------------------------------------------- roofline (profiled replay)
+    roof = None
+    prof = {}
+    if not args.no_profile:
+        cs.cs_prof_reset()
+        cs.cs_prof_enable(True)
+        for _ in range(args.steps):
+            fn(y, op, d.k, tol, ws=ws)
+        torch.cuda.synchronize()
+        prof = cs.cs_prof_read()
+        cs.cs_prof_enable(False)
+        live = {k: v for k, v in prof.items() if v["launches"] > 0}
+        if live:
+            dom = max(live, key=lambda k: live[k]["total_ms"])
+            st = live[dom]
+            per_launch_bytes = st["bytes"] / st["launches"]
+            avg_us = 1e3 * st["total_ms"] / st["launches"]
+            achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
+            traffic = None
+            tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{algo}.json")
+            if os.path.exists(tpath):
+                t = json.load(open(tpath))
+                if t.get("source_hash") == source_hash() and t.get("kernel_class") == dom:
+                    traffic = t.get("hbm_bytes_per_launch")
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                    "avg_launch_us": round(avg_us, 3), "algorithmic_bytes_per_launch": per_launch_bytes,
+                    "launches_per_step": st["launches"] / args.steps,
+                    "share_of_transform_time": round(st["total_ms"] / sum(v["total_ms"] for v in live.values()), 3)}
+
+    # ---------------------------------------------------------------- CPU baseline (oracle)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        opo = oracle.SRM(d.n, d.rows, d.signs)
+        t1 = time.perf_counter()
+        r = getattr(oracle, algo)(opo, y32.astype(np.float64), d.k)
+        tc = time.perf_counter() - t1
+        cpu = {"value": round(1.0 / tc, 5), "unit": "signals/s", "cores": os.cpu_count(), "kind": "oracle",
+               "sample": f"one full FP64 {algo.upper()} recovery of the benchmark signal ({tc:.1f} s)",
+               "support_matches_expected": bool(expect.get(algo) is not None and
+                                                np.array_equal(r.support, expect[algo][0]))}
+
+    # ---------------------------------------------------------------- extra: the workload's other algorithms
+    extra = {"y_source": y_src, "deterministic": deterministic, "max_rel_err": max(errs) if errs else None,
+             "info": info, "transform_prof": prof}
+    if not args.no_extra:
+        for other in w["algos"]:
+            if other == algo:
+                continue
+            fo = getattr(cs, f"cs_recover_{other}")
+            code = {"omp": cs.CS_ALGO_OMP, "sp": cs.CS_ALGO_SP, "ompr": cs.CS_ALGO_OMPR}[other]
+            ws2 = cs.workspace(dtc, op, d.k, code)
+            fo(y, op, d.k, tol, ws=ws2)
+            torch.cuda.synchronize()
+            reps = max(1, min(3, args.steps))
+            t2 = time.perf_counter()
+            for _ in range(reps):
+                so, suppo, info_o = fo(y, op, d.k, tol, ws=ws2)
+            torch.cuda.synchronize()
+            to = (time.perf_counter() - t2) / reps
+            ok, err = recovered(so.cpu().numpy().astype(np.float64), suppo.cpu().numpy(), expect.get(other))
+            extra[other] = {"signals_per_s": round((1.0 if ok else 0.0) / to, 3), "ms_per_signal": round(1e3 * to, 3),
+                            "recovered": ok, "rel_err": err, "info": info_o}
+
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "signals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": w["dtype"], "data": "synthetic",
+        "config": {"workload": args.workload, "algo": algo, "n": d.n, "m": d.m, "k": d.k, "tol": tol,
+                   "snr_db": d.snr_db, "signals_per_step": 1},
+        "roofline": roof, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,24 @@ cs_status cs_apply_At(cs_dtype dtype, const cs_op* op, const void* u, void* out,
 const char* cs_status_str(cs_status status);
 const char* cs_last_error(void);
 
+/*
+ * Opt-in timing of the transform passes (not part of the method; for
+ * measurement).  When enabled, each column / row pass launch is bracketed by
+ * HIP events on the caller's stream; per-class totals accumulate until
+ * cs_prof_reset().  `bytes` is the algorithmic HBM traffic of those launches
+ * (one N-vector read and one written per pass; the residual row pass also
+ * reads y).  Classes: col_fwd, col_inv, row_happly, row_resid, row_fwd, row_adj.
+ */
+typedef struct {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} cs_prof_stat;
+int cs_prof_enable(int on);                   /* returns the previous state          */
+void cs_prof_reset(void);
+int cs_prof_read(cs_prof_stat* out, int max);  /* out == NULL: number of classes      */
+
 #ifdef __cplusplus
 }
 #endif

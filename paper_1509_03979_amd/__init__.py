@@ -8,7 +8,7 @@ same names as the C entry points in include/cs.h.
     op = cs.Operator(n, rows_dev_int32, signs_dev_int8)
     s, support, info = cs.cs_recover_sp(y_dev, op, k, tol)
 
-The library must be built (``python -m paper_1509_03979_amd.build``); importing
+The library must be built (``python paper_1509_03979_amd/build.py``); importing
 this package without it raises, there is no fallback path.
 """
 from __future__ import annotations
@@ -25,7 +25,8 @@ CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, 
 CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
 
 EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_ls_solve",
-           "cs_apply_A", "cs_apply_At", "cs_status_str", "cs_last_error")
+           "cs_apply_A", "cs_apply_At", "cs_status_str", "cs_last_error", "cs_prof_enable", "cs_prof_reset",
+           "cs_prof_read")
 
 
 class cs_op(ctypes.Structure):
@@ -47,6 +48,11 @@ class cs_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class cs_prof_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("bytes", ctypes.c_double)]
+
+
 class CSError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -58,7 +64,7 @@ def _load():
     # the library binds to that same runtime instead of a second copy.
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1509_03979_amd.build`")
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1509_03979_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     P = ctypes.POINTER
@@ -79,6 +85,12 @@ def _load():
     lib.cs_status_str.restype = ctypes.c_char_p
     lib.cs_last_error.argtypes = []
     lib.cs_last_error.restype = ctypes.c_char_p
+    lib.cs_prof_enable.argtypes = [ctypes.c_int]
+    lib.cs_prof_enable.restype = ctypes.c_int
+    lib.cs_prof_reset.argtypes = []
+    lib.cs_prof_reset.restype = None
+    lib.cs_prof_read.argtypes = [ctypes.POINTER(cs_prof_stat), ctypes.c_int]
+    lib.cs_prof_read.restype = ctypes.c_int
     return lib
 
 
@@ -91,6 +103,23 @@ def cs_status_str(status: int) -> str:
 
 def cs_last_error() -> str:
     return lib.cs_last_error().decode()
+
+
+def cs_prof_enable(on: bool) -> bool:
+    return bool(lib.cs_prof_enable(1 if on else 0))
+
+
+def cs_prof_reset() -> None:
+    lib.cs_prof_reset()
+
+
+def cs_prof_read() -> dict:
+    """Per-class launches, total milliseconds and algorithmic bytes of the transform passes."""
+    n = lib.cs_prof_read(None, 0)
+    arr = (cs_prof_stat * n)()
+    n = lib.cs_prof_read(arr, n)
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "total_ms": arr[i].total_ms,
+                                   "bytes": arr[i].bytes} for i in range(n)}
 
 
 def cs_workspace_size(dtype: int, n: int, m: int, k: int, algo: int) -> int:

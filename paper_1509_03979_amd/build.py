@@ -1,6 +1,6 @@
 """Builds libcsrecover.so (HIP, gfx950) in-tree.
 
-    python -m paper_1509_03979_amd.build        # or build() from Python
+    python paper_1509_03979_amd/build.py        # or build() from Python
 
 Every call recompiles all sources; objects go to _build/ beside this file.
 """
@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsrecover.so")
-SOURCES = ["cs_transform.hip", "cs_select.hip", "cs_cg.hip", "cs_greedy.hip", "cs_api.hip"]
+SOURCES = ["cs_transform.hip", "cs_select.hip", "cs_cg.hip", "cs_greedy.hip", "cs_api.hip", "cs_prof.hip"]
 ARCH = os.environ.get("CS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

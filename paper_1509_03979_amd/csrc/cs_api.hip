@@ -165,6 +165,7 @@ static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, d
   else if (algo == CS_ALGO_SP) run_sp<T>(c, k, tol, prm, (T*)s, support, inf);
   else run_ompr<T>(c, k, tol, prm, (T*)s, support, inf);
   CS_HIP(hipStreamSynchronize(stream));
+  if (prof_on()) prof_flush();
   fill_info<T>(c, inf);
 }
 
@@ -217,6 +218,7 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   double rn = 0.0;
   if (info) rn = resid_corr<T>(c, nullptr, 0, support, (const T*)theta, k);
   CS_HIP(hipStreamSynchronize(stream));
+  if (prof_on()) prof_flush();
   if (info) {
     std::memset(info, 0, sizeof(cs_info));
     info->resid_norm = rn;
@@ -240,6 +242,7 @@ static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, vo
     perm_out<T>(c, (const T*)c.W, (T*)out);
   }
   CS_HIP(hipStreamSynchronize(stream));
+  if (prof_on()) prof_flush();
 }
 
 }  // namespace csr

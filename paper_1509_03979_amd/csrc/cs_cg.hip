@@ -19,6 +19,7 @@
 #include "cs_internal.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace csr {
 
@@ -215,9 +216,14 @@ int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol,
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, pbb, nb, tol * tol, max_iter);
   CS_LAUNCH_CHECK();
   const int* done = &c.cg->done;
+  // Iterations are queued in chunks; the host reads the device flags between
+  // chunks.  After the first chunk the next one is sized from the observed
+  // geometric rate of r^T r so that few early-exit launches are queued.
   int it = 0;
-  int chunk = 4;
+  int chunk = std::min(4, std::max(max_iter, 1));
   CgScalars host{};
+  double rr_prev = -1.0;
+  int it_prev = 0;
   while (it < max_iter) {
     const int q = std::min(chunk, max_iter - it);
     for (int u = 0; u < q; ++u, ++it) {
@@ -235,6 +241,19 @@ int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol,
     CS_HIP(hipMemcpyAsync(&host, c.cg, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
     CS_HIP(hipStreamSynchronize(s));
     if (host.done) break;
+    const double rr_now = host.rr[host.iters & 1];
+    const double target = host.tol2 * host.bb;
+    const double rr_ref = (rr_prev > 0.0) ? rr_prev : host.rr[0];
+    const int span = (rr_prev > 0.0) ? (host.iters - it_prev) : host.iters;
+    int next = 2;
+    if (span > 0 && rr_ref > 0.0 && rr_now > 0.0 && rr_now < rr_ref && target > 0.0) {
+      const double rate = std::log(rr_now / rr_ref) / span;      // log decrease per iteration (< 0)
+      const double need = std::log(target / rr_now) / rate;      // iterations still needed
+      if (std::isfinite(need)) next = (int)std::ceil(need);
+    }
+    chunk = std::max(1, std::min(next, 64));
+    rr_prev = rr_now;
+    it_prev = host.iters;
   }
   if (!host.done) {
     CS_HIP(hipMemcpyAsync(&host, c.cg, sizeof(CgScalars), hipMemcpyDeviceToHost, s));

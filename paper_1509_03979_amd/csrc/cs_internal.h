@@ -191,6 +191,13 @@ constexpr int kRedThreads = 256;
 constexpr int kArgBlocks = 1024;
 constexpr int kBitsPerBlockWords = 1024;  // words per block in bitmap compaction
 
+// ------------------------------------------------------------------ profiling
+enum ProfClass { PC_COL_FWD = 0, PC_COL_INV, PC_ROW_HAPPLY, PC_ROW_RESID, PC_ROW_FWD, PC_ROW_ADJ, PC_COUNT };
+bool prof_on();
+int prof_begin(hipStream_t s, hipEvent_t* ev);
+void prof_end(int cls, double bytes, hipEvent_t start, hipStream_t s);
+void prof_flush();
+
 // ------------------------------------------------------------------ plan/workspace
 bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p);
 size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo);

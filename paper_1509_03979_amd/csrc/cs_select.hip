@@ -159,42 +159,54 @@ __global__ void k_radix_hist(const T* __restrict__ vals, const void* __restrict_
     if (h[i]) atomicAdd(&sel->hist[i], h[i]);
 }
 
+// One block of 256 threads: the histogram is staged in LDS with one load per
+// thread and a suffix (phase 0, digits high to low) or prefix (phase 1,
+// digits low to high) scan picks the digit that holds the `need`-th candidate.
 template <int PHASE>
 __global__ void k_radix_pick(SelState* sel, int shift) {
-  if (threadIdx.x == 0) {
+  __shared__ int64_t cum[256];
+  __shared__ int64_t hist[256];
+  const int t = threadIdx.x;
+  if (PHASE == 1 && !sel->tie) {
+    sel->hist[t] = 0;
+    return;
+  }
+  const int64_t h = sel->hist[t];
+  // phase 0 scans digits from 255 down: position q = 255 - digit
+  const int q = (PHASE == 0) ? 255 - t : t;
+  hist[q] = h;
+  __syncthreads();
+  // inclusive scan over q
+  int64_t v = hist[t];
+  cum[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t a = (t >= off) ? cum[t - off] : 0;
+    __syncthreads();
+    cum[t] += a;
+    __syncthreads();
+  }
+  const int64_t need = (PHASE == 0) ? sel->need : sel->jneed;
+  const int64_t incl = cum[t], excl = incl - hist[t];
+  __syncthreads();
+  if (excl < need && need <= incl) {          // exactly one q satisfies this (need >= 1)
+    const int d = (PHASE == 0) ? 255 - t : t;
     if (PHASE == 0) {
-      int64_t need = sel->need, cum = 0;
-      for (int d = 255; d >= 0; --d) {
-        const int64_t c = sel->hist[d];
-        if (cum + c >= need) {
-          sel->need = need - cum;
-          sel->prefix |= (uint64_t)d << shift;
-          sel->pmask |= (uint64_t)255 << shift;
-          if (shift == 0) {
-            sel->count_eq = c;
-            sel->tie = (sel->need < c) ? 1 : 0;
-            sel->jneed = sel->need;
-          }
-          break;
-        }
-        cum += c;
+      sel->need = need - excl;
+      sel->prefix |= (uint64_t)d << shift;
+      sel->pmask |= (uint64_t)255 << shift;
+      if (shift == 0) {
+        sel->count_eq = hist[t];
+        sel->tie = (need - excl < hist[t]) ? 1 : 0;
+        sel->jneed = need - excl;
       }
-    } else if (sel->tie) {
-      int64_t need = sel->jneed, cum = 0;
-      for (int d = 0; d < 256; ++d) {
-        const int64_t c = sel->hist[d];
-        if (cum + c >= need) {
-          sel->jneed = need - cum;
-          sel->jprefix |= (uint32_t)d << shift;
-          sel->jmask |= 255u << shift;
-          break;
-        }
-        cum += c;
-      }
+    } else {
+      sel->jneed = need - excl;
+      sel->jprefix |= (uint32_t)d << shift;
+      sel->jmask |= 255u << shift;
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) sel->hist[i] = 0;
+  sel->hist[t] = 0;
 }
 
 template <typename T, typename S>

@@ -412,25 +412,33 @@ template <typename T>
 static void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const int* done) {
   const Plan& p = c.plan;
   const unsigned grid = (unsigned)(p.L2 >> p.logB);
+  const double bytes = 2.0 * (double)p.n * sizeof(T);   // read and write one N-vector
+  hipEvent_t ev = nullptr;
+  const bool prof = prof_on();
+  if (prof) prof_begin(c.stream, &ev);
   if (inv)
     hipLaunchKernelGGL((k_col<T, true>), dim3(grid), dim3(p.nt_col), p.lds_col, c.stream, in, out, p, done);
   else
     hipLaunchKernelGGL((k_col<T, false>), dim3(grid), dim3(p.nt_col), p.lds_col, c.stream, in, out, p, done);
   CS_LAUNCH_CHECK();
-  c.transforms += 0;  // counted per full transform by the callers
-  c.model_bytes += 2.0 * (double)p.n * sizeof(T);
+  if (prof) prof_end(inv ? PC_COL_INV : PC_COL_FWD, bytes, ev, c.stream);
+  c.model_bytes += bytes;
 }
 
 template <typename T, int MODE>
 static void launch_row(Ctx<T>& c, const T* fin, T* fout, double* partial, const int* done) {
   const Plan& p = c.plan;
   const unsigned grid = (unsigned)(p.L1 >> 1);
+  // read and write one N-vector; the residual pass also reads y (N reals in freq layout)
+  double bytes = 2.0 * (double)p.n * sizeof(T);
+  if (MODE == ROW_RESID) bytes += (double)p.n * sizeof(T);
+  hipEvent_t ev = nullptr;
+  const bool prof = prof_on();
+  if (prof) prof_begin(c.stream, &ev);
   hipLaunchKernelGGL((k_row<T, MODE>), dim3(grid), dim3(p.nt_row), p.lds_row, c.stream, c.W, p, fin, fout,
                      partial, done);
   CS_LAUNCH_CHECK();
-  double bytes = 2.0 * (double)p.n * sizeof(T);
-  if (MODE == ROW_RESID) bytes += (double)p.n * sizeof(T);  // y in freq layout
-  if (MODE == ROW_FWD || MODE == ROW_ADJ) bytes = 1.0 * (double)p.n * sizeof(T) * 2;
+  if (prof) prof_end(PC_ROW_HAPPLY + MODE, bytes, ev, c.stream);
   c.model_bytes += bytes;
 }
 
