@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsrecover.so")
-SOURCES = ["cs_transform.hip", "cs_select.hip", "cs_cg.hip", "cs_greedy.hip", "cs_api.hip", "cs_prof.hip"]
+SOURCES = ["cs_inst_f32.hip", "cs_inst_f64.hip", "cs_transform.hip", "cs_select.hip", "cs_cg.hip", "cs_greedy.hip",
+           "cs_api.hip", "cs_prof.hip"]
 ARCH = os.environ.get("CS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -45,7 +46,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    workers = min(len(SOURCES), max(1, (os.cpu_count() or 2) // 2))
+    workers = min(len(SOURCES), max(1, os.cpu_count() or 2))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

@@ -34,7 +34,8 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   c.Dx = cv.take<T>(n);
   c.C0 = cv.take<T>(n);
   c.Yf = cv.take<T>(n);
-  c.tw_sub = cv.take<Cx<T>>(kTwSub);
+  c.tw_col = cv.take<Cx<T>>(kTwStage);
+  c.tw_row = cv.take<Cx<T>>(kTwStage);
   c.tw_lo = cv.take<Cx<T>>(kTwLo);
   c.tw_hi = cv.take<Cx<T>>(std::max<int64_t>(1, 4 * n / kTwLo));
   c.mask = cv.take<uint32_t>(p.words);
@@ -83,7 +84,6 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   const size_t need = carve(c, p, kmax, nullptr);
   if (ws_bytes < need) throw Error(CS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   carve(c, p, kmax, (char*)ws);
-  p.tw_sub = c.tw_sub;
   p.tw_lo = c.tw_lo;
   p.tw_hi = c.tw_hi;
   p.mask = c.mask;

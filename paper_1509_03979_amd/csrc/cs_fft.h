@@ -1,20 +1,55 @@
-// Workgroup-cooperative FFTs held in LDS.
+// Workgroup-cooperative FFTs held in LDS, with every size, stride and thread
+// count fixed at compile time.
 //
-// A set of `count` independent length-n FFTs sits in LDS; element e of FFT f
-// is at buf[e * es + f * fs].  The transform runs as a sequence of Stockham
-// autosort stages (radix 16/8/4/2, Govindaraju et al., SC'08 formulation):
-// stage with span Ns reads the R inputs of butterfly j at j + r n/R, applies
-// twiddles W_{Ns R}^{r (j mod Ns)}, does an R-point DFT in registers and
-// writes output r to (j / Ns) Ns R + (j mod Ns) + r Ns.  Each stage reads all
-// its inputs into registers, synchronises, then writes in place, so one LDS
-// buffer suffices.  Output is in natural order.
+// A set of CNT independent length-N FFTs sits in LDS.  Two layouts are used:
+//   column-major (CM): element e of FFT f at e * CNT + f  (column strips)
+//   row-major:         element e of FFT f at e + f * N    (row pairs)
+// The transform is a sequence of Stockham autosort stages (Govindaraju et al.,
+// SC'08 formulation): the stage of span NS reads the R inputs of butterfly j
+// at j + r N/R, multiplies input r by W_{NS R}^{r (j mod NS)}, does an R-point
+// DFT in registers and writes output r to (j / NS) NS R + (j mod NS) + r NS.
+// Radix 16 while at least 4 bits remain, then one radix 8/4/2 stage.  A stage
+// reads all its inputs into registers, synchronises, then writes in place.
+// Output is in natural order.  Forward uses exp(-2 pi i ...), inverse
+// exp(+2 pi i ...), both unnormalised.
 //
-// Forward = exp(-2 pi i ...) kernel, inverse = exp(+2 pi i ...), unnormalised.
+// LDS addresses are padded by one element every 16 (lp): radix-16 writes
+// have a 16-element lane stride, which unpadded sends a wave's lanes to the
+// same banks.  Because every displacement used below is either a multiple
+// of 16 or smaller than 16 from a 16-aligned base, lp(base + d) = lp(base)
+// + d + d/16, so each access is a per-thread base plus an immediate offset.
+//
+// Stage twiddles come from a per-size table laid out stage after stage, each
+// stage as [k][r-1] = W_{NS R}^{r k} (k < NS, 1 <= r < R), so the R-1 factors
+// of a butterfly are contiguous.
 #pragma once
 
 #include "cs_internal.h"
 
 namespace csr {
+
+__device__ __forceinline__ int lp(int a) { return a + (a >> 4); }
+__host__ __device__ constexpr int lp_size(int n) { return n + (n >> 4) + 1; }
+
+__host__ __device__ constexpr int stage_lr(int logn, int logns) {
+  return (logn - logns) >= 4 ? 4 : (logn - logns);
+}
+__host__ __device__ constexpr int tw_stage_count(int logn, int logns) {
+  return logns == 0 ? 0 : (1 << logns) * ((1 << stage_lr(logn, logns)) - 1);
+}
+// offset of stage `logns` in the table of size-2^logn FFTs
+__host__ __device__ constexpr int tw_stage_offset(int logn, int logns) {
+  int off = 0, ns = 0;
+  while (ns < logns) {
+    off += tw_stage_count(logn, ns);
+    ns += stage_lr(logn, ns);
+  }
+  return off;
+}
+__host__ __device__ constexpr int tw_table_count(int logn) { return tw_stage_offset(logn, logn); }
+
+// threads per workgroup for E elements (16 per thread, at least one wave)
+__host__ __device__ constexpr int nt_for(int e) { return e / 16 < 64 ? 64 : (e / 16 > 1024 ? 1024 : e / 16); }
 
 template <typename T, bool INV>
 __device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) {   // a * (-i) forward, a * (+i) inverse
@@ -43,7 +78,6 @@ __device__ __forceinline__ void dft8(Cx<T>* a) {
   const T h = (T)0.70710678118654752440;
   dft4<T, INV>(a[0], a[2], a[4], a[6]);
   dft4<T, INV>(a[1], a[3], a[5], a[7]);
-  // odd outputs times W_8^k, k = 0..3
   Cx<T> o1 = a[3], o2 = a[5], o3 = a[7];
   // W_8^1 = (1 - i)/sqrt2 forward, (1 + i)/sqrt2 inverse
   o1 = INV ? cx(h * (o1.re - o1.im), h * (o1.re + o1.im)) : cx(h * (o1.re + o1.im), h * (o1.im - o1.re));
@@ -72,8 +106,10 @@ __device__ __forceinline__ void dft16(Cx<T>* a) {
   const T ci[8] = {(T)0, s1, h, c1, (T)1, c1, h, s1};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    Cx<T> w = cx(cr[k], sg * ci[k]);
-    Cx<T> t = (k == 0) ? o[0] : cmul(o[k], w);
+    Cx<T> t;
+    if (k == 0) t = o[0];
+    else if (k == 4) t = mul_mi<T, INV>(o[4]);
+    else t = cmul(o[k], cx(cr[k], sg * ci[k]));
     a[k] = e[k] + t;
     a[k + 8] = e[k] - t;
   }
@@ -87,42 +123,42 @@ __device__ __forceinline__ void dft_r(Cx<T>* a) {
   else dft16<T, INV>(a);
 }
 
-template <int R> struct LogR;
-template <> struct LogR<2> { static constexpr int v = 1; };
-template <> struct LogR<4> { static constexpr int v = 2; };
-template <> struct LogR<8> { static constexpr int v = 3; };
-template <> struct LogR<16> { static constexpr int v = 4; };
-
-// One radix-R Stockham stage.  F_FAST selects the thread-to-butterfly map:
-// true  -> consecutive threads take consecutive FFTs (use when fs == 1),
-// false -> consecutive threads take consecutive butterflies (use when es == 1).
-template <typename T, int R, bool INV, bool F_FAST, int MAXB>
-__device__ __forceinline__ void fft_stage(Cx<T>* buf, int logn, int logNs, int logcount, int es, int fs,
-                                          const Cx<T>* __restrict__ twsub) {
-  constexpr int LR = LogR<R>::v;
-  const int lognb = logn - LR;
-  const int nb = 1 << lognb;
-  const int total = nb << logcount;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int Ns = 1 << logNs;
-  // twiddle W_{Ns R}^{m} = W_{8192}^{m * 8192 / (Ns R)}
-  const int twshift = kTwSubLog - (logNs + LR);
+template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGNS>
+__device__ __forceinline__ void ct_stage(Cx<T>* buf, const Cx<T>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN, CNT = 1 << LOGCNT;
+  constexpr int LR = stage_lr(LOGN, LOGNS), R = 1 << LR;
+  constexpr int NB = N >> LR, TOTAL = NB * CNT;
+  constexpr int MAXB = (TOTAL + NT - 1) / NT;
+  constexpr int NS = 1 << LOGNS;
+  constexpr int ES = CM ? CNT : 1, FS = CM ? 1 : N;
+  constexpr int TWOFF = tw_stage_offset(LOGN, LOGNS);
+  constexpr bool RD_FAST = ((NB * ES) % 16) == 0;
+  constexpr bool WR_FAST = ((NS * ES) % 16) == 0;
+  constexpr bool WR_SMALL = (NS == 1) && (ES == 1) && (R == 16) && (FS % 16 == 0);
+  const int tid = threadIdx.x;
   Cx<T> v[MAXB][R];
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int w = tid + q * nt;
-    if (w < total) {
+    const int w = tid + q * NT;
+    if (TOTAL % NT == 0 || w < TOTAL) {
       int j, f;
-      if (F_FAST) { f = w & ((1 << logcount) - 1); j = w >> logcount; }
-      else { j = w & (nb - 1); f = w >> lognb; }
-      const int base = j * es + f * fs;
+      if (CM) { f = w & (CNT - 1); j = w >> LOGCNT; }
+      else { j = w & (NB - 1); f = w >> (LOGN - LR); }
+      const int base = j * ES + f * FS;
+      if (RD_FAST) {
+        const int pb = lp(base);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[base + r * nb * es];
-      if (logNs > 0) {
-        const int k = j & (Ns - 1);
+        for (int r = 0; r < R; ++r) v[q][r] = buf[pb + r * NB * ES + ((r * NB * ES) >> 4)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = buf[lp(base + r * NB * ES)];
+      }
+      if (LOGNS > 0) {
+        const int k = j & (NS - 1);
+        const Cx<T>* tp = tw + TWOFF + k * (R - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> t = twsub[(r * k) << twshift];
+          const Cx<T> t = tp[r - 1];
           v[q][r] = INV ? cmulc(v[q][r], t) : cmul(v[q][r], t);
         }
       }
@@ -132,42 +168,36 @@ __device__ __forceinline__ void fft_stage(Cx<T>* buf, int logn, int logNs, int l
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < MAXB; ++q) {
-    const int w = tid + q * nt;
-    if (w < total) {
+    const int w = tid + q * NT;
+    if (TOTAL % NT == 0 || w < TOTAL) {
       int j, f;
-      if (F_FAST) { f = w & ((1 << logcount) - 1); j = w >> logcount; }
-      else { j = w & (nb - 1); f = w >> lognb; }
-      const int k = j & (Ns - 1);
-      const int d = ((j >> logNs) << (logNs + LR)) + k;
-      const int base = d * es + f * fs;
+      if (CM) { f = w & (CNT - 1); j = w >> LOGCNT; }
+      else { j = w & (NB - 1); f = w >> (LOGN - LR); }
+      const int k = j & (NS - 1);
+      const int d = ((j >> LOGNS) << (LOGNS + LR)) + k;
+      const int base = d * ES + f * FS;
+      if (WR_FAST) {
+        const int pb = lp(base);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * Ns * es] = v[q][r];
+        for (int r = 0; r < R; ++r) buf[pb + r * NS * ES + ((r * NS * ES) >> 4)] = v[q][r];
+      } else if (WR_SMALL) {
+        const int pb = lp(base);           // base is a multiple of 16 and r < 16
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[pb + r] = v[q][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lp(base + r * NS * ES)] = v[q][r];
+      }
     }
   }
   __syncthreads();
 }
 
-// Full FFT of `1 << logcount` length-2^logn sequences in LDS, EPT elements per
-// thread at most (blockDim.x * EPT >= 2^(logn + logcount)).
-template <typename T, bool INV, bool F_FAST, int EPT>
-__device__ __forceinline__ void lds_fft(Cx<T>* buf, int logn, int logcount, int es, int fs,
-                                        const Cx<T>* __restrict__ twsub) {
-  int logNs = 0;
-  int rem = logn;
-  while (rem > 0) {
-    if (rem >= 4 && EPT >= 16) {
-      fft_stage<T, 16, INV, F_FAST, (EPT >= 16 ? EPT / 16 : 1)>(buf, logn, logNs, logcount, es, fs, twsub);
-      rem -= 4; logNs += 4;
-    } else if (rem >= 3) {
-      fft_stage<T, 8, INV, F_FAST, EPT / 8>(buf, logn, logNs, logcount, es, fs, twsub);
-      rem -= 3; logNs += 3;
-    } else if (rem == 2) {
-      fft_stage<T, 4, INV, F_FAST, EPT / 4>(buf, logn, logNs, logcount, es, fs, twsub);
-      rem -= 2; logNs += 2;
-    } else {
-      fft_stage<T, 2, INV, F_FAST, EPT / 2>(buf, logn, logNs, logcount, es, fs, twsub);
-      rem -= 1; logNs += 1;
-    }
+template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGNS = 0>
+__device__ __forceinline__ void ct_fft(Cx<T>* buf, const Cx<T>* __restrict__ tw) {
+  if constexpr (LOGNS < LOGN) {
+    ct_stage<T, INV, NT, LOGN, LOGCNT, CM, LOGNS>(buf, tw);
+    ct_fft<T, INV, NT, LOGN, LOGCNT, CM, LOGNS + stage_lr(LOGN, LOGNS)>(buf, tw);
   }
 }
 

@@ -75,14 +75,12 @@ struct Plan {
   int B, logB;            // column strip width of the column passes
   int nt_col, nt_row;     // threads per workgroup of the column / row passes
   size_t lds_col, lds_row;
-  const void* tw_sub;     // W_{8192}^k, k in [0, 8192)       (Cx<T>)
   const void* tw_lo;      // W_{4N}^i, i in [0, 4096)          (Cx<T>)
   const void* tw_hi;      // W_{4N}^{4096 h}, h in [0, 4N/4096) (Cx<T>)
   const uint32_t* mask;   // N bits in freq-layout: bit 2f+h = row sampled
 };
 
-constexpr int kTwSub = 8192;
-constexpr int kTwSubLog = 13;
+constexpr int kTwStage = 8192;   // entries reserved for one stage-twiddle table (size 2^13 needs 8176)
 constexpr int kTwLo = 4096;
 constexpr int kTwLoLog = 12;
 
@@ -163,7 +161,8 @@ struct Ctx {
   T* C0;                   // A^T y (raw, unsigned by the sign flip), dense
   T* Yf;                   // y in freq-layout (N reals)
   // twiddles and mask
-  Cx<T>* tw_sub; Cx<T>* tw_lo; Cx<T>* tw_hi;
+  Cx<T>* tw_col; Cx<T>* tw_row;   // stage twiddles of the L1- and L2-point FFTs
+  Cx<T>* tw_lo; Cx<T>* tw_hi;
   uint32_t* mask;
   // bitmaps over natural indices (N bits each)
   uint32_t* bits[3];

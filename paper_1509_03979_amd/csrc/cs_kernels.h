@@ -1,0 +1,337 @@
+// Transform pass kernels, specialised per four-step shape.
+//
+// Column pass k_col<T, INV, LOGL1, LOGB>: one workgroup owns a strip of
+// B = 2^LOGB adjacent columns of the L1 x L2 view of z and runs B length-L1
+// FFTs on it in LDS (column-major layout, so a global row segment of B
+// complex values maps to B consecutive LDS slots).
+//
+// Row pass k_row<T, LOGL2>: one workgroup owns a mirror row pair and runs
+// four-step twiddle -> row FFT -> DCT post-processing -> mask or residual ->
+// DCT pre-processing -> inverse row FFT -> conjugate twiddle; the mode (H-apply,
+// residual, forward-only, adjoint-only) is a uniform argument.
+#pragma once
+
+#include "cs_fft.h"
+
+namespace csr {
+
+// ------------------------------------------------------------------ shapes
+struct Shape {
+  int logL1, logL2, logB;
+};
+
+// Four-step split for an L = 2^l point complex FFT (N = 2^(l+1) real points).
+// Rows of L2 <= 8192 (FP32) / 4096 (FP64) complex fit two to a workgroup in
+// 136 KB of padded LDS; very large N keep L2 at that maximum so column strips
+// stay 16 x 8 B = 128 B wide; smaller N split evenly for parallelism.
+__host__ __device__ constexpr Shape shape_for(bool f64, int l) {
+  const int maxL2 = f64 ? 12 : 13;
+  const int maxE = f64 ? 8192 : 16384;
+  int logL1 = (l >= 22) ? (l - maxL2) : ((l - maxL2) > (l / 2) ? (l - maxL2) : (l / 2));
+  if (logL1 < 1) logL1 = 1;
+  const int logL2 = l - logL1;
+  int B = 16;
+  if (B > (1 << logL2)) B = 1 << logL2;
+  if (B > maxE / (1 << logL1)) B = maxE / (1 << logL1);
+  while (B > 4 && ((1 << logL2) / B) < 256) B >>= 1;
+  int logB = 0;
+  while ((1 << logB) < B) ++logB;
+  return Shape{logL1, logL2, logB};
+}
+
+constexpr int kMinL = 3;    // N = 16
+constexpr int kMaxL = 25;   // N = 2^26
+
+// ------------------------------------------------------------------ column pass
+template <typename T, bool INV, int LOGL1, int LOGB>
+__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB))) void k_col(const Cx<T>* __restrict__ in,
+                                                                      Cx<T>* __restrict__ out, Plan p,
+                                                                      const int* __restrict__ done,
+                                                                      const Cx<T>* __restrict__ tw) {
+  constexpr int E = 1 << (LOGL1 + LOGB), B = 1 << LOGB;
+  constexpr int NT = nt_for(E);
+  constexpr int EPT = (E + NT - 1) / NT;
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Cx<T>* buf = (Cx<T>*)smem_raw;
+  const int tid = threadIdx.x;
+  const int g = xcd_order(blockIdx.x, gridDim.x);
+  const size_t c0 = (size_t)g << LOGB;
+  const size_t L2 = (size_t)p.L2;
+  // thread tid handles e = tid + q NT: row n1 = e >> LOGB, column b = e & (B-1)
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + q * NT;
+    if (E % NT == 0 || e < E) buf[lp(e)] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
+  }
+  __syncthreads();
+  ct_fft<T, INV, NT, LOGL1, LOGB, true>(buf, tw);
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = tid + q * NT;
+    if (E % NT == 0 || e < E) out[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))] = buf[lp(e)];
+  }
+}
+
+// ------------------------------------------------------------------ row pass
+// Workgroup w owns rows ra = w, rb = L1 - w (w >= 1) or ra = 0, rb = L1/2 (w = 0).
+// Row r, element k2 holds Z[r + L1 k2]; the mirror bin L - k of k = r + L1 k2
+// is row L1 - r, element L2 - 1 - k2 (r >= 1) or row 0, element L2 - k2 (r = 0).
+//
+// Item t enumerates the bin pairs {k, L-k} of the two rows:
+//   w >= 1: t in [0, L2): (ra, t) with (rb, L2-1-t)
+//   w == 0: t in [0, L2/2]: (0, t) with (0, (L2-t) mod L2); t = 0 is bin 0;
+//           t in (L2/2, L2]: (rb, t') with (rb, L2-1-t'), t' = t - L2/2 - 1.
+struct RowItem {
+  int sa, sb;       // LDS slots (row select * L2 + element) of self and partner
+  int64_t fa, fb;   // freq-layout slots of self and partner
+  int64_t k;        // bin index of self
+  bool zero;        // bin 0 (self-contained)
+};
+
+__device__ __forceinline__ RowItem row_item(int t, int w, int ra, int rb, int L1, int L2) {
+  RowItem it;
+  int rsel, k2, rsel2, k22;
+  if (w > 0) {
+    rsel = 0; k2 = t; rsel2 = 1; k22 = L2 - 1 - t;
+  } else if (t <= L2 / 2) {
+    rsel = 0; k2 = t; rsel2 = 0; k22 = (L2 - t) & (L2 - 1);
+  } else {
+    const int tt = t - L2 / 2 - 1;
+    rsel = 1; k2 = tt; rsel2 = 1; k22 = L2 - 1 - tt;
+  }
+  const int rowA = rsel ? rb : ra;
+  const int rowB = rsel2 ? rb : ra;
+  it.sa = rsel * L2 + k2;
+  it.sb = rsel2 * L2 + k22;
+  it.fa = (int64_t)rowA * L2 + k2;
+  it.fb = (int64_t)rowB * L2 + k22;
+  it.k = (int64_t)rowA + (int64_t)L1 * k2;
+  it.zero = (it.k == 0);
+  return it;
+}
+
+__device__ __forceinline__ uint32_t mask2(const uint32_t* __restrict__ mask, int64_t f) {
+  return (mask[(2 * f) >> 5] >> ((2 * f) & 31)) & 3u;
+}
+
+// W_L^{r n2} = W_4N^{8 ((r n2) mod L)}
+template <typename T>
+__device__ __forceinline__ Cx<T> row_tw(const Plan& p, uint32_t r, uint32_t n2) {
+  return tw4n<T>(p, ((r * n2) & (uint32_t)(p.L - 1)) << 3);
+}
+
+template <typename T, int LOGL2>
+__global__ __launch_bounds__(nt_for(2 << LOGL2)) void k_row(Cx<T>* __restrict__ buf, Plan p, int mode,
+                                                            const T* __restrict__ fin, T* __restrict__ fout,
+                                                            double* __restrict__ partial,
+                                                            const int* __restrict__ done,
+                                                            const Cx<T>* __restrict__ tw) {
+  constexpr int L2 = 1 << LOGL2;
+  constexpr int NT = nt_for(2 * L2);
+  constexpr bool SPLIT = NT <= L2;                 // threads tile each row exactly
+  constexpr int PER_ROW = SPLIT ? L2 / NT : 1;
+  if (done && *done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Cx<T>* lds = (Cx<T>*)smem_raw;
+  __shared__ double red[NT / 64];
+  const int w = blockIdx.x;
+  const int L1 = p.L1;
+  const int ra = w, rb = (w == 0) ? (L1 >> 1) : (L1 - w);
+  const int tid = threadIdx.x;
+  const T c = (T)sqrt(2.0 / (double)p.n);
+  const T rsn = (T)(1.0 / sqrt((double)p.n));
+  const T h = (T)0.70710678118654752440;
+
+  // four-step twiddle W_L^{r n2}: for n2 = tid + NT qq it is W_L^{r tid} W_L^{r NT qq}
+  Cx<T> tb0 = cx((T)1, (T)0), tb1 = cx((T)1, (T)0);
+  if (SPLIT) {
+    tb0 = row_tw<T>(p, (uint32_t)ra, (uint32_t)tid);
+    tb1 = row_tw<T>(p, (uint32_t)rb, (uint32_t)tid);
+  }
+
+  if (mode != ROW_ADJ) {
+    if (SPLIT) {
+#pragma unroll
+      for (int q = 0; q < 2 * PER_ROW; ++q) {
+        const int rs = q >= PER_ROW;
+        const int qq = q - rs * PER_ROW;
+        const int n2 = tid + NT * qq;
+        const int r = rs ? rb : ra;
+        const Cx<T> twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
+        lds[lp(rs * L2 + n2)] = cmul(buf[(size_t)r * L2 + n2], twv);
+      }
+    } else {
+      for (int e = tid; e < 2 * L2; e += NT) {
+        const int rs = e >> LOGL2, n2 = e & (L2 - 1);
+        const int r = rs ? rb : ra;
+        lds[lp(rs * L2 + n2)] = cmul(buf[(size_t)r * L2 + n2], row_tw<T>(p, (uint32_t)r, (uint32_t)n2));
+      }
+    }
+    __syncthreads();
+    ct_fft<T, false, NT, LOGL2, 1, false>(lds, tw);
+  }
+
+  // Makhoul twiddles for item t = tid + NT qi (rows w >= 1): k = ra + L1 t, so
+  // W_4N^k = W_4N^{ra + L1 tid} W_4N^{L1 NT qi}, and W_4N^{4k} likewise.
+  Cx<T> kb1 = cx((T)1, (T)0), kb4 = cx((T)1, (T)0);
+  const bool fast_items = SPLIT && w > 0;
+  if (fast_items) {
+    const uint32_t k0 = (uint32_t)ra + (uint32_t)L1 * (uint32_t)tid;
+    kb1 = tw4n<T>(p, k0);
+    kb4 = tw4n<T>(p, 4u * k0);
+  }
+
+  double acc = 0.0;
+  const int nitems = (w > 0) ? L2 : (L2 + 1);
+  int qi = 0;
+  for (int t = tid; t < nitems; t += NT, ++qi) {
+    const RowItem it = row_item(t, w, ra, rb, L1, L2);
+    const int sa = lp(it.sa), sb = lp(it.sb);
+    T xa0, xa1, xb0, xb1;   // X_k, X_{N-k} (self slot) and X_{L-k}, X_{L+k} (partner slot)
+    Cx<T> wk = cx((T)1, (T)0), WN = cx((T)1, (T)0);
+    if (!it.zero) {
+      if (fast_items) {
+        const uint32_t st = (uint32_t)L1 * (uint32_t)NT * (uint32_t)qi;
+        wk = cmul(kb1, tw4n<T>(p, st));
+        WN = cmul(kb4, tw4n<T>(p, 4u * st));
+      } else {
+        wk = tw4n<T>(p, (uint32_t)it.k);
+        WN = tw4n<T>(p, (uint32_t)(4 * it.k));
+      }
+    }
+    if (mode != ROW_ADJ) {
+      const Cx<T> Zk = lds[sa];
+      if (it.zero) {
+        xa0 = (Zk.re + Zk.im) * rsn;
+        xa1 = (Zk.re - Zk.im) * rsn;
+        xb0 = xb1 = (T)0;
+      } else {
+        const Cx<T> Zm = lds[sb];
+        const Cx<T> E = scale(Zk + conj(Zm), (T)0.5);
+        const Cx<T> D = Zk - conj(Zm);
+        const Cx<T> O = cx(D.im * (T)0.5, -D.re * (T)0.5);   // D / (2i)
+        const Cx<T> WO = cmul(WN, O);
+        const Cx<T> Vk = E + WO;
+        const Cx<T> Vm = conj(E - WO);
+        const Cx<T> wm = cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));  // e^{-i pi/4} conj(wk)
+        const Cx<T> a = cmul(wk, Vk), b = cmul(wm, Vm);
+        xa0 = c * a.re; xa1 = -c * a.im;
+        xb0 = c * b.re; xb1 = -c * b.im;
+      }
+    } else {
+      xa0 = fin[2 * it.fa]; xa1 = fin[2 * it.fa + 1];
+      xb0 = fin[2 * it.fb]; xb1 = fin[2 * it.fb + 1];
+    }
+    if (mode != ROW_ADJ) {
+      const uint32_t ma = mask2(p.mask, it.fa);
+      const uint32_t mb = it.zero ? 0u : mask2(p.mask, it.fb);
+      if (mode == ROW_RESID) {
+        xa0 = fin[2 * it.fa] - xa0;
+        xa1 = fin[2 * it.fa + 1] - xa1;
+        xb0 = it.zero ? (T)0 : fin[2 * it.fb] - xb0;
+        xb1 = it.zero ? (T)0 : fin[2 * it.fb + 1] - xb1;
+      }
+      xa0 = (ma & 1u) ? xa0 : (T)0;
+      xa1 = (ma & 2u) ? xa1 : (T)0;
+      xb0 = (mb & 1u) ? xb0 : (T)0;
+      xb1 = (mb & 2u) ? xb1 : (T)0;
+      if (mode == ROW_RESID) {
+        // a self-paired bin (k = L/2) has fa == fb: count its two outputs once
+        const bool self = (!it.zero) && (it.fa == it.fb);
+        acc += (double)xa0 * xa0 + (double)xa1 * xa1;
+        if (!self) acc += (double)xb0 * xb0 + (double)xb1 * xb1;
+      }
+      if (mode == ROW_FWD) {
+        fout[2 * it.fa] = xa0; fout[2 * it.fa + 1] = xa1;
+        if (!it.zero) { fout[2 * it.fb] = xb0; fout[2 * it.fb + 1] = xb1; }
+        continue;
+      }
+    }
+    // pre-process for the inverse
+    if (it.zero) {
+      lds[sa] = cx((xa0 + xa1) * rsn, (xa0 - xa1) * rsn);
+    } else {
+      const Cx<T> wm = cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));
+      const Cx<T> Vk = scale(cmulc(cx(xa0, -xa1), wk), c);    // conj(wk) (Xk - i X_{N-k}) c
+      const Cx<T> Vm = scale(cmulc(cx(xb0, -xb1), wm), c);
+      const Cx<T> E = scale(Vk + conj(Vm), (T)0.5);
+      const Cx<T> O = scale(cmulc(Vk - conj(Vm), WN), (T)0.5);
+      lds[sa] = cx(E.re - O.im, E.im + O.re);               // E + i O
+      lds[sb] = cx(E.re + O.im, -E.im + O.re);              // conj(E) + i conj(O)
+    }
+  }
+  if (mode == ROW_RESID) {
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < NT / 64; ++i) s += red[i];
+      partial[w] = s;
+    }
+  }
+  if (mode == ROW_FWD) return;
+  __syncthreads();
+  ct_fft<T, true, NT, LOGL2, 1, false>(lds, tw);
+  if (SPLIT) {
+#pragma unroll
+    for (int q = 0; q < 2 * PER_ROW; ++q) {
+      const int rs = q >= PER_ROW;
+      const int qq = q - rs * PER_ROW;
+      const int n2 = tid + NT * qq;
+      const int r = rs ? rb : ra;
+      const Cx<T> twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
+      buf[(size_t)r * L2 + n2] = cmulc(lds[lp(rs * L2 + n2)], twv);
+    }
+  } else {
+    for (int e = tid; e < 2 * L2; e += NT) {
+      const int rs = e >> LOGL2, n2 = e & (L2 - 1);
+      const int r = rs ? rb : ra;
+      buf[(size_t)r * L2 + n2] = cmulc(lds[lp(rs * L2 + n2)], row_tw<T>(p, (uint32_t)r, (uint32_t)n2));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ stage twiddle tables
+// Fills the stage table of the size-2^logn FFT (layout in cs_fft.h).
+template <typename T>
+__global__ void k_stage_twiddles(Cx<T>* __restrict__ out, int logn) {
+  const int total = tw_table_count(logn);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    int ns = 0, off = 0;
+    while (true) {
+      const int lr = stage_lr(logn, ns);
+      const int cnt = tw_stage_count(logn, ns);
+      if (i < off + cnt) {
+        const int R = 1 << lr;
+        const int loc = i - off;
+        const int k = loc / (R - 1), r = loc % (R - 1) + 1;
+        // W_{NS R}^{r k} = exp(-2 pi i r k / (NS R))
+        const int64_t den = (int64_t)1 << (ns + lr);
+        const int64_t num = ((int64_t)r * k) % den;
+        double sv, cv;
+        sincospi(2.0 * (double)num / (double)den, &sv, &cv);
+        out[i] = cx<T>((T)cv, (T)(-sv));
+        break;
+      }
+      off += cnt;
+      ns += lr;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ dispatch tables
+template <typename T>
+struct KernelSet {
+  void (*col_fwd)(const Cx<T>*, Cx<T>*, Plan, const int*, const Cx<T>*);
+  void (*col_inv)(const Cx<T>*, Cx<T>*, Plan, const int*, const Cx<T>*);
+  void (*row)(Cx<T>*, Plan, int, const T*, T*, double*, const int*, const Cx<T>*);
+  int nt_col, nt_row;
+};
+
+// Kernel set for L = 2^l (defined in the per-type instantiation units).
+template <typename T> const KernelSet<T>& kernels_for(int l);
+
+}  // namespace csr
