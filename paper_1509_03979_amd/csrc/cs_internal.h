@@ -73,6 +73,7 @@ struct Plan {
   int logL;
   int L1, L2, logL1, logL2;
   int B, logB;            // column strip width of the column passes
+  int alt;                // 1 when an alternative (tuning) shape is in use
   int nt_col, nt_row;     // threads per workgroup of the column / row passes
   size_t lds_col, lds_row;
   const void* tw_lo;      // W_{4N}^i, i in [0, 4096)          (Cx<T>)

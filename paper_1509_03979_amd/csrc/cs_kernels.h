@@ -21,18 +21,27 @@ struct Shape {
 };
 
 // Four-step split for an L = 2^l point complex FFT (N = 2^(l+1) real points).
-// Rows of L2 <= 8192 (FP32) / 4096 (FP64) complex fit two to a workgroup in
-// 136 KB of padded LDS; very large N keep L2 at that maximum so column strips
-// stay 16 x 8 B = 128 B wide; smaller N split evenly for parallelism.
+// Measured on MI355X: what matters most is that two or more workgroups of
+// each pass fit on a CU (so one's global-memory phase overlaps another's LDS
+// FFT), i.e. at most ~68 KB of padded LDS per workgroup.  Large N therefore
+// use rows of 4096 (FP32) / 2048 (FP64) complex and column strips of
+// B * L1 <= 8192 (FP32) / 4096 (FP64) elements; smaller N split L about evenly
+// with L1 >= L2 (more row-pair workgroups), and strips stay >= 4 columns wide
+// (32 B segments) unless the row count is small.  Every shape keeps each
+// workgroup within 128 KB of LDS (plus padding).
 __host__ __device__ constexpr Shape shape_for(bool f64, int l) {
-  const int maxL2 = f64 ? 12 : 13;
-  const int maxE = f64 ? 8192 : 16384;
-  int logL1 = (l >= 22) ? (l - maxL2) : ((l - maxL2) > (l / 2) ? (l - maxL2) : (l / 2));
+  const int maxL2 = f64 ? 11 : 12;
+  const int maxL1 = f64 ? 13 : 14;      // one column of L1 complex values within 128 KB
+  const int maxE = f64 ? 4096 : 8192;
+  int logL1 = (l + 1) / 2;
+  if (l >= 18) logL1 = l / 2;
+  if (l - logL1 > maxL2) logL1 = l - maxL2;
+  if (logL1 > maxL1) logL1 = maxL1;     // then L2 takes the rest (two rows still within 128 KB)
   if (logL1 < 1) logL1 = 1;
   const int logL2 = l - logL1;
   int B = 16;
   if (B > (1 << logL2)) B = 1 << logL2;
-  if (B > maxE / (1 << logL1)) B = maxE / (1 << logL1);
+  while (B > 1 && B * (1 << logL1) > maxE) B >>= 1;
   while (B > 4 && ((1 << logL2) / B) < 256) B >>= 1;
   int logB = 0;
   while ((1 << logB) < B) ++logB;
@@ -333,5 +342,13 @@ struct KernelSet {
 
 // Kernel set for L = 2^l (defined in the per-type instantiation units).
 template <typename T> const KernelSet<T>& kernels_for(int l);
+// Kernel set of an alternative instantiated shape, or nullptr.
+template <typename T> const KernelSet<T>* kernels_alt(Shape s);
+
+template <typename T>
+inline const KernelSet<T>& kernels_plan(const Plan& p) {
+  if (p.alt) return *kernels_alt<T>(Shape{p.logL1, p.logL2, p.logB});
+  return kernels_for<T>(p.logL);
+}
 
 }  // namespace csr

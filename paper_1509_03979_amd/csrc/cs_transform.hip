@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace csr {
 
@@ -37,7 +39,16 @@ bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p) {
   while ((int64_t(1) << p.logn) < n) ++p.logn;
   p.L = n / 2;
   p.logL = p.logn - 1;
-  const Shape sh = shape_for(dt == CS_F64, p.logL);
+  Shape sh = shape_for(dt == CS_F64, p.logL);
+  // Tuning override "logL1,logL2,logB" (must multiply to this L and be instantiated).
+  if (const char* ov = std::getenv("CS_SHAPE")) {
+    Shape o{0, 0, 0};
+    if (std::sscanf(ov, "%d,%d,%d", &o.logL1, &o.logL2, &o.logB) == 3 && o.logL1 + o.logL2 == p.logL &&
+        !(o.logL1 == sh.logL1 && o.logL2 == sh.logL2 && o.logB == sh.logB)) {
+      const bool ok = (dt == CS_F32) ? kernels_alt<float>(o) != nullptr : kernels_alt<double>(o) != nullptr;
+      if (ok) { sh = o; p.alt = 1; }
+    }
+  }
   p.logL1 = sh.logL1;
   p.logL2 = sh.logL2;
   p.logB = sh.logB;
@@ -211,7 +222,7 @@ double norm2_host(Ctx<T>& c, const T* v, int64_t count) {
 template <typename T>
 static void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const int* done) {
   const Plan& p = c.plan;
-  const KernelSet<T>& ks = kernels_for<T>(p.logL);
+  const KernelSet<T>& ks = kernels_plan<T>(p);
   const unsigned grid = (unsigned)(p.L2 >> p.logB);
   const double bytes = 2.0 * (double)p.n * sizeof(T);   // read and write one N-vector
   hipEvent_t ev = nullptr;
@@ -227,7 +238,7 @@ static void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const i
 template <typename T>
 static void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done) {
   const Plan& p = c.plan;
-  const KernelSet<T>& ks = kernels_for<T>(p.logL);
+  const KernelSet<T>& ks = kernels_plan<T>(p);
   const unsigned grid = (unsigned)(p.L1 >> 1);
   // read and write one N-vector; the residual pass also reads y (N reals in freq layout)
   double bytes = 2.0 * (double)p.n * sizeof(T);
@@ -357,6 +368,14 @@ void prepare_kernels() {
     CS_HIP(hipFuncSetAttribute((const void*)ks.col_inv, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     CS_HIP(hipFuncSetAttribute((const void*)ks.row, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   }
+  for (int a = 1; a <= 13; ++a)
+    for (int b = 1; b <= 13; ++b)
+      for (int lb = 0; lb <= 4; ++lb)
+        if (const KernelSet<T>* ks = kernels_alt<T>(Shape{a, b, lb})) {
+          CS_HIP(hipFuncSetAttribute((const void*)ks->col_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+          CS_HIP(hipFuncSetAttribute((const void*)ks->col_inv, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+          CS_HIP(hipFuncSetAttribute((const void*)ks->row, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+        }
   ready.store(1);
 }
 
