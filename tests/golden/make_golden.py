@@ -4,7 +4,8 @@
     python tests/golden/make_golden.py sp_n2p24           # SP, N = 2^24 (noiseless)
 
 Each file holds the measurements the GPU consumes (float32 y, from the
-oracle's FP64 y = A s + noise) and the oracle's outputs on float64(float32(y)):
+oracle's FP64 y = A s + noise; only up to N = 2^20, larger workloads recompute
+y with measurements()) and the oracle's outputs on float64(float32(y)):
 support, values, stop reason, outer iterations, the smallest decision margin.
 Nothing here touches the GPU library.
 """
@@ -36,10 +37,10 @@ def measurements(name: str, sig: int = 0):
     return w, d, op, y32
 
 
-def run(name: str, sig: int = 0):
+def run(name: str, sig: int = 0, store_y: bool = True):
     w, d, op, y32 = measurements(name, sig)
     y = y32.astype(np.float64)
-    out = {"y": y32}
+    out = {"y": y32} if store_y else {}
     meta = {"workload": name, "sig": sig, "n": d.n, "m": d.m, "k": d.k}
     for algo in w["algos"]:
         t = time.perf_counter()
@@ -58,5 +59,7 @@ def run(name: str, sig: int = 0):
 
 
 if __name__ == "__main__":
+    # y is stored for workloads small enough to keep in the repository (N <= 2^20);
+    # larger ones recompute it with the oracle (measurements()).
     for nm in sys.argv[1:]:
-        run(nm)
+        run(nm, store_y=synth.WORKLOADS[nm]["n"] <= 2 ** 20)

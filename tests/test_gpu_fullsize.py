@@ -1,0 +1,94 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration bench.py
+times (same workspace sizing, same defaults).
+
+* OMP, N = 4096, M = 1024, K = 50, FP64, noiseless, tol 1e-10: ten signals,
+  each against the FP64 oracle run here.
+* SP and OMPR, N = 2^20, M = 2^18, K = 4096, FP32, 40 dB: against the stored
+  FP64 oracle results (tests/golden, written by make_golden.py from oracle/
+  only; the oracle's OMPR takes ~20 minutes on 8 cores).
+* SP, N = 2^24, M = 2^21, K = 2^16, FP32, noiseless: y from the FP64 oracle;
+  the expected output is the drawn s itself (noiseless y and an exact
+  support make the least-squares fit on it equal s; the oracle's SP recovers
+  that support, recorded in tests/golden/sp_n2p24_sig0.npz when present), and
+  the final residual must be orthogonal to A_S (Theorems 1-2).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import announce, rel, to_dev, torch_dev
+from tests.problems import build
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("sig", range(10))
+def test_omp_n4096_fp64(sig):
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    w = synth.WORKLOADS["omp_n4096"]
+    d = synth.workload_problem("omp_n4096", sig)
+    op, y = build(d, "f64")
+    ref = oracle.omp(op, y, d.k)
+    dop = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+    announce("omp_n4096 sig", sig)
+    s, supp, info = cs.cs_recover_omp(to_dev(y, torch.float64), dop, d.k, w["tol"])
+    assert np.array_equal(supp.cpu().numpy(), ref.support)
+    assert np.array_equal(ref.support, d.supp)            # noiseless, |s_i| >= 0.1: exact recovery
+    assert rel(s.cpu().numpy(), ref.s) <= 1e-5
+    assert info["flags"] == 0
+
+
+def _golden(name):
+    path = os.path.join(GOLD, f"{name}_sig0.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path, allow_pickle=False)
+
+
+@pytest.mark.parametrize("algo", ["sp", "ompr"])
+def test_sp_ompr_n2p20_fp32(algo):
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    w = synth.WORKLOADS["sp_ompr_n2p20"]
+    d = synth.workload_problem("sp_ompr_n2p20", 0)
+    g = _golden("sp_ompr_n2p20")
+    dop = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+    announce("sp_ompr_n2p20", algo)
+    s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(g["y"], torch.float32), dop, d.k, w["tol"])
+    supp = supp.cpu().numpy()
+    es = g[f"{algo}_support"]
+    assert np.array_equal(supp, es), (np.setdiff1d(supp, es)[:10], np.setdiff1d(es, supp)[:10])
+    ref = np.zeros(d.n)
+    ref[es] = g[f"{algo}_values"]
+    assert rel(s.cpu().numpy(), ref) <= 1e-5
+    meta = json.loads(str(g["meta"]))
+    assert info["outer_iters"] == meta[algo]["iters"]
+
+
+def test_sp_n2p24_fp32():
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    w = synth.WORKLOADS["sp_n2p24"]
+    d = synth.workload_problem("sp_n2p24", 0)
+    op, y = build(d, "f32")
+    dop = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+    announce("sp_n2p24")
+    s, supp, info = cs.cs_recover_sp(to_dev(y, torch.float32), dop, d.k, w["tol"])
+    supp = supp.cpu().numpy()
+    s = s.cpu().numpy().astype(np.float64)
+    assert np.array_equal(supp, d.supp)
+    assert rel(s, d.s_dense()) <= 1e-5
+    path = os.path.join(GOLD, "sp_n2p24_sig0.npz")
+    if os.path.exists(path):
+        g = np.load(path, allow_pickle=False)
+        assert np.array_equal(g["sp_support"], supp)
+    # residual orthogonality on a sample of the support columns (Theorems 1-2)
+    r = y - op.apply(s)
+    cols = op.columns(supp[:: max(1, supp.size // 512)])
+    assert np.linalg.norm(cols.T @ r) <= 1e-5 * np.linalg.norm(cols.T @ y)
