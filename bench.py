@@ -70,12 +70,13 @@ def load_inputs(name: str, torch, cs):
     op = cs.Operator.from_numpy(d.n, d.rows, d.signs)
     gold_path = os.path.join(ROOT, "tests", "golden", f"{name}_sig0.npz")
     expect = {}
-    if os.path.exists(gold_path):
-        g = np.load(gold_path, allow_pickle=False)
-        y32 = g["y"]
+    g = np.load(gold_path, allow_pickle=False) if os.path.exists(gold_path) else None
+    if g is not None:
         for algo in w["algos"]:
             if f"{algo}_support" in g:
                 expect[algo] = (g[f"{algo}_support"].astype(np.int64), g[f"{algo}_values"])
+    if g is not None and "y" in g:
+        y32 = g["y"]
         y_src = "stored FP64 oracle measurements"
     else:
         s64 = torch.as_tensor(d.s_dense(), dtype=torch.float64, device="cuda")
@@ -85,7 +86,10 @@ def load_inputs(name: str, torch, cs):
         y_src = "y = A s computed by the library in FP64"
         if d.noise is None:
             # noiseless: the least-squares fit on the true support is s itself
+            # (the stored oracle run, when present, recovered that support)
             for algo in w["algos"]:
+                if algo in expect and not np.array_equal(expect[algo][0], d.supp):
+                    raise RuntimeError("stored oracle support differs from the drawn support")
                 expect[algo] = (d.supp.astype(np.int64), d.vals)
     dt = torch.float32 if w["dtype"] == "f32" else torch.float64
     y_dev = torch.as_tensor(y32 if w["dtype"] == "f32" else y32.astype(np.float64), dtype=dt, device="cuda")

@@ -137,8 +137,7 @@ template <typename T>
 static void load_measurements(Ctx<T>& c, const T* y) {
   scatter_freq<T>(c, y, c.Yf);
   c.ynorm = norm2_host<T>(c, y, c.plan.m);
-  transform_adj<T>(c, c.Yf);
-  CS_HIP(hipMemcpyAsync(c.C0, c.W, sizeof(T) * c.plan.n, hipMemcpyDeviceToDevice, c.stream));
+  transform_adj<T>(c, c.Yf, c.C0);
 }
 
 template <typename T>
@@ -207,8 +206,7 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   hipLaunchKernelGGL(k_check_support, dim3((k + 255) / 256), dim3(256), 0, stream, support, k, op->n, c.ibuf + 16);
   CS_LAUNCH_CHECK();
   int32_t bad = 0;
-  CS_HIP(hipMemcpyAsync(&bad, c.ibuf + 16, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-  CS_HIP(hipStreamSynchronize(stream));
+  dev_read(stream, c.ibuf + 16, &bad, sizeof(int32_t));
   if (bad) throw Error(CS_E_INVALID, "support must be strictly ascending in [0, N)");
   load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
@@ -238,7 +236,7 @@ static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, vo
     gather_freq<T>(c, c.Yf, (T*)out);
   } else {
     scatter_freq<T>(c, (const T*)in, c.Yf);
-    transform_adj<T>(c, c.Yf);
+    transform_adj<T>(c, c.Yf, (T*)c.W);
     perm_out<T>(c, (const T*)c.W, (T*)out);
   }
   CS_HIP(hipStreamSynchronize(stream));

@@ -238,8 +238,7 @@ int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol,
                          c.cg, nb, it, max_iter);
       CS_LAUNCH_CHECK();
     }
-    CS_HIP(hipMemcpyAsync(&host, c.cg, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-    CS_HIP(hipStreamSynchronize(s));
+    dev_read(s, c.cg, &host, sizeof(CgScalars));
     if (host.done) break;
     const double rr_now = host.rr[host.iters & 1];
     const double target = host.tol2 * host.bb;
@@ -255,10 +254,7 @@ int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol,
     rr_prev = rr_now;
     it_prev = host.iters;
   }
-  if (!host.done) {
-    CS_HIP(hipMemcpyAsync(&host, c.cg, sizeof(CgScalars), hipMemcpyDeviceToHost, s));
-    CS_HIP(hipStreamSynchronize(s));
-  }
+  if (!host.done) dev_read(s, c.cg, &host, sizeof(CgScalars));
   const bool conv = host.rr[host.iters & 1] <= host.tol2 * host.bb;
   if (!conv && !(host.flags & CS_F_CG_BREAKDOWN)) c.flags |= CS_F_CG_MAXITER;
   c.flags |= host.flags;
@@ -272,8 +268,7 @@ double resid_corr(Ctx<T>& c, const int32_t* old_list, int old_k, const int32_t* 
   scatter_signed<T>(c, c.Dx, list, x, k);
   transform_resid<T>(c, c.Dx);
   double r2 = 0.0;
-  CS_HIP(hipMemcpyAsync(&r2, &c.cg->resid2, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  CS_HIP(hipStreamSynchronize(c.stream));
+  dev_read(c.stream, &c.cg->resid2, &r2, sizeof(double));
   return std::sqrt(r2);
 }
 

@@ -8,7 +8,8 @@
 // SC'08 formulation): the stage of span NS reads the R inputs of butterfly j
 // at j + r N/R, multiplies input r by W_{NS R}^{r (j mod NS)}, does an R-point
 // DFT in registers and writes output r to (j / NS) NS R + (j mod NS) + r NS.
-// Radix 16 while at least 4 bits remain, then one radix 8/4/2 stage.  A stage
+// Radix 16 (or the per-thread element count, if smaller) while enough bits
+// remain, then one smaller stage.  A stage
 // reads all its inputs into registers, synchronises, then writes in place.
 // Output is in natural order.  Forward uses exp(-2 pi i ...), inverse
 // exp(+2 pi i ...), both unnormalised.
@@ -31,25 +32,30 @@ namespace csr {
 __device__ __forceinline__ int lp(int a) { return a + (a >> 4); }
 __host__ __device__ constexpr int lp_size(int n) { return n + (n >> 4) + 1; }
 
-__host__ __device__ constexpr int stage_lr(int logn, int logns) {
-  return (logn - logns) >= 4 ? 4 : (logn - logns);
+// Radix of the stage at span 2^logns: the largest of 16 / 8 / 4 / 2 that does not
+// exceed 2^loge (the elements each thread holds) or the bits that remain.
+__host__ __device__ constexpr int stage_lr(int logn, int logns, int loge) {
+  const int cap = loge < 4 ? loge : 4;
+  return (logn - logns) >= cap ? cap : (logn - logns);
 }
-__host__ __device__ constexpr int tw_stage_count(int logn, int logns) {
-  return logns == 0 ? 0 : (1 << logns) * ((1 << stage_lr(logn, logns)) - 1);
+__host__ __device__ constexpr int tw_stage_count(int logn, int logns, int loge) {
+  return logns == 0 ? 0 : (1 << logns) * ((1 << stage_lr(logn, logns, loge)) - 1);
 }
 // offset of stage `logns` in the table of size-2^logn FFTs
-__host__ __device__ constexpr int tw_stage_offset(int logn, int logns) {
+__host__ __device__ constexpr int tw_stage_offset(int logn, int logns, int loge) {
   int off = 0, ns = 0;
   while (ns < logns) {
-    off += tw_stage_count(logn, ns);
-    ns += stage_lr(logn, ns);
+    off += tw_stage_count(logn, ns, loge);
+    ns += stage_lr(logn, ns, loge);
   }
   return off;
 }
-__host__ __device__ constexpr int tw_table_count(int logn) { return tw_stage_offset(logn, logn); }
+__host__ __device__ constexpr int tw_table_count(int logn, int loge) { return tw_stage_offset(logn, logn, loge); }
 
-// threads per workgroup for E elements (16 per thread, at least one wave)
-__host__ __device__ constexpr int nt_for(int e) { return e / 16 < 64 ? 64 : (e / 16 > 1024 ? 1024 : e / 16); }
+// threads per workgroup for E elements at 2^loge per thread (one wave to 1024 threads)
+__host__ __device__ constexpr int nt_for(int e, int loge) {
+  return (e >> loge) < 64 ? 64 : ((e >> loge) > 1024 ? 1024 : (e >> loge));
+}
 
 template <typename T, bool INV>
 __device__ __forceinline__ Cx<T> mul_mi(Cx<T> a) {   // a * (-i) forward, a * (+i) inverse
@@ -123,15 +129,15 @@ __device__ __forceinline__ void dft_r(Cx<T>* a) {
   else dft16<T, INV>(a);
 }
 
-template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGNS>
+template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGE, int LOGNS>
 __device__ __forceinline__ void ct_stage(Cx<T>* buf, const Cx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN, CNT = 1 << LOGCNT;
-  constexpr int LR = stage_lr(LOGN, LOGNS), R = 1 << LR;
+  constexpr int LR = stage_lr(LOGN, LOGNS, LOGE), R = 1 << LR;
   constexpr int NB = N >> LR, TOTAL = NB * CNT;
   constexpr int MAXB = (TOTAL + NT - 1) / NT;
   constexpr int NS = 1 << LOGNS;
   constexpr int ES = CM ? CNT : 1, FS = CM ? 1 : N;
-  constexpr int TWOFF = tw_stage_offset(LOGN, LOGNS);
+  constexpr int TWOFF = tw_stage_offset(LOGN, LOGNS, LOGE);
   constexpr bool RD_FAST = ((NB * ES) % 16) == 0;
   constexpr bool WR_FAST = ((NS * ES) % 16) == 0;
   constexpr bool WR_SMALL = (NS == 1) && (ES == 1) && (R == 16) && (FS % 16 == 0);
@@ -193,11 +199,11 @@ __device__ __forceinline__ void ct_stage(Cx<T>* buf, const Cx<T>* __restrict__ t
   __syncthreads();
 }
 
-template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGNS = 0>
+template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGE, int LOGNS = 0>
 __device__ __forceinline__ void ct_fft(Cx<T>* buf, const Cx<T>* __restrict__ tw) {
   if constexpr (LOGNS < LOGN) {
-    ct_stage<T, INV, NT, LOGN, LOGCNT, CM, LOGNS>(buf, tw);
-    ct_fft<T, INV, NT, LOGN, LOGCNT, CM, LOGNS + stage_lr(LOGN, LOGNS)>(buf, tw);
+    ct_stage<T, INV, NT, LOGN, LOGCNT, CM, LOGE, LOGNS>(buf, tw);
+    ct_fft<T, INV, NT, LOGN, LOGCNT, CM, LOGE, LOGNS + stage_lr(LOGN, LOGNS, LOGE)>(buf, tw);
   }
 }
 

@@ -139,11 +139,10 @@ void run_omp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32
   T* x = c.cx;
   fill_u32(bitsS, words, 0u, s);
   fill<T>(c.Dx, c.plan.n, (T)0, s);
-  // the first correlation is A^T r_0 = A^T y, already in C0
-  CS_HIP(hipMemcpyAsync(c.W, c.C0, sizeof(T) * c.plan.n, hipMemcpyDeviceToDevice, s));
   double rn = 0.0;
   for (int i = 1; i <= K; ++i) {
-    argmax_excl<T>(c, (const T*)c.W, bitsS, c.ibuf);                      // line 03
+    // the first correlation is A^T r_0 = A^T y, already in C0
+    argmax_excl<T>(c, i == 1 ? (const T*)c.C0 : (const T*)c.W, bitsS, c.ibuf);   // line 03
     hipLaunchKernelGGL(k_set_bit_dev, dim3(1), dim3(64), 0, s, bitsS, (const int32_t*)c.ibuf);   // line 04
     CS_LAUNCH_CHECK();
     bits_to_list<T>(c, bitsS, nxt, i);
@@ -241,8 +240,7 @@ void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int3
     hipLaunchKernelGGL(k_ompr_drop<T>, dim3(1), dim3(1024), 0, s, xI, lI, K, (const T*)c.W, c.signs, c.plan.n,
                        (T)eta, (const int32_t*)c.ibuf, c.ibuf + 1);
     CS_LAUNCH_CHECK();
-    CS_HIP(hipMemcpyAsync(jd, c.ibuf, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    CS_HIP(hipStreamSynchronize(s));
+    dev_read(s, c.ibuf, jd, 2 * sizeof(int32_t));
     if (jd[0] < 0 || jd[1] == jd[0]) { stopped = true; break; }
     hipLaunchKernelGGL(k_swap_bits, dim3(1), dim3(64), 0, s, bI, (const int32_t*)c.ibuf);
     CS_LAUNCH_CHECK();

@@ -73,6 +73,7 @@ struct Plan {
   int logL;
   int L1, L2, logL1, logL2;
   int B, logB;            // column strip width of the column passes
+  int logE;               // log2 elements per thread in the LDS FFTs
   int alt;                // 1 when an alternative (tuning) shape is in use
   int nt_col, nt_row;     // threads per workgroup of the column / row passes
   size_t lds_col, lds_row;
@@ -218,8 +219,13 @@ template <typename T> void transform_fwd(Ctx<T>& c, const T* in, T* outf); // ou
 template <typename T> void perm_in(Ctx<T>& c, const T* x, T* dense);      // dense[vpos(j)] = sign_j x_j
 template <typename T> void perm_out(Ctx<T>& c, const T* dense, T* x);     // x_j = sign_j dense[vpos(j)]
 template <typename T> void prepare_kernels();                             // LDS limits, once per process
-template <typename T> void transform_adj(Ctx<T>& c, const T* inf);        // W = F^T (freq input), v-order
+template <typename T> void transform_adj(Ctx<T>& c, const T* inf, T* out); // out = F^T (freq input), v-order
 template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
+// Reads `bytes` (a multiple of 4, at most 4096) of device memory on the host:
+// a one-block kernel copies them into a pinned, device-mapped host buffer
+// (one per calling thread, kept for the life of the process), then the stream
+// is synchronised.  Cheaper than a pageable device-to-host copy.
+void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes);
 template <typename T> double norm2_host(Ctx<T>& c, const T* v, int64_t count);   // ||v||, synchronises
 void fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
 

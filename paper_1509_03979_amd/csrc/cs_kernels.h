@@ -1,9 +1,10 @@
 // Transform pass kernels, specialised per four-step shape.
 //
-// Column pass k_col<T, INV, LOGL1, LOGB>: one workgroup owns a strip of
+// Column pass k_col<T, INV, LOGL1, LOGB, LOGE>: one workgroup owns a strip of
 // B = 2^LOGB adjacent columns of the L1 x L2 view of z and runs B length-L1
 // FFTs on it in LDS (column-major layout, so a global row segment of B
-// complex values maps to B consecutive LDS slots).
+// complex values maps to B consecutive LDS slots).  `in` and `out` may be the
+// same buffer: a workgroup reads its whole strip before writing it back.
 //
 // Row pass k_row<T, LOGL2>: one workgroup owns a mirror row pair and runs
 // four-step twiddle -> row FFT -> DCT post-processing -> mask or residual ->
@@ -18,6 +19,7 @@ namespace csr {
 // ------------------------------------------------------------------ shapes
 struct Shape {
   int logL1, logL2, logB;
+  int logE;               // log2 of the elements each thread holds (caps the radix)
 };
 
 // Four-step split for an L = 2^l point complex FFT (N = 2^(l+1) real points).
@@ -45,20 +47,23 @@ __host__ __device__ constexpr Shape shape_for(bool f64, int l) {
   while (B > 4 && ((1 << logL2) / B) < 256) B >>= 1;
   int logB = 0;
   while ((1 << logB) < B) ++logB;
-  return Shape{logL1, logL2, logB};
+  // Mid-size problems have too few workgroups to fill 256 CUs with 16 elements
+  // per thread; hold fewer (smaller radix, more LDS stages, more waves).
+  const int logE = (l >= 21) ? 4 : (l >= 17 ? 3 : 2);
+  return Shape{logL1, logL2, logB, logE};
 }
 
 constexpr int kMinL = 3;    // N = 16
 constexpr int kMaxL = 25;   // N = 2^26
 
 // ------------------------------------------------------------------ column pass
-template <typename T, bool INV, int LOGL1, int LOGB>
-__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB))) void k_col(const Cx<T>* __restrict__ in,
-                                                                      Cx<T>* __restrict__ out, Plan p,
+template <typename T, bool INV, int LOGL1, int LOGB, int LOGE>
+__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const Cx<T>* in,
+                                                                      Cx<T>* out, Plan p,
                                                                       const int* __restrict__ done,
                                                                       const Cx<T>* __restrict__ tw) {
   constexpr int E = 1 << (LOGL1 + LOGB), B = 1 << LOGB;
-  constexpr int NT = nt_for(E);
+  constexpr int NT = nt_for(E, LOGE);
   constexpr int EPT = (E + NT - 1) / NT;
   if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB))) void k_col(const Cx<T>
     if (E % NT == 0 || e < E) buf[lp(e)] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
   }
   __syncthreads();
-  ct_fft<T, INV, NT, LOGL1, LOGB, true>(buf, tw);
+  ct_fft<T, INV, NT, LOGL1, LOGB, true, LOGE>(buf, tw);
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
     const int e = tid + q * NT;
@@ -130,14 +135,14 @@ __device__ __forceinline__ Cx<T> row_tw(const Plan& p, uint32_t r, uint32_t n2) 
   return tw4n<T>(p, ((r * n2) & (uint32_t)(p.L - 1)) << 3);
 }
 
-template <typename T, int LOGL2>
-__global__ __launch_bounds__(nt_for(2 << LOGL2)) void k_row(Cx<T>* __restrict__ buf, Plan p, int mode,
+template <typename T, int LOGL2, int LOGE>
+__global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row(Cx<T>* __restrict__ buf, Plan p, int mode,
                                                             const T* __restrict__ fin, T* __restrict__ fout,
                                                             double* __restrict__ partial,
                                                             const int* __restrict__ done,
                                                             const Cx<T>* __restrict__ tw) {
   constexpr int L2 = 1 << LOGL2;
-  constexpr int NT = nt_for(2 * L2);
+  constexpr int NT = nt_for(2 * L2, LOGE);
   constexpr bool SPLIT = NT <= L2;                 // threads tile each row exactly
   constexpr int PER_ROW = SPLIT ? L2 / NT : 1;
   if (done && *done) return;
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(nt_for(2 << LOGL2)) void k_row(Cx<T>* __restrict__ 
       }
     }
     __syncthreads();
-    ct_fft<T, false, NT, LOGL2, 1, false>(lds, tw);
+    ct_fft<T, false, NT, LOGL2, 1, false, LOGE>(lds, tw);
   }
 
   // Makhoul twiddles for item t = tid + NT qi (rows w >= 1): k = ra + L1 t, so
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(nt_for(2 << LOGL2)) void k_row(Cx<T>* __restrict__ 
   }
   if (mode == ROW_FWD) return;
   __syncthreads();
-  ct_fft<T, true, NT, LOGL2, 1, false>(lds, tw);
+  ct_fft<T, true, NT, LOGL2, 1, false, LOGE>(lds, tw);
   if (SPLIT) {
 #pragma unroll
     for (int q = 0; q < 2 * PER_ROW; ++q) {
@@ -306,13 +311,13 @@ __global__ __launch_bounds__(nt_for(2 << LOGL2)) void k_row(Cx<T>* __restrict__ 
 // ------------------------------------------------------------------ stage twiddle tables
 // Fills the stage table of the size-2^logn FFT (layout in cs_fft.h).
 template <typename T>
-__global__ void k_stage_twiddles(Cx<T>* __restrict__ out, int logn) {
-  const int total = tw_table_count(logn);
+__global__ void k_stage_twiddles(Cx<T>* __restrict__ out, int logn, int loge) {
+  const int total = tw_table_count(logn, loge);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     int ns = 0, off = 0;
     while (true) {
-      const int lr = stage_lr(logn, ns);
-      const int cnt = tw_stage_count(logn, ns);
+      const int lr = stage_lr(logn, ns, loge);
+      const int cnt = tw_stage_count(logn, ns, loge);
       if (i < off + cnt) {
         const int R = 1 << lr;
         const int loc = i - off;
@@ -347,7 +352,7 @@ template <typename T> const KernelSet<T>* kernels_alt(Shape s);
 
 template <typename T>
 inline const KernelSet<T>& kernels_plan(const Plan& p) {
-  if (p.alt) return *kernels_alt<T>(Shape{p.logL1, p.logL2, p.logB});
+  if (p.alt) return *kernels_alt<T>(Shape{p.logL1, p.logL2, p.logB, p.logE});
   return kernels_for<T>(p.logL);
 }
 

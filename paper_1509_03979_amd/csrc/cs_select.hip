@@ -294,8 +294,7 @@ int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scr
   hipLaunchKernelGGL(k_bits_diff, dim3(nblk(words, 256)), dim3(256), 0, s, a, b, words, scratch);
   CS_LAUNCH_CHECK();
   int32_t h = 0;
-  CS_HIP(hipMemcpyAsync(&h, scratch, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  CS_HIP(hipStreamSynchronize(s));
+  dev_read(s, scratch, &h, sizeof(int32_t));
   return h == 0;
 }
 

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 namespace csr {
 
@@ -40,11 +41,11 @@ bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p) {
   p.L = n / 2;
   p.logL = p.logn - 1;
   Shape sh = shape_for(dt == CS_F64, p.logL);
-  // Tuning override "logL1,logL2,logB" (must multiply to this L and be instantiated).
+  // Tuning override "logL1,logL2,logB,logE" (must multiply to this L and be instantiated).
   if (const char* ov = std::getenv("CS_SHAPE")) {
-    Shape o{0, 0, 0};
-    if (std::sscanf(ov, "%d,%d,%d", &o.logL1, &o.logL2, &o.logB) == 3 && o.logL1 + o.logL2 == p.logL &&
-        !(o.logL1 == sh.logL1 && o.logL2 == sh.logL2 && o.logB == sh.logB)) {
+    Shape o{0, 0, 0, 0};
+    if (std::sscanf(ov, "%d,%d,%d,%d", &o.logL1, &o.logL2, &o.logB, &o.logE) == 4 && o.logL1 + o.logL2 == p.logL &&
+        !(o.logL1 == sh.logL1 && o.logL2 == sh.logL2 && o.logB == sh.logB && o.logE == sh.logE)) {
       const bool ok = (dt == CS_F32) ? kernels_alt<float>(o) != nullptr : kernels_alt<double>(o) != nullptr;
       if (ok) { sh = o; p.alt = 1; }
     }
@@ -52,13 +53,14 @@ bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p) {
   p.logL1 = sh.logL1;
   p.logL2 = sh.logL2;
   p.logB = sh.logB;
+  p.logE = sh.logE;
   p.L1 = 1 << p.logL1;
   p.L2 = 1 << p.logL2;
   p.B = 1 << p.logB;
   const size_t cs = (dt == CS_F32) ? 8 : 16;
   const int ecol = p.B * p.L1, erow = 2 * p.L2;
-  p.nt_col = nt_for(ecol);
-  p.nt_row = nt_for(erow);
+  p.nt_col = nt_for(ecol, p.logE);
+  p.nt_row = nt_for(erow, p.logE);
   p.lds_col = cs * lp_size(ecol);
   p.lds_row = cs * lp_size(erow);
   return true;
@@ -119,11 +121,11 @@ template <typename T>
 void setup_operator(Ctx<T>& c) {
   const Plan& p = c.plan;
   hipStream_t s = c.stream;
-  hipLaunchKernelGGL(k_stage_twiddles<T>, dim3(nblk(tw_table_count(p.logL1), 256)), dim3(256), 0, s, c.tw_col,
-                     p.logL1);
+  hipLaunchKernelGGL(k_stage_twiddles<T>, dim3(nblk(tw_table_count(p.logL1, p.logE), 256)), dim3(256), 0, s,
+                     c.tw_col, p.logL1, p.logE);
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_stage_twiddles<T>, dim3(nblk(tw_table_count(p.logL2), 256)), dim3(256), 0, s, c.tw_row,
-                     p.logL2);
+  hipLaunchKernelGGL(k_stage_twiddles<T>, dim3(nblk(tw_table_count(p.logL2, p.logE), 256)), dim3(256), 0, s,
+                     c.tw_row, p.logL2, p.logE);
   CS_LAUNCH_CHECK();
   const int64_t n4 = 4 * p.n;
   hipLaunchKernelGGL(k_twiddle<T>, dim3(nblk(kTwLo, 256)), dim3(256), 0, s, c.tw_lo, (int64_t)kTwLo, n4,
@@ -139,10 +141,35 @@ void setup_operator(Ctx<T>& c) {
   hipLaunchKernelGGL(k_check_signs, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.signs, p.n, c.ibuf);
   CS_LAUNCH_CHECK();
   int32_t bad = 0;
-  CS_HIP(hipMemcpyAsync(&bad, c.ibuf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  CS_HIP(hipStreamSynchronize(s));
+  dev_read(s, c.ibuf, &bad, sizeof(int32_t));
   if (bad & 1) throw Error(CS_E_OP, "operator rows must be strictly ascending in [0, N)");
   if (bad & 2) throw Error(CS_E_OP, "operator signs must be +1 or -1");
+}
+
+// ------------------------------------------------------------------ host reads
+__global__ void k_post(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int words) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+}
+
+namespace {
+struct HostBox {
+  void* h = nullptr;
+  void* d = nullptr;
+};
+thread_local HostBox g_box;
+}  // namespace
+
+void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
+  if (bytes % 4 || bytes > 4096) throw Error(CS_E_INVALID, "dev_read size");
+  if (!g_box.h) {
+    CS_HIP(hipHostMalloc(&g_box.h, 4096, hipHostMallocMapped | hipHostMallocCoherent));
+    CS_HIP(hipHostGetDevicePointer(&g_box.d, g_box.h, 0));
+  }
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, (uint32_t*)g_box.d, (int)(bytes / 4));
+  CS_LAUNCH_CHECK();
+  CS_HIP(hipStreamSynchronize(s));
+  std::memcpy(host, g_box.h, bytes);
 }
 
 // ------------------------------------------------------------------ freq-layout scatter / gather
@@ -213,8 +240,7 @@ double norm2_host(Ctx<T>& c, const T* v, int64_t count) {
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, c.stream, c.partial2, (int)grid, &c.cg->resid2);
   CS_LAUNCH_CHECK();
   double r2 = 0.0;
-  CS_HIP(hipMemcpyAsync(&r2, &c.cg->resid2, sizeof(double), hipMemcpyDeviceToHost, c.stream));
-  CS_HIP(hipStreamSynchronize(c.stream));
+  dev_read(c.stream, &c.cg->resid2, &r2, sizeof(double));
   return std::sqrt(r2);
 }
 
@@ -279,9 +305,9 @@ void transform_fwd(Ctx<T>& c, const T* in, T* outf) {
 }
 
 template <typename T>
-void transform_adj(Ctx<T>& c, const T* inf) {
+void transform_adj(Ctx<T>& c, const T* inf, T* out) {
   launch_row<T>(c, ROW_ADJ, inf, nullptr, nullptr, nullptr);
-  launch_col<T>(c, c.W, c.W, true, nullptr);
+  launch_col<T>(c, c.W, (Cx<T>*)out, true, nullptr);
   c.transforms += 1;
 }
 
@@ -368,10 +394,11 @@ void prepare_kernels() {
     CS_HIP(hipFuncSetAttribute((const void*)ks.col_inv, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     CS_HIP(hipFuncSetAttribute((const void*)ks.row, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   }
-  for (int a = 1; a <= 13; ++a)
+  for (int a = 1; a <= 14; ++a)
     for (int b = 1; b <= 13; ++b)
       for (int lb = 0; lb <= 4; ++lb)
-        if (const KernelSet<T>* ks = kernels_alt<T>(Shape{a, b, lb})) {
+        for (int le = 1; le <= 4; ++le)
+        if (const KernelSet<T>* ks = kernels_alt<T>(Shape{a, b, lb, le})) {
           CS_HIP(hipFuncSetAttribute((const void*)ks->col_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
           CS_HIP(hipFuncSetAttribute((const void*)ks->col_inv, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
           CS_HIP(hipFuncSetAttribute((const void*)ks->row, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
@@ -389,7 +416,7 @@ void prepare_kernels() {
   template void transform_happly<T>(Ctx<T>&, const T*, const int*);             \
   template void transform_resid<T>(Ctx<T>&, const T*);                          \
   template void transform_fwd<T>(Ctx<T>&, const T*, T*);                        \
-  template void transform_adj<T>(Ctx<T>&, const T*);                            \
+  template void transform_adj<T>(Ctx<T>&, const T*, T*);                        \
   template void perm_in<T>(Ctx<T>&, const T*, T*);                              \
   template void perm_out<T>(Ctx<T>&, const T*, T*);                             \
   template void prepare_kernels<T>();                                           \
