@@ -31,7 +31,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   const int64_t n = p.n;
   c.W = cv.take<Cx<T>>(p.L);
   c.Dd = cv.take<T>(n);
-  c.Dx = cv.take<T>(n);
+  c.Cc = c.Dd;   // the operator entry points and the drivers never need both
   c.C0 = cv.take<T>(n);
   c.Yf = cv.take<T>(n);
   c.tw_col = cv.take<Cx<T>>(kTwStage);
@@ -40,6 +40,8 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   c.tw_hi = cv.take<Cx<T>>(std::max<int64_t>(1, 4 * n / kTwLo));
   c.mask = cv.take<uint32_t>(p.words);
   for (int i = 0; i < 3; ++i) c.bits[i] = cv.take<uint32_t>(p.words);
+  for (int i = 0; i < 3; ++i) c.wpre[i] = cv.take<uint32_t>(p.words);
+  c.nbits = cv.take<uint32_t>(p.words);
   const size_t kk = (size_t)std::max(kmax, 1) + 1;
   for (int i = 0; i < 3; ++i) c.list[i] = cv.take<int32_t>(kk);
   c.cb = cv.take<T>(kk);
@@ -51,6 +53,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   c.cx3 = cv.take<T>(kk);
   c.partial = cv.take<double>(4 * kRedBlocks);
   c.partial2 = cv.take<double>(std::max<int64_t>(kRedBlocks, p.L1));
+  c.pgrid = cv.take<double>(std::max<int64_t>(kRedBlocks, p.L2 >> p.logB));
   c.argpart = cv.take<ArgKey>(kArgBlocks);
   c.ibuf = cv.take<int32_t>(64);
   c.blockcnt = cv.take<uint32_t>((p.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords + 2);
@@ -62,7 +65,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
 static int kmax_for(cs_algo algo, int32_t k) {
   switch (algo) {
     case CS_ALGO_SP: return 2 * k;
-    case CS_ALGO_OMPR: return k + 1;
+    case CS_ALGO_OMPR: return k;
     case CS_ALGO_OPERATOR: return 1;
     default: return k;
   }
@@ -132,12 +135,12 @@ static cs_params defaults(const cs_params* p) {
   return d;
 }
 
-// Loads y: freq-layout copy, ||y||, and c0 = A^T y (raw v-order) into C0.
+// Loads y: freq-layout copy, ||y||, and F^T D^T y (key order) into C0.
 template <typename T>
 static void load_measurements(Ctx<T>& c, const T* y) {
   scatter_freq<T>(c, y, c.Yf);
   c.ynorm = norm2_host<T>(c, y, c.plan.m);
-  transform_adj<T>(c, c.Yf, c.C0);
+  transform_adj<T>(c, c.Yf, c.C0, true);
 }
 
 template <typename T>
@@ -188,12 +191,40 @@ static cs_status recover(cs_algo algo, cs_dtype dt, const void* y, const cs_op* 
   }
 }
 
-// ------------------------------------------------------------------ support validation for cs_ls_solve
+// ------------------------------------------------------------------ cs_ls_solve helpers
 __global__ void k_check_support(const int32_t* __restrict__ sup, int k, int64_t n, int32_t* bad) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
   const int32_t j = sup[i];
   if (j < 0 || j >= n || (i > 0 && sup[i - 1] >= j)) atomicOr(bad, 1);
+}
+
+// key bitmap of a natural-index support
+__global__ void k_support_bits(const int32_t* __restrict__ sup, int k, const Plan pl, uint32_t* __restrict__ bits) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const uint32_t p = (uint32_t)key_of_nat(sup[i], pl);
+  atomicOr(&bits[p >> 5], 1u << (p & 31));
+}
+
+__device__ __forceinline__ uint32_t rank_of(const uint32_t* __restrict__ bits, const uint32_t* __restrict__ wpre,
+                                            uint32_t p) {
+  return wpre[p >> 5] + __popc(bits[p >> 5] & ((1u << (p & 31)) - 1u));
+}
+
+// Between support order with natural coordinates and key order with
+// sign-flipped coordinates.  TO_KEY: xkey[rank(key(sup[i]))] = sign xnat[i];
+// otherwise xnat[i] = sign xkey[rank(key(sup[i]))].
+template <typename T, bool TO_KEY>
+__global__ void k_reorder(const int32_t* __restrict__ sup, int k, const Plan pl, const int8_t* __restrict__ signs,
+                          const uint32_t* __restrict__ bits, const uint32_t* __restrict__ wpre, T* xnat, T* xkey) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const int32_t j = sup[i];
+  const uint32_t slot = rank_of(bits, wpre, (uint32_t)key_of_nat(j, pl));
+  const bool neg = signs[j] < 0;
+  if (TO_KEY) xkey[slot] = neg ? -xnat[i] : xnat[i];
+  else xnat[i] = neg ? -xkey[slot] : xkey[slot];
 }
 
 template <typename T>
@@ -203,18 +234,31 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   ctx_init<T>(c, op, k, ws, ws_bytes, stream);
   setup_operator<T>(c);
   fill<int32_t>(c.ibuf + 16, 1, 0, stream);
-  hipLaunchKernelGGL(k_check_support, dim3((k + 255) / 256), dim3(256), 0, stream, support, k, op->n, c.ibuf + 16);
+  const unsigned gk = (unsigned)((k + 255) / 256);
+  hipLaunchKernelGGL(k_check_support, dim3(gk), dim3(256), 0, stream, support, k, op->n, c.ibuf + 16);
   CS_LAUNCH_CHECK();
   int32_t bad = 0;
   dev_read(stream, c.ibuf + 16, &bad, sizeof(int32_t));
   if (bad) throw Error(CS_E_INVALID, "support must be strictly ascending in [0, N)");
   load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
-  if (x0) CS_HIP(hipMemcpyAsync(theta, x0, sizeof(T) * k, hipMemcpyDeviceToDevice, stream));
+  // the CG works in key order: build the key bitmap, list and prefixes
+  fill_u32(c.bits[0], c.plan.words, 0u, stream);
+  hipLaunchKernelGGL(k_support_bits, dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.bits[0]);
+  CS_LAUNCH_CHECK();
+  bits_to_list<T>(c, c.bits[0], c.list[0], k, c.wpre[0]);
+  const Supp S{c.bits[0], c.wpre[0], c.list[0], k};
+  if (x0)
+    hipLaunchKernelGGL((k_reorder<T, true>), dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0],
+                       c.wpre[0], (T*)x0, c.cx);
+  CS_LAUNCH_CHECK();
   const int cap = prm.cg_max_iter > 0 ? prm.cg_max_iter : 2 * k + 50;
-  cg_solve<T>(c, support, k, (T*)theta, x0 != nullptr, tol, cap);
+  cg_solve<T>(c, S, c.cx, x0 != nullptr, tol, cap);
+  hipLaunchKernelGGL((k_reorder<T, false>), dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0],
+                     c.wpre[0], (T*)theta, c.cx);
+  CS_LAUNCH_CHECK();
   double rn = 0.0;
-  if (info) rn = resid_corr<T>(c, nullptr, 0, support, (const T*)theta, k);
+  if (info) rn = resid_corr<T>(c, S, c.cx);
   CS_HIP(hipStreamSynchronize(stream));
   if (prof_on()) prof_flush();
   if (info) {
@@ -231,12 +275,12 @@ static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, vo
   ctx_init<T>(c, op, 1, ws, ws_bytes, stream);
   setup_operator<T>(c);
   if (!adjoint) {
-    perm_in<T>(c, (const T*)in, c.Dx);
-    transform_fwd<T>(c, c.Dx, c.Yf);
+    perm_in<T>(c, (const T*)in, c.Dd);
+    transform_fwd<T>(c, c.Dd, c.Yf);
     gather_freq<T>(c, c.Yf, (T*)out);
   } else {
     scatter_freq<T>(c, (const T*)in, c.Yf);
-    transform_adj<T>(c, c.Yf, (T*)c.W);
+    transform_adj<T>(c, c.Yf, (T*)c.W, false);
     perm_out<T>(c, (const T*)c.W, (T*)out);
   }
   CS_HIP(hipStreamSynchronize(stream));

@@ -1,21 +1,28 @@
 // CG subsystem: the CG function of Algorithm 1 (lines 11-24) on the weighted
 // normal equations of Eq. (11),
 //     H theta = b,   H = W_S A^T A W_S,   b = W_S A^T y,
-// restricted to the support S (the rows and columns of H off S are zero, so
-// the iteration lives on compact |S|-vectors, Theorem 5's argument).
+// restricted to the support S (rows and columns of H off S are zero, so the
+// iteration lives on compact |S|-vectors, as in the proof of Theorem 5).
 //
 //   r_0 = b - H x_0 (x_0 = 0: r_0 = b), d_0 = r_0
 //   alpha = r^T r / d^T H d;  x += alpha d;  r -= alpha H d
 //   beta = r_new^T r_new / r^T r;  d = r_new + beta d
 // until ||r|| <= tol ||b|| (relative form of the line-15 test).
 //
-// H d is one pass of the transform subsystem over the dense direction buffer
-// (sign flip and scatter of d onto S are fused into the update kernel that
-// produces d).  Inner products are accumulated in FP64 with a fixed-order
-// two-level reduction (per-block partials, then every consumer block sums the
-// partials in the same order), so results are run-to-run deterministic.
-// Scalars stay on the device; the host queues iterations in chunks and reads
-// the `done` flag between chunks.
+// Compact vectors are ordered by key (the order of the column passes) and
+// hold sign-flipped coordinates theta' = R theta, R = diag(+-1) the sign flip
+// of the operator: H' = R H R and b' = R b give the same inner products, so the
+// iterates are those of the plain CG, and the column passes move raw values.
+// One iteration is four launches:
+//   1. forward column pass in COL_DIR mode: d = r + beta d on the support;
+//   2. row pass (DCT post-processing, row mask of D, pre-processing);
+//   3. inverse column pass in COL_Q mode: q = (H d)_S and d^T q;
+//   4. update: alpha, x += alpha d, r -= alpha q, r^T r, beta, convergence.
+// Inner products accumulate in FP64 as per-workgroup partials that the last
+// workgroup to finish reduces in index order (a ticket counter picks it), so
+// results are deterministic and consumers read one scalar.  Scalars stay on the device; every kernel of an iteration
+// exits early once `done` is set, and the host reads the flags between chunks
+// of queued iterations.
 #include "cs_internal.h"
 
 #include <algorithm>
@@ -47,18 +54,13 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, int
   return block_sum(s);
 }
 
-template <typename T>
-__device__ __forceinline__ T sgn_apply(int8_t s, T v) { return s < 0 ? -v : v; }
-
-// b_i = sign_j * C0[vpos(j)], j = S_i;  partial b^T b
+// b'_i = (F^T D^T y)[k_i] for the support keys k_i; partial b^T b
 template <typename T>
 __global__ void k_cg_gather_b(const T* __restrict__ C0, const int32_t* __restrict__ list, int k,
-                              const int8_t* __restrict__ signs, int64_t n, T* __restrict__ b,
-                              double* __restrict__ pbb) {
+                              T* __restrict__ b, double* __restrict__ pbb) {
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-    const int64_t j = list[i];
-    const T v = sgn_apply(signs[j], C0[vpos(j, n)]);
+    const T v = C0[list[i]];
     b[i] = v;
     acc += (double)v * (double)v;
   }
@@ -66,49 +68,25 @@ __global__ void k_cg_gather_b(const T* __restrict__ C0, const int32_t* __restric
   if (threadIdx.x == 0) pbb[blockIdx.x] = acc;
 }
 
-// x = 0, r = d = b, Dd[vpos(S_i)] = sign * d_i;  partial r^T r
+// cold start: x = 0, r = b; partial r^T r
 template <typename T>
-__global__ void k_cg_init_cold(const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
-                               T* __restrict__ Dd, const int32_t* __restrict__ list, int k,
-                               const int8_t* __restrict__ signs, int64_t n, double* __restrict__ prr) {
+__global__ void k_cg_init_cold(const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r, int k,
+                               double* __restrict__ prr) {
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
     const T v = b[i];
     x[i] = (T)0;
     r[i] = v;
-    d[i] = v;
-    const int64_t j = list[i];
-    Dd[vpos(j, n)] = sgn_apply(signs[j], v);
     acc += (double)v * (double)v;
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) prr[blockIdx.x] = acc;
 }
 
-// After W = H x0 (v-order): r = b - (H x0)_S, d = r, Dd = sign * d on S.
-template <typename T>
-__global__ void k_cg_init_warm(const T* __restrict__ Wv, const T* __restrict__ b, T* __restrict__ r,
-                               T* __restrict__ d, T* __restrict__ Dd, const int32_t* __restrict__ list, int k,
-                               const int8_t* __restrict__ signs, int64_t n, double* __restrict__ prr) {
-  double acc = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-    const int64_t j = list[i];
-    const int64_t p = vpos(j, n);
-    const int8_t s = signs[j];
-    const T v = b[i] - sgn_apply(s, Wv[p]);
-    r[i] = v;
-    d[i] = v;
-    Dd[p] = sgn_apply(s, v);
-    acc += (double)v * (double)v;
-  }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) prr[blockIdx.x] = acc;
-}
-
-__global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, const double* __restrict__ pbb, int np,
-                           double tol2, int max_iter) {
-  const double rr = sum_partials(prr, np);
-  const double bb = sum_partials(pbb, np);
+__global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, int nrr, const double* __restrict__ pbb,
+                           int nbb, double tol2, int max_iter) {
+  const double rr = sum_partials(prr, nrr);
+  const double bb = sum_partials(pbb, nbb);
   if (threadIdx.x == 0) {
     cg->rr[0] = rr;
     cg->rr[1] = rr;
@@ -116,38 +94,25 @@ __global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, const 
     cg->tol2 = tol2;
     cg->iters = 0;
     cg->flags = 0;
+    cg->cnt_q = 0u;
+    cg->cnt_u = 0u;
     const bool fin = isfinite(rr) && isfinite(bb);
     if (!fin) cg->flags |= CS_F_NONFINITE;
     cg->done = (!fin || rr <= tol2 * bb || max_iter <= 0) ? 1 : 0;
   }
 }
 
-// q_i = sign * W[vpos(S_i)];  partial d^T q
+// alpha = rr / d^T q (d^T q from the inverse pass); x += alpha d; r -= alpha q;
+// per-block r^T r, and the last block to finish reduces them (fixed order) to
+// the next rr, beta and the convergence test.
 template <typename T>
-__global__ void k_cg_q(const T* __restrict__ Wv, const int32_t* __restrict__ list, int k,
-                       const int8_t* __restrict__ signs, int64_t n, const T* __restrict__ d, T* __restrict__ q,
-                       double* __restrict__ pdq, const CgScalars* __restrict__ cg) {
+__global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ d, const T* __restrict__ q,
+                            int k, double* __restrict__ prr, CgScalars* cg, int it, int max_iter) {
+  __shared__ int last;
   if (cg->done) return;
-  double acc = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-    const int64_t j = list[i];
-    const T v = sgn_apply(signs[j], Wv[vpos(j, n)]);
-    q[i] = v;
-    acc += (double)d[i] * (double)v;
-  }
-  acc = block_sum(acc);
-  if (threadIdx.x == 0) pdq[blockIdx.x] = acc;
-}
-
-// alpha = rr / dq; x += alpha d; r -= alpha q; partial r^T r
-template <typename T>
-__global__ void k_cg_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ d, const T* __restrict__ q,
-                        int k, const double* __restrict__ pdq, double* __restrict__ prr, CgScalars* cg, int np,
-                        int it) {
-  if (cg->done) return;
-  const double dq = sum_partials(pdq, np);
+  const double dq = cg->dq;
   const double rr = cg->rr[it & 1];
-  if (!(dq > 0.0) || !isfinite(dq)) {           // H not positive on d (Theorem 3 fails)
+  if (!(dq > 0.0) || !isfinite(dq)) {           // H not positive on d (Theorem 3's condition fails)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       cg->flags |= CS_F_CG_BREAKDOWN;
       cg->done = 1;
@@ -163,62 +128,77 @@ __global__ void k_cg_xr(T* __restrict__ x, T* __restrict__ r, const T* __restric
     acc += (double)rv * (double)rv;
   }
   acc = block_sum(acc);
-  if (threadIdx.x == 0) prr[blockIdx.x] = acc;
-}
-
-// beta = rr_new / rr; d = r + beta d; Dd = sign * d on S; convergence test.
-template <typename T>
-__global__ void k_cg_d(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ Dd,
-                       const int32_t* __restrict__ list, int k, const int8_t* __restrict__ signs, int64_t n,
-                       const double* __restrict__ prr, CgScalars* cg, int np, int it, int max_iter) {
-  if (cg->done) return;
-  const double rr_new = sum_partials(prr, np);
-  const double rr = cg->rr[it & 1];
-  const T beta = (T)(rr_new / rr);
-  const bool conv = rr_new <= cg->tol2 * cg->bb;
-  if (!conv) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-      const T dv = r[i] + beta * d[i];
-      d[i] = dv;
-      const int64_t j = list[i];
-      Dd[vpos(j, n)] = sgn_apply(signs[j], dv);
+  if (threadIdx.x == 0) {
+    prr[blockIdx.x] = acc;
+    __threadfence();
+    last = atomicAdd(&cg->cnt_u, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    const volatile double* vp = prr;
+    double s = 0.0;
+    for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) s += vp[i];
+    const double rr_new = block_sum(s);
+    if (threadIdx.x == 0) {
+      const bool fin = isfinite(rr_new);
+      cg->rr[(it + 1) & 1] = rr_new;
+      cg->beta = rr_new / rr;
+      cg->iters = it + 1;
+      cg->cnt_u = 0u;
+      if (!fin) cg->flags |= CS_F_NONFINITE;
+      if (!fin || rr_new <= cg->tol2 * cg->bb || it + 1 >= max_iter) cg->done = 1;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    cg->rr[(it + 1) & 1] = rr_new;
-    cg->iters = it + 1;
-    if (!isfinite(rr_new)) cg->flags |= CS_F_NONFINITE;
-    if (conv || !isfinite(rr_new) || it + 1 >= max_iter) cg->done = 1;
-  }
 }
 
 template <typename T>
-int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol, int max_iter) {
+int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter) {
   hipStream_t s = c.stream;
-  const int64_t n = c.plan.n;
+  const int k = S.k;
   const int nb = red_blocks(k);
+  const int ncol = (int)(c.plan.L2 >> c.plan.logB);   // column-pass workgroups
   double* prr = c.partial;
   double* pbb = c.partial + kRedBlocks;
-  double* pdq = c.partial + 2 * kRedBlocks;
-  fill<T>(c.Dd, n, (T)0, s);
-  hipLaunchKernelGGL(k_cg_gather_b<T>, dim3(nb), dim3(kRedThreads), 0, s, c.C0, list, k, c.signs, n, c.cb, pbb);
+  double* pdq = c.pgrid;
+  hipLaunchKernelGGL(k_cg_gather_b<T>, dim3(nb), dim3(kRedThreads), 0, s, c.C0, S.list, k, c.cb, pbb);
   CS_LAUNCH_CHECK();
   if (warm) {
-    scatter_signed<T>(c, c.Dd, list, x, k);
-    transform_happly<T>(c, c.Dd, nullptr);
-    hipLaunchKernelGGL(k_cg_init_warm<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.W, c.cb, c.cr, c.cd,
-                       c.Dd, list, k, c.signs, n, prr);
+    // r = b - H x0, d = r through the transform, partial r^T r per column workgroup
+    ColIO<T> in = col_io<T>(c, COL_X, &S);
+    in.x = x;
+    launch_col<T>(c, nullptr, c.W, false, in);
+    launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, nullptr);
+    ColIO<T> out = col_io<T>(c, COL_R, &S);
+    out.r = c.cr;
+    out.d = c.cd;
+    out.b = c.cb;
+    out.pout = c.pgrid;
+    launch_col<T>(c, c.W, nullptr, true, out);
+    c.transforms += 2;
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, c.pgrid, ncol, pbb, nb, tol * tol,
+                       max_iter);
   } else {
-    hipLaunchKernelGGL(k_cg_init_cold<T>, dim3(nb), dim3(kRedThreads), 0, s, c.cb, x, c.cr, c.cd, c.Dd, list, k,
-                       c.signs, n, prr);
+    hipLaunchKernelGGL(k_cg_init_cold<T>, dim3(nb), dim3(kRedThreads), 0, s, c.cb, x, c.cr, k, prr);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, nb, pbb, nb, tol * tol, max_iter);
   }
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, pbb, nb, tol * tol, max_iter);
-  CS_LAUNCH_CHECK();
+
+  ColIO<T> dir = col_io<T>(c, COL_DIR, &S);
+  dir.r = c.cr;
+  dir.d = c.cd;
+  dir.cg = c.cg;
+  ColIO<T> qio = col_io<T>(c, COL_Q, &S);
+  qio.q = c.cq;
+  qio.d = c.cd;
+  qio.pout = pdq;
+  qio.cg = c.cg;
   const int* done = &c.cg->done;
-  // Iterations are queued in chunks; the host reads the device flags between
-  // chunks.  After the first chunk the next one is sized from the observed
-  // geometric rate of r^T r so that few early-exit launches are queued.
+
+  // Iterations are queued in chunks; the host reads the flags between chunks.
+  // After the first chunk the next is sized from the observed geometric rate
+  // of r^T r so that few early-exit launches are queued.
   int it = 0;
   int chunk = std::min(4, std::max(max_iter, 1));
   CgScalars host{};
@@ -227,15 +207,13 @@ int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol,
   while (it < max_iter) {
     const int q = std::min(chunk, max_iter - it);
     for (int u = 0; u < q; ++u, ++it) {
-      transform_happly<T>(c, c.Dd, done);
-      hipLaunchKernelGGL(k_cg_q<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.W, list, k, c.signs, n, c.cd,
-                         c.cq, pdq, c.cg);
-      CS_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_cg_xr<T>, dim3(nb), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, pdq, prr, c.cg,
-                         nb, it);
-      CS_LAUNCH_CHECK();
-      hipLaunchKernelGGL(k_cg_d<T>, dim3(nb), dim3(kRedThreads), 0, s, c.cr, c.cd, c.Dd, list, k, c.signs, n, prr,
-                         c.cg, nb, it, max_iter);
+      dir.it = it;
+      launch_col<T>(c, nullptr, c.W, false, dir);
+      launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done);
+      launch_col<T>(c, c.W, nullptr, true, qio);
+      c.transforms += 2;
+      hipLaunchKernelGGL(k_cg_update<T>, dim3(nb), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr, c.cg, it,
+                         max_iter);
       CS_LAUNCH_CHECK();
     }
     dev_read(s, c.cg, &host, sizeof(CgScalars));
@@ -263,18 +241,49 @@ int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol,
 }
 
 template <typename T>
-double resid_corr(Ctx<T>& c, const int32_t* old_list, int old_k, const int32_t* list, const T* x, int k) {
-  if (old_list && old_k > 0) scatter_zero<T>(c, c.Dx, old_list, old_k);
-  scatter_signed<T>(c, c.Dx, list, x, k);
-  transform_resid<T>(c, c.Dx);
+double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
+  ColIO<T> in = col_io<T>(c, COL_X, &S);
+  in.x = const_cast<T*>(x);
+  launch_col<T>(c, nullptr, c.W, false, in);
+  launch_row<T>(c, ROW_RESID, c.Yf, nullptr, c.partial2, nullptr);
+  launch_col<T>(c, c.W, (Cx<T>*)c.Cc, true, col_io<T>(c, COL_KEY, nullptr));
+  c.transforms += 2;
+  sum_partials_to(c.partial2, (int)(c.plan.L1 >> 1), &c.cg->resid2, c.stream);
   double r2 = 0.0;
   dev_read(c.stream, &c.cg->resid2, &r2, sizeof(double));
   return std::sqrt(r2);
 }
 
-template int cg_solve<float>(Ctx<float>&, const int32_t*, int, float*, bool, double, int);
-template int cg_solve<double>(Ctx<double>&, const int32_t*, int, double*, bool, double, int);
-template double resid_corr<float>(Ctx<float>&, const int32_t*, int, const int32_t*, const float*, int);
-template double resid_corr<double>(Ctx<double>&, const int32_t*, int, const int32_t*, const double*, int);
+// out[i] = x[position of to[i] in from] or 0 (both lists ascending)
+template <typename T>
+__global__ void k_remap(const int32_t* __restrict__ from, const T* __restrict__ x, int kfrom,
+                        const int32_t* __restrict__ to, T* __restrict__ out, int kto) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kto) return;
+  const int32_t key = to[i];
+  int lo = 0, hi = kfrom - 1;
+  T v = (T)0;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int32_t m = from[mid];
+    if (m == key) { v = x[mid]; break; }
+    if (m < key) lo = mid + 1; else hi = mid - 1;
+  }
+  out[i] = v;
+}
+
+template <typename T>
+void remap(Ctx<T>& c, const int32_t* from, const T* x, int kfrom, const int32_t* to, T* out, int kto) {
+  if (kto <= 0) return;
+  hipLaunchKernelGGL(k_remap<T>, dim3((kto + 255) / 256), dim3(256), 0, c.stream, from, x, kfrom, to, out, kto);
+  CS_LAUNCH_CHECK();
+}
+
+#define CS_INST(T)                                                                    \
+  template int cg_solve<T>(Ctx<T>&, const Supp&, T*, bool, double, int);            \
+  template double resid_corr<T>(Ctx<T>&, const Supp&, const T*);                    \
+  template void remap<T>(Ctx<T>&, const int32_t*, const T*, int, const int32_t*, T*, int);
+CS_INST(float)
+CS_INST(double)
 
 }  // namespace csr

@@ -2,11 +2,14 @@
 // OMPR (the other two greedy algorithms of Sec. IV), all built from the same
 // three steps: correlation A^T r, support selection, CG least squares.
 //
-// State lives on the device: supports as sorted int32 lists plus N-bit
-// bitmaps, solutions as compact vectors, the current solution also scattered
-// (sign-flipped, v-order) into the dense buffer Dx that the residual pass
-// reads.  Warm starts gather the previous solution from Dx, which is zero off
-// the previous support, so new indices start at 0.
+// State lives on the device: supports as N-bit bitmaps over keys (the order
+// of the column passes), with ascending key lists and per-word prefix counts
+// that the column passes use to find a key's compact slot; solutions are
+// compact vectors in that order, in sign-flipped coordinates (x'_j = sign_j
+// x_j; the correlations kept are F^T D^T r, so x' + eta F^T D^T r = sign (x +
+// eta A^T r) and every magnitude the selections compare is unchanged).  Warm
+// starts carry the previous solution over to the new support by key (new
+// indices start at 0).  Selection breaks ties by natural index.
 //
 // Decision rules follow the SP/OMPR readings documented with the oracle:
 //   SP:   stop with T' when T' == T; stop with (T, x) when ||r'|| > ||r||.
@@ -20,24 +23,6 @@
 namespace csr {
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
-
-// out[i] = vals[position of sub[i] in sup] (sub is a subset of sup, both ascending)
-template <typename T>
-__global__ void k_subset_gather(const int32_t* __restrict__ sup, const T* __restrict__ vals, int ksup,
-                                const int32_t* __restrict__ sub, T* __restrict__ out, int ksub) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ksub) return;
-  const int32_t key = sub[i];
-  int lo = 0, hi = ksup - 1;
-  T v = (T)0;
-  while (lo <= hi) {
-    const int mid = (lo + hi) >> 1;
-    const int32_t m = sup[mid];
-    if (m == key) { v = vals[mid]; break; }
-    if (m < key) lo = mid + 1; else hi = mid - 1;
-  }
-  out[i] = v;
-}
 
 // OMPR drop step.  Candidates I u {j}: z_i = x_i + eta (A^T r)_i, z_j = eta (A^T r)_j.
 // The dropped element is the last under (|z| desc, index asc): the smallest
@@ -55,8 +40,8 @@ __device__ __forceinline__ bool dkey_gt(uint64_t ah, uint32_t al, uint64_t bh, u
 
 template <typename T>
 __global__ void k_ompr_drop(const T* __restrict__ x, const int32_t* __restrict__ list, int k,
-                            const T* __restrict__ Wv, const int8_t* __restrict__ signs, int64_t n, T eta,
-                            const int32_t* __restrict__ jptr, int32_t* __restrict__ out) {
+                            const T* __restrict__ Wv, const Plan pl, T eta, const int32_t* __restrict__ jptr,
+                            int32_t* __restrict__ out) {
   // single block of 1024 threads
   __shared__ uint64_t sh_h[16];
   __shared__ uint32_t sh_l[16];
@@ -64,18 +49,17 @@ __global__ void k_ompr_drop(const T* __restrict__ x, const int32_t* __restrict__
   uint32_t bl = 0;
   const int32_t jn = *jptr;
   for (int i = threadIdx.x; i <= k; i += blockDim.x) {
-    int64_t j;
-    T z;
+    int64_t j, key;
     if (i < k) {
-      j = list[i];
-      const T cv = signs[j] < 0 ? -Wv[vpos(j, n)] : Wv[vpos(j, n)];
-      z = x[i] + eta * cv;
+      key = list[i];
+      j = nat_of_key(key, pl);
     } else {
       j = jn;
       if (j < 0) continue;
-      const T cv = signs[j] < 0 ? -Wv[vpos(j, n)] : Wv[vpos(j, n)];
-      z = eta * cv;
+      key = key_of_nat(j, pl);
     }
+    const T cv = Wv[key];   // sign_j (A^T r)_j
+    const T z = (i < k) ? x[i] + eta * cv : eta * cv;
     const uint64_t h = ~mag_bits2(z);
     const uint32_t l = (uint32_t)j;
     if (dkey_gt(h, l, bh, bl)) { bh = h; bl = l; }
@@ -94,34 +78,46 @@ __global__ void k_ompr_drop(const T* __restrict__ x, const int32_t* __restrict__
   }
 }
 
-__global__ void k_swap_bits(uint32_t* bits, const int32_t* __restrict__ jd) {
-  // jd[0] = j to set, jd[1] = index to clear
+// key bitmap update for a swap: jd[0] = index to add, jd[1] = index to drop (natural)
+__global__ void k_swap_bits(uint32_t* bits, const int32_t* __restrict__ jd, const Plan pl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const uint32_t j = (uint32_t)jd[0], d = (uint32_t)jd[1];
-    bits[d >> 5] &= ~(1u << (d & 31));
-    bits[j >> 5] |= 1u << (j & 31);
+    const uint32_t pj = (uint32_t)key_of_nat(jd[0], pl), pd = (uint32_t)key_of_nat(jd[1], pl);
+    bits[pd >> 5] &= ~(1u << (pd & 31));
+    bits[pj >> 5] |= 1u << (pj & 31);
   }
 }
 
-__global__ void k_set_bit_dev(uint32_t* bits, const int32_t* __restrict__ jp) {
+// add the natural index *jp to a key bitmap
+__global__ void k_set_bit_dev(uint32_t* bits, const int32_t* __restrict__ jp, const Plan pl) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int32_t j = *jp;
-    if (j >= 0) bits[(uint32_t)j >> 5] |= 1u << ((uint32_t)j & 31);
+    if (j >= 0) {
+      const uint32_t p = (uint32_t)key_of_nat(j, pl);
+      bits[p >> 5] |= 1u << (p & 31);
+    }
   }
 }
 
+// dense output s[j] = sign_j x'_i for j = nat_of_key(list[i]), and the
+// natural-index bitmap of the support
 template <typename T>
-__global__ void k_scatter_plain(T* __restrict__ s, const int32_t* __restrict__ list, const T* __restrict__ x, int k) {
+__global__ void k_output(T* __restrict__ s, uint32_t* __restrict__ nbits, const int32_t* __restrict__ list,
+                         const T* __restrict__ x, int k, const Plan pl, const int8_t* __restrict__ signs) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < k) s[list[i]] = x[i];
+  if (i < k) {
+    const uint32_t j = (uint32_t)nat_of_key(list[i], pl);
+    s[j] = signs[j] < 0 ? -x[i] : x[i];
+    atomicOr(&nbits[j >> 5], 1u << (j & 31));
+  }
 }
 
 template <typename T>
 void write_output(Ctx<T>& c, const int32_t* list, const T* x, int k, T* s_out, int32_t* supp_out) {
   fill<T>(s_out, c.plan.n, (T)0, c.stream);
-  hipLaunchKernelGGL(k_scatter_plain<T>, dim3(nblk(k, 256)), dim3(256), 0, c.stream, s_out, list, x, k);
+  fill_u32(c.nbits, c.plan.words, 0u, c.stream);
+  hipLaunchKernelGGL(k_output<T>, dim3(nblk(k, 256)), dim3(256), 0, c.stream, s_out, c.nbits, list, x, k, c.plan, c.signs);
   CS_LAUNCH_CHECK();
-  CS_HIP(hipMemcpyAsync(supp_out, list, sizeof(int32_t) * k, hipMemcpyDeviceToDevice, c.stream));
+  bits_to_list<T>(c, c.nbits, supp_out, k, nullptr);   // ascending natural indices
 }
 
 static inline int cg_cap(const cs_params& prm, int k) {
@@ -132,27 +128,27 @@ static inline int cg_cap(const cs_params& prm, int k) {
 template <typename T>
 void run_omp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info) {
   hipStream_t s = c.stream;
-  const int64_t words = c.plan.words;
-  uint32_t* bitsS = c.bits[0];
-  int32_t* cur = c.list[0];
-  int32_t* nxt = c.list[1];
-  T* x = c.cx;
-  fill_u32(bitsS, words, 0u, s);
-  fill<T>(c.Dx, c.plan.n, (T)0, s);
+  uint32_t* bits = c.bits[0];            // support so far (keys)
+  int cur = 0, nxt = 1;                   // list / prefix slots of the old and new support
+  T* xc = c.cx;
+  T* xn = c.cx3;
+  fill_u32(bits, c.plan.words, 0u, s);
   double rn = 0.0;
   for (int i = 1; i <= K; ++i) {
-    // the first correlation is A^T r_0 = A^T y, already in C0
-    argmax_excl<T>(c, i == 1 ? (const T*)c.C0 : (const T*)c.W, bitsS, c.ibuf);   // line 03
-    hipLaunchKernelGGL(k_set_bit_dev, dim3(1), dim3(64), 0, s, bitsS, (const int32_t*)c.ibuf);   // line 04
+    // line 03: the first correlation is A^T r_0 = A^T y, already in C0
+    argmax_excl<T>(c, i == 1 ? (const T*)c.C0 : (const T*)c.Cc, bits, c.ibuf);
+    hipLaunchKernelGGL(k_set_bit_dev, dim3(1), dim3(64), 0, s, bits, (const int32_t*)c.ibuf, c.plan);  // line 04
     CS_LAUNCH_CHECK();
-    bits_to_list<T>(c, bitsS, nxt, i);
+    bits_to_list<T>(c, bits, c.list[nxt], i, c.wpre[nxt]);
+    const Supp S{bits, c.wpre[nxt], c.list[nxt], i};
     const bool warm = prm.warm_start != 0 && i > 1;
-    if (warm) gather_signed<T>(c, c.Dx, nxt, x, i);
-    cg_solve<T>(c, nxt, i, x, warm, tol, cg_cap(prm, i));              // line 06
-    rn = resid_corr<T>(c, cur, i - 1, nxt, x, i);                       // line 07 (+ next line 03's A^T r)
+    if (warm) remap<T>(c, c.list[cur], xc, i - 1, c.list[nxt], xn, i);
+    cg_solve<T>(c, S, xn, warm, tol, cg_cap(prm, i));      // line 06
+    rn = resid_corr<T>(c, S, xn);                           // line 07 (+ the next line 03's A^T r)
     std::swap(cur, nxt);
+    std::swap(xc, xn);
   }
-  write_output<T>(c, cur, x, K, s_out, supp_out);
+  write_output<T>(c, c.list[cur], xc, K, s_out, supp_out);
   if (info) { info->outer_iters = K; info->resid_norm = rn; }
 }
 
@@ -161,42 +157,36 @@ template <typename T>
 void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info) {
   hipStream_t s = c.stream;
   const int64_t words = c.plan.words;
-  uint32_t* bT = c.bits[0];
-  uint32_t* bU = c.bits[1];   // T u D
-  uint32_t* bN = c.bits[2];   // D, then T'
-  int32_t* lT = c.list[0];
-  int32_t* lU = c.list[1];
-  int32_t* lN = c.list[2];
-  T* xT = c.cx;               // on T
-  T* xU = c.cx2;              // on T u D
-  T* xN = c.cx3;              // on T'
+  int iT = 0, iU = 1, iN = 2;   // slots: current T, T u D, T'
+  T* xT = c.cx;
+  T* xU = c.cx2;
+  T* xN = c.cx3;
   const bool warm = prm.warm_start != 0;
   const int max_outer = prm.max_outer > 0 ? prm.max_outer : 100;
+  auto supp = [&](int i, int k) { return Supp{c.bits[i], c.wpre[i], c.list[i], k}; };
 
-  fill<T>(c.Dx, c.plan.n, (T)0, s);
-  topk_dense<T>(c, c.C0, nullptr, K, bT);
-  bits_to_list<T>(c, bT, lT, K);
-  cg_solve<T>(c, lT, K, xT, false, tol, cg_cap(prm, K));
-  double rn = resid_corr<T>(c, nullptr, 0, lT, xT, K);
+  topk_dense<T>(c, c.C0, nullptr, K, c.bits[iT]);
+  bits_to_list<T>(c, c.bits[iT], c.list[iT], K, c.wpre[iT]);
+  cg_solve<T>(c, supp(iT, K), xT, false, tol, cg_cap(prm, K));
+  double rn = resid_corr<T>(c, supp(iT, K), xT);
   int rounds = 0;
   bool stopped = false;
   for (int l = 1; l <= max_outer; ++l) {
     rounds = l;
-    topk_dense<T>(c, (const T*)c.W, bT, K, bN);          // D: top-K of |A^T r| outside T
-    bits_or(bT, bN, bU, words, s);
-    bits_to_list<T>(c, bU, lU, 2 * K);
-    if (warm) gather_signed<T>(c, c.Dx, lU, xU, 2 * K);
-    cg_solve<T>(c, lU, 2 * K, xU, warm, tol, cg_cap(prm, 2 * K));
-    topk_compact<T>(c, xU, lU, 2 * K, K, bN);             // T': top-K of |x~| over T u D
-    bits_to_list<T>(c, bN, lN, K);
-    if (warm)
-      hipLaunchKernelGGL(k_subset_gather<T>, dim3(nblk(K, 256)), dim3(256), 0, s, lU, xU, 2 * K, lN, xN, K);
-    CS_LAUNCH_CHECK();
-    cg_solve<T>(c, lN, K, xN, warm, tol, cg_cap(prm, K));
-    const bool same = bits_equal(bN, bT, words, c.ibuf + 8, s);
-    const double rn2 = resid_corr<T>(c, lT, K, lN, xN, K);
+    topk_dense<T>(c, (const T*)c.Cc, c.bits[iT], K, c.bits[iN]);   // D: top-K of |A^T r| outside T
+    bits_or(c.bits[iT], c.bits[iN], c.bits[iU], words, s);
+    bits_to_list<T>(c, c.bits[iU], c.list[iU], 2 * K, c.wpre[iU]);
+    if (warm) remap<T>(c, c.list[iT], xT, K, c.list[iU], xU, 2 * K);
+    cg_solve<T>(c, supp(iU, 2 * K), xU, warm, tol, cg_cap(prm, 2 * K));
+    topk_compact<T>(c, xU, c.list[iU], 2 * K, K, c.bits[iN]);     // T': top-K of |x~| over T u D
+    bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
+    if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
+    cg_solve<T>(c, supp(iN, K), xN, warm, tol, cg_cap(prm, K));
+    const bool same = bits_equal(c.bits[iN], c.bits[iT], words, c.ibuf + 8, s);
+    const double rn2 = resid_corr<T>(c, supp(iN, K), xN);
     if (same) {
-      std::swap(lT, lN); std::swap(bT, bN); std::swap(xT, xN);
+      std::swap(iT, iN);
+      std::swap(xT, xN);
       rn = rn2;
       stopped = true;
       break;
@@ -205,11 +195,12 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
       stopped = true;
       break;
     }
-    std::swap(lT, lN); std::swap(bT, bN); std::swap(xT, xN);
+    std::swap(iT, iN);
+    std::swap(xT, xN);
     rn = rn2;
   }
   if (!stopped) c.flags |= CS_F_OUTER_MAXITER;
-  write_output<T>(c, lT, xT, K, s_out, supp_out);
+  write_output<T>(c, c.list[iT], xT, K, s_out, supp_out);
   if (info) { info->outer_iters = rounds; info->resid_norm = rn; }
 }
 
@@ -217,42 +208,42 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
 template <typename T>
 void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info) {
   hipStream_t s = c.stream;
-  uint32_t* bI = c.bits[0];
-  int32_t* lI = c.list[0];
-  int32_t* lN = c.list[1];
+  uint32_t* bits = c.bits[0];
+  int cur = 0, nxt = 1;
   T* xI = c.cx;
   T* xN = c.cx3;
   const bool warm = prm.warm_start != 0;
   const int max_outer = prm.max_outer > 0 ? prm.max_outer : 4 * K;
   const double eta = prm.ompr_eta > 0 ? prm.ompr_eta : (double)c.plan.n / (double)c.plan.m;
 
-  fill<T>(c.Dx, c.plan.n, (T)0, s);
-  topk_dense<T>(c, c.C0, nullptr, K, bI);
-  bits_to_list<T>(c, bI, lI, K);
-  cg_solve<T>(c, lI, K, xI, false, tol, cg_cap(prm, K));
-  double rn = resid_corr<T>(c, nullptr, 0, lI, xI, K);
+  topk_dense<T>(c, c.C0, nullptr, K, bits);
+  bits_to_list<T>(c, bits, c.list[cur], K, c.wpre[cur]);
+  cg_solve<T>(c, Supp{bits, c.wpre[cur], c.list[cur], K}, xI, false, tol, cg_cap(prm, K));
+  double rn = resid_corr<T>(c, Supp{bits, c.wpre[cur], c.list[cur], K}, xI);
   int swaps = 0;
   bool stopped = false;
   int32_t jd[2];
   for (int t = 1; t <= max_outer; ++t) {
     if (rn <= 1e-12 * c.ynorm) { stopped = true; break; }
-    argmax_excl<T>(c, (const T*)c.W, bI, c.ibuf);
-    hipLaunchKernelGGL(k_ompr_drop<T>, dim3(1), dim3(1024), 0, s, xI, lI, K, (const T*)c.W, c.signs, c.plan.n,
+    argmax_excl<T>(c, (const T*)c.Cc, bits, c.ibuf);
+    hipLaunchKernelGGL(k_ompr_drop<T>, dim3(1), dim3(1024), 0, s, xI, c.list[cur], K, (const T*)c.Cc, c.plan,
                        (T)eta, (const int32_t*)c.ibuf, c.ibuf + 1);
     CS_LAUNCH_CHECK();
     dev_read(s, c.ibuf, jd, 2 * sizeof(int32_t));
     if (jd[0] < 0 || jd[1] == jd[0]) { stopped = true; break; }
-    hipLaunchKernelGGL(k_swap_bits, dim3(1), dim3(64), 0, s, bI, (const int32_t*)c.ibuf);
+    hipLaunchKernelGGL(k_swap_bits, dim3(1), dim3(64), 0, s, bits, (const int32_t*)c.ibuf, c.plan);
     CS_LAUNCH_CHECK();
-    bits_to_list<T>(c, bI, lN, K);
-    if (warm) gather_signed<T>(c, c.Dx, lN, xN, K);
-    cg_solve<T>(c, lN, K, xN, warm, tol, cg_cap(prm, K));
-    rn = resid_corr<T>(c, lI, K, lN, xN, K);
-    std::swap(lI, lN); std::swap(xI, xN);
+    bits_to_list<T>(c, bits, c.list[nxt], K, c.wpre[nxt]);
+    const Supp S{bits, c.wpre[nxt], c.list[nxt], K};
+    if (warm) remap<T>(c, c.list[cur], xI, K, c.list[nxt], xN, K);
+    cg_solve<T>(c, S, xN, warm, tol, cg_cap(prm, K));
+    rn = resid_corr<T>(c, S, xN);
+    std::swap(cur, nxt);
+    std::swap(xI, xN);
     ++swaps;
   }
   if (!stopped) c.flags |= CS_F_OUTER_MAXITER;
-  write_output<T>(c, lI, xI, K, s_out, supp_out);
+  write_output<T>(c, c.list[cur], xI, K, s_out, supp_out);
   if (info) { info->outer_iters = swaps; info->resid_norm = rn; }
 }
 

@@ -104,6 +104,32 @@ __host__ __device__ __forceinline__ int64_t fpos(int64_t q, const Plan& p) {
   return 2 * f + h;
 }
 
+// Key order.  The greedy drivers index candidates by key, an order that
+// follows the column passes: position p (complex element m = p/2 = n1 L2 + c,
+// half h = p mod 2) belongs to strip g = c / B; keys number strips first, then
+// rows, then the strip's columns, then the half, so the support bits and the
+// correlation values one column workgroup touches are contiguous.
+__host__ __device__ __forceinline__ int64_t key_of_pos(int64_t p, const Plan& pl) {
+  const int64_t m = p >> 1, h = p & 1;
+  const int64_t n1 = m >> pl.logL2, c = m & (pl.L2 - 1);
+  const int64_t g = c >> pl.logB, b = c & (pl.B - 1);
+  return ((((g << pl.logL1) + n1) << pl.logB | b) << 1) | h;
+}
+__host__ __device__ __forceinline__ int64_t pos_of_key(int64_t k, const Plan& pl) {
+  const int64_t h = k & 1;
+  int64_t t = k >> 1;
+  const int64_t b = t & (pl.B - 1);
+  t >>= pl.logB;
+  const int64_t n1 = t & (pl.L1 - 1), g = t >> pl.logL1;
+  return (((n1 << pl.logL2) + (g << pl.logB) + b) << 1) | h;
+}
+__host__ __device__ __forceinline__ int64_t nat_of_key(int64_t k, const Plan& pl) {
+  return vinv(pos_of_key(k, pl), pl.n);
+}
+__host__ __device__ __forceinline__ int64_t key_of_nat(int64_t j, const Plan& pl) {
+  return key_of_pos(vpos(j, pl.n), pl);
+}
+
 // W_{4N}^idx = exp(-2 pi i idx / (4N)), idx in [0, 4N), from the two-level table.
 template <typename T>
 __device__ __forceinline__ Cx<T> tw4n(const Plan& p, uint32_t idx) {
@@ -119,6 +145,44 @@ __device__ __forceinline__ int xcd_order(int b, int nb) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// ------------------------------------------------------------------ compact column-pass I/O
+// The CG works on compact vectors indexed by the support's rank in key order
+// (key_of_pos).  Its support is an ascending key list plus an N-bit key bitmap
+// with, per 32-bit word, the number of set bits in all earlier words (wpre):
+// the compact slot of key k is wpre[k/32] + popcount(bits below k in its
+// word), which gives each column strip its range of slots.  The CG runs in
+// sign-flipped coordinates (x' = R x for the diagonal sign flip R), which
+// leaves every inner product unchanged and lets the column passes move raw
+// values.
+enum ColMode {
+  COL_DENSE = 0,   // forward: read a dense v-order input; inverse: write dense v-order output
+  COL_X = 1,       // forward: input = x on the support
+  COL_DIR = 2,     // forward: d = r + beta d (d = r at iteration 0), input = d
+  COL_Q = 3,       // inverse: q = output on the support, d^T q (last workgroup reduces)
+  COL_R = 4,       // inverse: r = b - output, d = r, partial r^T r per workgroup
+  COL_KEY = 5      // inverse: write dense key-order output
+};
+
+template <typename T>
+struct ColIO {
+  int mode;
+  int it;                  // COL_DIR: iteration index
+  int max_iter;            // COL_DIR: iteration cap
+  int npin;                // COL_DIR: number of r^T r partials in pin
+  int kcap;                // compact length; slots at or beyond it are ignored
+  const uint32_t* sbits;   // support bitmap over keys
+  const uint32_t* wpre;    // per-word exclusive prefix counts of sbits
+  const int32_t* list;     // ascending support keys (kcap of them)
+  T* x;
+  T* r;
+  T* d;
+  T* q;
+  const T* b;
+  const double* pin;       // COL_DIR: r^T r partials of the previous update
+  double* pout;            // COL_Q / COL_R: one partial per workgroup
+  struct CgScalars* cg;    // nullable: no early exit, no scalar updates
+};
+
 // ------------------------------------------------------------------ context
 // Per-call state: plan, workspace carving, device scalars.
 struct CgScalars {
@@ -126,9 +190,13 @@ struct CgScalars {
   double bb;              // b^T b
   double tol2;            // tol^2
   double resid2;          // ||y - A x||^2 of the last residual pass
+  double dq;              // d^T H d of the current iteration
+  double beta;            // next direction update coefficient
   int32_t done;
   int32_t iters;
   int32_t flags;
+  uint32_t cnt_q;         // workgroups finished in the current d^T H d pass
+  uint32_t cnt_u;         // blocks finished in the current update
   int32_t pad;
 };
 
@@ -158,22 +226,25 @@ struct Ctx {
   int kmax;                // largest support handled by the compact buffers
   // dense N-vectors (v-order unless noted)
   Cx<T>* W;                // transform work buffer (L complex)
-  T* Dd;                   // CG direction, dense
-  T* Dx;                   // current solution, dense
-  T* C0;                   // A^T y (raw, unsigned by the sign flip), dense
+  T* Dd;                   // dense scratch (operator input)
+  T* Cc;                   // correlation F^T D^T r, key order (shares Dd's memory)
+  T* C0;                   // F^T D^T y (A^T y before the sign flip), key order
   T* Yf;                   // y in freq-layout (N reals)
-  // twiddles and mask
+  // twiddles, masks
   Cx<T>* tw_col; Cx<T>* tw_row;   // stage twiddles of the L1- and L2-point FFTs
   Cx<T>* tw_lo; Cx<T>* tw_hi;
-  uint32_t* mask;
-  // bitmaps over natural indices (N bits each)
+  uint32_t* mask;          // row mask of D, freq-layout bits
+  // supports: key bitmaps, ascending key lists and per-word prefix counts
   uint32_t* bits[3];
-  // compact buffers (kmax each)
   int32_t* list[3];
+  uint32_t* wpre[3];
+  uint32_t* nbits;         // natural-index bitmap for the output support
+  // compact buffers (kmax each, key order, sign-flipped coordinates)
   T *cb, *cx, *cr, *cd, *cq, *cx2, *cx3;
   // reductions
-  double* partial;         // >= 2 * kRedBlocks doubles
-  double* partial2;
+  double* partial;         // 4 * kRedBlocks doubles
+  double* partial2;        // row-pass partials (L1/2)
+  double* pgrid;           // column-pass partials (one per column workgroup)
   ArgKey* argpart;         // kArgBlocks
   int32_t* ibuf;           // small int scratch (>= 64)
   uint32_t* blockcnt;      // bitmap compaction block counts
@@ -185,6 +256,14 @@ struct Ctx {
   int64_t cg_iters = 0;
   double model_bytes = 0;
   int32_t flags = 0;
+};
+
+// A support as the CG sees it.
+struct Supp {
+  const uint32_t* bits;    // key bitmap
+  const uint32_t* wpre;    // per-word exclusive prefix counts
+  const int32_t* list;     // ascending keys
+  int k;
 };
 
 constexpr int kRedBlocks = 256;   // blocks of the compact reductions
@@ -209,17 +288,9 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
 // ------------------------------------------------------------------ transform launchers
 enum RowMode { ROW_HAPPLY = 0, ROW_RESID = 1, ROW_FWD = 2, ROW_ADJ = 3 };
 
-template <typename T> void setup_operator(Ctx<T>& c);                  // twiddles + mask (+ validation)
+template <typename T> void setup_operator(Ctx<T>& c);                  // twiddles, masks (+ validation)
 template <typename T> void scatter_freq(Ctx<T>& c, const T* u, T* outf); // u [M] -> freq layout
 template <typename T> void gather_freq(Ctx<T>& c, const T* inf, T* out); // freq layout -> [M]
-// dense v-order `in` -> W -> (row pass mode) -> W (v-order result unless FWD/ADJ)
-template <typename T> void transform_happly(Ctx<T>& c, const T* in, const int* done);
-template <typename T> void transform_resid(Ctx<T>& c, const T* in);      // W = A^T(y - A x), resid2 partials
-template <typename T> void transform_fwd(Ctx<T>& c, const T* in, T* outf); // outf = masked DCT in freq layout
-template <typename T> void perm_in(Ctx<T>& c, const T* x, T* dense);      // dense[vpos(j)] = sign_j x_j
-template <typename T> void perm_out(Ctx<T>& c, const T* dense, T* x);     // x_j = sign_j dense[vpos(j)]
-template <typename T> void prepare_kernels();                             // LDS limits, once per process
-template <typename T> void transform_adj(Ctx<T>& c, const T* inf, T* out); // out = F^T (freq input), v-order
 template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
 // Reads `bytes` (a multiple of 4, at most 4096) of device memory on the host:
 // a one-block kernel copies them into a pinned, device-mapped host buffer
@@ -228,29 +299,41 @@ template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes);
 template <typename T> double norm2_host(Ctx<T>& c, const T* v, int64_t count);   // ||v||, synchronises
 void fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
+void sum_partials_to(const double* partial, int np, double* out, hipStream_t s);   // *out = sum (one block)
 
-// ------------------------------------------------------------------ compact <-> dense
-template <typename T> void scatter_signed(Ctx<T>& c, T* dense, const int32_t* list, const T* vals, int k);
-template <typename T> void scatter_zero(Ctx<T>& c, T* dense, const int32_t* list, int k);
-template <typename T> void gather_signed(Ctx<T>& c, const T* dense, const int32_t* list, T* vals, int k);
+template <typename T> void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<T>& io);
+template <typename T> void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done);
+template <typename T> ColIO<T> col_io(Ctx<T>& c, int mode, const Supp* S);   // compact I/O on support S
+template <typename T> void transform_fwd(Ctx<T>& c, const T* in, T* outf); // outf = masked DCT in freq layout
+// out = F^T (freq input), in v-order or (key_order) key order
+template <typename T> void transform_adj(Ctx<T>& c, const T* inf, T* out, bool key_order);
+template <typename T> void perm_in(Ctx<T>& c, const T* x, T* dense);      // dense[vpos(j)] = sign_j x_j
+template <typename T> void perm_out(Ctx<T>& c, const T* dense, T* x);     // x_j = sign_j dense[vpos(j)]
+template <typename T> void prepare_kernels();                             // LDS limits, once per process
 
 // ------------------------------------------------------------------ selection
 template <typename T> void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j);
 template <typename T> void topk_dense(Ctx<T>& c, const T* dense, const uint32_t* excl, int k, uint32_t* out_bits);
 template <typename T> void topk_compact(Ctx<T>& c, const T* vals, const int32_t* list, int count, int k, uint32_t* out_bits);
-template <typename T> int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect);
+template <typename T> int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uint32_t* wpre);
 void bits_or(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t words, hipStream_t s);
-void bits_set_list(uint32_t* bits, const int32_t* list, int k, hipStream_t s);
 int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, hipStream_t s);
 
 // ------------------------------------------------------------------ CG
+// Solves the weighted normal equations on support S; x (compact, key order,
+// sign-flipped coordinates) is the start point when `warm`, and receives the
+// solution.
 template <typename T>
-int cg_solve(Ctx<T>& c, const int32_t* list, int k, T* x, bool warm, double tol, int max_iter);
+int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter);
 
-// residual + correlation for the solution (list, x): updates Dx, leaves
-// c = raw A^T (y - A x) in W (v-order) and returns ||y - A x|| on the host.
+// r = y - A x and F^T D^T r (key order, in Cc) for the solution x on S;
+// returns ||r|| (synchronises).
 template <typename T>
-double resid_corr(Ctx<T>& c, const int32_t* old_list, int old_k, const int32_t* list, const T* x, int k);
+double resid_corr(Ctx<T>& c, const Supp& S, const T* x);
+
+// out[i] = x[slot of to[i] in from] or 0 when absent (both ascending key lists).
+template <typename T>
+void remap(Ctx<T>& c, const int32_t* from, const T* x, int kfrom, const int32_t* to, T* out, int kto);
 
 // ------------------------------------------------------------------ drivers
 template <typename T>

@@ -57,33 +57,147 @@ constexpr int kMinL = 3;    // N = 16
 constexpr int kMaxL = 25;   // N = 2^26
 
 // ------------------------------------------------------------------ column pass
+__device__ __forceinline__ double wg_sum(double v, double* red, int nwaves) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < nwaves; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// First compact slot at or after key `key`: the support keys below it.
+template <typename T>
+__device__ __forceinline__ uint32_t slot_at(const ColIO<T>& io, size_t key, int64_t words) {
+  const size_t w = key >> 5;
+  if ((int64_t)w >= words) return (uint32_t)io.kcap;
+  const uint32_t s = io.wpre[w] + __popc(io.sbits[w] & ((1u << (key & 31)) - 1u));
+  return s < (uint32_t)io.kcap ? s : (uint32_t)io.kcap;
+}
+
+// Column pass: one workgroup owns a strip of B = 2^LOGB adjacent columns of
+// the L1 x L2 view of z and runs B length-L1 FFTs on it in LDS (column-major,
+// so a global row segment of B complex values maps to B consecutive LDS
+// slots).  Forward passes read a dense v-order input or build it from the
+// compact CG vectors; inverse passes write a dense v-order output, a dense
+// key-order output or gather the support entries back into the compact
+// vectors.  In key order element e of strip g is complex slot g E + e, so the
+// strip's support is one contiguous range of compact slots [s0, s1): the
+// compact side touches only those entries (coalesced), never the N-bit
+// bitmap.  `in` and `out` may be the same buffer in v-order modes: a
+// workgroup reads its whole strip before writing it back.
 template <typename T, bool INV, int LOGL1, int LOGB, int LOGE>
-__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const Cx<T>* in,
-                                                                      Cx<T>* out, Plan p,
-                                                                      const int* __restrict__ done,
-                                                                      const Cx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const Cx<T>* in, Cx<T>* out, Plan p,
+                                                                           ColIO<T> io,
+                                                                           const Cx<T>* __restrict__ tw) {
   constexpr int E = 1 << (LOGL1 + LOGB), B = 1 << LOGB;
   constexpr int NT = nt_for(E, LOGE);
   constexpr int EPT = (E + NT - 1) / NT;
-  if (done && *done) return;
+  constexpr int NW = NT / 64;
+  __shared__ double red[NW];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<T>* buf = (Cx<T>*)smem_raw;
+  T* bufr = (T*)smem_raw;
   const int tid = threadIdx.x;
   const int g = xcd_order(blockIdx.x, gridDim.x);
   const size_t c0 = (size_t)g << LOGB;
+  const size_t kb = (size_t)g * E;      // first key-order complex slot of the strip
   const size_t L2 = (size_t)p.L2;
-  // thread tid handles e = tid + q NT: row n1 = e >> LOGB, column b = e & (B-1)
+  const bool compact = io.mode != COL_DENSE && io.mode != COL_KEY;
+  uint32_t s0 = 0, s1 = 0;
+  if (compact) {
+    s0 = slot_at(io, 2 * kb, p.words);
+    s1 = slot_at(io, 2 * (kb + E), p.words);
+  }
+  // thread tid handles e = tid + q NT: row n1 = e >> LOGB, column b = e & (B-1),
+  // v-order complex element n1 L2 + c0 + b, keys 2 (kb + e) and 2 (kb + e) + 1
+  if (!INV && compact) {
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = tid + q * NT;
-    if (E % NT == 0 || e < E) buf[lp(e)] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT;
+      if (E % NT == 0 || e < E) buf[lp(e)] = cx((T)0, (T)0);
+    }
+    if (io.cg && io.cg->done) return;
+    const bool dir = io.mode == COL_DIR, first = io.it == 0;
+    const T beta = (dir && !first) ? (T)io.cg->beta : (T)0;
+    __syncthreads();
+    for (uint32_t sl = s0 + tid; sl < s1; sl += NT) {
+      const uint32_t key = (uint32_t)io.list[sl];
+      const int64_t e = (int64_t)(key >> 1) - (int64_t)kb;
+      if (e < 0 || e >= E) continue;   // only a list shorter than kcap leaves stale entries here
+      T val;
+      if (dir) {
+        val = first ? io.r[sl] : io.r[sl] + beta * io.d[sl];
+        io.d[sl] = val;
+      } else {
+        val = io.x[sl];
+      }
+      bufr[2 * lp((int)e) + (key & 1)] = val;
+    }
+  } else {
+    if (io.cg && io.cg->done) return;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT;
+      if (E % NT == 0 || e < E) buf[lp(e)] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
+    }
   }
   __syncthreads();
   ct_fft<T, INV, NT, LOGL1, LOGB, true, LOGE>(buf, tw);
+  if (INV && compact) {
+    const bool qm = io.mode == COL_Q;
+    double acc = 0.0;
+    for (uint32_t sl = s0 + tid; sl < s1; sl += NT) {
+      const uint32_t key = (uint32_t)io.list[sl];
+      const int64_t e = (int64_t)(key >> 1) - (int64_t)kb;
+      if (e < 0 || e >= E) continue;
+      const T val = bufr[2 * lp((int)e) + (key & 1)];
+      if (qm) {
+        io.q[sl] = val;
+        acc += (double)io.d[sl] * (double)val;
+      } else {
+        const T rv = io.b[sl] - val;
+        io.r[sl] = rv;
+        io.d[sl] = rv;
+        acc += (double)rv * (double)rv;
+      }
+    }
+    const double tot = wg_sum(acc, red, NW);
+    // COL_Q: the last workgroup to finish reduces all partials (fixed order) to d^T H d
+    __shared__ int last;
+    if (tid == 0) {
+      io.pout[blockIdx.x] = tot;
+      last = 0;
+      if (qm && io.cg) {
+        __threadfence();
+        last = atomicAdd(&io.cg->cnt_q, 1u) == gridDim.x - 1;
+      }
+    }
+    __syncthreads();
+    if (last) {
+      __threadfence();
+      const volatile double* vp = io.pout;
+      double sdq = 0.0;
+      for (unsigned i = tid; i < gridDim.x; i += NT) sdq += vp[i];
+      sdq = wg_sum(sdq, red, NW);
+      if (tid == 0) {
+        io.cg->dq = sdq;
+        io.cg->cnt_q = 0u;
+      }
+    }
+  } else if (INV && io.mode == COL_KEY) {
 #pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = tid + q * NT;
-    if (E % NT == 0 || e < E) out[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))] = buf[lp(e)];
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT;
+      if (E % NT == 0 || e < E) out[kb + e] = buf[lp(e)];
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT;
+      if (E % NT == 0 || e < E) out[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))] = buf[lp(e)];
+    }
   }
 }
 
@@ -339,8 +453,8 @@ __global__ void k_stage_twiddles(Cx<T>* __restrict__ out, int logn, int loge) {
 // ------------------------------------------------------------------ dispatch tables
 template <typename T>
 struct KernelSet {
-  void (*col_fwd)(const Cx<T>*, Cx<T>*, Plan, const int*, const Cx<T>*);
-  void (*col_inv)(const Cx<T>*, Cx<T>*, Plan, const int*, const Cx<T>*);
+  void (*col_fwd)(const Cx<T>*, Cx<T>*, Plan, ColIO<T>, const Cx<T>*);
+  void (*col_inv)(const Cx<T>*, Cx<T>*, Plan, ColIO<T>, const Cx<T>*);
   void (*row)(Cx<T>*, Plan, int, const T*, T*, double*, const int*, const Cx<T>*);
   int nt_col, nt_row;
 };

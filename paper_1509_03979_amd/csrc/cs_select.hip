@@ -2,6 +2,9 @@
 // the top-K selections of SP and OMPR.
 //
 // Every selection ranks candidates by (magnitude descending, index ascending).
+// Candidates live at keys k (the key order of the column passes; natural index
+// j = nat_of_key(k)); sets of selected candidates are N-bit bitmaps over keys,
+// and the natural index decides ties.
 // Magnitudes are compared through their IEEE bit patterns, which order like the
 // values for non-negative numbers; a key of 0 marks an excluded candidate and
 // every admissible key is bits(|v|) + 1.
@@ -61,14 +64,15 @@ __device__ __forceinline__ ArgKey block_max_key(ArgKey best) {
 
 // ------------------------------------------------------------------ argmax outside a set
 template <typename T>
-__global__ void k_argmax_partial(const T* __restrict__ dense, const uint32_t* __restrict__ excl, int64_t n,
+__global__ void k_argmax_partial(const T* __restrict__ dense, const uint32_t* __restrict__ excl, const Plan pl,
                                  ArgKey* __restrict__ part, SelState* sel) {
+  const int64_t n = pl.n;
   ArgKey best{0, 0, 0};
   bool bad = false;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += st) {
-    const int64_t j = vinv(p, n);
-    if (excl && bit_of(excl, j)) continue;
+    if (excl && bit_of(excl, p)) continue;
+    const int64_t j = nat_of_key(p, pl);
     const T v = dense[p];
     bad |= !finite_v(v);
     ArgKey k{mag_bits(v) + 1, 0xFFFFFFFFu - (uint32_t)j, 0};
@@ -91,31 +95,34 @@ template <typename T>
 void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j) {
   const int64_t n = c.plan.n;
   const unsigned grid = (unsigned)std::min<int64_t>(kArgBlocks, nblk(n, 256));
-  hipLaunchKernelGGL(k_argmax_partial<T>, dim3(grid), dim3(256), 0, c.stream, dense, excl, n, c.argpart, c.sel);
+  hipLaunchKernelGGL(k_argmax_partial<T>, dim3(grid), dim3(256), 0, c.stream, dense, excl, c.plan, c.argpart, c.sel);
   CS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, c.stream, c.argpart, (int)grid, out_j);
   CS_LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------------ radix select
-// Candidate sources.  Dense: position p of a v-order vector, index vinv(p),
-// excluded through a bitmap.  Compact: entry i of vals, index list[i].
+// Candidate sources.  Dense: key k of a key-order vector, excluded through a
+// key bitmap.  Compact: entry i of vals at key list[i].  Both report the key
+// (for marking) and the natural index (for ties).
 struct DenseSrc {};
 struct CompactSrc {};
 
 template <typename T, typename S>
-__device__ __forceinline__ void cand(const T* __restrict__ vals, const void* __restrict__ aux, int64_t i, int64_t n,
-                                     uint64_t& key, uint32_t& j, bool& bad) {
+__device__ __forceinline__ void cand(const T* __restrict__ vals, const void* __restrict__ aux, int64_t i,
+                                     const Plan& pl, uint64_t& key, uint32_t& j, uint32_t& pos, bool& bad) {
   if constexpr (std::is_same<S, DenseSrc>::value) {
     const uint32_t* excl = (const uint32_t*)aux;
-    j = (uint32_t)vinv(i, n);
-    if (excl && bit_of(excl, j)) { key = 0; return; }
+    pos = (uint32_t)i;
+    j = (uint32_t)nat_of_key(i, pl);
+    if (excl && bit_of(excl, i)) { key = 0; return; }
     const T v = vals[i];
     bad |= !finite_v(v);
     key = mag_bits(v) + 1;
   } else {
     const int32_t* list = (const int32_t*)aux;
-    j = (uint32_t)list[i];
+    pos = (uint32_t)list[i];
+    j = (uint32_t)nat_of_key(pos, pl);
     const T v = vals[i];
     bad |= !finite_v(v);
     key = mag_bits(v) + 1;
@@ -134,7 +141,7 @@ __global__ void k_sel_init(SelState* sel, int64_t need) {
 // phase 1: histogram of index digit among keys equal to the threshold whose
 //          index matches the index prefix (only when the tie-break is active).
 template <typename T, typename S, int PHASE>
-__global__ void k_radix_hist(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, int64_t n,
+__global__ void k_radix_hist(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, const Plan pl,
                              SelState* sel, int shift) {
   __shared__ uint32_t h[256];
   if (PHASE == 1 && !sel->tie) return;
@@ -145,8 +152,8 @@ __global__ void k_radix_hist(const T* __restrict__ vals, const void* __restrict_
   bool bad = false;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
-    uint64_t key; uint32_t j;
-    cand<T, S>(vals, aux, i, n, key, j, bad);
+    uint64_t key; uint32_t j, pos;
+    cand<T, S>(vals, aux, i, pl, key, j, pos, bad);
     if (PHASE == 0) {
       if ((key & pmask) == prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
     } else {
@@ -210,7 +217,7 @@ __global__ void k_radix_pick(SelState* sel, int shift) {
 }
 
 template <typename T, typename S>
-__global__ void k_radix_mark(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, int64_t n,
+__global__ void k_radix_mark(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, const Plan pl,
                              const SelState* __restrict__ sel, uint32_t* __restrict__ bits) {
   const uint64_t tau = sel->prefix;
   const int tie = sel->tie;
@@ -218,35 +225,35 @@ __global__ void k_radix_mark(const T* __restrict__ vals, const void* __restrict_
   bool bad = false;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
-    uint64_t key; uint32_t j;
-    cand<T, S>(vals, aux, i, n, key, j, bad);
+    uint64_t key; uint32_t j, pos;
+    cand<T, S>(vals, aux, i, pl, key, j, pos, bad);
     if (key == 0) continue;
-    if (key > tau || (key == tau && (!tie || j <= jt))) atomicOr(&bits[j >> 5], 1u << (j & 31));
+    if (key > tau || (key == tau && (!tie || j <= jt))) atomicOr(&bits[pos >> 5], 1u << (pos & 31));
   }
 }
 
 template <typename T, typename S>
 static void radix_topk(Ctx<T>& c, const T* vals, const void* aux, int64_t count, int k, uint32_t* out_bits) {
   hipStream_t s = c.stream;
-  const int64_t n = c.plan.n;
+  const Plan& pl = c.plan;
   const unsigned grid = (unsigned)std::min<int64_t>(1024, nblk(count, 256));
   fill_u32(out_bits, c.plan.words, 0u, s);
   hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c.sel, (int64_t)k);
   CS_LAUNCH_CHECK();
   const int width = (sizeof(T) == 4) ? 32 : 64;
   for (int shift = width - 8; shift >= 0; shift -= 8) {
-    hipLaunchKernelGGL((k_radix_hist<T, S, 0>), dim3(grid), dim3(256), 0, s, vals, aux, count, n, c.sel, shift);
+    hipLaunchKernelGGL((k_radix_hist<T, S, 0>), dim3(grid), dim3(256), 0, s, vals, aux, count, pl, c.sel, shift);
     CS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_radix_pick<0>, dim3(1), dim3(256), 0, s, c.sel, shift);
     CS_LAUNCH_CHECK();
   }
   for (int shift = 24; shift >= 0; shift -= 8) {
-    hipLaunchKernelGGL((k_radix_hist<T, S, 1>), dim3(grid), dim3(256), 0, s, vals, aux, count, n, c.sel, shift);
+    hipLaunchKernelGGL((k_radix_hist<T, S, 1>), dim3(grid), dim3(256), 0, s, vals, aux, count, pl, c.sel, shift);
     CS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_radix_pick<1>, dim3(1), dim3(256), 0, s, c.sel, shift);
     CS_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL((k_radix_mark<T, S>), dim3(grid), dim3(256), 0, s, vals, aux, count, n, c.sel, out_bits);
+  hipLaunchKernelGGL((k_radix_mark<T, S>), dim3(grid), dim3(256), 0, s, vals, aux, count, pl, c.sel, out_bits);
   CS_LAUNCH_CHECK();
 }
 
@@ -338,9 +345,10 @@ __global__ void k_bits_scan(uint32_t* cnt, int nb) {
   if (threadIdx.x == 0) cnt[nb] = carry;
 }
 
-// 256 threads, 4 words each.
+// 256 threads, 4 words each.  Also records, per word, the number of set bits
+// in all earlier words (wpre, nullable).
 __global__ void k_bits_write(const uint32_t* __restrict__ bits, int64_t words, const uint32_t* __restrict__ cnt,
-                             int32_t* __restrict__ list, int limit) {
+                             int32_t* __restrict__ list, int limit, uint32_t* __restrict__ wpre) {
   __shared__ uint32_t sh[256];
   const int64_t w0 = (int64_t)blockIdx.x * kBitsPerBlockWords + threadIdx.x * 4;
   uint32_t wv[4];
@@ -361,6 +369,7 @@ __global__ void k_bits_write(const uint32_t* __restrict__ bits, int64_t words, c
   uint32_t pos = cnt[blockIdx.x] + sh[threadIdx.x] - mine;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
+    if (wpre && w0 + q < words) wpre[w0 + q] = pos;
     uint32_t v = wv[q];
     while (v) {
       const int b = __ffs(v) - 1;
@@ -372,7 +381,7 @@ __global__ void k_bits_write(const uint32_t* __restrict__ bits, int64_t words, c
 }
 
 template <typename T>
-int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect) {
+int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uint32_t* wpre) {
   const int64_t words = c.plan.words;
   const int nb = (int)((words + kBitsPerBlockWords - 1) / kBitsPerBlockWords);
   hipStream_t s = c.stream;
@@ -380,7 +389,7 @@ int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect) {
   CS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_bits_scan, dim3(1), dim3(1024), 0, s, c.blockcnt, nb);
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bits_write, dim3(nb), dim3(256), 0, s, bits, words, c.blockcnt, list, expect);
+  hipLaunchKernelGGL(k_bits_write, dim3(nb), dim3(256), 0, s, bits, words, c.blockcnt, list, expect, wpre);
   CS_LAUNCH_CHECK();
   return nb;   // total count is left in blockcnt[nb]
 }
@@ -389,7 +398,7 @@ int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect) {
   template void argmax_excl<T>(Ctx<T>&, const T*, const uint32_t*, int32_t*);           \
   template void topk_dense<T>(Ctx<T>&, const T*, const uint32_t*, int, uint32_t*);      \
   template void topk_compact<T>(Ctx<T>&, const T*, const int32_t*, int, int, uint32_t*); \
-  template int bits_to_list<T>(Ctx<T>&, const uint32_t*, int32_t*, int);
+  template int bits_to_list<T>(Ctx<T>&, const uint32_t*, int32_t*, int, uint32_t*);
 CS_INST(float)
 CS_INST(double)
 

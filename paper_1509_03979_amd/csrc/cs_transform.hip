@@ -232,6 +232,11 @@ __global__ void k_sumsq_partial(const T* __restrict__ v, int64_t count, double* 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+void sum_partials_to(const double* partial, int np, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, s, partial, np, out);
+  CS_LAUNCH_CHECK();
+}
+
 template <typename T>
 double norm2_host(Ctx<T>& c, const T* v, int64_t count) {
   const unsigned grid = (unsigned)std::min<int64_t>(kRedBlocks, nblk(count, 256));
@@ -246,23 +251,44 @@ double norm2_host(Ctx<T>& c, const T* v, int64_t count) {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-static void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const int* done) {
+ColIO<T> col_io(Ctx<T>& c, int mode, const Supp* S) {
+  ColIO<T> io{};
+  io.mode = mode;
+  if (S) {
+    io.sbits = S->bits;
+    io.wpre = S->wpre;
+    io.list = S->list;
+    io.kcap = S->k;
+  }
+  return io;
+}
+
+template <typename T>
+void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<T>& io) {
   const Plan& p = c.plan;
   const KernelSet<T>& ks = kernels_plan<T>(p);
   const unsigned grid = (unsigned)(p.L2 >> p.logB);
-  const double bytes = 2.0 * (double)p.n * sizeof(T);   // read and write one N-vector
+  // A dense pass reads and writes one N-vector.  A compact side replaces one
+  // of them by the k support keys and the compact vectors it moves: x read
+  // (COL_X); r, d read and d written (COL_DIR); d read and q written (COL_Q);
+  // b read, r and d written (COL_R).
+  double bytes = 2.0 * (double)p.n * sizeof(T);
+  if (io.mode != COL_DENSE && io.mode != COL_KEY) {
+    static const int vec[6] = {0, 1, 3, 2, 3, 0};
+    bytes = (double)p.n * sizeof(T) + (double)io.kcap * (4.0 + vec[io.mode] * (double)sizeof(T));
+  }
   hipEvent_t ev = nullptr;
   const bool prof = prof_on();
   if (prof) prof_begin(c.stream, &ev);
   auto fn = inv ? ks.col_inv : ks.col_fwd;
-  fn<<<dim3(grid), dim3(ks.nt_col), p.lds_col, c.stream>>>(in, out, p, done, c.tw_col);
+  fn<<<dim3(grid), dim3(ks.nt_col), p.lds_col, c.stream>>>(in, out, p, io, c.tw_col);
   CS_LAUNCH_CHECK();
   if (prof) prof_end(inv ? PC_COL_INV : PC_COL_FWD, bytes, ev, c.stream);
   c.model_bytes += bytes;
 }
 
 template <typename T>
-static void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done) {
+void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done) {
   const Plan& p = c.plan;
   const KernelSet<T>& ks = kernels_plan<T>(p);
   const unsigned grid = (unsigned)(p.L1 >> 1);
@@ -279,82 +305,17 @@ static void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* parti
 }
 
 template <typename T>
-void transform_happly(Ctx<T>& c, const T* in, const int* done) {
-  launch_col<T>(c, (const Cx<T>*)in, c.W, false, done);
-  launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done);
-  launch_col<T>(c, c.W, c.W, true, done);
-  c.transforms += 2;
-}
-
-template <typename T>
-void transform_resid(Ctx<T>& c, const T* in) {
-  launch_col<T>(c, (const Cx<T>*)in, c.W, false, nullptr);
-  launch_row<T>(c, ROW_RESID, c.Yf, nullptr, c.partial2, nullptr);
-  launch_col<T>(c, c.W, c.W, true, nullptr);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, c.stream, c.partial2, c.plan.L1 >> 1,
-                     &c.cg->resid2);
-  CS_LAUNCH_CHECK();
-  c.transforms += 2;
-}
-
-template <typename T>
 void transform_fwd(Ctx<T>& c, const T* in, T* outf) {
-  launch_col<T>(c, (const Cx<T>*)in, c.W, false, nullptr);
+  launch_col<T>(c, (const Cx<T>*)in, c.W, false, col_io<T>(c, COL_DENSE, nullptr));
   launch_row<T>(c, ROW_FWD, nullptr, outf, nullptr, nullptr);
   c.transforms += 1;
 }
 
 template <typename T>
-void transform_adj(Ctx<T>& c, const T* inf, T* out) {
+void transform_adj(Ctx<T>& c, const T* inf, T* out, bool key_order) {
   launch_row<T>(c, ROW_ADJ, inf, nullptr, nullptr, nullptr);
-  launch_col<T>(c, c.W, (Cx<T>*)out, true, nullptr);
+  launch_col<T>(c, c.W, (Cx<T>*)out, true, col_io<T>(c, key_order ? COL_KEY : COL_DENSE, nullptr));
   c.transforms += 1;
-}
-
-// ------------------------------------------------------------------ compact <-> dense
-template <typename T>
-__global__ void k_scatter_signed(T* __restrict__ dense, const int32_t* __restrict__ list,
-                                 const T* __restrict__ vals, int k, const int8_t* __restrict__ signs, int64_t n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  const int64_t j = list[i];
-  dense[vpos(j, n)] = signs[j] < 0 ? -vals[i] : vals[i];
-}
-template <typename T>
-__global__ void k_scatter_zero(T* __restrict__ dense, const int32_t* __restrict__ list, int k, int64_t n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  dense[vpos(list[i], n)] = (T)0;
-}
-template <typename T>
-__global__ void k_gather_signed(const T* __restrict__ dense, const int32_t* __restrict__ list,
-                                T* __restrict__ vals, int k, const int8_t* __restrict__ signs, int64_t n) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  const int64_t j = list[i];
-  const T v = dense[vpos(j, n)];
-  vals[i] = signs[j] < 0 ? -v : v;
-}
-
-template <typename T>
-void scatter_signed(Ctx<T>& c, T* dense, const int32_t* list, const T* vals, int k) {
-  if (k <= 0) return;
-  hipLaunchKernelGGL(k_scatter_signed<T>, dim3(nblk(k, 256)), dim3(256), 0, c.stream, dense, list, vals, k,
-                     c.signs, c.plan.n);
-  CS_LAUNCH_CHECK();
-}
-template <typename T>
-void scatter_zero(Ctx<T>& c, T* dense, const int32_t* list, int k) {
-  if (k <= 0) return;
-  hipLaunchKernelGGL(k_scatter_zero<T>, dim3(nblk(k, 256)), dim3(256), 0, c.stream, dense, list, k, c.plan.n);
-  CS_LAUNCH_CHECK();
-}
-template <typename T>
-void gather_signed(Ctx<T>& c, const T* dense, const int32_t* list, T* vals, int k) {
-  if (k <= 0) return;
-  hipLaunchKernelGGL(k_gather_signed<T>, dim3(nblk(k, 256)), dim3(256), 0, c.stream, dense, list, vals, k,
-                     c.signs, c.plan.n);
-  CS_LAUNCH_CHECK();
 }
 
 template <typename T>
@@ -407,22 +368,20 @@ void prepare_kernels() {
 }
 
 // ------------------------------------------------------------------ instantiations
-#define CS_INST(T)                                                              \
-  template void fill<T>(T*, int64_t, T, hipStream_t);                           \
-  template double norm2_host<T>(Ctx<T>&, const T*, int64_t);                    \
-  template void setup_operator<T>(Ctx<T>&);                                     \
-  template void scatter_freq<T>(Ctx<T>&, const T*, T*);                         \
-  template void gather_freq<T>(Ctx<T>&, const T*, T*);                          \
-  template void transform_happly<T>(Ctx<T>&, const T*, const int*);             \
-  template void transform_resid<T>(Ctx<T>&, const T*);                          \
-  template void transform_fwd<T>(Ctx<T>&, const T*, T*);                        \
-  template void transform_adj<T>(Ctx<T>&, const T*, T*);                        \
-  template void perm_in<T>(Ctx<T>&, const T*, T*);                              \
-  template void perm_out<T>(Ctx<T>&, const T*, T*);                             \
-  template void prepare_kernels<T>();                                           \
-  template void scatter_signed<T>(Ctx<T>&, T*, const int32_t*, const T*, int); \
-  template void scatter_zero<T>(Ctx<T>&, T*, const int32_t*, int);             \
-  template void gather_signed<T>(Ctx<T>&, const T*, const int32_t*, T*, int);
+#define CS_INST(T)                                                                      \
+  template void fill<T>(T*, int64_t, T, hipStream_t);                                   \
+  template double norm2_host<T>(Ctx<T>&, const T*, int64_t);                            \
+  template void setup_operator<T>(Ctx<T>&);                                             \
+  template void scatter_freq<T>(Ctx<T>&, const T*, T*);                                 \
+  template void gather_freq<T>(Ctx<T>&, const T*, T*);                                  \
+  template ColIO<T> col_io<T>(Ctx<T>&, int, const Supp*);                               \
+  template void launch_col<T>(Ctx<T>&, const Cx<T>*, Cx<T>*, bool, const ColIO<T>&);   \
+  template void launch_row<T>(Ctx<T>&, int, const T*, T*, double*, const int*);         \
+  template void transform_fwd<T>(Ctx<T>&, const T*, T*);                                \
+  template void transform_adj<T>(Ctx<T>&, const T*, T*, bool);                              \
+  template void perm_in<T>(Ctx<T>&, const T*, T*);                                      \
+  template void perm_out<T>(Ctx<T>&, const T*, T*);                                     \
+  template void prepare_kernels<T>();
 CS_INST(float)
 CS_INST(double)
 template void fill<int32_t>(int32_t*, int64_t, int32_t, hipStream_t);

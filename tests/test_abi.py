@@ -37,8 +37,8 @@ def test_workspace_is_linear_in_n_and_k():
         a, b = sz(2 ** 20, 4096, dt=dt), sz(2 ** 21, 4096, dt=dt)
         assert 1.9 < b / a < 2.1
         esz = 4 if dt == cs.CS_F32 else 8
-        # about five dense N-vectors plus bitmaps
-        assert 5 * esz * 2 ** 20 <= a <= 7 * esz * 2 ** 20
+        # four dense N-vectors plus bitmaps
+        assert 4 * esz * 2 ** 20 <= a <= 6 * esz * 2 ** 20
         k1, k2 = sz(2 ** 20, 1000, dt=dt), sz(2 ** 20, 31000, dt=dt)
         assert 0 < k2 - k1 <= 30000 * 2 * (3 * 4 + 7 * esz) + 8192
     assert cs.cs_workspace_size(cs.CS_F32, 1000, 100, 10, cs.CS_ALGO_SP) == 0     # N not a power of two
