@@ -154,6 +154,23 @@ cs_status cs_ls_solve(cs_dtype dtype, const void* y, const cs_op* op, const int3
                       const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
                       hipStream_t stream);
 
+/*
+ * Backward of a recovery on its frozen final support.  On `support` [k]
+ * (device int32, strictly ascending) the recovered coefficients are the
+ * least-squares solution of Eq. (10)-(11), s_S = (A_S^T A_S)^-1 A_S^T y,
+ * linear in y, and s is zero off the support.  Given grad_s [N] = dL/ds
+ * (dense; only its entries on the support are read) this writes
+ *     grad_y [M] = dL/dy = A_S (A_S^T A_S)^-1 (dL/ds)_S.
+ * It is one more solve of the CG function of Algorithm 1, with right-hand
+ * side (dL/ds)_S (same `tol` semantics and cs_info fields as cs_ls_solve),
+ * followed by one forward apply of A on the support.  The workspace is sized
+ * by cs_workspace_size(..., k, CS_ALGO_LS).
+ */
+cs_status cs_adjoint_ls(cs_dtype dtype, const cs_op* op, const int32_t* support, int32_t k,
+                        const void* grad_s, double tol, void* grad_y,
+                        const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                        hipStream_t stream);
+
 /* out [M] = A x for a dense x [N] (Sec. III-D: sign flip, DCT-II, row pick). */
 cs_status cs_apply_A(cs_dtype dtype, const cs_op* op, const void* x, void* out,
                      void* ws, size_t ws_bytes, hipStream_t stream);
@@ -168,9 +185,11 @@ const char* cs_last_error(void);
  * Opt-in timing of the transform passes (not part of the method; for
  * measurement).  When enabled, each column / row pass launch is bracketed by
  * HIP events on the caller's stream; per-class totals accumulate until
- * cs_prof_reset().  `bytes` is the algorithmic HBM traffic of those launches
- * (one N-vector read and one written per pass; the residual row pass also
- * reads y).  Classes: col_fwd, col_inv, row_happly, row_resid, row_fwd, row_adj.
+ * cs_prof_reset().  `bytes` is the algorithmic HBM traffic of those launches:
+ * one N-vector read and one written per pass, except that a column pass on
+ * the compact CG vectors replaces one of them by the k support keys and the
+ * compact values it moves, and the residual row pass also reads y.
+ * Classes: col_fwd, col_inv, row_happly, row_resid, row_fwd, row_adj.
  */
 typedef struct {
   char name[32];

@@ -25,8 +25,8 @@ CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, 
 CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
 
 EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_ls_solve",
-           "cs_apply_A", "cs_apply_At", "cs_status_str", "cs_last_error", "cs_prof_enable", "cs_prof_reset",
-           "cs_prof_read")
+           "cs_adjoint_ls", "cs_apply_A", "cs_apply_At", "cs_status_str", "cs_last_error", "cs_prof_enable",
+           "cs_prof_reset", "cs_prof_read")
 
 
 class cs_op(ctypes.Structure):
@@ -77,6 +77,8 @@ def _load():
     lib.cs_ls_solve.argtypes = [ctypes.c_int, vp, P(cs_op), vp, i32, dbl, vp, vp, P(cs_params), vp, sz,
                                 P(cs_info), vp]
     lib.cs_ls_solve.restype = ctypes.c_int
+    lib.cs_adjoint_ls.argtypes = [ctypes.c_int, P(cs_op), vp, i32, vp, dbl, vp, P(cs_params), vp, sz, P(cs_info), vp]
+    lib.cs_adjoint_ls.restype = ctypes.c_int
     for name in ("cs_apply_A", "cs_apply_At"):
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, P(cs_op), vp, vp, vp, sz, vp]
@@ -240,6 +242,68 @@ def cs_ls_solve(y, op: Operator, support, tol: float, x0=None, ws=None, stream=N
                          _ptr(ws), ws.numel(), ctypes.byref(info), _stream_ptr(stream))
     _check(st)
     return theta, info.as_dict()
+
+
+def cs_adjoint_ls(grad_s, op: Operator, support, tol: float, ws=None, stream=None, **kw):
+    """dL/dy [M] from dL/ds [N] on the frozen support: A_S (A_S^T A_S)^-1 (dL/ds)_S -> (grad_y, info)."""
+    torch = _torch()
+    dt = _dtype_code(grad_s)
+    k = int(support.numel())
+    grad_s = grad_s.contiguous()
+    if grad_s.numel() != op.n or not grad_s.is_cuda:
+        raise ValueError("grad_s must be a device vector of length N")
+    grad_y = torch.empty(op.m, dtype=grad_s.dtype, device=grad_s.device)
+    if ws is None:
+        ws = workspace(dt, op, k, CS_ALGO_LS, grad_s.device)
+    info = cs_info()
+    prm = _params(**kw)
+    st = lib.cs_adjoint_ls(dt, ctypes.byref(op.c), _ptr(support.contiguous()), k, _ptr(grad_s), float(tol),
+                           _ptr(grad_y), ctypes.byref(prm), _ptr(ws), ws.numel(), ctypes.byref(info),
+                           _stream_ptr(stream))
+    _check(st)
+    return grad_y, info.as_dict()
+
+
+def _recover_fn(name: str):
+    import torch
+
+    fwd = {"omp": cs_recover_omp, "sp": cs_recover_sp, "ompr": cs_recover_ompr}[name]
+
+    class _Recover(torch.autograd.Function):
+        """s = recover(y); the backward is cs_adjoint_ls on the frozen final support."""
+
+        @staticmethod
+        def forward(ctx, y, op, k, tol, adj_tol=None):
+            s, supp, _ = fwd(y, op, k, tol)
+            ctx.save_for_backward(supp)
+            ctx.op = op
+            ctx.tol = tol if adj_tol is None else adj_tol
+            ctx.mark_non_differentiable(supp)
+            return s, supp
+
+        @staticmethod
+        def backward(ctx, grad_s, grad_supp):
+            (supp,) = ctx.saved_tensors
+            grad_y, _ = cs_adjoint_ls(grad_s, ctx.op, supp, ctx.tol)
+            return grad_y, None, None, None, None
+
+    _Recover.__name__ = name.upper() + "Recover"
+    return _Recover
+
+
+class _LazyFn:
+    def __init__(self, name):
+        self.name = name
+        self.fn = None
+
+    def apply(self, y, op, k, tol, adj_tol=None):
+        """-> (s [N], support [K]); s is differentiable with respect to y."""
+        if self.fn is None:
+            self.fn = _recover_fn(self.name)
+        return self.fn.apply(y, op, k, tol, adj_tol)
+
+
+OMPRecover, SPRecover, OMPRRecover = _LazyFn("omp"), _LazyFn("sp"), _LazyFn("ompr")
 
 
 def cs_apply_A(x, op: Operator, ws=None, stream=None):

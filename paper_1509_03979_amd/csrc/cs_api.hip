@@ -227,27 +227,35 @@ __global__ void k_reorder(const int32_t* __restrict__ sup, int k, const Plan pl,
   else xnat[i] = neg ? -xkey[slot] : xkey[slot];
 }
 
+// Validates a natural-index support and builds its key bitmap, list and
+// prefix counts in slot 0 (the CG works in key order).
+template <typename T>
+static Supp support_keys(Ctx<T>& c, const int32_t* support, int32_t k) {
+  hipStream_t stream = c.stream;
+  fill<int32_t>(c.ibuf + 16, 1, 0, stream);
+  const unsigned gk = (unsigned)((k + 255) / 256);
+  hipLaunchKernelGGL(k_check_support, dim3(gk), dim3(256), 0, stream, support, k, c.plan.n, c.ibuf + 16);
+  CS_LAUNCH_CHECK();
+  int32_t bad = 0;
+  dev_read(stream, c.ibuf + 16, &bad, sizeof(int32_t));
+  if (bad) throw Error(CS_E_INVALID, "support must be strictly ascending in [0, N)");
+  fill_u32(c.bits[0], c.plan.words, 0u, stream);
+  hipLaunchKernelGGL(k_support_bits, dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.bits[0]);
+  CS_LAUNCH_CHECK();
+  bits_to_list<T>(c, c.bits[0], c.list[0], k, c.wpre[0]);
+  return Supp{c.bits[0], c.wpre[0], c.list[0], k};
+}
+
 template <typename T>
 static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t k, double tol, const void* x0,
                  void* theta, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream) {
   Ctx<T> c{};
   ctx_init<T>(c, op, k, ws, ws_bytes, stream);
   setup_operator<T>(c);
-  fill<int32_t>(c.ibuf + 16, 1, 0, stream);
   const unsigned gk = (unsigned)((k + 255) / 256);
-  hipLaunchKernelGGL(k_check_support, dim3(gk), dim3(256), 0, stream, support, k, op->n, c.ibuf + 16);
-  CS_LAUNCH_CHECK();
-  int32_t bad = 0;
-  dev_read(stream, c.ibuf + 16, &bad, sizeof(int32_t));
-  if (bad) throw Error(CS_E_INVALID, "support must be strictly ascending in [0, N)");
+  const Supp S = support_keys<T>(c, support, k);
   load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
-  // the CG works in key order: build the key bitmap, list and prefixes
-  fill_u32(c.bits[0], c.plan.words, 0u, stream);
-  hipLaunchKernelGGL(k_support_bits, dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.bits[0]);
-  CS_LAUNCH_CHECK();
-  bits_to_list<T>(c, c.bits[0], c.list[0], k, c.wpre[0]);
-  const Supp S{c.bits[0], c.wpre[0], c.list[0], k};
   if (x0)
     hipLaunchKernelGGL((k_reorder<T, true>), dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0],
                        c.wpre[0], (T*)x0, c.cx);
@@ -264,6 +272,45 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   if (info) {
     std::memset(info, 0, sizeof(cs_info));
     info->resid_norm = rn;
+    fill_info<T>(c, info);
+  }
+}
+
+// b'[rank(key(sup[i]))] = sign_j g[j], j = sup[i]: the support entries of a
+// dense gradient, in key order and sign-flipped coordinates
+template <typename T>
+__global__ void k_grad_rhs(const int32_t* __restrict__ sup, int k, const Plan pl, const int8_t* __restrict__ signs,
+                           const uint32_t* __restrict__ bits, const uint32_t* __restrict__ wpre,
+                           const T* __restrict__ g, T* __restrict__ b) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  const int32_t j = sup[i];
+  const uint32_t slot = rank_of(bits, wpre, (uint32_t)key_of_nat(j, pl));
+  b[slot] = signs[j] < 0 ? -g[j] : g[j];
+}
+
+// dL/dy = A_S z with (A_S^T A_S) z = (dL/ds)_S: the CG on the sign-flipped
+// system with b' = R g, then the forward operator on the support.
+template <typename T>
+static void adj_t(const cs_op* op, const int32_t* support, int32_t k, const void* grad, double tol, void* grad_y,
+                  const cs_params* params, void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream) {
+  Ctx<T> c{};
+  ctx_init<T>(c, op, k, ws, ws_bytes, stream);
+  setup_operator<T>(c);
+  const unsigned gk = (unsigned)((k + 255) / 256);
+  const Supp S = support_keys<T>(c, support, k);
+  const cs_params prm = defaults(params);
+  hipLaunchKernelGGL(k_grad_rhs<T>, dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0], c.wpre[0],
+                     (const T*)grad, c.cb);
+  CS_LAUNCH_CHECK();
+  const int cap = prm.cg_max_iter > 0 ? prm.cg_max_iter : 2 * k + 50;
+  cg_solve<T>(c, S, c.cx, false, tol, cap, true);
+  apply_support<T>(c, S, c.cx, c.Yf);
+  gather_freq<T>(c, c.Yf, (T*)grad_y);
+  CS_HIP(hipStreamSynchronize(stream));
+  if (prof_on()) prof_flush();
+  if (info) {
+    std::memset(info, 0, sizeof(cs_info));
     fill_info<T>(c, info);
   }
 }
@@ -329,6 +376,26 @@ cs_status cs_ls_solve(cs_dtype dtype, const void* y, const cs_op* op, const int3
     check_ws(ws);
     if (dtype == CS_F32) ls_t<float>(y, op, support, k, tol, x0, theta, params, ws, ws_bytes, info, stream);
     else ls_t<double>(y, op, support, k, tol, x0, theta, params, ws, ws_bytes, info, stream);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
+}
+
+cs_status cs_adjoint_ls(cs_dtype dtype, const cs_op* op, const int32_t* support, int32_t k, const void* grad_s,
+                        double tol, void* grad_y, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                        hipStream_t stream) {
+  try {
+    check_shape(dtype, op, k, CS_ALGO_LS);
+    if (!support || !grad_s || !grad_y) throw Error(CS_E_INVALID, "null support, grad_s or grad_y");
+    check_tol(tol);
+    check_ws(ws);
+    if (dtype == CS_F32) adj_t<float>(op, support, k, grad_s, tol, grad_y, params, ws, ws_bytes, info, stream);
+    else adj_t<double>(op, support, k, grad_s, tol, grad_y, params, ws, ws_bytes, info, stream);
     return CS_OK;
   } catch (const Error& e) {
     g_last_error = e.what();

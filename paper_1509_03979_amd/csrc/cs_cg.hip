@@ -68,6 +68,18 @@ __global__ void k_cg_gather_b(const T* __restrict__ C0, const int32_t* __restric
   if (threadIdx.x == 0) pbb[blockIdx.x] = acc;
 }
 
+// partial b^T b of a right-hand side already in place
+template <typename T>
+__global__ void k_cg_bnorm(const T* __restrict__ b, int k, double* __restrict__ pbb) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const double v = (double)b[i];
+    acc += v * v;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) pbb[blockIdx.x] = acc;
+}
+
 // cold start: x = 0, r = b; partial r^T r
 template <typename T>
 __global__ void k_cg_init_cold(const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r, int k,
@@ -153,7 +165,7 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
 }
 
 template <typename T>
-int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter) {
+int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter, bool b_ready) {
   hipStream_t s = c.stream;
   const int k = S.k;
   const int nb = red_blocks(k);
@@ -161,7 +173,8 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   double* prr = c.partial;
   double* pbb = c.partial + kRedBlocks;
   double* pdq = c.pgrid;
-  hipLaunchKernelGGL(k_cg_gather_b<T>, dim3(nb), dim3(kRedThreads), 0, s, c.C0, S.list, k, c.cb, pbb);
+  if (b_ready) hipLaunchKernelGGL(k_cg_bnorm<T>, dim3(nb), dim3(kRedThreads), 0, s, c.cb, k, pbb);
+  else hipLaunchKernelGGL(k_cg_gather_b<T>, dim3(nb), dim3(kRedThreads), 0, s, c.C0, S.list, k, c.cb, pbb);
   CS_LAUNCH_CHECK();
   if (warm) {
     // r = b - H x0, d = r through the transform, partial r^T r per column workgroup
@@ -254,7 +267,16 @@ double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
   return std::sqrt(r2);
 }
 
-// out[i] = x[position of to[i] in from] or 0 (both lists ascending)
+template <typename T>
+void apply_support(Ctx<T>& c, const Supp& S, const T* x, T* outf) {
+  ColIO<T> in = col_io<T>(c, COL_X, &S);
+  in.x = const_cast<T*>(x);
+  launch_col<T>(c, nullptr, c.W, false, in);
+  launch_row<T>(c, ROW_FWD, nullptr, outf, nullptr, nullptr);
+  c.transforms += 1;
+}
+
+// out[i] = x[slot of to[i] in from] or 0 (both lists ascending)
 template <typename T>
 __global__ void k_remap(const int32_t* __restrict__ from, const T* __restrict__ x, int kfrom,
                         const int32_t* __restrict__ to, T* __restrict__ out, int kto) {
@@ -280,7 +302,8 @@ void remap(Ctx<T>& c, const int32_t* from, const T* x, int kfrom, const int32_t*
 }
 
 #define CS_INST(T)                                                                    \
-  template int cg_solve<T>(Ctx<T>&, const Supp&, T*, bool, double, int);            \
+  template int cg_solve<T>(Ctx<T>&, const Supp&, T*, bool, double, int, bool);      \
+  template void apply_support<T>(Ctx<T>&, const Supp&, const T*, T*);               \
   template double resid_corr<T>(Ctx<T>&, const Supp&, const T*);                    \
   template void remap<T>(Ctx<T>&, const int32_t*, const T*, int, const int32_t*, T*, int);
 CS_INST(float)

@@ -322,9 +322,15 @@ int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scr
 // ------------------------------------------------------------------ CG
 // Solves the weighted normal equations on support S; x (compact, key order,
 // sign-flipped coordinates) is the start point when `warm`, and receives the
-// solution.
+// solution.  The right-hand side is gathered from C0 unless `b_ready` (then
+// the caller has put it in cb).
 template <typename T>
-int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter);
+int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter, bool b_ready = false);
+
+// outf (freq layout, N reals) = masked DCT of the compact x placed on S: the
+// forward operator on the support, before the row pick.
+template <typename T>
+void apply_support(Ctx<T>& c, const Supp& S, const T* x, T* outf);
 
 // r = y - A x and F^T D^T r (key order, in Cc) for the solution x on S;
 // returns ||r|| (synchronises).

@@ -104,3 +104,28 @@ def test_apply_and_ls_validation():
     assert cs.lib.cs_ls_solve(cs.CS_F32, ctypes.c_void_p(FAKE), ctypes.byref(o), ctypes.c_void_p(FAKE), 5, 0.0,
                               None, ctypes.c_void_p(FAKE), None, ctypes.c_void_p(FAKE), 1 << 30, None,
                               None) == cs.CS_E_INVALID
+
+
+def test_adjoint_validation():
+    o = cs.cs_op(1024, 256, FAKE, FAKE)
+    adj = cs.lib.cs_adjoint_ls
+    p = ctypes.c_void_p(FAKE)
+    ok = dict(dt=cs.CS_F32, op=ctypes.byref(o), sup=p, k=10, g=p, tol=1e-6, gy=p, ws=p, wsb=1 << 30)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return adj(a["dt"], a["op"], a["sup"], a["k"], a["g"], a["tol"], a["gy"], None, a["ws"], a["wsb"], None,
+                   None)
+
+    assert call(dt=3) == cs.CS_E_INVALID
+    assert call(op=None) == cs.CS_E_INVALID
+    assert call(sup=None) == cs.CS_E_INVALID
+    assert call(g=None) == cs.CS_E_INVALID
+    assert call(gy=None) == cs.CS_E_INVALID
+    assert call(k=0) == cs.CS_E_INVALID
+    assert call(k=257) == cs.CS_E_SHAPE
+    assert call(tol=float("nan")) == cs.CS_E_INVALID
+    assert call(ws=None) == cs.CS_E_WORKSPACE
+    assert call(wsb=64) == cs.CS_E_WORKSPACE
+    o2 = cs.cs_op(1000, 256, FAKE, FAKE)
+    assert call(op=ctypes.byref(o2)) == cs.CS_E_SHAPE
