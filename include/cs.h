@@ -95,7 +95,9 @@ typedef struct {
   int32_t cg_max_iter;    /* CG iterations per solve; 0 -> 2|S| + 50                */
   int32_t max_outer;      /* SP rounds / OMPR swaps; 0 -> SP 100, OMPR 4K           */
   int32_t warm_start;     /* 1 (default) start CG from the previous solution; 0 cold */
-  int32_t reserved;
+  int32_t cg_block;       /* batched calls: threads per block of the per-signal CG
+                             kernels (64..1024, a multiple of 64); 0 -> 256.
+                             Single-signal calls ignore it.                          */
   double ompr_eta;        /* OMPR step eta; <= 0 -> N/M                             */
 } cs_params;
 
@@ -170,6 +172,34 @@ cs_status cs_adjoint_ls(cs_dtype dtype, const cs_op* op, const int32_t* support,
                         const void* grad_s, double tol, void* grad_y,
                         const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
                         hipStream_t stream);
+
+/*
+ * Batched recovery: `count` independent signals, each with its own operator
+ * (N, M, rows, signs), sparsity K, measurements and outputs, recovered by
+ * one call.  Every signal follows the same decision rules as the
+ * single-signal call (here OMPR, l = 1, as cs_recover_ompr) and gets the same
+ * kind of result; the signals advance together through batched device steps
+ * (per-size-class transform passes over all signals, then per-signal CG and
+ * selection work) that the library captures in a HIP graph and replays until
+ * every signal has stopped.  `items` is a host array of `count` descriptors
+ * whose pointers are device pointers; `info` is a host array of `count`
+ * entries (nullable).  Sizes follow the single-signal rules per signal.  The
+ * workspace is cs_workspace_size_batched() bytes (256-byte aligned).  The
+ * call synchronises `stream` and returns with all outputs complete.
+ */
+typedef struct {
+  cs_op op;               /* this signal's operator                                 */
+  const void* y;          /* device [M]                                             */
+  void* s;                /* device [N] output, dense                               */
+  int32_t* support;       /* device [K] output, strictly ascending                  */
+  int32_t k;              /* sparsity K                                             */
+  int32_t pad;
+} cs_batch_item;
+
+size_t cs_workspace_size_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, cs_algo algo);
+cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, double tol,
+                                  const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                                  hipStream_t stream);
 
 /* out [M] = A x for a dense x [N] (Sec. III-D: sign flip, DCT-II, row pick). */
 cs_status cs_apply_A(cs_dtype dtype, const cs_op* op, const void* x, void* out,

@@ -25,8 +25,8 @@ CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, 
 CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
 
 EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_ls_solve",
-           "cs_adjoint_ls", "cs_apply_A", "cs_apply_At", "cs_status_str", "cs_last_error", "cs_prof_enable",
-           "cs_prof_reset", "cs_prof_read")
+           "cs_adjoint_ls", "cs_workspace_size_batched", "cs_recover_ompr_batched", "cs_apply_A", "cs_apply_At",
+           "cs_status_str", "cs_last_error", "cs_prof_enable", "cs_prof_reset", "cs_prof_read")
 
 
 class cs_op(ctypes.Structure):
@@ -36,7 +36,7 @@ class cs_op(ctypes.Structure):
 
 class cs_params(ctypes.Structure):
     _fields_ = [("cg_max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ompr_eta", ctypes.c_double)]
+                ("warm_start", ctypes.c_int32), ("cg_block", ctypes.c_int32), ("ompr_eta", ctypes.c_double)]
 
 
 class cs_info(ctypes.Structure):
@@ -46,6 +46,11 @@ class cs_info(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class cs_batch_item(ctypes.Structure):
+    _fields_ = [("op", cs_op), ("y", ctypes.c_void_p), ("s", ctypes.c_void_p), ("support", ctypes.c_void_p),
+                ("k", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class cs_prof_stat(ctypes.Structure):
@@ -79,6 +84,11 @@ def _load():
     lib.cs_ls_solve.restype = ctypes.c_int
     lib.cs_adjoint_ls.argtypes = [ctypes.c_int, P(cs_op), vp, i32, vp, dbl, vp, P(cs_params), vp, sz, P(cs_info), vp]
     lib.cs_adjoint_ls.restype = ctypes.c_int
+    lib.cs_workspace_size_batched.argtypes = [ctypes.c_int, i32, P(cs_batch_item), ctypes.c_int]
+    lib.cs_workspace_size_batched.restype = sz
+    lib.cs_recover_ompr_batched.argtypes = [ctypes.c_int, i32, P(cs_batch_item), dbl, P(cs_params), vp, sz,
+                                            P(cs_info), vp]
+    lib.cs_recover_ompr_batched.restype = ctypes.c_int
     for name in ("cs_apply_A", "cs_apply_At"):
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, P(cs_op), vp, vp, vp, sz, vp]
@@ -180,8 +190,8 @@ class Operator:
                    torch.as_tensor(signs, dtype=torch.int8, device=device))
 
 
-def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0):
-    return cs_params(int(cg_max_iter), int(max_outer), int(warm_start), 0, float(ompr_eta))
+def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0, cg_block=0):
+    return cs_params(int(cg_max_iter), int(max_outer), int(warm_start), int(cg_block), float(ompr_eta))
 
 
 def workspace(dtype_code: int, op: Operator, k: int, algo: int, device=None):
@@ -304,6 +314,51 @@ class _LazyFn:
 
 
 OMPRecover, SPRecover, OMPRRecover = _LazyFn("omp"), _LazyFn("sp"), _LazyFn("ompr")
+
+
+class Batch:
+    """Outputs, descriptors and workspace of one batched call, reusable across
+    calls with the same signals (the measurements may change in place)."""
+
+    def __init__(self, ys, ops, ks, device=None):
+        torch = _torch()
+        if not (len(ys) == len(ops) == len(ks)) or len(ys) == 0:
+            raise ValueError("ys, ops and ks must be non-empty and of equal length")
+        self.ys = [y.contiguous() for y in ys]
+        self.dtype = self.ys[0].dtype
+        self.dt = _dtype_code(self.ys[0])
+        for y, op in zip(self.ys, ops):
+            if y.dtype != self.dtype or y.numel() != op.m or not y.is_cuda:
+                raise ValueError("every y must be a device vector of length M in one dtype")
+        dev = self.ys[0].device
+        self.ops = list(ops)
+        self.ks = [int(k) for k in ks]
+        self.s = [torch.empty(op.n, dtype=self.dtype, device=dev) for op in self.ops]
+        self.supp = [torch.empty(k, dtype=torch.int32, device=dev) for k in self.ks]
+        n = len(self.ys)
+        self.items = (cs_batch_item * n)()
+        for i in range(n):
+            it = self.items[i]
+            it.op = self.ops[i].c
+            it.y = _ptr(self.ys[i])
+            it.s = _ptr(self.s[i])
+            it.support = _ptr(self.supp[i])
+            it.k = self.ks[i]
+        nbytes = lib.cs_workspace_size_batched(self.dt, n, self.items, CS_ALGO_OMPR)
+        if nbytes == 0:
+            raise CSError(CS_E_SHAPE, "no batched workspace size for these signals")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+
+
+def cs_recover_ompr_batched(batch: "Batch", tol: float, stream=None, **kw):
+    """OMPR (l = 1) on every signal of `batch` in one batched call -> (s list, support list, info list)."""
+    n = len(batch.ys)
+    infos = (cs_info * n)()
+    prm = _params(**kw)
+    st = lib.cs_recover_ompr_batched(batch.dt, n, batch.items, float(tol), ctypes.byref(prm), _ptr(batch.ws),
+                                     batch.ws.numel(), infos, _stream_ptr(stream))
+    _check(st)
+    return batch.s, batch.supp, [infos[i].as_dict() for i in range(n)]
 
 
 def cs_apply_A(x, op: Operator, ws=None, stream=None):

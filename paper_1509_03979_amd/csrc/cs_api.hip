@@ -130,17 +130,10 @@ static cs_params defaults(const cs_params* p) {
     d.cg_max_iter = p->cg_max_iter;
     d.max_outer = p->max_outer;
     d.warm_start = p->warm_start;
+    d.cg_block = p->cg_block;
     d.ompr_eta = p->ompr_eta;
   }
   return d;
-}
-
-// Loads y: freq-layout copy, ||y||, and F^T D^T y (key order) into C0.
-template <typename T>
-static void load_measurements(Ctx<T>& c, const T* y) {
-  scatter_freq<T>(c, y, c.Yf);
-  c.ynorm = norm2_host<T>(c, y, c.plan.m);
-  transform_adj<T>(c, c.Yf, c.C0, true);
 }
 
 template <typename T>
@@ -396,6 +389,43 @@ cs_status cs_adjoint_ls(cs_dtype dtype, const cs_op* op, const int32_t* support,
     check_ws(ws);
     if (dtype == CS_F32) adj_t<float>(op, support, k, grad_s, tol, grad_y, params, ws, ws_bytes, info, stream);
     else adj_t<double>(op, support, k, grad_s, tol, grad_y, params, ws, ws_bytes, info, stream);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
+}
+
+size_t cs_workspace_size_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, cs_algo algo) {
+  if (dtype != CS_F32 && dtype != CS_F64) return 0;
+  if (count < 1 || !items || algo != CS_ALGO_OMPR) return 0;
+  for (int i = 0; i < count; ++i) {
+    const cs_op& o = items[i].op;
+    if (cs_workspace_size(dtype, o.n, o.m, items[i].k, algo) == 0) return 0;
+  }
+  return batch_layout(dtype, count, items, nullptr);
+}
+
+cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, double tol,
+                                  const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                                  hipStream_t stream) {
+  try {
+    if (count < 1 || !items) throw Error(CS_E_INVALID, "count must be >= 1 with a non-null item array");
+    for (int i = 0; i < count; ++i) {
+      check_shape(dtype, &items[i].op, items[i].k, CS_ALGO_OMPR);
+      if (!items[i].y || !items[i].s || !items[i].support) throw Error(CS_E_INVALID, "null y, s or support in batch");
+    }
+    check_tol(tol);
+    check_ws(ws);
+    const cs_params prm = defaults(params);
+    const int cgb = (params && params->cg_block > 0) ? params->cg_block : 256;
+    if (cgb < 64 || cgb > 1024 || (cgb & 63)) throw Error(CS_E_INVALID, "cg_block must be a multiple of 64 in [64, 1024]");
+    if (dtype == CS_F32) run_ompr_batched<float>(count, items, tol, prm, cgb, ws, ws_bytes, info, stream);
+    else run_ompr_batched<double>(count, items, tol, prm, cgb, ws, ws_bytes, info, stream);
+    if (prof_on()) prof_flush();
     return CS_OK;
   } catch (const Error& e) {
     g_last_error = e.what();

@@ -1,0 +1,198 @@
+// Device helpers shared by the selection, CG and batched-driver units:
+// magnitude keys, block reductions, and the bitmap-to-list compaction bodies.
+#pragma once
+
+#include "cs_internal.h"
+
+namespace csr {
+
+// IEEE bit pattern of |v|: orders like the value for non-negative numbers.
+template <typename T> __device__ __forceinline__ uint64_t mag_bits(T v);
+template <> __device__ __forceinline__ uint64_t mag_bits<float>(float v) { return (uint64_t)__float_as_uint(fabsf(v)); }
+template <> __device__ __forceinline__ uint64_t mag_bits<double>(double v) {
+  return (uint64_t)__double_as_longlong(fabs(v));
+}
+template <typename T> __device__ __forceinline__ bool finite_v(T v) { return isfinite(v); }
+
+__device__ __forceinline__ bool bit_of(const uint32_t* __restrict__ b, int64_t j) {
+  return (b[j >> 5] >> (j & 31)) & 1u;
+}
+
+__device__ __forceinline__ bool key_gt(const ArgKey& a, const ArgKey& b) {
+  return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo);
+}
+
+__device__ __forceinline__ ArgKey shfl_down_key(ArgKey k, int off) {
+  ArgKey r;
+  r.hi = __shfl_down((unsigned long long)k.hi, off, 64);
+  r.lo = __shfl_down(k.lo, off, 64);
+  r.pad = 0;
+  return r;
+}
+
+// Block-wide max of ArgKey (any block size up to 1024); result valid in thread 0.
+__device__ __forceinline__ ArgKey block_max_key(ArgKey best) {
+  __shared__ ArgKey sh[16];
+  for (int off = 32; off > 0; off >>= 1) {
+    ArgKey o = shfl_down_key(best, off);
+    if (key_gt(o, best)) best = o;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
+      if (key_gt(sh[i], best)) best = sh[i];
+  }
+  __syncthreads();
+  return best;
+}
+
+// Block sum in a fixed order, broadcast to every thread (any block size up to
+// 1024, a multiple of 64).
+__device__ __forceinline__ double block_sum_any(double v) {
+  __shared__ double sh[16];
+  __shared__ double res;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    res = s;
+  }
+  __syncthreads();
+  const double r = res;
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ OMPR drop step
+// Candidates I u {j}: z_i = x'_i + eta c_i on the support (compact x' and the
+// key-order correlation c = F^T D^T r, sign-flipped coordinates), z_j = eta
+// c_j for the entering index j (natural, < 0: none).  The dropped element is
+// the last under (|z| desc, index asc): the smallest |z|, ties to the larger
+// index, found as a max-reduction over (~bits(|z|), index).  Returns the
+// dropped natural index in thread 0 (any block size up to 1024).
+__device__ __forceinline__ bool dkey_gt(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
+  return ah > bh || (ah == bh && al > bl);
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t ompr_drop_body(const T* __restrict__ x, const int32_t* __restrict__ list, int k,
+                                                  const T* __restrict__ cc, const Plan& pl, T eta, int32_t jn) {
+  __shared__ uint64_t sh_h[16];
+  __shared__ uint32_t sh_l[16];
+  uint64_t bh = 0;
+  uint32_t bl = 0;
+  for (int i = threadIdx.x; i <= k; i += blockDim.x) {
+    int64_t j, key;
+    if (i < k) {
+      key = list[i];
+      j = nat_of_key(key, pl);
+    } else {
+      j = jn;
+      if (j < 0) continue;
+      key = key_of_nat(j, pl);
+    }
+    const T cv = cc[key];   // sign_j (A^T r)_j
+    const T z = (i < k) ? x[i] + eta * cv : eta * cv;
+    const uint64_t h = ~mag_bits(z);
+    const uint32_t l = (uint32_t)j;
+    if (dkey_gt(h, l, bh, bl)) { bh = h; bl = l; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t oh = __shfl_down((unsigned long long)bh, off, 64);
+    const uint32_t ol = __shfl_down(bl, off, 64);
+    if (dkey_gt(oh, ol, bh, bl)) { bh = oh; bl = ol; }
+  }
+  if ((threadIdx.x & 63) == 0) { sh_h[threadIdx.x >> 6] = bh; sh_l[threadIdx.x >> 6] = bl; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      if (dkey_gt(sh_h[w], sh_l[w], bh, bl)) { bh = sh_h[w]; bl = sh_l[w]; }
+  }
+  __syncthreads();
+  return (int32_t)bl;
+}
+
+// ------------------------------------------------------------------ bitmap -> ascending index list
+// Block b covers words [1024 b, 1024 b + 1024): count its set bits (256 threads).
+__device__ __forceinline__ void bits_count_body(const uint32_t* __restrict__ bits, int64_t words,
+                                                uint32_t* __restrict__ cnt, int b) {
+  __shared__ uint32_t red[4];
+  const int64_t w0 = (int64_t)b * kBitsPerBlockWords;
+  uint32_t s = 0;
+  for (int i = threadIdx.x; i < kBitsPerBlockWords; i += blockDim.x) {
+    const int64_t w = w0 + i;
+    if (w < words) s += __popc(bits[w]);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[b] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Exclusive scan of cnt[0..nb) in place (one block of 1024 threads); total -> cnt[nb].
+__device__ __forceinline__ void bits_scan_body(uint32_t* cnt, int nb) {
+  __shared__ uint32_t sh[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < nb; base += 1024) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = (i < nb) ? cnt[i] : 0u;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) cnt[i] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[nb] = carry;
+}
+
+// Block b (256 threads, 4 words each) writes the indices of its set bits at
+// their ranks (at most `limit` of them) and, per word, the number of set bits
+// in all earlier words (wpre, nullable).
+__device__ __forceinline__ void bits_write_body(const uint32_t* __restrict__ bits, int64_t words,
+                                                const uint32_t* __restrict__ cnt, int32_t* __restrict__ list,
+                                                int limit, uint32_t* __restrict__ wpre, int b) {
+  __shared__ uint32_t sh[256];
+  const int64_t w0 = (int64_t)b * kBitsPerBlockWords + threadIdx.x * 4;
+  uint32_t wv[4];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    wv[q] = (w0 + q < words) ? bits[w0 + q] : 0u;
+    mine += __popc(wv[q]);
+  }
+  sh[threadIdx.x] = mine;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t pos = cnt[b] + sh[threadIdx.x] - mine;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (wpre && w0 + q < words) wpre[w0 + q] = pos;
+    uint32_t v = wv[q];
+    while (v) {
+      const int bit = __ffs(v) - 1;
+      v &= v - 1;
+      if ((int)pos < limit) list[pos] = (int32_t)((w0 + q) * 32 + bit);
+      ++pos;
+    }
+  }
+}
+
+}  // namespace csr

@@ -14,7 +14,7 @@
 // Decision rules follow the SP/OMPR readings documented with the oracle:
 //   SP:   stop with T' when T' == T; stop with (T, x) when ||r'|| > ||r||.
 //   OMPR: l = 1, z = x + eta A^T r on I u {j}; stop when j ranks last.
-#include "cs_internal.h"
+#include "cs_device.h"
 
 #include <algorithm>
 #include <cmath>
@@ -24,58 +24,13 @@ namespace csr {
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
-// OMPR drop step.  Candidates I u {j}: z_i = x_i + eta (A^T r)_i, z_j = eta (A^T r)_j.
-// The dropped element is the last under (|z| desc, index asc): the smallest
-// |z|, ties to the larger index.  Packed as a max-reduction over
-// (~bits(|z|), index).
-template <typename T> __device__ __forceinline__ uint64_t mag_bits2(T v);
-template <> __device__ __forceinline__ uint64_t mag_bits2<float>(float v) { return (uint64_t)__float_as_uint(fabsf(v)); }
-template <> __device__ __forceinline__ uint64_t mag_bits2<double>(double v) {
-  return (uint64_t)__double_as_longlong(fabs(v));
-}
-
-__device__ __forceinline__ bool dkey_gt(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
-  return ah > bh || (ah == bh && al > bl);
-}
-
+// OMPR drop step (one block of 1024 threads): out[0] = dropped natural index.
 template <typename T>
 __global__ void k_ompr_drop(const T* __restrict__ x, const int32_t* __restrict__ list, int k,
-                            const T* __restrict__ Wv, const Plan pl, T eta, const int32_t* __restrict__ jptr,
+                            const T* __restrict__ cc, const Plan pl, T eta, const int32_t* __restrict__ jptr,
                             int32_t* __restrict__ out) {
-  // single block of 1024 threads
-  __shared__ uint64_t sh_h[16];
-  __shared__ uint32_t sh_l[16];
-  uint64_t bh = 0;
-  uint32_t bl = 0;
-  const int32_t jn = *jptr;
-  for (int i = threadIdx.x; i <= k; i += blockDim.x) {
-    int64_t j, key;
-    if (i < k) {
-      key = list[i];
-      j = nat_of_key(key, pl);
-    } else {
-      j = jn;
-      if (j < 0) continue;
-      key = key_of_nat(j, pl);
-    }
-    const T cv = Wv[key];   // sign_j (A^T r)_j
-    const T z = (i < k) ? x[i] + eta * cv : eta * cv;
-    const uint64_t h = ~mag_bits2(z);
-    const uint32_t l = (uint32_t)j;
-    if (dkey_gt(h, l, bh, bl)) { bh = h; bl = l; }
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t oh = __shfl_down((unsigned long long)bh, off, 64);
-    const uint32_t ol = __shfl_down(bl, off, 64);
-    if (dkey_gt(oh, ol, bh, bl)) { bh = oh; bl = ol; }
-  }
-  if ((threadIdx.x & 63) == 0) { sh_h[threadIdx.x >> 6] = bh; sh_l[threadIdx.x >> 6] = bl; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-      if (dkey_gt(sh_h[w], sh_l[w], bh, bl)) { bh = sh_h[w]; bl = sh_l[w]; }
-    out[0] = (int32_t)bl;
-  }
+  const int32_t d = ompr_drop_body<T>(x, list, k, cc, pl, eta, *jptr);
+  if (threadIdx.x == 0) out[0] = d;
 }
 
 // key bitmap update for a swap: jd[0] = index to add, jd[1] = index to drop (natural)

@@ -22,6 +22,7 @@
 #include <cstddef>
 #include <string>
 #include <stdexcept>
+#include <vector>
 
 #include "../../include/cs.h"
 
@@ -258,6 +259,46 @@ struct Ctx {
   int32_t flags = 0;
 };
 
+// ------------------------------------------------------------------ batched recovery
+// Per-signal phase of the batched OMPR driver.  One batched step moves every
+// signal one stage along: a warm-started CG solve (WARM, then ITER per
+// iteration), the residual and correlation (RESID), the OMPR swap (SELECT).
+enum BPhase { BP_WARM = 0, BP_ITER = 1, BP_RESID = 2, BP_SELECT = 3, BP_DONE = 4 };
+
+struct BState {
+  int32_t phase;
+  int32_t cur;            // list / x slot of the current support (0 or 1)
+  int32_t it;             // CG iteration within the current solve
+  int32_t swaps;          // OMPR swaps done
+  int32_t k, max_outer, cg_cap, flags;
+  int32_t warm, jd[2], pad;
+  int64_t cg_iters, transforms;
+  double rn, bb, tol2, eta, ynorm, model_bytes;
+};
+
+template <typename T>
+struct BSig {              // device-side view of one signal of a batch
+  Plan plan;
+  Cx<T>* W;
+  T* Cc;
+  T* C0;
+  T* Yf;
+  const Cx<T>* tw_col;
+  const Cx<T>* tw_row;
+  uint32_t* bits;          // support key bitmap
+  uint32_t* wpre[2];
+  int32_t* list[2];
+  T* cb;
+  T* cx[2];
+  T *cr, *cd, *cq;
+  double* pgrid;           // column-pass partials
+  double* prow;            // row-pass partials
+  ArgKey* argpart;
+  uint32_t* blockcnt;
+  CgScalars* cg;
+  BState* st;
+};
+
 // A support as the CG sees it.
 struct Supp {
   const uint32_t* bits;    // key bitmap
@@ -290,6 +331,8 @@ enum RowMode { ROW_HAPPLY = 0, ROW_RESID = 1, ROW_FWD = 2, ROW_ADJ = 3 };
 
 template <typename T> void setup_operator(Ctx<T>& c);                  // twiddles, masks (+ validation)
 template <typename T> void scatter_freq(Ctx<T>& c, const T* u, T* outf); // u [M] -> freq layout
+// y -> Yf (freq layout), ||y|| -> ynorm, F^T D^T y (key order) -> C0
+template <typename T> void load_measurements(Ctx<T>& c, const T* y);
 template <typename T> void gather_freq(Ctx<T>& c, const T* inf, T* out); // freq layout -> [M]
 template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
 // Reads `bytes` (a multiple of 4, at most 4096) of device memory on the host:
@@ -350,5 +393,12 @@ template <typename T>
 void run_ompr(Ctx<T>& c, int k, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info);
 template <typename T>
 void write_output(Ctx<T>& c, const int32_t* list, const T* x, int k, T* s_out, int32_t* supp_out);
+
+// Batched OMPR: workspace layout (per-signal offsets appended to offs when
+// non-null; returns the total bytes, 0 if a size is unsupported) and driver.
+size_t batch_layout(cs_dtype dt, int count, const cs_batch_item* items, std::vector<size_t>* offs);
+template <typename T>
+void run_ompr_batched(int count, const cs_batch_item* items, double tol, const cs_params& prm, int cg_threads,
+                      void* ws, size_t ws_bytes, cs_info* infos, hipStream_t stream);
 
 }  // namespace csr

@@ -88,9 +88,8 @@ __device__ __forceinline__ uint32_t slot_at(const ColIO<T>& io, size_t key, int6
 // bitmap.  `in` and `out` may be the same buffer in v-order modes: a
 // workgroup reads its whole strip before writing it back.
 template <typename T, bool INV, int LOGL1, int LOGB, int LOGE>
-__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const Cx<T>* in, Cx<T>* out, Plan p,
-                                                                           ColIO<T> io,
-                                                                           const Cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan& p, const ColIO<T>& io,
+                                         const Cx<T>* __restrict__ tw, int g) {
   constexpr int E = 1 << (LOGL1 + LOGB), B = 1 << LOGB;
   constexpr int NT = nt_for(E, LOGE);
   constexpr int EPT = (E + NT - 1) / NT;
@@ -100,7 +99,6 @@ __global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const
   Cx<T>* buf = (Cx<T>*)smem_raw;
   T* bufr = (T*)smem_raw;
   const int tid = threadIdx.x;
-  const int g = xcd_order(blockIdx.x, gridDim.x);
   const size_t c0 = (size_t)g << LOGB;
   const size_t kb = (size_t)g * E;      // first key-order complex slot of the strip
   const size_t L2 = (size_t)p.L2;
@@ -201,6 +199,67 @@ __global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const
   }
 }
 
+template <typename T, bool INV, int LOGL1, int LOGB, int LOGE>
+__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const Cx<T>* in, Cx<T>* out, Plan p,
+                                                                           ColIO<T> io,
+                                                                           const Cx<T>* __restrict__ tw) {
+  col_body<T, INV, LOGL1, LOGB, LOGE>(in, out, p, io, tw, xcd_order(blockIdx.x, gridDim.x));
+}
+
+// Compact I/O of one batched signal in its current phase (mode < 0: idle).
+template <typename T, bool INV>
+__device__ __forceinline__ ColIO<T> batch_io(const BSig<T>& s, int phase) {
+  ColIO<T> io{};
+  io.mode = -1;
+  if (phase > BP_RESID) return io;
+  const int cur = s.st->cur;
+  io.sbits = s.bits;
+  io.wpre = s.wpre[cur];
+  io.list = s.list[cur];
+  io.kcap = s.st->k;
+  if (!INV) {
+    if (phase == BP_ITER) {
+      io.mode = COL_DIR;
+      io.it = s.st->it;
+      io.r = s.cr;
+      io.d = s.cd;
+      io.cg = s.cg;
+    } else {
+      io.mode = COL_X;
+      io.x = s.cx[cur];
+    }
+  } else {
+    if (phase == BP_WARM) {
+      io.mode = COL_R;
+      io.r = s.cr;
+      io.d = s.cd;
+      io.b = s.cb;
+      io.pout = s.pgrid;
+    } else if (phase == BP_ITER) {
+      io.mode = COL_Q;
+      io.q = s.cq;
+      io.d = s.cd;
+      io.pout = s.pgrid;
+      io.cg = s.cg;
+    } else {
+      io.mode = COL_KEY;
+    }
+  }
+  return io;
+}
+
+// Batched column pass: blockIdx.y picks the signal (ids[] of one size class).
+template <typename T, bool INV, int LOGL1, int LOGB, int LOGE>
+__global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col_b(const BSig<T>* __restrict__ sigs,
+                                                                             const int32_t* __restrict__ ids) {
+  const BSig<T>& s = sigs[ids[blockIdx.y]];
+  const int phase = s.st->phase;
+  const ColIO<T> io = batch_io<T, INV>(s, phase);
+  if (io.mode < 0) return;
+  col_body<T, INV, LOGL1, LOGB, LOGE>((const Cx<T>*)s.W, INV && phase == BP_RESID ? (Cx<T>*)s.Cc : s.W, s.plan, io,
+                                      s.tw_col, xcd_order(blockIdx.x, gridDim.x));
+}
+
 // ------------------------------------------------------------------ row pass
 // Workgroup w owns rows ra = w, rb = L1 - w (w >= 1) or ra = 0, rb = L1/2 (w = 0).
 // Row r, element k2 holds Z[r + L1 k2]; the mirror bin L - k of k = r + L1 k2
@@ -250,20 +309,16 @@ __device__ __forceinline__ Cx<T> row_tw(const Plan& p, uint32_t r, uint32_t n2) 
 }
 
 template <typename T, int LOGL2, int LOGE>
-__global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row(Cx<T>* __restrict__ buf, Plan p, int mode,
-                                                            const T* __restrict__ fin, T* __restrict__ fout,
-                                                            double* __restrict__ partial,
-                                                            const int* __restrict__ done,
-                                                            const Cx<T>* __restrict__ tw) {
+__device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p, int mode,
+                                         const T* __restrict__ fin, T* __restrict__ fout,
+                                         double* __restrict__ partial, const Cx<T>* __restrict__ tw, int w) {
   constexpr int L2 = 1 << LOGL2;
   constexpr int NT = nt_for(2 * L2, LOGE);
   constexpr bool SPLIT = NT <= L2;                 // threads tile each row exactly
   constexpr int PER_ROW = SPLIT ? L2 / NT : 1;
-  if (done && *done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<T>* lds = (Cx<T>*)smem_raw;
   __shared__ double red[NT / 64];
-  const int w = blockIdx.x;
   const int L1 = p.L1;
   const int ra = w, rb = (w == 0) ? (L1 >> 1) : (L1 - w);
   const int tid = threadIdx.x;
@@ -422,6 +477,28 @@ __global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row(Cx<T>* __restr
   }
 }
 
+template <typename T, int LOGL2, int LOGE>
+__global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row(Cx<T>* __restrict__ buf, Plan p, int mode,
+                                                            const T* __restrict__ fin, T* __restrict__ fout,
+                                                            double* __restrict__ partial,
+                                                            const int* __restrict__ done,
+                                                            const Cx<T>* __restrict__ tw) {
+  if (done && *done) return;
+  row_body<T, LOGL2, LOGE>(buf, p, mode, fin, fout, partial, tw, blockIdx.x);
+}
+
+// Batched row pass: H-apply in the CG phases, residual in BP_RESID.
+template <typename T, int LOGL2, int LOGE>
+__global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row_b(const BSig<T>* __restrict__ sigs,
+                                                              const int32_t* __restrict__ ids) {
+  const BSig<T>& s = sigs[ids[blockIdx.y]];
+  const int phase = s.st->phase;
+  if (phase > BP_RESID) return;
+  const bool res = phase == BP_RESID;
+  row_body<T, LOGL2, LOGE>(s.W, s.plan, res ? ROW_RESID : ROW_HAPPLY, res ? s.Yf : nullptr, nullptr,
+                           res ? s.prow : nullptr, s.tw_row, blockIdx.x);
+}
+
 // ------------------------------------------------------------------ stage twiddle tables
 // Fills the stage table of the size-2^logn FFT (layout in cs_fft.h).
 template <typename T>
@@ -456,6 +533,9 @@ struct KernelSet {
   void (*col_fwd)(const Cx<T>*, Cx<T>*, Plan, ColIO<T>, const Cx<T>*);
   void (*col_inv)(const Cx<T>*, Cx<T>*, Plan, ColIO<T>, const Cx<T>*);
   void (*row)(Cx<T>*, Plan, int, const T*, T*, double*, const int*, const Cx<T>*);
+  void (*col_fwd_b)(const BSig<T>*, const int32_t*);
+  void (*col_inv_b)(const BSig<T>*, const int32_t*);
+  void (*row_b)(const BSig<T>*, const int32_t*);
   int nt_col, nt_row;
 };
 

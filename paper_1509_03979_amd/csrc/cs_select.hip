@@ -14,53 +14,13 @@
 //    second radix select over the indices (ascending) keeps the lowest ones.
 //    Selected indices are marked in an N-bit bitmap and compacted to a sorted
 //    list with a block prefix sum, so supports come out ascending.
-#include "cs_internal.h"
+#include "cs_device.h"
 
 #include <algorithm>
 
 namespace csr {
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
-
-template <typename T> __device__ __forceinline__ uint64_t mag_bits(T v);
-template <> __device__ __forceinline__ uint64_t mag_bits<float>(float v) { return (uint64_t)__float_as_uint(fabsf(v)); }
-template <> __device__ __forceinline__ uint64_t mag_bits<double>(double v) {
-  return (uint64_t)__double_as_longlong(fabs(v));
-}
-template <typename T> __device__ __forceinline__ bool finite_v(T v) { return isfinite(v); }
-
-__device__ __forceinline__ bool bit_of(const uint32_t* __restrict__ b, int64_t j) {
-  return (b[j >> 5] >> (j & 31)) & 1u;
-}
-
-__device__ __forceinline__ bool key_gt(const ArgKey& a, const ArgKey& b) {
-  return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo);
-}
-
-__device__ __forceinline__ ArgKey shfl_down_key(ArgKey k, int off) {
-  ArgKey r;
-  r.hi = __shfl_down((unsigned long long)k.hi, off, 64);
-  r.lo = __shfl_down(k.lo, off, 64);
-  r.pad = 0;
-  return r;
-}
-
-// Block-wide max of ArgKey; result valid in thread 0.
-__device__ __forceinline__ ArgKey block_max_key(ArgKey best) {
-  __shared__ ArgKey sh[16];
-  for (int off = 32; off > 0; off >>= 1) {
-    ArgKey o = shfl_down_key(best, off);
-    if (key_gt(o, best)) best = o;
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) sh[wave] = best;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < (int)(blockDim.x >> 6); ++i)
-      if (key_gt(sh[i], best)) best = sh[i];
-  }
-  return best;
-}
 
 // ------------------------------------------------------------------ argmax outside a set
 template <typename T>
@@ -305,79 +265,13 @@ int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scr
   return h == 0;
 }
 
-// Bitmap -> ascending index list.  Block b covers words [1024 b, 1024 b + 1024).
 __global__ void k_bits_count(const uint32_t* __restrict__ bits, int64_t words, uint32_t* __restrict__ cnt) {
-  __shared__ uint32_t red[4];
-  const int64_t w0 = (int64_t)blockIdx.x * kBitsPerBlockWords;
-  uint32_t s = 0;
-  for (int i = threadIdx.x; i < kBitsPerBlockWords; i += blockDim.x) {
-    const int64_t w = w0 + i;
-    if (w < words) s += __popc(bits[w]);
-  }
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  bits_count_body(bits, words, cnt, blockIdx.x);
 }
-
-// exclusive scan of cnt[0..nb) in place (single block, 1024 threads); total -> cnt[nb]
-__global__ void k_bits_scan(uint32_t* cnt, int nb) {
-  __shared__ uint32_t sh[1024];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nb; base += 1024) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = (i < nb) ? cnt[i] : 0u;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
-      __syncthreads();
-      sh[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < nb) cnt[i] = carry + sh[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += sh[1023];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) cnt[nb] = carry;
-}
-
-// 256 threads, 4 words each.  Also records, per word, the number of set bits
-// in all earlier words (wpre, nullable).
+__global__ void k_bits_scan(uint32_t* cnt, int nb) { bits_scan_body(cnt, nb); }
 __global__ void k_bits_write(const uint32_t* __restrict__ bits, int64_t words, const uint32_t* __restrict__ cnt,
                              int32_t* __restrict__ list, int limit, uint32_t* __restrict__ wpre) {
-  __shared__ uint32_t sh[256];
-  const int64_t w0 = (int64_t)blockIdx.x * kBitsPerBlockWords + threadIdx.x * 4;
-  uint32_t wv[4];
-  uint32_t mine = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    wv[q] = (w0 + q < words) ? bits[w0 + q] : 0u;
-    mine += __popc(wv[q]);
-  }
-  sh[threadIdx.x] = mine;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
-    __syncthreads();
-    sh[threadIdx.x] += t;
-    __syncthreads();
-  }
-  uint32_t pos = cnt[blockIdx.x] + sh[threadIdx.x] - mine;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (wpre && w0 + q < words) wpre[w0 + q] = pos;
-    uint32_t v = wv[q];
-    while (v) {
-      const int b = __ffs(v) - 1;
-      v &= v - 1;
-      if ((int)pos < limit) list[pos] = (int32_t)((w0 + q) * 32 + b);
-      ++pos;
-    }
-  }
+  bits_write_body(bits, words, cnt, list, limit, wpre, blockIdx.x);
 }
 
 template <typename T>

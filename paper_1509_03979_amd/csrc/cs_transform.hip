@@ -249,6 +249,14 @@ double norm2_host(Ctx<T>& c, const T* v, int64_t count) {
   return std::sqrt(r2);
 }
 
+// Loads y: freq-layout copy, ||y||, and F^T D^T y (key order) into C0.
+template <typename T>
+void load_measurements(Ctx<T>& c, const T* y) {
+  scatter_freq<T>(c, y, c.Yf);
+  c.ynorm = norm2_host<T>(c, y, c.plan.m);
+  transform_adj<T>(c, c.Yf, c.C0, true);
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename T>
 ColIO<T> col_io(Ctx<T>& c, int mode, const Supp* S) {
@@ -354,6 +362,9 @@ void prepare_kernels() {
     CS_HIP(hipFuncSetAttribute((const void*)ks.col_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     CS_HIP(hipFuncSetAttribute((const void*)ks.col_inv, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
     CS_HIP(hipFuncSetAttribute((const void*)ks.row, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    CS_HIP(hipFuncSetAttribute((const void*)ks.col_fwd_b, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    CS_HIP(hipFuncSetAttribute((const void*)ks.col_inv_b, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+    CS_HIP(hipFuncSetAttribute((const void*)ks.row_b, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
   }
   for (int a = 1; a <= 14; ++a)
     for (int b = 1; b <= 13; ++b)
@@ -363,6 +374,9 @@ void prepare_kernels() {
           CS_HIP(hipFuncSetAttribute((const void*)ks->col_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
           CS_HIP(hipFuncSetAttribute((const void*)ks->col_inv, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
           CS_HIP(hipFuncSetAttribute((const void*)ks->row, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+          CS_HIP(hipFuncSetAttribute((const void*)ks->col_fwd_b, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+          CS_HIP(hipFuncSetAttribute((const void*)ks->col_inv_b, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+          CS_HIP(hipFuncSetAttribute((const void*)ks->row_b, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
         }
   ready.store(1);
 }
@@ -378,6 +392,7 @@ void prepare_kernels() {
   template void launch_col<T>(Ctx<T>&, const Cx<T>*, Cx<T>*, bool, const ColIO<T>&);   \
   template void launch_row<T>(Ctx<T>&, int, const T*, T*, double*, const int*);         \
   template void transform_fwd<T>(Ctx<T>&, const T*, T*);                                \
+  template void load_measurements<T>(Ctx<T>&, const T*);                                \
   template void transform_adj<T>(Ctx<T>&, const T*, T*, bool);                              \
   template void perm_in<T>(Ctx<T>&, const T*, T*);                                      \
   template void perm_out<T>(Ctx<T>&, const T*, T*);                                     \

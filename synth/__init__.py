@@ -120,21 +120,23 @@ def workload_problem(name: str, sig: int = 0) -> Draw:
     return draw_problem(w["cfg"], sig, w["n"], w["m"], w["k"], w["values"], w["snr_db"])
 
 
-def batched_sizes(n_signals: int = 256, cfg: int = 4):
-    """Per-signal sizes of the batched OMPR workload: N_i in {2^14..2^18},
-    M_i/N_i ~ U[0.2, 0.4], K_i/N_i ~ U[0.005, 0.02] (K_i >= 1)."""
+def batched_sizes(n_signals: int = 256, cfg: int = 4, log_n=(14, 18)):
+    """Per-signal sizes of the batched OMPR workload: N_i in {2^14..2^18}
+    (or 2^log_n[0] .. 2^log_n[1]), M_i/N_i ~ U[0.2, 0.4], K_i/N_i ~ U[0.005,
+    0.02] (K_i >= 1)."""
     out = []
+    lo, hi = log_n
     for sig in range(n_signals):
         r = rng_for(cfg, sig, STREAM_SIZES)
-        n = 2 ** (14 + int(r.integers(0, 5)))
+        n = 2 ** (lo + int(r.integers(0, hi - lo + 1)))
         m = int(round(n * r.uniform(0.2, 0.4)))
         k = max(1, int(round(n * r.uniform(0.005, 0.02))))
         out.append((n, m, k))
     return out
 
 
-def batched_problem(sig: int, cfg: int = 4) -> Draw:
-    n, m, k = batched_sizes(sig + 1, cfg)[sig]
+def batched_problem(sig: int, cfg: int = 4, log_n=(14, 18)) -> Draw:
+    n, m, k = batched_sizes(sig + 1, cfg, log_n)[sig]
     return draw_problem(cfg, sig, n, m, k, "normal", 30.0)
 
 
