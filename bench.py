@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled replay (roofline)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched OMPR leg (256 signals)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated SP leg (64 signals)")
+    ap.add_argument("--no-single-loop", action="store_true", help="batched leg: skip the single-signal loop")
     return ap.parse_args()
 
 
@@ -107,6 +110,120 @@ def recovered(s, supp, exp) -> tuple[bool, float]:
     ref[es] = ev
     err = float(np.linalg.norm(s - ref) / np.linalg.norm(ref))
     return err <= REL_TOL, err
+
+
+def batched_leg(torch, cs, count: int, loop_single: bool) -> dict:
+    """Batched OMPR over the 256-signal workload (N_i in 2^14..2^18): one batched
+    call per step, checked against the stored FP64 oracle results, beside the
+    single-signal call looped over the same signals."""
+    import synth
+    tol = synth.BATCHED_WORKLOAD["tol"]
+    ys, ops, ks, draws = [], [], [], []
+    for sig in range(count):
+        d = synth.batched_problem(sig)
+        op = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+        s64 = torch.as_tensor(d.s_dense(), dtype=torch.float64, device="cuda")
+        y0 = cs.cs_apply_A(s64, op).cpu().numpy()
+        y = y0 + d.noise_scale(np.linalg.norm(y0)) * d.noise
+        ys.append(torch.as_tensor(y.astype(np.float32), device="cuda"))
+        ops.append(op)
+        ks.append(d.k)
+        draws.append(d)
+    # autotuner: transform shape per N, then the CG block size on a 32-signal slice
+    import paper_1509_03979_amd.tune as tune
+    ns = sorted({d.n for d in draws})
+    shapes = tune.tune_shapes(ns, "f32", reps=10)
+    small = cs.Batch(ys[:32], ops[:32], ks[:32])
+    cgt = tune.tune_cg_block(lambda b: cs.cs_recover_ompr_batched(small, tol, cg_block=b), reps=1)
+    cgb = cgt["cg_block"]
+    batch = cs.Batch(ys, ops, ks)
+    cs.cs_recover_ompr_batched(batch, tol, cg_block=cgb)            # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s_list, supp_list, infos = cs.cs_recover_ompr_batched(batch, tol, cg_block=cgb)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    gold = os.path.join(ROOT, "tests", "golden", f"ompr_batched_{count}.npz")
+    ok = checked = 0
+    y_match = None
+    if os.path.exists(gold):
+        g = np.load(gold, allow_pickle=False)
+        meta = json.loads(str(g["meta"]))["signals"]
+        offs = g["offsets"]
+        y_match = True
+        for i in range(count):
+            es = g["support"][offs[i]:offs[i + 1]].astype(np.int64)
+            ref = np.zeros(draws[i].n)
+            ref[es] = g["values"][offs[i]:offs[i + 1]]
+            good, _ = recovered(s_list[i].cpu().numpy().astype(np.float64), supp_list[i].cpu().numpy(), (es, ref[es]))
+            ok += int(good)
+            checked += 1
+            yn = float(torch.linalg.norm(ys[i].double()))
+            y_match &= abs(yn - meta[i]["y_norm"]) <= 1e-6 * meta[i]["y_norm"]
+    mb = sum(i["model_bytes"] for i in infos)
+    out = {"signals": count, "tol": tol, "seconds_per_batch": round(tb, 4), "signals_per_s": round(count / tb, 2),
+           "recovered": ok, "checked_against_oracle": checked,
+           "recovered_signals_per_s": round(ok / tb, 2) if checked else None,
+           "inputs_match_oracle_y_norms": y_match,
+           "swaps": sum(i["outer_iters"] for i in infos), "cg_iters": sum(i["cg_iters"] for i in infos),
+           "model_gbytes": round(mb / 1e9, 3), "model_gb_per_s": round(mb / tb / 1e9, 1),
+           "model_hbm_frac": round(mb / tb / 1e9 / HBM_PEAK_GBS, 4),
+           "tuned": {"shapes": {str(n): {"shape": list(r["shape"]), "default": list(r["default"]),
+                                         "ms_per_happly": round(r["ms"], 4)} for n, r in shapes.items()},
+                     "cg_block": cgb, "cg_block_seconds": {str(k): round(v, 4) for k, v in cgt["all"].items()}}}
+    if loop_single:
+        t1 = time.perf_counter()
+        for i in range(count):
+            cs.cs_recover_ompr(ys[i], ops[i], ks[i], tol)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t1
+        out.update({"single_loop_seconds": round(tl, 3), "batched_speedup": round(tl / tb, 2)})
+    return out
+
+
+def adjoint_leg(torch, cs, batch: int, reps: int = 3) -> dict:
+    """Differentiated SP on the 64-signal workload (N = 2^16, M = 2^14, K = 300):
+    forward recovery, and forward + backward of L = sum_b ||s_b - t_b||^2 with
+    respect to y through the adjoint CG, beside the forward alone."""
+    import synth
+    w = synth.WORKLOADS["sp_adjoint_n2p16"]
+    ys, ops, ts = [], [], []
+    for sig in range(batch):
+        d = synth.workload_problem("sp_adjoint_n2p16", sig)
+        op = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+        s64 = torch.as_tensor(d.s_dense(), dtype=torch.float64, device="cuda")
+        y0 = cs.cs_apply_A(s64, op).cpu().numpy()
+        y = y0 + d.noise_scale(np.linalg.norm(y0)) * d.noise
+        ys.append(torch.as_tensor(y.astype(np.float32), device="cuda"))
+        ops.append(op)
+        ts.append(torch.as_tensor(d.s_dense(), dtype=torch.float32, device="cuda"))
+    k, tol = w["k"], w["tol"]
+
+    def fwd():
+        return [cs.SPRecover.apply(ys[b], ops[b], k, tol)[0] for b in range(batch)]
+
+    def fwd_bwd():
+        yl = [y.detach().requires_grad_(True) for y in ys]
+        loss = sum(((cs.SPRecover.apply(yl[b], ops[b], k, tol)[0] - ts[b]) ** 2).sum() for b in range(batch))
+        loss.backward()
+        return yl
+
+    fwd()
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fwd()
+    torch.cuda.synchronize()
+    tf = (time.perf_counter() - t0) / reps
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t1) / reps
+    return {"batch": batch, "forward_s": round(tf, 4), "forward_backward_s": round(tb, 4),
+            "forward_signals_per_s": round(batch / tf, 1), "forward_backward_signals_per_s": round(batch / tb, 1),
+            "backward_over_forward": round((tb - tf) / tf, 3)}
 
 
 def main():
@@ -217,6 +334,11 @@ def main():
             ok, err = recovered(so.cpu().numpy().astype(np.float64), suppo.cpu().numpy(), expect.get(other))
             extra[other] = {"signals_per_s": round((1.0 if ok else 0.0) / to, 3), "ms_per_signal": round(1e3 * to, 3),
                             "recovered": ok, "rel_err": err, "info": info_o}
+
+    if not args.no_batched:
+        extra["ompr_batched_256"] = batched_leg(torch, cs, 256, not args.no_single_loop)
+    if not args.no_adjoint:
+        extra["sp_adjoint_n2p16"] = adjoint_leg(torch, cs, 64)
 
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "signals/s", "n_gpus": 1, "steps": args.steps,

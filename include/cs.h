@@ -208,6 +208,31 @@ cs_status cs_apply_A(cs_dtype dtype, const cs_op* op, const void* x, void* out,
 cs_status cs_apply_At(cs_dtype dtype, const cs_op* op, const void* u, void* out,
                       void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Tuning of the transform passes.  The DCT of Sec. III-D runs as an
+ * N/2-point complex FFT split four-step into L1 x L2 (column passes over
+ * strips of 2^log_b columns, row passes over row pairs, 2^log_e elements per
+ * thread).  Several splits are compiled per N; which is fastest depends on
+ * the device, so a tuner can time them and install its choice for the rest of
+ * the process.  Results are the same up to rounding whichever split runs.
+ *
+ * cs_shape_candidates: the compiled shapes for N, the default first; writes
+ *   up to `max` into out (out == NULL: returns the count only).
+ * cs_set_shape: makes `shape` (one of the candidates) the shape of every later
+ *   call at this N in this process; NULL restores the default.  Not to be
+ *   called while other calls run.  Workspace sizes do not depend on it.
+ * cs_time_shape: average milliseconds of one H-apply (the three transform
+ *   passes of one CG iteration, on a dense N-vector) with `shape`, over `reps`
+ *   applies on `stream`; workspace as for cs_apply_A.
+ */
+typedef struct {
+  int32_t log_l1, log_l2, log_b, log_e;
+} cs_shape;
+int cs_shape_candidates(cs_dtype dtype, int64_t n, cs_shape* out, int32_t max);
+cs_status cs_set_shape(cs_dtype dtype, int64_t n, const cs_shape* shape);
+cs_status cs_time_shape(cs_dtype dtype, const cs_op* op, const cs_shape* shape, int32_t reps, void* ws,
+                        size_t ws_bytes, hipStream_t stream, double* ms_per_apply);
+
 const char* cs_status_str(cs_status status);
 const char* cs_last_error(void);
 

@@ -20,7 +20,7 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-WORKERS = os.cpu_count() or 1
+WORKERS = int(os.environ.get("CS_ORACLE_WORKERS", 0)) or os.cpu_count() or 1   # scipy.fft threads
 
 
 def _dct_scale(k: np.ndarray, n: int) -> np.ndarray:

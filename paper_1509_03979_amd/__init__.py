@@ -26,7 +26,8 @@ CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4
 
 EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_ls_solve",
            "cs_adjoint_ls", "cs_workspace_size_batched", "cs_recover_ompr_batched", "cs_apply_A", "cs_apply_At",
-           "cs_status_str", "cs_last_error", "cs_prof_enable", "cs_prof_reset", "cs_prof_read")
+           "cs_shape_candidates", "cs_set_shape", "cs_time_shape", "cs_status_str", "cs_last_error",
+           "cs_prof_enable", "cs_prof_reset", "cs_prof_read")
 
 
 class cs_op(ctypes.Structure):
@@ -51,6 +52,14 @@ class cs_info(ctypes.Structure):
 class cs_batch_item(ctypes.Structure):
     _fields_ = [("op", cs_op), ("y", ctypes.c_void_p), ("s", ctypes.c_void_p), ("support", ctypes.c_void_p),
                 ("k", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class cs_shape(ctypes.Structure):
+    _fields_ = [("log_l1", ctypes.c_int32), ("log_l2", ctypes.c_int32), ("log_b", ctypes.c_int32),
+                ("log_e", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.log_l1, self.log_l2, self.log_b, self.log_e)
 
 
 class cs_prof_stat(ctypes.Structure):
@@ -93,6 +102,12 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, P(cs_op), vp, vp, vp, sz, vp]
         f.restype = ctypes.c_int
+    lib.cs_shape_candidates.argtypes = [ctypes.c_int, i64, P(cs_shape), i32]
+    lib.cs_shape_candidates.restype = ctypes.c_int
+    lib.cs_set_shape.argtypes = [ctypes.c_int, i64, P(cs_shape)]
+    lib.cs_set_shape.restype = ctypes.c_int
+    lib.cs_time_shape.argtypes = [ctypes.c_int, P(cs_op), P(cs_shape), i32, vp, sz, vp, P(dbl)]
+    lib.cs_time_shape.restype = ctypes.c_int
     lib.cs_status_str.argtypes = [ctypes.c_int]
     lib.cs_status_str.restype = ctypes.c_char_p
     lib.cs_last_error.argtypes = []
@@ -359,6 +374,29 @@ def cs_recover_ompr_batched(batch: "Batch", tol: float, stream=None, **kw):
                                      batch.ws.numel(), infos, _stream_ptr(stream))
     _check(st)
     return batch.s, batch.supp, [infos[i].as_dict() for i in range(n)]
+
+
+def cs_shape_candidates(dtype_code: int, n: int) -> list:
+    """Compiled four-step shapes (log_l1, log_l2, log_b, log_e) for N, the default first."""
+    cnt = lib.cs_shape_candidates(dtype_code, n, None, 0)
+    arr = (cs_shape * max(cnt, 1))()
+    cnt = lib.cs_shape_candidates(dtype_code, n, arr, cnt)
+    return [arr[i].as_tuple() for i in range(cnt)]
+
+
+def cs_set_shape(dtype_code: int, n: int, shape) -> None:
+    """Install a candidate shape for every later call at this N (None: the default)."""
+    _check(lib.cs_set_shape(dtype_code, n, ctypes.byref(cs_shape(*shape)) if shape is not None else None))
+
+
+def cs_time_shape(dtype_code: int, op: Operator, shape, reps: int = 20, ws=None, stream=None) -> float:
+    """Average ms of one H-apply (three transform passes) with `shape`."""
+    if ws is None:
+        ws = workspace(dtype_code, op, 1, CS_ALGO_OPERATOR)
+    ms = ctypes.c_double(0.0)
+    _check(lib.cs_time_shape(dtype_code, ctypes.byref(op.c), ctypes.byref(cs_shape(*shape)), int(reps), _ptr(ws),
+                             ws.numel(), _stream_ptr(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 def cs_apply_A(x, op: Operator, ws=None, stream=None):

@@ -2,6 +2,7 @@
 // entry points declared in include/cs.h.
 #include "cs_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -51,9 +52,18 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   c.cq = cv.take<T>(kk);
   c.cx2 = cv.take<T>(kk);
   c.cx3 = cv.take<T>(kk);
+  // partial buffers sized for every compiled shape of this N, so a workspace
+  // stays valid whichever shape is in use
+  int64_t rows = kRedBlocks, strips = kRedBlocks;
+  Shape cand[16];
+  const int nc = shape_candidates(sizeof(T) == 8 ? CS_F64 : CS_F32, p.logL, cand, 16);
+  for (int i = 0; i < nc; ++i) {
+    rows = std::max<int64_t>(rows, int64_t(1) << cand[i].logL1);
+    strips = std::max<int64_t>(strips, int64_t(1) << (cand[i].logL2 - cand[i].logB));
+  }
   c.partial = cv.take<double>(4 * kRedBlocks);
-  c.partial2 = cv.take<double>(std::max<int64_t>(kRedBlocks, p.L1));
-  c.pgrid = cv.take<double>(std::max<int64_t>(kRedBlocks, p.L2 >> p.logB));
+  c.partial2 = cv.take<double>(rows);
+  c.pgrid = cv.take<double>(strips);
   c.argpart = cv.take<ArgKey>(kArgBlocks);
   c.ibuf = cv.take<int32_t>(64);
   c.blockcnt = cv.take<uint32_t>((p.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords + 2);
@@ -80,10 +90,10 @@ size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo alg
 }
 
 template <typename T>
-void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s) {
+void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s, const Shape* force) {
   Plan p;
   const cs_dtype dt = sizeof(T) == 4 ? CS_F32 : CS_F64;
-  if (!choose_plan(dt, op->n, op->m, p)) throw Error(CS_E_SHAPE, "unsupported N");
+  if (!choose_plan(dt, op->n, op->m, p, force)) throw Error(CS_E_SHAPE, "unsupported N or shape");
   const size_t need = carve(c, p, kmax, nullptr);
   if (ws_bytes < need) throw Error(CS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   carve(c, p, kmax, (char*)ws);
@@ -97,6 +107,9 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   c.kmax = kmax;
   prepare_kernels<T>();
 }
+
+template void ctx_init<float>(Ctx<float>&, const cs_op*, int, void*, size_t, hipStream_t, const Shape*);
+template void ctx_init<double>(Ctx<double>&, const cs_op*, int, void*, size_t, hipStream_t, const Shape*);
 
 // ------------------------------------------------------------------ validation
 static void check_shape(cs_dtype dt, const cs_op* op, int32_t k, cs_algo algo) {
@@ -308,6 +321,37 @@ static void adj_t(const cs_op* op, const int32_t* support, int32_t k, const void
   }
 }
 
+// Average time of one H-apply (forward column pass, row pass, inverse column
+// pass on a dense N-vector) with the given shape.
+template <typename T>
+static double time_shape_t(const cs_op* op, const Shape& sh, int reps, void* ws, size_t ws_bytes,
+                           hipStream_t stream) {
+  Ctx<T> c{};
+  ctx_init<T>(c, op, 1, ws, ws_bytes, stream, &sh);
+  setup_operator<T>(c);
+  fill<T>(c.Dd, c.plan.n, (T)0, stream);
+  auto happly = [&]() {
+    launch_col<T>(c, (const Cx<T>*)c.Dd, c.W, false, col_io<T>(c, COL_DENSE, nullptr));
+    launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, nullptr);
+    launch_col<T>(c, c.W, c.W, true, col_io<T>(c, COL_DENSE, nullptr));
+  };
+  happly();
+  happly();
+  hipEvent_t a = nullptr, b = nullptr;
+  CS_HIP(hipEventCreate(&a));
+  CS_HIP(hipEventCreate(&b));
+  CS_HIP(hipEventRecord(a, stream));
+  for (int i = 0; i < reps; ++i) happly();
+  CS_HIP(hipEventRecord(b, stream));
+  CS_HIP(hipEventSynchronize(b));
+  float ms = 0.f;
+  CS_HIP(hipEventElapsedTime(&ms, a, b));
+  CS_HIP(hipEventDestroy(a));
+  CS_HIP(hipEventDestroy(b));
+  if (prof_on()) prof_flush();
+  return (double)ms / reps;
+}
+
 template <typename T>
 static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, void* ws, size_t ws_bytes,
                     hipStream_t stream) {
@@ -462,6 +506,55 @@ cs_status cs_apply_A(cs_dtype dtype, const cs_op* op, const void* x, void* out, 
 cs_status cs_apply_At(cs_dtype dtype, const cs_op* op, const void* u, void* out, void* ws, size_t ws_bytes,
                       hipStream_t stream) {
   return apply_entry(true, dtype, op, u, out, ws, ws_bytes, stream);
+}
+
+static int log2_exact(int64_t n) {
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l;
+}
+
+int cs_shape_candidates(cs_dtype dtype, int64_t n, cs_shape* out, int32_t max) {
+  if ((dtype != CS_F32 && dtype != CS_F64) || n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) return 0;
+  Shape tmp[16];
+  const int cnt = shape_candidates(dtype, log2_exact(n) - 1, tmp, 16);
+  if (!out) return cnt;
+  const int w = std::min<int>(cnt, std::max<int32_t>(max, 0));
+  for (int i = 0; i < w; ++i) out[i] = cs_shape{tmp[i].logL1, tmp[i].logL2, tmp[i].logB, tmp[i].logE};
+  return w;
+}
+
+cs_status cs_set_shape(cs_dtype dtype, int64_t n, const cs_shape* shape) {
+  if ((dtype != CS_F32 && dtype != CS_F64) || n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) {
+    g_last_error = "N must be a power of two in [16, 2^26] and dtype CS_F32 or CS_F64";
+    return CS_E_SHAPE;
+  }
+  Shape sh{0, 0, 0, 0};
+  if (shape) sh = Shape{shape->log_l1, shape->log_l2, shape->log_b, shape->log_e};
+  if (!set_shape_override(dtype, log2_exact(n) - 1, shape ? &sh : nullptr)) {
+    g_last_error = "shape is not one of cs_shape_candidates() for this N";
+    return CS_E_SHAPE;
+  }
+  return CS_OK;
+}
+
+cs_status cs_time_shape(cs_dtype dtype, const cs_op* op, const cs_shape* shape, int32_t reps, void* ws,
+                        size_t ws_bytes, hipStream_t stream, double* ms_per_apply) {
+  try {
+    check_shape(dtype, op, 1, CS_ALGO_OPERATOR);
+    if (!shape || !ms_per_apply || reps < 1) throw Error(CS_E_INVALID, "null shape or result, or reps < 1");
+    check_ws(ws);
+    const Shape sh{shape->log_l1, shape->log_l2, shape->log_b, shape->log_e};
+    *ms_per_apply = (dtype == CS_F32) ? time_shape_t<float>(op, sh, reps, ws, ws_bytes, stream)
+                                      : time_shape_t<double>(op, sh, reps, ws, ws_bytes, stream);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
 }
 
 const char* cs_status_str(cs_status status) {

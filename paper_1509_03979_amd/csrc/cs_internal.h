@@ -65,6 +65,13 @@ template <typename T>
 __device__ __forceinline__ Cx<T> scale(Cx<T> a, T s) { return cx(a.re * s, a.im * s); }
 
 // ------------------------------------------------------------------ plan
+// Four-step shape of the N/2-point complex FFT: L1 = 2^logL1 rows of
+// L2 = 2^logL2, column strips of 2^logB columns, 2^logE elements per thread.
+struct Shape {
+  int logL1, logL2, logB;
+  int logE;               // log2 of the elements each thread holds (caps the radix)
+};
+
 // Everything the transform kernels need for one N, passed by value.
 struct Plan {
   int64_t n, m;
@@ -320,11 +327,19 @@ void prof_end(int cls, double bytes, hipEvent_t start, hipStream_t s);
 void prof_flush();
 
 // ------------------------------------------------------------------ plan/workspace
-bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p);
+// Plan for N: the shape given in `force`, else the process-wide choice for
+// this N (set_shape_override), else the default.  False if N or the shape is
+// unsupported.
+bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p, const Shape* force = nullptr);
+// Compiled shapes for L = 2^l, the default first; returns how many (<= max).
+int shape_candidates(cs_dtype dt, int l, Shape* out, int max);
+// Installs (s != nullptr) or clears the process-wide shape for L = 2^l.
+bool set_shape_override(cs_dtype dt, int l, const Shape* s);
 size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo);
 
 template <typename T>
-void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s);
+void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s,
+              const Shape* force = nullptr);
 
 // ------------------------------------------------------------------ transform launchers
 enum RowMode { ROW_HAPPLY = 0, ROW_RESID = 1, ROW_FWD = 2, ROW_ADJ = 3 };

@@ -17,10 +17,6 @@
 namespace csr {
 
 // ------------------------------------------------------------------ shapes
-struct Shape {
-  int logL1, logL2, logB;
-  int logE;               // log2 of the elements each thread holds (caps the radix)
-};
 
 // Four-step split for an L = 2^l point complex FFT (N = 2^(l+1) real points).
 // Measured on MI355X: what matters most is that two or more workgroups of
@@ -541,8 +537,11 @@ struct KernelSet {
 
 // Kernel set for L = 2^l (defined in the per-type instantiation units).
 template <typename T> const KernelSet<T>& kernels_for(int l);
-// Kernel set of an alternative instantiated shape, or nullptr.
-template <typename T> const KernelSet<T>* kernels_alt(Shape s);
+// Kernel set of an alternative instantiated shape, or nullptr.  With
+// list_out, instead lists (up to *list_max, count returned in *list_max) the
+// alternatives for the same L as s.
+template <typename T>
+const KernelSet<T>* kernels_alt(Shape s, Shape* list_out = nullptr, int* list_max = nullptr);
 
 template <typename T>
 inline const KernelSet<T>& kernels_plan(const Plan& p) {

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -30,7 +31,40 @@ void hip_check(hipError_t e, const char* what, const char* file, int line) {
 }
 
 // ------------------------------------------------------------------ plan
-bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p) {
+namespace {
+std::mutex g_shape_mu;
+Shape g_shape_over[2][kMaxL + 1];   // [FP64][log2 L]; logL1 == 0: no override
+}  // namespace
+
+static bool same_shape(const Shape& a, const Shape& b) {
+  return a.logL1 == b.logL1 && a.logL2 == b.logL2 && a.logB == b.logB && a.logE == b.logE;
+}
+
+static bool shape_compiled(cs_dtype dt, const Shape& s) {
+  if (s.logL1 + s.logL2 < kMinL || s.logL1 + s.logL2 > kMaxL) return false;
+  if (same_shape(s, shape_for(dt == CS_F64, s.logL1 + s.logL2))) return true;
+  return (dt == CS_F32) ? kernels_alt<float>(s) != nullptr : kernels_alt<double>(s) != nullptr;
+}
+
+int shape_candidates(cs_dtype dt, int l, Shape* out, int max) {
+  if (max < 1 || l < kMinL || l > kMaxL) return 0;
+  out[0] = shape_for(dt == CS_F64, l);
+  int cnt = max - 1;
+  const Shape probe{l / 2, l - l / 2, 0, 0};
+  if (dt == CS_F32) kernels_alt<float>(probe, out + 1, &cnt);
+  else kernels_alt<double>(probe, out + 1, &cnt);
+  return 1 + cnt;
+}
+
+bool set_shape_override(cs_dtype dt, int l, const Shape* s) {
+  if (l < kMinL || l > kMaxL) return false;
+  if (s && (s->logL1 + s->logL2 != l || !shape_compiled(dt, *s))) return false;
+  std::lock_guard<std::mutex> g(g_shape_mu);
+  g_shape_over[dt == CS_F64][l] = s ? *s : Shape{0, 0, 0, 0};
+  return true;
+}
+
+bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p, const Shape* force) {
   if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) return false;
   p = Plan{};
   p.n = n;
@@ -40,12 +74,24 @@ bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p) {
   while ((int64_t(1) << p.logn) < n) ++p.logn;
   p.L = n / 2;
   p.logL = p.logn - 1;
-  Shape sh = shape_for(dt == CS_F64, p.logL);
+  const Shape def = shape_for(dt == CS_F64, p.logL);
+  Shape sh = def;
+  {
+    // process-wide choice (the autotuner's), else the default
+    std::lock_guard<std::mutex> g(g_shape_mu);
+    const Shape& o = g_shape_over[dt == CS_F64][p.logL];
+    if (o.logL1 != 0) sh = o;
+  }
+  if (force) {
+    if (force->logL1 + force->logL2 != p.logL || !shape_compiled(dt, *force)) return false;
+    sh = *force;
+  }
+  if (!same_shape(sh, def)) p.alt = 1;
   // Tuning override "logL1,logL2,logB,logE" (must multiply to this L and be instantiated).
   if (const char* ov = std::getenv("CS_SHAPE")) {
     Shape o{0, 0, 0, 0};
-    if (std::sscanf(ov, "%d,%d,%d,%d", &o.logL1, &o.logL2, &o.logB, &o.logE) == 4 && o.logL1 + o.logL2 == p.logL &&
-        !(o.logL1 == sh.logL1 && o.logL2 == sh.logL2 && o.logB == sh.logB && o.logE == sh.logE)) {
+    if (!force && std::sscanf(ov, "%d,%d,%d,%d", &o.logL1, &o.logL2, &o.logB, &o.logE) == 4 &&
+        o.logL1 + o.logL2 == p.logL && !same_shape(o, def)) {
       const bool ok = (dt == CS_F32) ? kernels_alt<float>(o) != nullptr : kernels_alt<double>(o) != nullptr;
       if (ok) { sh = o; p.alt = 1; }
     }

@@ -115,6 +115,12 @@ WORKLOADS = {
 }
 
 
+# The batched workload: 256 signals with their own sizes (batched_sizes),
+# N(0,1) nonzeros, 30 dB noise, FP32, OMPR, CG tol 1e-6.
+BATCHED_WORKLOAD = dict(cfg=4, count=256, log_n=(14, 18), values="normal", snr_db=30.0, dtype="f32", tol=1e-6,
+                        algos=("ompr",))
+
+
 def workload_problem(name: str, sig: int = 0) -> Draw:
     w = WORKLOADS[name]
     return draw_problem(w["cfg"], sig, w["n"], w["m"], w["k"], w["values"], w["snr_db"])

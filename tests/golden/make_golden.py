@@ -2,6 +2,7 @@
 
     python tests/golden/make_golden.py sp_ompr_n2p20      # SP and OMPR, N = 2^20
     python tests/golden/make_golden.py sp_n2p24           # SP, N = 2^24 (noiseless)
+    python tests/golden/make_golden.py ompr_batched_256 6 # batched OMPR, 256 signals, 6 processes
 
 Each file holds the measurements the GPU consumes (float32 y, from the
 oracle's FP64 y = A s + noise; only up to N = 2^20, larger workloads recompute
@@ -58,7 +59,60 @@ def run(name: str, sig: int = 0, store_y: bool = True):
     print("wrote", path)
 
 
+def _batched_one(args):
+    """Oracle OMPR on one signal of the batched workload (least squares by the
+    oracle's FP64 CG route, tol 1e-13; cross-checked against the explicit
+    routes by the pins)."""
+    cfg, sig, part_dir = args
+    path = os.path.join(part_dir, f"sig{sig:03d}.npz")
+    if os.path.exists(path):
+        return sig
+    d = synth.batched_problem(sig, cfg)
+    op = oracle.SRM(d.n, d.rows, d.signs)
+    y0 = op.apply_sparse(d.supp, d.vals)
+    y = (y0 + d.noise_scale(np.linalg.norm(y0)) * d.noise).astype(np.float32)
+    t = time.perf_counter()
+    r = oracle.ompr(op, y.astype(np.float64), d.k, ls_route="cg")
+    dt = time.perf_counter() - t
+    margins = [m for (_, _, m) in r.trace]
+    meta = {"sig": sig, "n": d.n, "m": d.m, "k": d.k, "stop": r.stop, "iters": int(r.iters),
+            "resid_norm": r.resid_norm, "min_margin": float(min(margins)) if margins else None, "seconds": dt,
+            "y_norm": float(np.linalg.norm(y.astype(np.float64))), "y_sum": float(np.sum(y.astype(np.float64)))}
+    np.savez(path + ".tmp.npz", meta=json.dumps(meta), support=r.support.astype(np.int32), values=r.s[r.support])
+    os.replace(path + ".tmp.npz", path)
+    print("batched sig", sig, meta, flush=True)
+    return sig
+
+
+def run_batched(count: int = 256, cfg: int = 4, procs: int = 6, part_dir: str | None = None):
+    """All signals of the batched OMPR workload, largest first, in `procs`
+    processes; per-signal parts are kept in part_dir so a run can resume, then
+    packed into one file (concatenated supports and values + per-signal meta)."""
+    import multiprocessing as mp
+    part_dir = part_dir or os.path.join(ROOT, "_work", "golden_batched_parts")
+    os.makedirs(part_dir, exist_ok=True)
+    sizes = synth.batched_sizes(count, cfg)
+    order = sorted(range(count), key=lambda i: -sizes[i][0] * sizes[i][2])
+    with mp.get_context("spawn").Pool(procs) as pool:
+        for _ in pool.imap_unordered(_batched_one, [(cfg, i, part_dir) for i in order]):
+            pass
+    metas, supps, vals = [], [], []
+    for sig in range(count):
+        z = np.load(os.path.join(part_dir, f"sig{sig:03d}.npz"), allow_pickle=False)
+        metas.append(json.loads(str(z["meta"])))
+        supps.append(z["support"])
+        vals.append(z["values"])
+    offs = np.cumsum([0] + [s.size for s in supps]).astype(np.int64)
+    path = os.path.join(OUT, f"ompr_batched_{count}.npz")
+    np.savez_compressed(path, meta=json.dumps({"cfg": cfg, "count": count, "ls_route": "cg", "signals": metas}),
+                        offsets=offs, support=np.concatenate(supps), values=np.concatenate(vals))
+    print("wrote", path)
+
+
 if __name__ == "__main__":
+    if sys.argv[1:2] == ["ompr_batched_256"]:
+        run_batched(256, 4, int(sys.argv[2]) if len(sys.argv) > 2 else 6)
+        sys.exit(0)
     # y is stored for workloads small enough to keep in the repository (N <= 2^20);
     # larger ones recompute it with the oracle (measurements()).
     for nm in sys.argv[1:]:

@@ -129,3 +129,59 @@ def test_adjoint_validation():
     assert call(wsb=64) == cs.CS_E_WORKSPACE
     o2 = cs.cs_op(1000, 256, FAKE, FAKE)
     assert call(op=ctypes.byref(o2)) == cs.CS_E_SHAPE
+
+
+def test_shape_tuning_abi():
+    for n in (16, 2 ** 14, 2 ** 18, 2 ** 20, 2 ** 24, 2 ** 26):
+        for dt in (cs.CS_F32, cs.CS_F64):
+            cand = cs.cs_shape_candidates(dt, n)
+            assert cand, (n, dt)
+            l = n.bit_length() - 2                       # log2(N / 2)
+            assert all(a + b == l for a, b, _, _ in cand)
+            assert len(set(cand)) == len(cand)
+            for sh in cand:                              # every candidate installs, then the default returns
+                cs.cs_set_shape(dt, n, sh)
+            cs.cs_set_shape(dt, n, None)
+    assert cs.lib.cs_shape_candidates(cs.CS_F32, 1000, None, 0) == 0
+    assert cs.lib.cs_shape_candidates(7, 1024, None, 0) == 0
+    with pytest.raises(cs.CSError):
+        cs.cs_set_shape(cs.CS_F32, 2 ** 16, (9, 7, 2, 2))   # 9 + 7 is not log2(N/2) = 15
+    with pytest.raises(cs.CSError):
+        cs.cs_set_shape(cs.CS_F32, 2 ** 16, (8, 7, 0, 1))   # not compiled
+    o = cs.cs_op(1 << 16, 100, FAKE, FAKE)
+    ms = ctypes.c_double()
+    sh = cs.cs_shape(8, 7, 2, 2)
+    assert cs.lib.cs_time_shape(cs.CS_F32, ctypes.byref(o), None, 5, ctypes.c_void_p(FAKE), 1 << 30, None,
+                                ctypes.byref(ms)) == cs.CS_E_INVALID
+    assert cs.lib.cs_time_shape(cs.CS_F32, ctypes.byref(o), ctypes.byref(sh), 0, ctypes.c_void_p(FAKE), 1 << 30,
+                                None, ctypes.byref(ms)) == cs.CS_E_INVALID
+    assert cs.lib.cs_time_shape(cs.CS_F32, ctypes.byref(o), ctypes.byref(sh), 5, ctypes.c_void_p(FAKE), 10, None,
+                                ctypes.byref(ms)) == cs.CS_E_WORKSPACE
+
+
+def test_batched_validation():
+    items = (cs.cs_batch_item * 2)()
+    for i in range(2):
+        items[i].op = cs.cs_op(1024, 256, FAKE, FAKE)
+        items[i].y = items[i].s = items[i].support = FAKE
+        items[i].k = 10
+    f = cs.lib.cs_recover_ompr_batched
+    ok = cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_OMPR)
+    assert ok > 2 * cs.cs_workspace_size(cs.CS_F32, 1024, 256, 10, cs.CS_ALGO_OMPR)
+    assert cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_SP) == 0
+    assert cs.lib.cs_workspace_size_batched(cs.CS_F32, 0, items, cs.CS_ALGO_OMPR) == 0
+    ws = ctypes.c_void_p(FAKE)
+    assert f(cs.CS_F32, 0, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_INVALID
+    assert f(cs.CS_F32, 2, None, 1e-6, None, ws, ok, None, None) == cs.CS_E_INVALID
+    assert f(cs.CS_F32, 2, items, 0.0, None, ws, ok, None, None) == cs.CS_E_INVALID
+    assert f(cs.CS_F32, 2, items, 1e-6, None, None, ok, None, None) == cs.CS_E_WORKSPACE
+    prm = cs.cs_params(0, 0, 1, 100, 0.0)                  # cg_block not a multiple of 64
+    assert f(cs.CS_F32, 2, items, 1e-6, ctypes.byref(prm), ws, ok, None, None) == cs.CS_E_INVALID
+    items[1].k = 300                                      # K > M
+    assert f(cs.CS_F32, 2, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_SHAPE
+    items[1].k = 10
+    items[1].op = cs.cs_op(1000, 256, FAKE, FAKE)         # N not a power of two
+    assert f(cs.CS_F32, 2, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_SHAPE
+    items[1].op = cs.cs_op(1024, 256, FAKE, FAKE)
+    items[0].y = None
+    assert f(cs.CS_F32, 2, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_INVALID
