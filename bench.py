@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched OMPR leg (256 signals)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated SP leg (64 signals)")
     ap.add_argument("--no-single-loop", action="store_true", help="batched leg: skip the single-signal loop")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="end with three plain device copies of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -349,6 +351,12 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, "extra": extra,
     }
     print(json.dumps(line), flush=True)
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

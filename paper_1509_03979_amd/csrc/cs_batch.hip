@@ -6,16 +6,18 @@
 // stage along the OMPR loop of the single-signal driver:
 //   WARM    r = b - H x (warm start), r^T r, CG set-up
 //   ITER    one CG iteration (Algorithm 1 lines 16-23)
-//   RESID   r = y - A x, ||r|| and the correlation F^T D^T r
-//   SELECT  argmax outside the support, the drop step, the swap and the new
-//           support's list, prefix counts, remapped x and right-hand side
+//   RESID   r = y - A x, ||r||, the correlation F^T D^T r and its argmax
+//   SELECT  the stop tests, the drop step and the swap: the new support's
+//           list, prefix counts, remapped x and right-hand side
 // with the same decision rules, so each signal follows the path the
 // single-signal OMPR takes.  A step is a fixed sequence of launches: the three
 // transform passes once per size class (the signal in blockIdx.y, its shape a
-// template parameter), then one CG kernel and the selection kernels over all
-// signals, each returning at once for signals in another phase.  The host
-// captures several steps in a HIP graph and replays it until a device counter
-// of unfinished signals reads zero.
+// template parameter), then two per-signal kernels (CG / residual / argmax,
+// then the swap), each returning at once for signals in another phase.  The
+// host captures several steps and a compaction of the still-running signals
+// in a HIP graph and replays it until none is left, capturing a smaller
+// graph over the running signals once half of them, or a whole size class,
+// have stopped.
 #include "cs_device.h"
 #include "cs_kernels.h"
 
@@ -27,7 +29,13 @@
 
 namespace csr {
 
-constexpr int kBArgBlocks = 64;   // argmax blocks per signal
+constexpr int kBArgBlocks = 64;   // most argmax blocks per signal (fits the argpart buffer)
+
+// argmax blocks of a signal: one per 4096 candidates, 1 .. kBArgBlocks
+__host__ __device__ __forceinline__ int arg_blocks(int64_t n) {
+  const int64_t b = n >> 12;
+  return (int)(b < 1 ? 1 : (b > kBArgBlocks ? kBArgBlocks : b));
+}
 constexpr int kBSteps = 8;        // batched steps per graph replay
 
 // x = 0 and b = C0 on the initial support; b^T b
@@ -52,18 +60,36 @@ __global__ void k_b_start(const BSig<T>* __restrict__ sigs) {
   }
 }
 
-// Per-signal scalar work after the transform passes of a step (one block per
-// signal): the CG start (WARM), the CG update (ITER), the residual norm (RESID).
+// Per-signal scalar work after the transform passes of a step.  Block 0 of
+// each signal: the CG start (WARM), the CG update (ITER) or the residual norm
+// (RESID, then SELECT).  Every block of a signal whose correlation is fresh
+// (phase RESID, or SELECT once block 0 has moved it on) also computes its
+// share of the argmax of |c| outside the support.  ids[blockIdx.y] picks the
+// signal.
 template <typename T>
-__global__ void k_b_post(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.x];
+__global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __restrict__ ids) {
+  const BSig<T>& s = sigs[ids[blockIdx.y]];
   BState* st = s.st;
   const int phase = st->phase;
   if (phase > BP_RESID) return;
   const Plan& p = s.plan;
+  const int tid = threadIdx.x;
+  const int nab = arg_blocks(p.n);
+  if (phase == BP_RESID && (int)blockIdx.x < nab) {
+    ArgKey best{0, 0, 0};
+    const int64_t stp = (int64_t)nab * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + tid; q < p.n; q += stp) {
+      if (bit_of(s.bits, q)) continue;
+      const int64_t j = nat_of_key(q, p);
+      ArgKey kk{mag_bits(s.Cc[q]) + 1, 0xFFFFFFFFu - (uint32_t)j, 0};
+      if (key_gt(kk, best)) best = kk;
+    }
+    best = block_max_key(best);
+    if (tid == 0) s.argpart[blockIdx.x] = best;
+  }
+  if (blockIdx.x != 0) return;
   CgScalars* cg = s.cg;
   const int k = st->k;
-  const int tid = threadIdx.x;
   const double nb = (double)p.n * sizeof(T), kb = (double)k, esz = (double)sizeof(T);
   if (phase == BP_WARM) {
     const int ncol = (int)(p.L2 >> p.logB);
@@ -146,38 +172,25 @@ __global__ void k_b_post(const BSig<T>* __restrict__ sigs) {
   }
 }
 
-// argmax of |c| outside the support: per-signal partials
+// One OMPR swap per signal (one block of 1024 threads): the entering index j
+// (argmax partials), the stop tests, the drop step, then the new support
+// edited in place of a rebuild: bitmap bits, the ascending key list and
+// prefix counts with one key out and one in, the warm-start x (the shared
+// keys keep their values, the new one starts at 0) and b = C0 on the new list.
 template <typename T>
-__global__ void k_b_argmax(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.y];
-  if (s.st->phase != BP_SELECT) return;
-  const Plan& pl = s.plan;
-  ArgKey best{0, 0, 0};
-  const int64_t stp = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < pl.n; q += stp) {
-    if (bit_of(s.bits, q)) continue;
-    const int64_t j = nat_of_key(q, pl);
-    ArgKey kk{mag_bits(s.Cc[q]) + 1, 0xFFFFFFFFu - (uint32_t)j, 0};
-    if (key_gt(kk, best)) best = kk;
-  }
-  best = block_max_key(best);
-  if (threadIdx.x == 0) s.argpart[blockIdx.x] = best;
-}
-
-// The OMPR decision of one swap (one block of 1024 threads per signal): the
-// entering index j, the stop tests, the drop step and the bitmap update.
-template <typename T>
-__global__ void k_b_select(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.x];
+__global__ void k_b_select(const BSig<T>* __restrict__ sigs, const int32_t* __restrict__ ids) {
+  const BSig<T>& s = sigs[ids[blockIdx.x]];
   BState* st = s.st;
   if (st->phase != BP_SELECT) return;
-  __shared__ int32_t sj;
+  __shared__ int32_t sj, sd, spd, spj;
   __shared__ int go;
+  const int tid = threadIdx.x;
   ArgKey best{0, 0, 0};
-  for (int i = threadIdx.x; i < kBArgBlocks; i += blockDim.x)
+  const int nab = arg_blocks(s.plan.n);
+  for (int i = tid; i < nab; i += blockDim.x)
     if (key_gt(s.argpart[i], best)) best = s.argpart[i];
   best = block_max_key(best);
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     const int32_t j = best.hi ? (int32_t)(0xFFFFFFFFu - best.lo) : -1;
     go = 0;
     if (st->swaps >= st->max_outer) {
@@ -192,104 +205,106 @@ __global__ void k_b_select(const BSig<T>* __restrict__ sigs) {
   }
   __syncthreads();
   if (!go) return;
-  const int cur = st->cur;
-  const int32_t d = ompr_drop_body<T>(s.cx[cur], s.list[cur], st->k, s.Cc, s.plan, (T)st->eta, sj);
-  if (threadIdx.x == 0) {
+  const int cur = st->cur, nxt = cur ^ 1, k = st->k;
+  const int32_t d = ompr_drop_body<T>(s.cx[cur], s.list[cur], k, s.Cc, s.plan, (T)st->eta, sj);
+  if (tid == 0) {
+    sd = d;
+    go = d != sj;
     st->jd[0] = sj;
     st->jd[1] = d;
-    if (d == sj) {
-      st->phase = BP_DONE;
-    } else {
-      const uint32_t pj = (uint32_t)key_of_nat(sj, s.plan), pd = (uint32_t)key_of_nat(d, s.plan);
-      s.bits[pd >> 5] &= ~(1u << (pd & 31));
-      s.bits[pj >> 5] |= 1u << (pj & 31);
-      st->swaps += 1;
-    }
+    if (!go) st->phase = BP_DONE;
+    spd = -1;
+    spj = 0;
   }
-}
-
-// new support list and prefix counts in slot cur ^ 1
-template <typename T>
-__global__ void k_b_bits_count(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.y];
-  if (s.st->phase != BP_SELECT) return;
-  const int64_t words = s.plan.words;
-  if ((int64_t)blockIdx.x * kBitsPerBlockWords >= words) return;
-  bits_count_body(s.bits, words, s.blockcnt, blockIdx.x);
-}
-template <typename T>
-__global__ void k_b_bits_scan(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.x];
-  if (s.st->phase != BP_SELECT) return;
-  bits_scan_body(s.blockcnt, (int)((s.plan.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords));
-}
-template <typename T>
-__global__ void k_b_bits_write(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.y];
-  const BState* st = s.st;
-  if (st->phase != BP_SELECT) return;
-  const int64_t words = s.plan.words;
-  if ((int64_t)blockIdx.x * kBitsPerBlockWords >= words) return;
-  const int nxt = st->cur ^ 1;
-  bits_write_body(s.bits, words, s.blockcnt, s.list[nxt], st->k, s.wpre[nxt], blockIdx.x);
-}
-
-// warm start: x_new[i] = x_old at the same key, 0 for the new index
-template <typename T>
-__global__ void k_b_remap(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.y];
-  const BState* st = s.st;
-  if (st->phase != BP_SELECT) return;
-  const int k = st->k;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k) return;
-  const int cur = st->cur, nxt = cur ^ 1;
-  const int32_t* from = s.list[cur];
-  const int32_t key = s.list[nxt][i];
-  T v = (T)0;
-  if (st->warm) {
-    int lo = 0, hi = k - 1;
-    while (lo <= hi) {
-      const int mid = (lo + hi) >> 1;
-      const int32_t m = from[mid];
-      if (m == key) { v = s.cx[cur][mid]; break; }
-      if (m < key) lo = mid + 1; else hi = mid - 1;
-    }
+  __syncthreads();
+  if (!go) return;
+  const int32_t kj = (int32_t)key_of_nat(sj, s.plan), kd = (int32_t)key_of_nat(sd, s.plan);
+  const int32_t* old = s.list[cur];
+  // pd: slot of kd in the old list; pj: old keys below kj (kj is not in it)
+  for (int i = tid; i < k; i += blockDim.x) {
+    const int32_t v = old[i];
+    if (v == kd) spd = i;
+    if (v < kj && (i + 1 == k || old[i + 1] > kj)) spj = i + 1;
   }
-  s.cx[nxt][i] = v;
-}
-
-// switch to the new support: b = C0 on it, b^T b, next solve
-template <typename T>
-__global__ void k_b_finish(const BSig<T>* __restrict__ sigs) {
-  const BSig<T>& s = sigs[blockIdx.x];
-  BState* st = s.st;
-  if (st->phase != BP_SELECT) return;
-  const int k = st->k, nxt = st->cur ^ 1;
-  const int32_t* list = s.list[nxt];
+  __syncthreads();
+  const int pd = spd, pj = spj;
+  if (pd < 0) {              // the dropped index is always on the support; stop rather than read past the list
+    if (tid == 0) st->phase = BP_DONE;
+    return;
+  }
+  const int q = pj - (pd < pj ? 1 : 0);          // slot of kj in the new list
+  int32_t* nl = s.list[nxt];
+  const T* xo = s.cx[cur];
+  T* xn = s.cx[nxt];
+  const bool warm = st->warm != 0;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < k; i += blockDim.x) {
-    const T v = s.C0[list[i]];
-    s.cb[i] = v;
-    acc += (double)v * (double)v;
+  for (int i = tid; i < k; i += blockDim.x) {
+    int32_t key;
+    T xv = (T)0;
+    if (i == q) {
+      key = kj;
+    } else {
+      const int r = i - (i > q ? 1 : 0);         // slot in the old list without kd
+      const int o = r + (r >= pd ? 1 : 0);
+      key = old[o];
+      if (warm) xv = xo[o];
+    }
+    nl[i] = key;
+    xn[i] = xv;
+    const T bv = s.C0[key];
+    s.cb[i] = bv;
+    acc += (double)bv * (double)bv;
   }
-  acc = block_sum_any(acc);
-  if (threadIdx.x == 0) {
+  // prefix counts: words after kj's word gain one, words after kd's lose one
+  const int64_t words = s.plan.words;
+  const int64_t wj = kj >> 5, wd = kd >> 5;
+  const uint32_t* wo = s.wpre[cur];
+  uint32_t* wn = s.wpre[nxt];
+  for (int64_t w = tid; w < words; w += blockDim.x) wn[w] = wo[w] + (w > wj ? 1u : 0u) - (w > wd ? 1u : 0u);
+  const double bb = block_sum_any(acc);
+  if (tid == 0) {
+    s.bits[kd >> 5] &= ~(1u << (kd & 31));
+    s.bits[kj >> 5] |= 1u << (kj & 31);
+    st->swaps += 1;
     st->cur = nxt;
-    st->bb = acc;
+    st->bb = bb;
     st->phase = BP_WARM;
   }
 }
 
-__global__ void k_b_active(const BState* __restrict__ st, int count, int32_t* __restrict__ out) {
-  __shared__ int32_t tot;
-  if (threadIdx.x == 0) tot = 0;
+// Compacts the ids of unfinished signals (kept in class order) and counts
+// them per class: out_cnt[c] for class c, out_cnt[ncls] in total.  One block
+// of 1024 threads.
+__global__ void k_b_compact(const BState* __restrict__ st, const int32_t* __restrict__ ids,
+                            const int32_t* __restrict__ cls_of, int cnt, int ncls, int32_t* __restrict__ out_ids,
+                            int32_t* __restrict__ out_cnt) {
+  __shared__ int32_t scan[1024];
+  __shared__ int32_t carry;
+  __shared__ int32_t ccnt[64];
+  const int tid = threadIdx.x;
+  if (tid == 0) carry = 0;
+  for (int c = tid; c < 64; c += blockDim.x) ccnt[c] = 0;
   __syncthreads();
-  int32_t n = 0;
-  for (int i = threadIdx.x; i < count; i += blockDim.x) n += st[i].phase != BP_DONE;
-  if (n) atomicAdd(&tot, n);
-  __syncthreads();
-  if (threadIdx.x == 0) *out = tot;
+  for (int base = 0; base < cnt; base += 1024) {
+    const int i = base + tid;
+    const int32_t id = (i < cnt) ? ids[i] : -1;
+    const int a = (i < cnt && st[id].phase != BP_DONE) ? 1 : 0;
+    if (a) atomicAdd(&ccnt[cls_of[i]], 1);
+    scan[tid] = a;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t t = tid >= off ? scan[tid - off] : 0;
+      __syncthreads();
+      scan[tid] += t;
+      __syncthreads();
+    }
+    if (a) out_ids[carry + scan[tid] - 1] = id;
+    __syncthreads();
+    if (tid == 1023) carry += scan[1023];
+    __syncthreads();
+  }
+  for (int c = tid; c < ncls; c += blockDim.x) out_cnt[c] = ccnt[c];
+  if (tid == 0) out_cnt[ncls] = carry;
 }
 
 // ------------------------------------------------------------------ host driver
@@ -306,8 +321,8 @@ size_t batch_layout(cs_dtype dt, int count, const cs_batch_item* items, std::vec
   }
   off = align256(off) + align256((size_t)count * sizeof(BSig<double>));
   off += align256((size_t)count * sizeof(BState));
-  off += align256((size_t)count * sizeof(int32_t));
-  off += 256;   // unfinished-signal counter
+  off += 3 * align256((size_t)count * sizeof(int32_t));   // active ids, their classes, compacted ids
+  off += 256;                                              // per-class counts (at most 64 classes)
   return off;
 }
 
@@ -328,15 +343,17 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
   off += align256((size_t)count * sizeof(BState));
   int32_t* d_ids = (int32_t*)(base + off);
   off += align256((size_t)count * sizeof(int32_t));
-  int32_t* d_active = (int32_t*)(base + off);
+  int32_t* d_cls = (int32_t*)(base + off);
+  off += align256((size_t)count * sizeof(int32_t));
+  int32_t* d_act = (int32_t*)(base + off);
+  off += align256((size_t)count * sizeof(int32_t));
+  int32_t* d_cnt = (int32_t*)(base + off);
 
   // per-signal set-up on the single-signal code: operator tables, y, A^T y,
   // the initial top-K support
   std::vector<Ctx<T>> cs(count);
   std::vector<BSig<T>> hs(count);
   std::vector<BState> hst(count);
-  int kmax = 1;
-  int64_t nbw = 1;
   for (int i = 0; i < count; ++i) {
     const cs_batch_item& it = items[i];
     Ctx<T>& c = cs[i];
@@ -370,82 +387,106 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
     b.ynorm = c.ynorm;
     b.model_bytes = c.model_bytes;
     b.transforms = c.transforms;
-    kmax = std::max(kmax, it.k);
-    nbw = std::max<int64_t>(nbw, (c.plan.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords);
   }
   // size classes: signals with the same N share the transform kernels
-  std::map<int, std::vector<int32_t>> cls;
-  for (int i = 0; i < count; ++i) cls[cs[i].plan.logn].push_back(i);
-  std::vector<int32_t> ids;
-  struct Cls { int first, cnt; Plan plan; };
-  std::vector<Cls> cl;
-  for (auto& kv : cls) {
-    cl.push_back(Cls{(int)ids.size(), (int)kv.second.size(), cs[kv.second[0]].plan});
-    ids.insert(ids.end(), kv.second.begin(), kv.second.end());
+  std::map<int, int> cls_index;
+  for (int i = 0; i < count; ++i) cls_index[cs[i].plan.logn] = 0;
+  std::vector<Plan> cls_plan;
+  for (auto& kv : cls_index) {
+    kv.second = (int)cls_plan.size();
+    for (int i = 0; i < count; ++i)
+      if (cs[i].plan.logn == kv.first) { cls_plan.push_back(cs[i].plan); break; }
   }
+  const int ncls = (int)cls_plan.size();
+  std::vector<int32_t> ids, cls_of;               // active signals in class order
+  for (int c = 0; c < ncls; ++c)
+    for (int i = 0; i < count; ++i)
+      if (cs[i].plan.logn == cls_plan[c].logn) { ids.push_back(i); cls_of.push_back(c); }
   CS_HIP(hipMemcpyAsync(d_sigs, hs.data(), count * sizeof(BSig<T>), hipMemcpyHostToDevice, stream));
   CS_HIP(hipMemcpyAsync(d_st, hst.data(), count * sizeof(BState), hipMemcpyHostToDevice, stream));
-  CS_HIP(hipMemcpyAsync(d_ids, ids.data(), count * sizeof(int32_t), hipMemcpyHostToDevice, stream));
   hipLaunchKernelGGL(k_b_start<T>, dim3(count), dim3(cg_threads), 0, stream, d_sigs);
   CS_LAUNCH_CHECK();
-  CS_HIP(hipStreamSynchronize(stream));   // the host arrays above go out of scope only after the copies
+  CS_HIP(hipStreamSynchronize(stream));   // the host arrays above are read by the copies
 
-  // capture kBSteps batched steps
+  // Capture kBSteps batched steps over the active signals `ids`, then the
+  // compaction of the ones still running.
   hipStream_t cap = nullptr;
   CS_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  CS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-  const unsigned nsig = (unsigned)count;
-  for (int stp = 0; stp < kBSteps; ++stp) {
-    for (const Cls& c : cl) {
-      const KernelSet<T>& ks = kernels_plan<T>(c.plan);
-      ks.col_fwd_b<<<dim3((unsigned)(c.plan.L2 >> c.plan.logB), c.cnt), dim3(ks.nt_col), c.plan.lds_col, cap>>>(
-          d_sigs, d_ids + c.first);
+  std::vector<int32_t> graph_cnt(ncls, 0);
+  auto build = [&]() {
+    const int na = (int)ids.size();
+    int nab = 1;
+    for (int32_t id : ids) nab = std::max(nab, arg_blocks(cs[id].plan.n));
+    CS_HIP(hipMemcpyAsync(d_ids, ids.data(), na * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    CS_HIP(hipMemcpyAsync(d_cls, cls_of.data(), na * sizeof(int32_t), hipMemcpyHostToDevice, stream));
+    CS_HIP(hipStreamSynchronize(stream));
+    std::vector<int> first(ncls, 0);
+    std::fill(graph_cnt.begin(), graph_cnt.end(), 0);
+    for (int i = na - 1; i >= 0; --i) { first[cls_of[i]] = i; ++graph_cnt[cls_of[i]]; }
+    CS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    for (int stp = 0; stp < kBSteps; ++stp) {
+      for (int pass = 0; pass < 3; ++pass) {
+        for (int c = 0; c < ncls; ++c) {
+          if (!graph_cnt[c]) continue;
+          const Plan& pl = cls_plan[c];
+          const KernelSet<T>& ks = kernels_plan<T>(pl);
+          const int32_t* cid = d_ids + first[c];
+          const dim3 gcol((unsigned)(pl.L2 >> pl.logB), (unsigned)graph_cnt[c]);
+          if (pass == 0) ks.col_fwd_b<<<gcol, dim3(ks.nt_col), pl.lds_col, cap>>>(d_sigs, cid);
+          else if (pass == 1)
+            ks.row_b<<<dim3((unsigned)(pl.L1 >> 1), (unsigned)graph_cnt[c]), dim3(ks.nt_row), pl.lds_row, cap>>>(
+                d_sigs, cid);
+          else ks.col_inv_b<<<gcol, dim3(ks.nt_col), pl.lds_col, cap>>>(d_sigs, cid);
+          CS_LAUNCH_CHECK();
+        }
+      }
+      hipLaunchKernelGGL(k_b_post<T>, dim3((unsigned)nab, (unsigned)na), dim3(cg_threads), 0, cap, d_sigs,
+                         (const int32_t*)d_ids);
+      hipLaunchKernelGGL(k_b_select<T>, dim3((unsigned)na), dim3(1024), 0, cap, d_sigs, (const int32_t*)d_ids);
       CS_LAUNCH_CHECK();
     }
-    for (const Cls& c : cl) {
-      const KernelSet<T>& ks = kernels_plan<T>(c.plan);
-      ks.row_b<<<dim3((unsigned)(c.plan.L1 >> 1), c.cnt), dim3(ks.nt_row), c.plan.lds_row, cap>>>(d_sigs,
-                                                                                                  d_ids + c.first);
-      CS_LAUNCH_CHECK();
-    }
-    for (const Cls& c : cl) {
-      const KernelSet<T>& ks = kernels_plan<T>(c.plan);
-      ks.col_inv_b<<<dim3((unsigned)(c.plan.L2 >> c.plan.logB), c.cnt), dim3(ks.nt_col), c.plan.lds_col, cap>>>(
-          d_sigs, d_ids + c.first);
-      CS_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_b_post<T>, dim3(nsig), dim3(cg_threads), 0, cap, d_sigs);
-    hipLaunchKernelGGL(k_b_argmax<T>, dim3(kBArgBlocks, nsig), dim3(256), 0, cap, d_sigs);
-    hipLaunchKernelGGL(k_b_select<T>, dim3(nsig), dim3(1024), 0, cap, d_sigs);
-    hipLaunchKernelGGL(k_b_bits_count<T>, dim3((unsigned)nbw, nsig), dim3(256), 0, cap, d_sigs);
-    hipLaunchKernelGGL(k_b_bits_scan<T>, dim3(nsig), dim3(1024), 0, cap, d_sigs);
-    hipLaunchKernelGGL(k_b_bits_write<T>, dim3((unsigned)nbw, nsig), dim3(256), 0, cap, d_sigs);
-    hipLaunchKernelGGL(k_b_remap<T>, dim3((unsigned)((kmax + 255) / 256), nsig), dim3(256), 0, cap, d_sigs);
-    hipLaunchKernelGGL(k_b_finish<T>, dim3(nsig), dim3(cg_threads), 0, cap, d_sigs);
+    hipLaunchKernelGGL(k_b_compact, dim3(1), dim3(1024), 0, cap, (const BState*)d_st, (const int32_t*)d_ids,
+                       (const int32_t*)d_cls, na, ncls, d_act, d_cnt);
     CS_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL(k_b_active, dim3(1), dim3(256), 0, cap, (const BState*)d_st, count, d_active);
-  CS_LAUNCH_CHECK();
-  CS_HIP(hipStreamEndCapture(cap, &graph));
-  CS_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    CS_HIP(hipStreamEndCapture(cap, &graph));
+    CS_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  };
+  auto drop = [&]() {
+    if (exec) CS_HIP(hipGraphExecDestroy(exec));
+    if (graph) CS_HIP(hipGraphDestroy(graph));
+    exec = nullptr;
+    graph = nullptr;
+  };
+  build();
 
-  // Replay until no signal is left.  Each swap takes at most cg_cap + 2 steps,
-  // so the bound below is never reached by a run that terminates as designed.
+  // Replay until no signal is left; re-capture over the running signals once
+  // half of them have stopped or a size class has emptied.  Each swap takes at
+  // most cg_cap + 2 steps, so the bound below is never reached by a run that
+  // terminates as designed.
   int64_t max_steps = 0;
   for (int i = 0; i < count; ++i)
     max_steps = std::max<int64_t>(max_steps, (int64_t)(hst[i].max_outer + 1) * (hst[i].cg_cap + 3) + 2);
   const int64_t max_replays = max_steps / kBSteps + 2;
-  int32_t active = count;
-  int64_t replays = 0;
-  while (active > 0 && replays < max_replays) {
+  std::vector<int32_t> cnt(ncls + 1, 0);
+  for (int64_t replays = 0; replays < max_replays; ++replays) {
     CS_HIP(hipGraphLaunch(exec, stream));
-    ++replays;
-    dev_read(stream, d_active, &active, sizeof(int32_t));
+    dev_read(stream, d_cnt, cnt.data(), (ncls + 1) * sizeof(int32_t));
+    const int total = cnt[ncls];
+    if (total == 0) break;
+    bool emptied = false;
+    for (int c = 0; c < ncls; ++c) emptied |= graph_cnt[c] > 0 && cnt[c] == 0;
+    if (emptied || 2 * total <= (int)ids.size()) {
+      ids.assign(total, 0);
+      CS_HIP(hipMemcpy(ids.data(), d_act, total * sizeof(int32_t), hipMemcpyDeviceToHost));
+      cls_of.resize(total);
+      for (int i = 0; i < total; ++i) cls_of[i] = cls_index[cs[ids[i]].plan.logn];
+      drop();
+      build();
+    }
   }
-  CS_HIP(hipGraphExecDestroy(exec));
-  CS_HIP(hipGraphDestroy(graph));
+  drop();
   CS_HIP(hipStreamDestroy(cap));
 
   CS_HIP(hipMemcpy(hst.data(), d_st, count * sizeof(BState), hipMemcpyDeviceToHost));

@@ -112,8 +112,8 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
       const int e = tid + q * NT;
       if (E % NT == 0 || e < E) buf[lp(e)] = cx((T)0, (T)0);
     }
-    if (io.cg && io.cg->done) return;
     const bool dir = io.mode == COL_DIR, first = io.it == 0;
+    if (dir && io.cg && io.cg->done) return;
     const T beta = (dir && !first) ? (T)io.cg->beta : (T)0;
     __syncthreads();
     for (uint32_t sl = s0 + tid; sl < s1; sl += NT) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
       bufr[2 * lp((int)e) + (key & 1)] = val;
     }
   } else {
-    if (io.cg && io.cg->done) return;
+    if (io.mode == COL_Q && io.cg && io.cg->done) return;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
@@ -203,44 +203,30 @@ __global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col(const
 }
 
 // Compact I/O of one batched signal in its current phase (mode < 0: idle).
+// The per-signal state is the same for the whole workgroup: read it once
+// into scalar registers and pick the two-slot members by select, so no
+// per-lane copies or private arrays are made.
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <typename T, bool INV>
 __device__ __forceinline__ ColIO<T> batch_io(const BSig<T>& s, int phase) {
   ColIO<T> io{};
-  io.mode = -1;
-  if (phase > BP_RESID) return io;
-  const int cur = s.st->cur;
+  const int cur = uniform_i32(s.st->cur);
   io.sbits = s.bits;
-  io.wpre = s.wpre[cur];
-  io.list = s.list[cur];
-  io.kcap = s.st->k;
-  if (!INV) {
-    if (phase == BP_ITER) {
-      io.mode = COL_DIR;
-      io.it = s.st->it;
-      io.r = s.cr;
-      io.d = s.cd;
-      io.cg = s.cg;
-    } else {
-      io.mode = COL_X;
-      io.x = s.cx[cur];
-    }
-  } else {
-    if (phase == BP_WARM) {
-      io.mode = COL_R;
-      io.r = s.cr;
-      io.d = s.cd;
-      io.b = s.cb;
-      io.pout = s.pgrid;
-    } else if (phase == BP_ITER) {
-      io.mode = COL_Q;
-      io.q = s.cq;
-      io.d = s.cd;
-      io.pout = s.pgrid;
-      io.cg = s.cg;
-    } else {
-      io.mode = COL_KEY;
-    }
-  }
+  io.wpre = cur ? s.wpre[1] : s.wpre[0];
+  io.list = cur ? s.list[1] : s.list[0];
+  io.kcap = uniform_i32(s.st->k);
+  io.it = uniform_i32(s.st->it);
+  io.x = cur ? s.cx[1] : s.cx[0];
+  io.r = s.cr;
+  io.d = s.cd;
+  io.q = s.cq;
+  io.b = s.cb;
+  io.pout = s.pgrid;
+  io.cg = s.cg;            // read only in the CG modes (COL_DIR, COL_Q)
+  if (!INV) io.mode = phase == BP_ITER ? COL_DIR : COL_X;
+  else io.mode = phase == BP_WARM ? COL_R : (phase == BP_ITER ? COL_Q : COL_KEY);
+  if (phase > BP_RESID) io.mode = -1;
   return io;
 }
 
@@ -248,8 +234,8 @@ __device__ __forceinline__ ColIO<T> batch_io(const BSig<T>& s, int phase) {
 template <typename T, bool INV, int LOGL1, int LOGB, int LOGE>
 __global__ __launch_bounds__(nt_for(1 << (LOGL1 + LOGB), LOGE)) void k_col_b(const BSig<T>* __restrict__ sigs,
                                                                              const int32_t* __restrict__ ids) {
-  const BSig<T>& s = sigs[ids[blockIdx.y]];
-  const int phase = s.st->phase;
+  const BSig<T>& s = sigs[uniform_i32(ids[blockIdx.y])];
+  const int phase = uniform_i32(s.st->phase);
   const ColIO<T> io = batch_io<T, INV>(s, phase);
   if (io.mode < 0) return;
   col_body<T, INV, LOGL1, LOGB, LOGE>((const Cx<T>*)s.W, INV && phase == BP_RESID ? (Cx<T>*)s.Cc : s.W, s.plan, io,
@@ -487,8 +473,8 @@ __global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row(Cx<T>* __restr
 template <typename T, int LOGL2, int LOGE>
 __global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row_b(const BSig<T>* __restrict__ sigs,
                                                               const int32_t* __restrict__ ids) {
-  const BSig<T>& s = sigs[ids[blockIdx.y]];
-  const int phase = s.st->phase;
+  const BSig<T>& s = sigs[uniform_i32(ids[blockIdx.y])];
+  const int phase = uniform_i32(s.st->phase);
   if (phase > BP_RESID) return;
   const bool res = phase == BP_RESID;
   row_body<T, LOGL2, LOGE>(s.W, s.plan, res ? ROW_RESID : ROW_HAPPLY, res ? s.Yf : nullptr, nullptr,
