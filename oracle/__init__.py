@@ -36,6 +36,6 @@ noiseless well-separated inputs, the M = N special case).
 from .operator import SRM, dct2_matrix  # noqa: F401
 from .gram import gram_generator, gram_matrix  # noqa: F401
 from .lsq import ls, ls_dense, ls_gram, ls_cg  # noqa: F401
-from .greedy import omp, sp, ompr, topk_order, argmax_excluding  # noqa: F401
+from .greedy import omp, sp, ompr, cosamp, topk_order, argmax_excluding  # noqa: F401
 from .bruteforce import l0_bruteforce  # noqa: F401
 from .adjoint import adjoint_gradient  # noqa: F401

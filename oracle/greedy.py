@@ -21,13 +21,17 @@ SP reading: T = top-K of |A^T y|, x = LS(T), r = y - A x; then repeat
   stop with (T', x') if T' == T; stop with (T, x) if ||r'|| > ||r||;
   otherwise continue with (T', x', r').  At most ``max_iter`` rounds.
 
-OMPR reading (replacement size l = 1, step eta = N/M so that eta * a_j^T r
-is on the scale of a coefficient, since ||a_j||^2 is M/N on average):
+OMPR reading (replacement size l, default 1; step eta = N/M so that
+eta * a_j^T r is on the scale of a coefficient, since ||a_j||^2 is M/N on
+average):
   I = top-K of |A^T y|, x = LS(I), r = y - A x; then repeat
-  stop if ||r|| <= 1e-12 ||y||;  c = A^T r;  j = argmax |c| outside I;
-  z = x + eta c on I u {j} (x_j = 0);  keep = top-K of |z| over I u {j};
-  stop if j is not kept; otherwise I = keep, x = LS(I), r = y - A x.
-  At most ``max_iter`` swaps.
+  stop if ||r|| <= 1e-12 ||y||;  c = A^T r;  J = top-l of |c| outside I
+  (for l = 1 the argmax);  z = x + eta c on I u J (x_J = 0);
+  keep = top-K of |z| over I u J;  stop if no index of J is kept;
+  otherwise I = keep, x = LS(I), r = y - A x.  At most ``max_iter`` steps.
+
+CoSaMP (Needell and Tropp, the other greedy neighbour named with OMPR): see
+``cosamp``.
 
 Every decision is logged with its margin (FP64 key gap between the last
 chosen and the first rejected candidate).
@@ -153,7 +157,7 @@ def sp(op: SRM, y, K: int, max_iter: int = 100, ls_route: str = "auto") -> Resul
 
 
 def ompr(op: SRM, y, K: int, eta: float | None = None, max_iter: int | None = None,
-         ls_route: str = "auto") -> Result:
+         ls_route: str = "auto", l: int = 1) -> Result:
     y = np.asarray(y, dtype=np.float64)
     if eta is None:
         eta = op.n / op.m
@@ -176,15 +180,20 @@ def ompr(op: SRM, y, K: int, eta: float | None = None, max_iter: int | None = No
         c = op.adjoint(r)
         excl = np.zeros(op.n, dtype=bool)
         excl[I] = True
-        j, m = argmax_excluding(c, excl)
-        trace.append((t, "argmax", m))
-        cand = np.append(I, j)
-        z = np.append(x + eta * c[I], eta * c[j])
+        if l == 1:
+            j, m = argmax_excluding(c, excl)
+            J = np.array([j], dtype=np.int64)
+            trace.append((t, "argmax", m))
+        else:
+            J, m = topk_excluding(c, excl, l)
+            trace.append((t, "enter_topl", m))
+        cand = np.append(I, J)
+        z = np.append(x + eta * c[I], eta * c[J])
         keys = np.abs(z)
         pos = topk_order(keys, cand, K)
         trace.append((t, "drop", _margin(keys, cand, K)))
         keep = np.sort(cand[pos])
-        if j not in set(keep.tolist()):
+        if not np.isin(J, keep).any():
             stop = "no replacement"
             break
         I = keep
@@ -193,3 +202,46 @@ def ompr(op: SRM, y, K: int, eta: float | None = None, max_iter: int | None = No
         swaps += 1
     return Result(_dense(op.n, I, x), np.asarray(I, dtype=np.int64), swaps,
                   float(np.linalg.norm(r)), trace, stop)
+
+
+def cosamp(op: SRM, y, K: int, max_iter: int = 100, ls_route: str = "auto") -> Result:
+    """CoSaMP (Needell and Tropp) on the same selection and least-squares steps.
+
+    Reading: starting from x = 0, r = y, each round takes the top-2K of |A^T r|
+    (over all indices: r is not orthogonal to the columns of a pruned x),
+    merges them with the current support, solves least squares on the union
+    (2K..3K columns), keeps the top-K magnitudes of that solution as the new
+    x (no second solve) and updates r = y - A x.  From the second round on it
+    stops with the new (T, x) when the support repeats, and with the previous
+    one when ||r|| grows, as SP does; at most ``max_iter`` rounds."""
+    y = np.asarray(y, dtype=np.float64)
+    ctx = LSContext(op, y, ls_route)
+    trace = []
+    T = np.zeros(0, dtype=np.int64)
+    x = np.zeros(0)
+    r = y.copy()
+    rn = float(np.linalg.norm(r))
+    stop = "max_iter"
+    it = 0
+    for it in range(1, max_iter + 1):
+        c = ctx.aty if it == 1 else op.adjoint(r)
+        Om, m = topk_excluding(c, None, 2 * K)
+        trace.append((it, "merge_top2k", m))
+        U = np.union1d(Om, T)
+        b = ctx.solve(U)
+        pos = topk_order(np.abs(b), U, K)
+        trace.append((it, "prune_topk", _margin(np.abs(b), U, K)))
+        order = np.argsort(U[pos])
+        Tn = U[pos][order]
+        xn = b[pos][order]
+        rv = y - op.apply_sparse(Tn, xn)
+        rnn = float(np.linalg.norm(rv))
+        if it > 1 and np.array_equal(Tn, T):
+            T, x, r, rn = Tn, xn, rv, rnn
+            stop = "support unchanged"
+            break
+        if it > 1 and rnn > rn:
+            stop = "residual increased"
+            break
+        T, x, r, rn = Tn, xn, rv, rnn
+    return Result(_dense(op.n, T, x), np.asarray(T, dtype=np.int64), it, rn, trace, stop)

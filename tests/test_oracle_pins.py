@@ -196,6 +196,24 @@ def test_p6_orthogonal_special_case():
     assert pin_orthogonal_special_case()
 
 
+def test_p6_orthogonal_special_case_cosamp_omprl():
+    """M = N: CoSaMP's first round gives H_K(A^T y), the second repeats it
+    (the new correlation vanishes on T and the solve on the union is c there);
+    OMPR with l = 3 and eta = 1 finds nothing to replace."""
+    rng = np.random.default_rng(13)
+    n, k = 512, 20
+    rows, signs = synth.draw_operator(rng, n, n)
+    op = oracle.SRM(n, rows, signs)
+    y = rng.standard_normal(n)
+    c = op.adjoint(y)
+    expect = np.sort(np.argsort(-np.abs(c), kind="stable")[:k])
+    r = oracle.cosamp(op, y, k)
+    assert np.array_equal(r.support, expect) and r.iters == 2 and r.stop == "support unchanged"
+    assert np.allclose(r.s[expect], c[expect], atol=1e-12)
+    q = oracle.ompr(op, y, k, eta=1.0, l=3)
+    assert np.array_equal(q.support, expect) and q.iters == 0 and q.stop == "no replacement"
+
+
 def test_p6_omp_picks_in_decreasing_magnitude():
     rng = np.random.default_rng(12)
     n = 128
@@ -239,8 +257,9 @@ def test_p7_bruteforce_is_optimal_for_greedy():
     for seed in range(10):
         d, op, y = problem(95, seed, 14, 8, 2, "normal", 15.0)
         _, _, rn = oracle.l0_bruteforce(op, y, 2)
-        for f in (oracle.omp, oracle.sp, oracle.ompr):
+        for f in (oracle.omp, oracle.sp, oracle.ompr, oracle.cosamp):
             assert f(op, y, 2).resid_norm >= rn - 1e-12
+        assert oracle.ompr(op, y, 2, l=2).resid_norm >= rn - 1e-12
 
 
 def test_p7_sp_ompr_single_atom_certificate():
@@ -291,11 +310,49 @@ def test_p7_sp_ompr_fixed_points():
         assert j not in cand[ogreedy.topk_order(np.abs(z), cand, 20)]
 
 
+def test_p7_ompr_l_fixed_point():
+    """OMPR with l = 4 stops only when none of the l entering indices survives
+    the top-K of |x + eta A^T r| over I u J."""
+    d, op, y = problem(101, 0, 1024, 300, 20, "normal", 15.0)
+    q = oracle.ompr(op, y, 20, l=4)
+    if q.stop == "no replacement":
+        I = q.support
+        c = op.adjoint(y - op.apply(q.s))
+        excl = np.zeros(op.n, dtype=bool)
+        excl[I] = True
+        J, _ = ogreedy.topk_excluding(c, excl, 4)
+        eta = op.n / op.m
+        z = np.append(q.s[I] + eta * c[I], eta * c[J])
+        cand = np.append(I, J)
+        assert not np.isin(J, cand[ogreedy.topk_order(np.abs(z), cand, 20)]).any()
+
+
+def test_cosamp_first_round_from_its_definition():
+    """One CoSaMP round from x = 0, written out with numpy's own sort: merge the
+    2K largest |A^T y|, solve least squares on them by dense lstsq, keep the K
+    largest entries of that solution (no second solve)."""
+    d, op, y = problem(102, 0, 2048, 600, 25, "normal", 25.0)
+    k = 25
+    r = oracle.cosamp(op, y, k, max_iter=1)
+    c = op.adjoint(y)
+    U = np.sort(np.lexsort((np.arange(op.n), -np.abs(c)))[:2 * k])
+    b = np.linalg.lstsq(op.columns(U), y, rcond=None)[0]
+    keep = np.lexsort((U, -np.abs(b)))[:k]
+    T = np.sort(U[keep])
+    assert np.array_equal(r.support, T)
+    assert np.allclose(r.s[T], b[np.searchsorted(U, T)], atol=1e-11)
+    # the pruned least-squares estimate is not the least-squares fit on T
+    assert not np.allclose(r.s[T], np.linalg.lstsq(op.columns(T), y, rcond=None)[0], atol=1e-6)
+
+
 # ------------------------------------------------------------------ exact recovery (north star)
-@pytest.mark.parametrize("algo", ["omp", "sp", "ompr"])
+@pytest.mark.parametrize("algo", ["omp", "sp", "ompr", "cosamp", "ompr_l3"])
 def test_exact_recovery_well_separated(algo):
     d, op, y = problem(97, 0, 4096, 1024, 50, "normal_min0.1")
-    r = getattr(oracle, algo)(op, y, 50)
+    if algo == "ompr_l3":
+        r = oracle.ompr(op, y, 50, l=3)
+    else:
+        r = getattr(oracle, algo)(op, y, 50)
     assert np.array_equal(r.support, d.supp)
     assert np.linalg.norm(r.s - d.s_dense()) <= 1e-12 * np.linalg.norm(d.vals)
     # final residual orthogonal to A_S
