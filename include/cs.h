@@ -62,7 +62,8 @@ typedef enum {
   CS_ALGO_SP = 1,       /* Subspace Pursuit (run in Sec. IV)                            */
   CS_ALGO_OMPR = 2,     /* OMP with Replacement, l = 1 (run in Sec. IV)                 */
   CS_ALGO_OPERATOR = 3, /* cs_apply_A / cs_apply_At only                                */
-  CS_ALGO_LS = 4        /* cs_ls_solve (the CG function of Algorithm 1 alone)           */
+  CS_ALGO_LS = 4,       /* cs_ls_solve (the CG function of Algorithm 1 alone)           */
+  CS_ALGO_COSAMP = 5    /* CoSaMP, the merge/prune neighbour of SP                      */
 } cs_algo;
 
 typedef enum {
@@ -99,6 +100,11 @@ typedef struct {
                              kernels (64..1024, a multiple of 64); 0 -> 256.
                              Single-signal calls ignore it.                          */
   double ompr_eta;        /* OMPR step eta; <= 0 -> N/M                             */
+  int32_t tol_abs;        /* 1: `tol` is absolute, each CG solve stops at
+                             ||b - H theta|| <= tol (the xi of Algorithm 1 line 15
+                             as printed); 0 (default): relative, <= tol ||b||     */
+  int32_t ompr_l;         /* OMPR replacement size l (indices swapped per step);
+                             0 -> 1                                                 */
 } cs_params;
 
 /* Filled on return when non-NULL (host memory). */
@@ -129,9 +135,16 @@ size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_alg
  *                  the 2K columns, prune to the top-K magnitudes, least
  *                  squares; stops when the support repeats or the residual
  *                  grows.
- * cs_recover_ompr: OMPR with l = 1: top-K of |A^T y|; then swaps of the best
- *                  outside correlation j against the smallest |x + eta A^T r|
- *                  on S u {j}; stops when j would be dropped.
+ * cs_recover_ompr: OMPR with replacement size l (cs_params.ompr_l, default 1):
+ *                  top-K of |A^T y|; then steps that take the l best
+ *                  correlations J outside S and keep the top-K of
+ *                  |x + eta A^T r| over S u J; stops when no index of J is
+ *                  kept (for l = 1: when j would be dropped).
+ * cs_recover_cosamp: CoSaMP on the same steps: from x = 0, rounds that merge
+ *                  the top-2K of |A^T r| with the support, solve least squares
+ *                  on the union, keep its K largest entries and update r;
+ *                  stops when the support repeats or the residual grows.
+ *                  Needs 3K <= M.
  * Ties in every selection rank by (magnitude descending, index ascending).
  */
 cs_status cs_recover_omp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol,
@@ -143,6 +156,9 @@ cs_status cs_recover_sp(cs_dtype dtype, const void* y, const cs_op* op, int32_t 
 cs_status cs_recover_ompr(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol,
                           void* s, int32_t* support, const cs_params* params,
                           void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream);
+cs_status cs_recover_cosamp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol,
+                            void* s, int32_t* support, const cs_params* params,
+                            void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream);
 
 /*
  * The CG function of Algorithm 1 (lines 11-24) on its own: solve the weighted

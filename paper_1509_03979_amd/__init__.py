@@ -20,11 +20,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcsrecover.so")
 
 CS_F32, CS_F64 = 0, 1
-CS_ALGO_OMP, CS_ALGO_SP, CS_ALGO_OMPR, CS_ALGO_OPERATOR, CS_ALGO_LS = 0, 1, 2, 3, 4
+CS_ALGO_OMP, CS_ALGO_SP, CS_ALGO_OMPR, CS_ALGO_OPERATOR, CS_ALGO_LS, CS_ALGO_COSAMP = 0, 1, 2, 3, 4, 5
 CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, -3, -4, -5
 CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
 
-EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_ls_solve",
+EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_recover_cosamp",
+           "cs_ls_solve",
            "cs_adjoint_ls", "cs_workspace_size_batched", "cs_recover_ompr_batched", "cs_apply_A", "cs_apply_At",
            "cs_shape_candidates", "cs_set_shape", "cs_time_shape", "cs_status_str", "cs_last_error",
            "cs_prof_enable", "cs_prof_reset", "cs_prof_read")
@@ -37,7 +38,8 @@ class cs_op(ctypes.Structure):
 
 class cs_params(ctypes.Structure):
     _fields_ = [("cg_max_iter", ctypes.c_int32), ("max_outer", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("cg_block", ctypes.c_int32), ("ompr_eta", ctypes.c_double)]
+                ("warm_start", ctypes.c_int32), ("cg_block", ctypes.c_int32), ("ompr_eta", ctypes.c_double),
+                ("tol_abs", ctypes.c_int32), ("ompr_l", ctypes.c_int32)]
 
 
 class cs_info(ctypes.Structure):
@@ -84,7 +86,7 @@ def _load():
     P = ctypes.POINTER
     lib.cs_workspace_size.argtypes = [ctypes.c_int, i64, i64, i32, ctypes.c_int]
     lib.cs_workspace_size.restype = sz
-    for name in ("cs_recover_omp", "cs_recover_sp", "cs_recover_ompr"):
+    for name in ("cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_recover_cosamp"):
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, vp, P(cs_op), i32, dbl, vp, vp, P(cs_params), vp, sz, P(cs_info), vp]
         f.restype = ctypes.c_int
@@ -205,8 +207,9 @@ class Operator:
                    torch.as_tensor(signs, dtype=torch.int8, device=device))
 
 
-def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0, cg_block=0):
-    return cs_params(int(cg_max_iter), int(max_outer), int(warm_start), int(cg_block), float(ompr_eta))
+def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0, cg_block=0, tol_abs=False, ompr_l=1):
+    return cs_params(int(cg_max_iter), int(max_outer), int(warm_start), int(cg_block), float(ompr_eta),
+                     int(bool(tol_abs)), int(ompr_l))
 
 
 def workspace(dtype_code: int, op: Operator, k: int, algo: int, device=None):
@@ -250,6 +253,11 @@ def cs_recover_sp(y, op: Operator, k: int, tol: float, ws=None, stream=None, **k
 def cs_recover_ompr(y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
     """OMPR (l = 1) with CG least squares -> (s, support, info)."""
     return _recover(lib.cs_recover_ompr, CS_ALGO_OMPR, y, op, k, tol, ws, stream, **kw)
+
+
+def cs_recover_cosamp(y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
+    """CoSaMP with CG least squares -> (s, support, info)."""
+    return _recover(lib.cs_recover_cosamp, CS_ALGO_COSAMP, y, op, k, tol, ws, stream, **kw)
 
 
 def cs_ls_solve(y, op: Operator, support, tol: float, x0=None, ws=None, stream=None, **kw):

@@ -75,7 +75,8 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
 static int kmax_for(cs_algo algo, int32_t k) {
   switch (algo) {
     case CS_ALGO_SP: return 2 * k;
-    case CS_ALGO_OMPR: return k;
+    case CS_ALGO_OMPR: return 2 * k;     // candidates I u J for replacement sizes up to K
+    case CS_ALGO_COSAMP: return 3 * k;
     case CS_ALGO_OPERATOR: return 1;
     default: return k;
   }
@@ -122,6 +123,7 @@ static void check_shape(cs_dtype dt, const cs_op* op, int32_t k, cs_algo algo) {
   if (k < 1) throw Error(CS_E_INVALID, "K must be >= 1");
   if (k > m) throw Error(CS_E_SHAPE, "K must not exceed M");
   if (algo == CS_ALGO_SP && (int64_t)2 * k > m) throw Error(CS_E_SHAPE, "SP needs 2K <= M");
+  if (algo == CS_ALGO_COSAMP && (int64_t)3 * k > m) throw Error(CS_E_SHAPE, "CoSaMP needs 3K <= M");
 }
 
 static void check_tol(double tol) {
@@ -139,12 +141,16 @@ static cs_params defaults(const cs_params* p) {
   d.max_outer = 0;
   d.warm_start = 1;
   d.ompr_eta = 0.0;
+  d.tol_abs = 0;
+  d.ompr_l = 1;
   if (p) {
     d.cg_max_iter = p->cg_max_iter;
     d.max_outer = p->max_outer;
     d.warm_start = p->warm_start;
     d.cg_block = p->cg_block;
     d.ompr_eta = p->ompr_eta;
+    d.tol_abs = p->tol_abs;
+    d.ompr_l = p->ompr_l > 0 ? p->ompr_l : 1;
   }
   return d;
 }
@@ -166,11 +172,13 @@ static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, d
   setup_operator<T>(c);
   load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
+  c.tol_abs = prm.tol_abs != 0;
   cs_info loc{};
   cs_info* inf = info ? info : &loc;
   std::memset(inf, 0, sizeof(cs_info));
   if (algo == CS_ALGO_OMP) run_omp<T>(c, k, tol, prm, (T*)s, support, inf);
   else if (algo == CS_ALGO_SP) run_sp<T>(c, k, tol, prm, (T*)s, support, inf);
+  else if (algo == CS_ALGO_COSAMP) run_cosamp<T>(c, k, tol, prm, (T*)s, support, inf);
   else run_ompr<T>(c, k, tol, prm, (T*)s, support, inf);
   CS_HIP(hipStreamSynchronize(stream));
   if (prof_on()) prof_flush();
@@ -184,6 +192,8 @@ static cs_status recover(cs_algo algo, cs_dtype dt, const void* y, const cs_op* 
     check_shape(dt, op, k, algo);
     if (!y || !s || !support) throw Error(CS_E_INVALID, "null y, s or support");
     check_tol(tol);
+    if (algo == CS_ALGO_OMPR && params && (params->ompr_l < 0 || params->ompr_l > k || params->ompr_l > op->n - k))
+      throw Error(CS_E_INVALID, "ompr_l must be in [1, min(K, N - K)] (0 means 1)");
     check_ws(ws);
     if (dt == CS_F32) recover_t<float>(algo, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
     else recover_t<double>(algo, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
@@ -262,6 +272,7 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   const Supp S = support_keys<T>(c, support, k);
   load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
+  c.tol_abs = prm.tol_abs != 0;
   if (x0)
     hipLaunchKernelGGL((k_reorder<T, true>), dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0],
                        c.wpre[0], (T*)x0, c.cx);
@@ -306,6 +317,7 @@ static void adj_t(const cs_op* op, const int32_t* support, int32_t k, const void
   const unsigned gk = (unsigned)((k + 255) / 256);
   const Supp S = support_keys<T>(c, support, k);
   const cs_params prm = defaults(params);
+  c.tol_abs = prm.tol_abs != 0;
   hipLaunchKernelGGL(k_grad_rhs<T>, dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0], c.wpre[0],
                      (const T*)grad, c.cb);
   CS_LAUNCH_CHECK();
@@ -381,7 +393,8 @@ size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_alg
   if (dtype != CS_F32 && dtype != CS_F64) return 0;
   if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1)) || m < 1 || m > n) return 0;
   if (algo != CS_ALGO_OPERATOR && (k < 1 || k > m)) return 0;
-  if (algo < CS_ALGO_OMP || algo > CS_ALGO_LS) return 0;
+  if (algo < CS_ALGO_OMP || algo > CS_ALGO_COSAMP) return 0;
+  if (algo == CS_ALGO_COSAMP && (int64_t)3 * k > m) return 0;
   return workspace_bytes(dtype, n, m, k, algo);
 }
 
@@ -401,6 +414,12 @@ cs_status cs_recover_ompr(cs_dtype dtype, const void* y, const cs_op* op, int32_
                           int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
                           hipStream_t stream) {
   return recover(CS_ALGO_OMPR, dtype, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+}
+
+cs_status cs_recover_cosamp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,
+                            int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                            hipStream_t stream) {
+  return recover(CS_ALGO_COSAMP, dtype, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
 }
 
 cs_status cs_ls_solve(cs_dtype dtype, const void* y, const cs_op* op, const int32_t* support, int32_t k, double tol,
@@ -458,6 +477,7 @@ cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_
                                   hipStream_t stream) {
   try {
     if (count < 1 || !items) throw Error(CS_E_INVALID, "count must be >= 1 with a non-null item array");
+    if (params && params->ompr_l > 1) throw Error(CS_E_INVALID, "the batched call runs OMPR with l = 1");
     for (int i = 0; i < count; ++i) {
       check_shape(dtype, &items[i].op, items[i].k, CS_ALGO_OMPR);
       if (!items[i].y || !items[i].s || !items[i].support) throw Error(CS_E_INVALID, "null y, s or support in batch");

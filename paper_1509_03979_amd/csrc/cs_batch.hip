@@ -101,13 +101,14 @@ __global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __rest
       cg->rr[0] = rr;
       cg->rr[1] = rr;
       cg->bb = bb;
+      cg->ref = st->tol_abs ? 1.0 : bb;
       cg->tol2 = st->tol2;
       cg->iters = 0;
       cg->flags = 0;
       cg->cnt_q = 0u;
       cg->cnt_u = 0u;
       const bool fin = isfinite(rr) && isfinite(bb);
-      const bool conv = rr <= st->tol2 * bb;
+      const bool conv = rr <= st->tol2 * cg->ref;
       const bool done = !fin || conv || st->cg_cap <= 0;
       if (!fin) st->flags |= CS_F_NONFINITE;
       else if (done && !conv) st->flags |= CS_F_CG_MAXITER;
@@ -150,7 +151,7 @@ __global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __rest
       cg->iters = it + 1;
       st->it = it + 1;
       st->cg_iters += 1;
-      const bool conv = rn <= cg->tol2 * cg->bb;
+      const bool conv = rn <= cg->tol2 * cg->ref;
       if (!fin) st->flags |= CS_F_NONFINITE;
       if (!fin || conv || it + 1 >= st->cg_cap) {
         if (fin && !conv) st->flags |= CS_F_CG_MAXITER;
@@ -383,6 +384,7 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
     b.cg_cap = prm.cg_max_iter > 0 ? prm.cg_max_iter : 2 * it.k + 50;
     b.warm = prm.warm_start != 0;
     b.tol2 = tol * tol;
+    b.tol_abs = prm.tol_abs != 0;
     b.eta = prm.ompr_eta > 0 ? prm.ompr_eta : (double)it.op.n / (double)it.op.m;
     b.ynorm = c.ynorm;
     b.model_bytes = c.model_bytes;

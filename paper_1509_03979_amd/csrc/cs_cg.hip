@@ -96,13 +96,14 @@ __global__ void k_cg_init_cold(const T* __restrict__ b, T* __restrict__ x, T* __
 }
 
 __global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, int nrr, const double* __restrict__ pbb,
-                           int nbb, double tol2, int max_iter) {
+                           int nbb, double tol2, int max_iter, int tol_abs) {
   const double rr = sum_partials(prr, nrr);
   const double bb = sum_partials(pbb, nbb);
   if (threadIdx.x == 0) {
     cg->rr[0] = rr;
     cg->rr[1] = rr;
     cg->bb = bb;
+    cg->ref = tol_abs ? 1.0 : bb;
     cg->tol2 = tol2;
     cg->iters = 0;
     cg->flags = 0;
@@ -110,7 +111,7 @@ __global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, int nr
     cg->cnt_u = 0u;
     const bool fin = isfinite(rr) && isfinite(bb);
     if (!fin) cg->flags |= CS_F_NONFINITE;
-    cg->done = (!fin || rr <= tol2 * bb || max_iter <= 0) ? 1 : 0;
+    cg->done = (!fin || rr <= tol2 * cg->ref || max_iter <= 0) ? 1 : 0;
   }
 }
 
@@ -159,7 +160,7 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
       cg->iters = it + 1;
       cg->cnt_u = 0u;
       if (!fin) cg->flags |= CS_F_NONFINITE;
-      if (!fin || rr_new <= cg->tol2 * cg->bb || it + 1 >= max_iter) cg->done = 1;
+      if (!fin || rr_new <= cg->tol2 * cg->ref || it + 1 >= max_iter) cg->done = 1;
     }
   }
 }
@@ -190,11 +191,11 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     launch_col<T>(c, c.W, nullptr, true, out);
     c.transforms += 2;
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, c.pgrid, ncol, pbb, nb, tol * tol,
-                       max_iter);
+                       max_iter, c.tol_abs);
   } else {
     hipLaunchKernelGGL(k_cg_init_cold<T>, dim3(nb), dim3(kRedThreads), 0, s, c.cb, x, c.cr, k, prr);
     CS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, nb, pbb, nb, tol * tol, max_iter);
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, nb, pbb, nb, tol * tol, max_iter, c.tol_abs);
   }
   CS_LAUNCH_CHECK();
 
@@ -232,7 +233,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     dev_read(s, c.cg, &host, sizeof(CgScalars));
     if (host.done) break;
     const double rr_now = host.rr[host.iters & 1];
-    const double target = host.tol2 * host.bb;
+    const double target = host.tol2 * host.ref;
     const double rr_ref = (rr_prev > 0.0) ? rr_prev : host.rr[0];
     const int span = (rr_prev > 0.0) ? (host.iters - it_prev) : host.iters;
     int next = 2;
@@ -246,7 +247,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     it_prev = host.iters;
   }
   if (!host.done) dev_read(s, c.cg, &host, sizeof(CgScalars));
-  const bool conv = host.rr[host.iters & 1] <= host.tol2 * host.bb;
+  const bool conv = host.rr[host.iters & 1] <= host.tol2 * host.ref;
   if (!conv && !(host.flags & CS_F_CG_BREAKDOWN)) c.flags |= CS_F_CG_MAXITER;
   c.flags |= host.flags;
   c.cg_iters += host.iters;

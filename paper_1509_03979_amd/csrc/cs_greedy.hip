@@ -159,6 +159,39 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
   if (info) { info->outer_iters = rounds; info->resid_norm = rn; }
 }
 
+// OMPR candidates I u J for l > 1: keys (the support keys, then J's) and
+// z = x + eta c on I, eta c on J.
+template <typename T>
+__global__ void k_ompr_cand(const T* __restrict__ x, const int32_t* __restrict__ list, int k,
+                            int32_t* __restrict__ keys, int l, const T* __restrict__ cc, T eta, T* __restrict__ z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) {
+    const int32_t key = list[i];
+    keys[i] = key;
+    z[i] = x[i] + eta * cc[key];
+  } else if (i < k + l) {
+    z[i] = eta * cc[keys[i]];      // J's keys are already in place
+  }
+}
+
+// One OMPR step with replacement size l > 1 (J = top-l outside I, keep the
+// top-K of |z| over I u J): writes the kept set into bits_new and returns
+// whether it differs from bits_cur.
+template <typename T>
+static bool ompr_step_l(Ctx<T>& c, int K, int l, T eta, const int32_t* list_cur, const T* x_cur,
+                        const uint32_t* bits_cur, uint32_t* bits_j, uint32_t* bits_new) {
+  hipStream_t s = c.stream;
+  int32_t* keys = c.list[2];
+  T* z = c.cx2;
+  topk_dense<T>(c, (const T*)c.Cc, bits_cur, l, bits_j);
+  bits_to_list<T>(c, bits_j, keys + K, l, nullptr);
+  hipLaunchKernelGGL(k_ompr_cand<T>, dim3(nblk(K + l, 256)), dim3(256), 0, s, x_cur, list_cur, K, keys, l,
+                     (const T*)c.Cc, eta, z);
+  CS_LAUNCH_CHECK();
+  topk_compact<T>(c, z, keys, K + l, K, bits_new);
+  return !bits_equal(bits_new, bits_cur, c.plan.words, c.ibuf + 8, s);
+}
+
 // ------------------------------------------------------------------ OMPR
 template <typename T>
 void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info) {
@@ -178,8 +211,24 @@ void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int3
   int swaps = 0;
   bool stopped = false;
   int32_t jd[2];
+  const int l = prm.ompr_l > 0 ? prm.ompr_l : 1;
   for (int t = 1; t <= max_outer; ++t) {
     if (rn <= 1e-12 * c.ynorm) { stopped = true; break; }
+    if (l > 1) {
+      // general replacement size: the kept set goes to bits[2], then becomes the support
+      if (!ompr_step_l<T>(c, K, l, (T)eta, c.list[cur], xI, bits, c.bits[1], c.bits[2])) { stopped = true; break; }
+      std::swap(c.bits[0], c.bits[2]);
+      bits = c.bits[0];
+      bits_to_list<T>(c, bits, c.list[nxt], K, c.wpre[nxt]);
+      const Supp S{bits, c.wpre[nxt], c.list[nxt], K};
+      if (warm) remap<T>(c, c.list[cur], xI, K, c.list[nxt], xN, K);
+      cg_solve<T>(c, S, xN, warm, tol, cg_cap(prm, K));
+      rn = resid_corr<T>(c, S, xN);
+      std::swap(cur, nxt);
+      std::swap(xI, xN);
+      ++swaps;
+      continue;
+    }
     argmax_excl<T>(c, (const T*)c.Cc, bits, c.ibuf);
     hipLaunchKernelGGL(k_ompr_drop<T>, dim3(1), dim3(1024), 0, s, xI, c.list[cur], K, (const T*)c.Cc, c.plan,
                        (T)eta, (const int32_t*)c.ibuf, c.ibuf + 1);
@@ -202,10 +251,67 @@ void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int3
   if (info) { info->outer_iters = swaps; info->resid_norm = rn; }
 }
 
+// ------------------------------------------------------------------ CoSaMP
+// Each round: merge the top-2K of |A^T r| with the support, least squares on
+// the union (2K..3K columns), prune to the K largest entries (no second
+// solve), residual.  Stops with the new (T, x) when the support repeats and
+// with the previous one when ||r|| grows (from the second round on).
+template <typename T>
+void run_cosamp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info) {
+  hipStream_t s = c.stream;
+  const int64_t words = c.plan.words;
+  int iT = 0, iU = 1, iN = 2;   // slots: current T, merged U, pruned T'
+  T* xT = c.cx;
+  T* xU = c.cx2;
+  T* xN = c.cx3;
+  const bool warm = prm.warm_start != 0;
+  const int max_outer = prm.max_outer > 0 ? prm.max_outer : 100;
+  double rn = c.ynorm;
+  int rounds = 0;
+  bool stopped = false;
+  for (int it = 1; it <= max_outer; ++it) {
+    rounds = it;
+    topk_dense<T>(c, it == 1 ? (const T*)c.C0 : (const T*)c.Cc, nullptr, 2 * K, c.bits[iU]);
+    if (it > 1) bits_or(c.bits[iU], c.bits[iT], c.bits[iU], words, s);
+    const int nb = bits_to_list<T>(c, c.bits[iU], c.list[iU], 3 * K, c.wpre[iU]);
+    uint32_t ku = 0;
+    dev_read(s, c.blockcnt + nb, &ku, sizeof(uint32_t));
+    const int kU = (int)std::min<uint32_t>(ku, (uint32_t)(3 * K));
+    const Supp SU{c.bits[iU], c.wpre[iU], c.list[iU], kU};
+    const bool w = warm && it > 1;
+    if (w) remap<T>(c, c.list[iT], xT, K, c.list[iU], xU, kU);
+    cg_solve<T>(c, SU, xU, w, tol, cg_cap(prm, kU));
+    topk_compact<T>(c, xU, c.list[iU], kU, K, c.bits[iN]);
+    bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
+    remap<T>(c, c.list[iU], xU, kU, c.list[iN], xN, K);
+    const bool same = it > 1 && bits_equal(c.bits[iN], c.bits[iT], words, c.ibuf + 8, s);
+    const Supp SN{c.bits[iN], c.wpre[iN], c.list[iN], K};
+    const double rn2 = resid_corr<T>(c, SN, xN);
+    if (same) {
+      std::swap(iT, iN);
+      std::swap(xT, xN);
+      rn = rn2;
+      stopped = true;
+      break;
+    }
+    if (it > 1 && rn2 > rn) {   // keep the previous (T, x)
+      stopped = true;
+      break;
+    }
+    std::swap(iT, iN);
+    std::swap(xT, xN);
+    rn = rn2;
+  }
+  if (!stopped) c.flags |= CS_F_OUTER_MAXITER;
+  write_output<T>(c, c.list[iT], xT, K, s_out, supp_out);
+  if (info) { info->outer_iters = rounds; info->resid_norm = rn; }
+}
+
 #define CS_INST(T)                                                                                   \
   template void run_omp<T>(Ctx<T>&, int, double, const cs_params&, T*, int32_t*, cs_info*);       \
   template void run_sp<T>(Ctx<T>&, int, double, const cs_params&, T*, int32_t*, cs_info*);        \
   template void run_ompr<T>(Ctx<T>&, int, double, const cs_params&, T*, int32_t*, cs_info*);      \
+  template void run_cosamp<T>(Ctx<T>&, int, double, const cs_params&, T*, int32_t*, cs_info*);    \
   template void write_output<T>(Ctx<T>&, const int32_t*, const T*, int, T*, int32_t*);
 CS_INST(float)
 CS_INST(double)

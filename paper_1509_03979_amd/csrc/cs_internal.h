@@ -200,6 +200,7 @@ struct CgScalars {
   double resid2;          // ||y - A x||^2 of the last residual pass
   double dq;              // d^T H d of the current iteration
   double beta;            // next direction update coefficient
+  double ref;             // the stopping test is r^T r <= tol2 * ref: ref = b^T b (relative) or 1 (absolute)
   int32_t done;
   int32_t iters;
   int32_t flags;
@@ -259,6 +260,7 @@ struct Ctx {
   CgScalars* cg;
   SelState* sel;
   double ynorm = 0;        // ||y||, FP64 accumulation
+  int tol_abs = 0;         // CG tolerance absolute (||r|| <= tol) instead of relative
   // host-side counters
   int64_t transforms = 0;
   int64_t cg_iters = 0;
@@ -278,7 +280,7 @@ struct BState {
   int32_t it;             // CG iteration within the current solve
   int32_t swaps;          // OMPR swaps done
   int32_t k, max_outer, cg_cap, flags;
-  int32_t warm, jd[2], pad;
+  int32_t warm, jd[2], tol_abs;
   int64_t cg_iters, transforms;
   double rn, bb, tol2, eta, ynorm, model_bytes;
 };
@@ -406,6 +408,8 @@ template <typename T>
 void run_sp(Ctx<T>& c, int k, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info);
 template <typename T>
 void run_ompr(Ctx<T>& c, int k, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info);
+template <typename T>
+void run_cosamp(Ctx<T>& c, int k, double tol, const cs_params& prm, T* s_out, int32_t* supp_out, cs_info* info);
 template <typename T>
 void write_output(Ctx<T>& c, const int32_t* list, const T* x, int k, T* s_out, int32_t* supp_out);
 

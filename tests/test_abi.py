@@ -60,7 +60,8 @@ def _call(fn, dt=cs.CS_F32, n=1024, m=256, k=10, tol=1e-6, y=FAKE, s=FAKE, supp=
               ctypes.c_void_p(ws) if ws else None, ws_bytes, None, None)
 
 
-@pytest.mark.parametrize("fn", [cs.lib.cs_recover_omp, cs.lib.cs_recover_sp, cs.lib.cs_recover_ompr])
+@pytest.mark.parametrize("fn", [cs.lib.cs_recover_omp, cs.lib.cs_recover_sp, cs.lib.cs_recover_ompr,
+                                cs.lib.cs_recover_cosamp])
 def test_host_validation(fn):
     assert _call(fn, dt=5) == cs.CS_E_INVALID
     assert _call(fn, op=False) == cs.CS_E_INVALID
@@ -86,6 +87,15 @@ def test_host_validation(fn):
 
 def test_sp_needs_2k_le_m():
     assert _call(cs.lib.cs_recover_sp, m=256, k=129) == cs.CS_E_SHAPE
+    assert _call(cs.lib.cs_recover_cosamp, m=256, k=86) == cs.CS_E_SHAPE         # CoSaMP: 3K <= M
+    assert _call(cs.lib.cs_recover_cosamp, m=256, k=85, ws_bytes=100) == cs.CS_E_WORKSPACE
+    assert cs.cs_workspace_size(cs.CS_F32, 1024, 256, 86, cs.CS_ALGO_COSAMP) == 0
+    o = cs.cs_op(1024, 256, FAKE, FAKE)
+    for l in (-1, 11):                                                            # OMPR l in [1, K]
+        prm = cs.cs_params(0, 0, 1, 0, 0.0, 0, l)
+        assert cs.lib.cs_recover_ompr(cs.CS_F32, ctypes.c_void_p(FAKE), ctypes.byref(o), 10, 1e-6,
+                                      ctypes.c_void_p(FAKE), ctypes.c_void_p(FAKE), ctypes.byref(prm),
+                                      ctypes.c_void_p(FAKE), 1 << 40, None, None) == cs.CS_E_INVALID
     assert _call(cs.lib.cs_recover_ompr, m=256, k=129, ws_bytes=100) == cs.CS_E_WORKSPACE  # passes shape checks
 
 
