@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated SP leg (64 signals)")
     ap.add_argument("--no-single-loop", action="store_true", help="batched leg: skip the single-signal loop")
     ap.add_argument("--no-tune", action="store_true", help="keep the default transform shape (no autotuner)")
+    ap.add_argument("--no-xi-sweep", action="store_true", help="skip the precision sweep on the paper's shape")
+    ap.add_argument("--xi-sweep-max-log-n", type=int, default=18, help="largest log2 N of the precision sweep")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="end with three plain device copies of this many MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -233,6 +235,45 @@ def adjoint_leg(torch, cs, batch: int, reps: int = 3) -> dict:
             "backward_over_forward": round((tb - tf) / tf, 3)}
 
 
+def xi_sweep_leg(torch, cs, ns, algos=("sp", "ompr", "omp")) -> dict:
+    """The precision experiment of the paper's Tables II-IV on its problem shape
+    (M = N/4, K = M/4, N(0,1) nonzeros, noise sigma 0.01), FP64: CG run to
+    'exact' precision (relative 1e-12) and stopped at the absolute thresholds
+    ||r|| <= 1e-10 and <= 1e-5 of Algorithm 1 line 15.  Per (algorithm, N):
+    seconds per recovery and reconstruction SNR 20 log10(||s|| / ||s_hat - s||),
+    with the SNR change against exact.  OMP (K iterations) runs up to N = 2^14,
+    OMPR up to 2^16."""
+    import synth
+    out = {}
+    for n in ns:
+        d = synth.paper_problem(n)
+        op = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+        s_true = torch.as_tensor(d.s_dense(), dtype=torch.float64, device="cuda")
+        y0 = cs.cs_apply_A(s_true, op).cpu().numpy()
+        y = torch.as_tensor(y0 + d.noise_scale(0.0) * d.noise, dtype=torch.float64, device="cuda")
+        s_np = d.s_dense()
+        for algo in algos:
+            if n > {"omp": 2 ** 14, "ompr": 2 ** 16}.get(algo, 2 ** 30):
+                continue
+            fn = getattr(cs, f"cs_recover_{algo}")
+            row = {}
+            for label, tol, absolute in [("exact", 1e-12, False)] + [(f"xi_{x:g}", x, True)
+                                                                     for x in synth.PAPER_SHAPED["xis"]]:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s_hat, supp, info = fn(y, op, d.k, tol, tol_abs=absolute)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                err = np.linalg.norm(s_hat.cpu().numpy() - s_np)
+                snr = float(20 * np.log10(np.linalg.norm(s_np) / err)) if err > 0 else float("inf")
+                row[label] = {"seconds": round(dt, 5), "snr_db": round(snr, 4), "cg_iters": info["cg_iters"],
+                              "outer_iters": info["outer_iters"]}
+            for label in row:
+                row[label]["snr_delta_vs_exact_db"] = round(row[label]["snr_db"] - row["exact"]["snr_db"], 4)
+            out[f"{algo}_n{n}"] = row
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -355,6 +396,8 @@ def main():
         extra["ompr_batched_256"] = batched_leg(torch, cs, 256, not args.no_single_loop)
     if not args.no_adjoint:
         extra["sp_adjoint_n2p16"] = adjoint_leg(torch, cs, 64)
+    if not args.no_xi_sweep:
+        extra["xi_sweep_paper_shape"] = xi_sweep_leg(torch, cs, [2 ** l for l in range(12, args.xi_sweep_max_log_n + 1, 2)])
 
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "signals/s", "n_gpus": 1, "steps": args.steps,

@@ -47,6 +47,7 @@ class Draw:
     vals: np.ndarray
     noise: np.ndarray | None
     snr_db: float | None
+    noise_sigma: float | None = None
 
     def s_dense(self) -> np.ndarray:
         s = np.zeros(self.n)
@@ -54,7 +55,10 @@ class Draw:
         return s
 
     def noise_scale(self, y0_norm: float) -> float:
-        """Noise standard deviation that gives ``snr_db``: ||y0|| / sqrt(M) * 10^(-SNR/20)."""
+        """Noise standard deviation: ``noise_sigma`` when given, else the one that
+        gives ``snr_db``: ||y0|| / sqrt(M) * 10^(-SNR/20)."""
+        if self.noise_sigma is not None:
+            return float(self.noise_sigma)
         if self.snr_db is None:
             return 0.0
         return float(y0_norm) / np.sqrt(self.m) * 10.0 ** (-self.snr_db / 20.0)
@@ -84,7 +88,7 @@ def draw_values(rng: np.random.Generator, k: int, kind: str) -> np.ndarray:
 
 
 def draw_problem(cfg: int, sig: int, n: int, m: int, k: int, values: str = "normal",
-                 snr_db: float | None = None) -> Draw:
+                 snr_db: float | None = None, noise_sigma: float | None = None) -> Draw:
     if not (1 <= k <= m <= n):
         raise ValueError("need 1 <= K <= M <= N")
     rows, signs = draw_operator(rng_for(cfg, sig, STREAM_OPERATOR), n, m)
@@ -92,9 +96,20 @@ def draw_problem(cfg: int, sig: int, n: int, m: int, k: int, values: str = "norm
     supp = np.sort(rs.choice(n, k, replace=False)).astype(np.int32)
     vals = draw_values(rs, k, values)
     noise = None
-    if snr_db is not None:
+    if snr_db is not None or noise_sigma is not None:
         noise = rng_for(cfg, sig, STREAM_NOISE).standard_normal(m)
-    return Draw(n, m, k, rows, signs, supp, vals, noise, snr_db)
+    return Draw(n, m, k, rows, signs, supp, vals, noise, snr_db, noise_sigma)
+
+
+# The paper's experimental set-up (Sec. IV-A): M = N/4, K = M/4, Gaussian
+# nonzeros with sigma_on = 1, additive noise with sigma = 0.01; the precision
+# experiment compares exact CG with the absolute thresholds 1e-10 and 1e-5.
+PAPER_SHAPED = dict(cfg=6, values="normal", noise_sigma=0.01, xis=(1e-10, 1e-5))
+
+
+def paper_problem(n: int, sig: int = 0) -> Draw:
+    w = PAPER_SHAPED
+    return draw_problem(w["cfg"], sig, n, n // 4, n // 16, w["values"], None, w["noise_sigma"])
 
 
 # ---------------------------------------------------------------- workloads

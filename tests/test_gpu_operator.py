@@ -145,3 +145,27 @@ def test_ls_iteration_bound_fp64():
         th, info = cs.cs_ls_solve(to_dev(y, torch.float64), dop, to_dev(d.supp, torch.int32), 1e-12)
         assert info["cg_iters"] <= k + 2
         assert rel(th.cpu().numpy(), oracle.ls(op, d.supp, y)) <= 1e-10
+
+
+@pytest.mark.parametrize("xi", [1e-10, 1e-5, 1e-2])
+def test_ls_solve_absolute_tolerance(xi):
+    """With tol_abs the CG of Algorithm 1 stops on the printed test ||r_j|| <= xi
+    (absolute): the normal-equation residual of the returned solution, computed
+    by the oracle, is at most xi (1% slack for the recursive residual), and a
+    looser xi takes no more iterations."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    n, m, k = 2 ** 14, 2 ** 12, 300
+    d = synth.draw_problem(72, 0, n, m, k, "normal", None, 0.01)
+    op = oracle.SRM(n, d.rows, d.signs)
+    y = op.apply_sparse(d.supp, d.vals) + 0.01 * d.noise
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    S = d.supp.astype(np.int32)
+    announce("ls_solve abs", xi)
+    th, info = cs.cs_ls_solve(to_dev(y, torch.float64), dop, to_dev(S, torch.int32), xi, tol_abs=True)
+    th = th.cpu().numpy()
+    a = op.columns(S)
+    r = a.T @ y - a.T @ (a @ th)
+    assert np.linalg.norm(r) <= 1.01 * xi, (np.linalg.norm(r), info)
+    _, info_loose = cs.cs_ls_solve(to_dev(y, torch.float64), dop, to_dev(S, torch.int32), 10 * xi, tol_abs=True)
+    assert info_loose["cg_iters"] <= info["cg_iters"]
