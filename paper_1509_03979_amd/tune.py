@@ -3,6 +3,7 @@
     import paper_1509_03979_amd.tune as tune
     choice = tune.tune(ns=[2**14, 2**15, 2**16, 2**17, 2**18], dtype="f32")   # times, installs, caches
     tune.load()                                                           # later processes: install cached
+    tune.load("f32", tune.SHIPPED)       # the cache shipped for MI355X (all workload sizes)
 
 For every N it times each compiled four-step shape (cs_shape_candidates) on
 one H-apply with the library's own timer (cs_time_shape, HIP events), keeps
@@ -114,6 +115,28 @@ def save_cg_block(cg_block: int, dtype: str = "f32", path: str | None = None) ->
     data = _read(path)
     data.setdefault(f"{_device_key(torch)}|{dtype}", {"shapes": {}})["cg_block"] = int(cg_block)
     _write(path, data)
+
+
+# The sizes the shipped workloads run at, per dtype.
+WORKLOAD_SIZES = {"f32": [2 ** 14, 2 ** 15, 2 ** 16, 2 ** 17, 2 ** 18, 2 ** 20, 2 ** 24], "f64": [2 ** 12]}
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_mi355x.json")
+
+
+def tune_workloads(path: str = SHIPPED, reps: int = 20, cg_block_fn=None) -> dict:
+    """Tunes every workload size (and, given cg_block_fn(b) that runs one batched
+    call, the batched CG block size) and writes the cache to `path`."""
+    import torch
+    data = _read(path)
+    for dtype, ns in WORKLOAD_SIZES.items():
+        res = tune_shapes(ns, dtype, reps)
+        ent = data.setdefault(f"{_device_key(torch)}|{dtype}", {"shapes": {}})
+        for n, r in res.items():
+            ent["shapes"][str(n)] = {"shape": list(r["shape"]), "ms": r["ms"], "default": list(r["default"]),
+                                     "all": r["all"]}
+    if cg_block_fn is not None:
+        data[f"{_device_key(torch)}|f32"]["cg_block"] = int(tune_cg_block(cg_block_fn)["cg_block"])
+    _write(path, data)
+    return data
 
 
 def load(dtype: str = "f32", path: str | None = None) -> dict:
