@@ -4,8 +4,11 @@ For A = D_rows F diag(signs) (Eq. (7) with F the orthonormal DCT-II), column
 j is  a_j[k] = signs_j c_k cos(pi (2j+1) k / (2N)),  k in rows.  The
 product-to-sum identity cos(a) cos(b) = (cos(a-b) + cos(a+b)) / 2 gives
 
-    (A_S^T A_S)[p, q] = 1/2 signs_i signs_j [ g(i - j) + g(i + j + 1) ],
+    (A_S^T A_S)[p, q] = 1/2 signs_i signs_j [ g(i' - j') + g(i' + j' + 1) ],
     g(m) = sum_{k in rows} c_k^2 cos(pi m k / N),     i = S[p], j = S[q],
+
+with i', j' the DCT input indices of i and j (i' = i without a permutation
+in the randomizer),
 
 a Toeplitz-plus-Hankel matrix whose generator g (even, 2N-periodic) comes
 from one length-2N FFT of the weighted row mask.  This is derived here from
@@ -36,6 +39,7 @@ def gram_matrix(op: SRM, supp, g: np.ndarray | None = None) -> np.ndarray:
         g = gram_generator(op)
     s = np.asarray(supp, dtype=np.int64)
     sg = op.signs[s]
-    diff = np.abs(s[:, None] - s[None, :])
-    summ = s[:, None] + s[None, :] + 1
+    q = op.dct_index(s)                       # the DCT input index of each column
+    diff = np.abs(q[:, None] - q[None, :])
+    summ = q[:, None] + q[None, :] + 1
     return 0.5 * (sg[:, None] * sg[None, :]) * (g[diff] + g[summ])

@@ -44,9 +44,14 @@ def dct2_matrix(n: int) -> np.ndarray:
 
 
 class SRM:
-    """A = D_rows . DCT-II . diag(signs), an M x N operator (FP64)."""
+    """A = D_rows . DCT-II . R, an M x N operator (FP64).
 
-    def __init__(self, n: int, rows, signs):
+    R is the randomizer: entry j of x goes to DCT input perm[j] with sign
+    signs[j] ((R x)[perm[j]] = signs[j] x[j]); perm = None is the identity, so
+    R = diag(signs).  The paper's R is a uniform random permutation (signs all
+    +1); the workloads here use the sign flip."""
+
+    def __init__(self, n: int, rows, signs, perm=None):
         rows = np.asarray(rows, dtype=np.int64)
         signs = np.asarray(signs)
         if rows.ndim != 1 or signs.shape != (n,):
@@ -59,12 +64,36 @@ class SRM:
         self.m = int(rows.size)
         self.rows = rows
         self.signs = signs.astype(np.float64)
+        self.perm = None
+        if perm is not None:
+            perm = np.asarray(perm, dtype=np.int64)
+            if perm.shape != (n,) or not np.array_equal(np.sort(perm), np.arange(n)):
+                raise ValueError("perm must be a permutation of [0, n)")
+            self.perm = perm
+
+    def _place(self, x: np.ndarray) -> np.ndarray:
+        """R x: the DCT input."""
+        v = self.signs * x
+        if self.perm is None:
+            return v
+        out = np.zeros(self.n)
+        out[self.perm] = v
+        return out
+
+    def _unplace(self, w: np.ndarray) -> np.ndarray:
+        """R^T w."""
+        return self.signs * (w if self.perm is None else w[self.perm])
+
+    def dct_index(self, j) -> np.ndarray:
+        """DCT input index of entry j of x."""
+        j = np.asarray(j, dtype=np.int64)
+        return j if self.perm is None else self.perm[j]
 
     # ---------------------------------------------------------- FFT route
     def apply(self, x: np.ndarray) -> np.ndarray:
         """A x for a dense N-vector x."""
         x = np.asarray(x, dtype=np.float64)
-        return sfft.dct(self.signs * x, type=2, norm="ortho", workers=WORKERS)[self.rows]
+        return sfft.dct(self._place(x), type=2, norm="ortho", workers=WORKERS)[self.rows]
 
     def apply_sparse(self, supp, vals) -> np.ndarray:
         """A x where x is zero off ``supp`` and equals ``vals`` on it."""
@@ -76,14 +105,14 @@ class SRM:
         """A^T u for an M-vector u: zero-fill, orthonormal DCT-III, sign flip."""
         full = np.zeros(self.n)
         full[self.rows] = np.asarray(u, dtype=np.float64)
-        return self.signs * sfft.idct(full, type=2, norm="ortho", workers=WORKERS)
+        return self._unplace(sfft.idct(full, type=2, norm="ortho", workers=WORKERS))
 
     # ---------------------------------------------------- formula route
     def columns(self, supp) -> np.ndarray:
         """Dense A_S (M x |S|) from the cosine formula."""
         j = np.asarray(supp, dtype=np.int64)[None, :]
         k = self.rows[:, None]
-        return _dct_scale(k, self.n) * _cos_table(k, j, self.n) * self.signs[j]
+        return _dct_scale(k, self.n) * _cos_table(k, self.dct_index(j), self.n) * self.signs[j]
 
     def dense(self) -> np.ndarray:
         return self.columns(np.arange(self.n))

@@ -48,6 +48,7 @@ class Draw:
     noise: np.ndarray | None
     snr_db: float | None
     noise_sigma: float | None = None
+    perm: np.ndarray | None = None     # randomizer permutation (int32[N]), or None
 
     def s_dense(self) -> np.ndarray:
         s = np.zeros(self.n)
@@ -88,17 +89,26 @@ def draw_values(rng: np.random.Generator, k: int, kind: str) -> np.ndarray:
 
 
 def draw_problem(cfg: int, sig: int, n: int, m: int, k: int, values: str = "normal",
-                 snr_db: float | None = None, noise_sigma: float | None = None) -> Draw:
+                 snr_db: float | None = None, noise_sigma: float | None = None,
+                 randomizer: str = "signs") -> Draw:
+    """randomizer: "signs" (R = random sign flip), "perm" (R = a uniform random
+    permutation, signs all +1: the paper's SRM) or "signed_perm" (both)."""
     if not (1 <= k <= m <= n):
         raise ValueError("need 1 <= K <= M <= N")
-    rows, signs = draw_operator(rng_for(cfg, sig, STREAM_OPERATOR), n, m)
+    ro = rng_for(cfg, sig, STREAM_OPERATOR)
+    rows, signs = draw_operator(ro, n, m)
+    perm = None
+    if randomizer in ("perm", "signed_perm"):
+        perm = ro.permutation(n).astype(np.int32)        # drawn after rows and signs
+        if randomizer == "perm":
+            signs = np.ones(n, dtype=np.int8)
     rs = rng_for(cfg, sig, STREAM_SIGNAL)
     supp = np.sort(rs.choice(n, k, replace=False)).astype(np.int32)
     vals = draw_values(rs, k, values)
     noise = None
     if snr_db is not None or noise_sigma is not None:
         noise = rng_for(cfg, sig, STREAM_NOISE).standard_normal(m)
-    return Draw(n, m, k, rows, signs, supp, vals, noise, snr_db, noise_sigma)
+    return Draw(n, m, k, rows, signs, supp, vals, noise, snr_db, noise_sigma, perm)
 
 
 # The paper's experimental set-up (Sec. IV-A): M = N/4, K = M/4, Gaussian
@@ -107,9 +117,9 @@ def draw_problem(cfg: int, sig: int, n: int, m: int, k: int, values: str = "norm
 PAPER_SHAPED = dict(cfg=6, values="normal", noise_sigma=0.01, xis=(1e-10, 1e-5))
 
 
-def paper_problem(n: int, sig: int = 0) -> Draw:
+def paper_problem(n: int, sig: int = 0, randomizer: str = "signs") -> Draw:
     w = PAPER_SHAPED
-    return draw_problem(w["cfg"], sig, n, n // 4, n // 16, w["values"], None, w["noise_sigma"])
+    return draw_problem(w["cfg"], sig, n, n // 4, n // 16, w["values"], None, w["noise_sigma"], randomizer)
 
 
 # ---------------------------------------------------------------- workloads

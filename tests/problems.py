@@ -11,7 +11,7 @@ import synth
 
 
 def build(d: synth.Draw, dtype: str = "f64"):
-    op = oracle.SRM(d.n, d.rows, d.signs)
+    op = oracle.SRM(d.n, d.rows, d.signs, d.perm)
     y0 = op.apply_sparse(d.supp, d.vals)
     y = y0 + d.noise_scale(np.linalg.norm(y0)) * d.noise if d.noise is not None else y0
     if dtype == "f32":
@@ -19,7 +19,7 @@ def build(d: synth.Draw, dtype: str = "f64"):
     return op, y
 
 
-def problem(cfg, sig, n, m, k, values="normal", snr_db=None, dtype="f64"):
-    d = synth.draw_problem(cfg, sig, n, m, k, values, snr_db)
+def problem(cfg, sig, n, m, k, values="normal", snr_db=None, dtype="f64", randomizer="signs"):
+    d = synth.draw_problem(cfg, sig, n, m, k, values, snr_db, randomizer=randomizer)
     op, y = build(d, dtype)
     return d, op, y

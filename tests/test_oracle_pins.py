@@ -484,3 +484,34 @@ def test_planted_mistake_is_caught(name, monkeypatch):
 
 def test_all_pins_pass_unmutated():
     assert all(p() for p in ALL_PINS + [_pin_ties])
+
+
+# ------------------------------------------------------------------ permutation randomizer
+@pytest.mark.parametrize("randomizer", ["perm", "signed_perm"])
+def test_p2_permutation_randomizer(randomizer):
+    """R as a permutation (the paper's SRM): the FFT route equals the cosine
+    formula, A A^T = I, the closed-form Gram equals A_S^T A_S, and A equals the
+    unpermuted operator applied to the scattered vector (x'[perm[j]] = x[j])."""
+    d = synth.draw_problem(103, 0, 512, 150, 10, "normal", None, randomizer=randomizer)
+    op = oracle.SRM(d.n, d.rows, d.signs, d.perm)
+    plain = oracle.SRM(d.n, d.rows, d.signs if randomizer == "signed_perm" else np.ones(d.n))
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(d.n)
+    u = rng.standard_normal(d.m)
+    assert np.allclose(op.apply(x), op.dense() @ x, atol=1e-12)
+    assert np.allclose(op.apply(op.adjoint(u)), u, atol=1e-13)
+    assert abs(op.apply(x) @ u - x @ op.adjoint(u)) < 1e-11
+    xs = np.zeros(d.n)
+    xs[d.perm] = d.signs * x                      # R x written out
+    assert np.allclose(op.apply(x), oracle.SRM(d.n, d.rows, np.ones(d.n)).apply(xs), atol=1e-13)
+    S = np.sort(rng.choice(d.n, 25, replace=False))
+    a = op.columns(S)
+    assert np.allclose(oracle.gram_matrix(op, S), a.T @ a, atol=1e-12)
+    assert not np.allclose(op.columns(S), plain.columns(S))        # the permutation matters
+    # recovery on the permuted operator: noiseless, well separated
+    dd = synth.draw_problem(104, 0, 2048, 512, 25, "normal_min0.1", None, randomizer=randomizer)
+    o2 = oracle.SRM(dd.n, dd.rows, dd.signs, dd.perm)
+    y = o2.apply_sparse(dd.supp, dd.vals)
+    for f in (oracle.omp, oracle.sp, oracle.ompr, oracle.cosamp):
+        r = f(o2, y, 25)
+        assert np.array_equal(r.support, dd.supp), f.__name__
