@@ -83,12 +83,17 @@ enum {
   CS_F_NONFINITE = 8       /* a non-finite value reached a selection or a norm        */
 };
 
-/* Sensing operator A = D F R (Eq. (7)). */
+/* Sensing operator A = D F R (Eq. (7)): D keeps rows, F is the orthonormal
+ * DCT-II, R the randomizer: entry j of x enters the DCT at index perm[j]
+ * with sign signs[j].  perm == NULL is the identity (R = diag(signs), the
+ * workloads here); the paper's R is a uniform random permutation (perm with
+ * all signs +1). */
 typedef struct {
   int64_t n;              /* signal length N                                        */
   int64_t m;              /* number of sampled rows M                               */
   const int32_t* rows;    /* device [m]: sampled DCT rows, strictly ascending      */
   const int8_t* signs;    /* device [n]: sign flips, each +1 or -1                  */
+  const int32_t* perm;    /* device [n] permutation of [0, N), or NULL              */
 } cs_op;
 
 /* Optional knobs; pass NULL for the defaults shown. */

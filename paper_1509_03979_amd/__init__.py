@@ -33,7 +33,7 @@ EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_o
 
 class cs_op(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("rows", ctypes.c_void_p),
-                ("signs", ctypes.c_void_p)]
+                ("signs", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
 
 
 class cs_params(ctypes.Structure):
@@ -186,25 +186,32 @@ def _ptr(t):
 
 
 class Operator:
-    """Sensing operator A = D F R (device descriptor): rows int32 [M] ascending, signs int8 [N]."""
+    """Sensing operator A = D F R (device descriptor): rows int32 [M] ascending,
+    signs int8 [N], and optionally perm int32 [N] (the randomizer's permutation;
+    None: R is the sign flip alone)."""
 
-    def __init__(self, n: int, rows, signs):
+    def __init__(self, n: int, rows, signs, perm=None):
         torch = _torch()
         if rows.dtype != torch.int32 or signs.dtype != torch.int8:
             raise TypeError("rows must be int32 and signs int8")
         if not (rows.is_cuda and signs.is_cuda):
             raise ValueError("rows and signs must be device tensors")
+        if perm is not None and (perm.dtype != torch.int32 or not perm.is_cuda or perm.numel() != n):
+            raise ValueError("perm must be an int32 device tensor of length N")
         self.n = int(n)
         self.m = int(rows.numel())
         self.rows = rows.contiguous()
         self.signs = signs.contiguous()
-        self.c = cs_op(self.n, self.m, self.rows.data_ptr(), self.signs.data_ptr())
+        self.perm = perm.contiguous() if perm is not None else None
+        self.c = cs_op(self.n, self.m, self.rows.data_ptr(), self.signs.data_ptr(),
+                       self.perm.data_ptr() if self.perm is not None else None)
 
     @classmethod
-    def from_numpy(cls, n, rows, signs, device="cuda"):
+    def from_numpy(cls, n, rows, signs, perm=None, device="cuda"):
         torch = _torch()
         return cls(n, torch.as_tensor(rows, dtype=torch.int32, device=device),
-                   torch.as_tensor(signs, dtype=torch.int8, device=device))
+                   torch.as_tensor(signs, dtype=torch.int8, device=device),
+                   torch.as_tensor(perm, dtype=torch.int32, device=device) if perm is not None else None)
 
 
 def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0, cg_block=0, tol_abs=False, ompr_l=1):

@@ -40,6 +40,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   c.tw_lo = cv.take<Cx<T>>(kTwLo);
   c.tw_hi = cv.take<Cx<T>>(std::max<int64_t>(1, 4 * n / kTwLo));
   c.mask = cv.take<uint32_t>(p.words);
+  c.pinv = cv.take<int32_t>(n);
   for (int i = 0; i < 3; ++i) c.bits[i] = cv.take<uint32_t>(p.words);
   for (int i = 0; i < 3; ++i) c.wpre[i] = cv.take<uint32_t>(p.words);
   c.nbits = cv.take<uint32_t>(p.words);
@@ -101,6 +102,8 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   p.tw_lo = c.tw_lo;
   p.tw_hi = c.tw_hi;
   p.mask = c.mask;
+  p.perm = op->perm;
+  p.pinv = op->perm ? c.pinv : nullptr;
   c.plan = p;
   c.stream = s;
   c.signs = op->signs;

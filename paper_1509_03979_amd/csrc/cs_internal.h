@@ -88,6 +88,8 @@ struct Plan {
   const void* tw_lo;      // W_{4N}^i, i in [0, 4096)          (Cx<T>)
   const void* tw_hi;      // W_{4N}^{4096 h}, h in [0, 4N/4096) (Cx<T>)
   const uint32_t* mask;   // N bits in freq-layout: bit 2f+h = row sampled
+  const int32_t* perm;    // randomizer permutation: entry j enters the DCT at perm[j] (null: identity)
+  const int32_t* pinv;    // its inverse (null with perm)
 };
 
 constexpr int kTwStage = 8192;   // entries reserved for one stage-twiddle table (size 2^13 needs 8176)
@@ -131,11 +133,15 @@ __host__ __device__ __forceinline__ int64_t pos_of_key(int64_t k, const Plan& pl
   const int64_t n1 = t & (pl.L1 - 1), g = t >> pl.logL1;
   return (((n1 << pl.logL2) + (g << pl.logB) + b) << 1) | h;
 }
-__host__ __device__ __forceinline__ int64_t nat_of_key(int64_t k, const Plan& pl) {
-  return vinv(pos_of_key(k, pl), pl.n);
+// Natural index j of x <-> DCT input index (through the randomizer's
+// permutation, device tables) <-> key.
+__device__ __forceinline__ int64_t nat_of_key(int64_t k, const Plan& pl) {
+  const int64_t q = vinv(pos_of_key(k, pl), pl.n);
+  return pl.pinv ? (int64_t)pl.pinv[q] : q;
 }
-__host__ __device__ __forceinline__ int64_t key_of_nat(int64_t j, const Plan& pl) {
-  return key_of_pos(vpos(j, pl.n), pl);
+__device__ __forceinline__ int64_t key_of_nat(int64_t j, const Plan& pl) {
+  const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
+  return key_of_pos(vpos(q, pl.n), pl);
 }
 
 // W_{4N}^idx = exp(-2 pi i idx / (4N)), idx in [0, 4N), from the two-level table.
@@ -243,6 +249,7 @@ struct Ctx {
   Cx<T>* tw_col; Cx<T>* tw_row;   // stage twiddles of the L1- and L2-point FFTs
   Cx<T>* tw_lo; Cx<T>* tw_hi;
   uint32_t* mask;          // row mask of D, freq-layout bits
+  int32_t* pinv;           // inverse of the randomizer's permutation (N entries)
   // supports: key bitmaps, ascending key lists and per-word prefix counts
   uint32_t* bits[3];
   int32_t* list[3];
@@ -367,8 +374,8 @@ template <typename T> ColIO<T> col_io(Ctx<T>& c, int mode, const Supp* S);   // 
 template <typename T> void transform_fwd(Ctx<T>& c, const T* in, T* outf); // outf = masked DCT in freq layout
 // out = F^T (freq input), in v-order or (key_order) key order
 template <typename T> void transform_adj(Ctx<T>& c, const T* inf, T* out, bool key_order);
-template <typename T> void perm_in(Ctx<T>& c, const T* x, T* dense);      // dense[vpos(j)] = sign_j x_j
-template <typename T> void perm_out(Ctx<T>& c, const T* dense, T* x);     // x_j = sign_j dense[vpos(j)]
+template <typename T> void perm_in(Ctx<T>& c, const T* x, T* dense);      // dense[vpos(perm j)] = sign_j x_j
+template <typename T> void perm_out(Ctx<T>& c, const T* dense, T* x);     // x_j = sign_j dense[vpos(perm j)]
 template <typename T> void prepare_kernels();                             // LDS limits, once per process
 
 // ------------------------------------------------------------------ selection

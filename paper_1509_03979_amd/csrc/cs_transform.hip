@@ -138,6 +138,16 @@ __global__ void k_mask_rows(const int32_t* __restrict__ rows, int64_t m, uint32_
   atomicOr(&mask[fp >> 5], 1u << (fp & 31));
 }
 
+// Inverse of the randomizer's permutation; flags an entry out of range or a
+// repeated one (pinv starts at -1).
+__global__ void k_perm_inverse(const int32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ pinv, int32_t* bad) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int32_t q = perm[j];
+  if (q < 0 || q >= n) { atomicOr(bad, 4); return; }
+  if (atomicCAS(&pinv[q], -1, (int32_t)j) != -1) atomicOr(bad, 4);
+}
+
 __global__ void k_check_signs(const int8_t* __restrict__ s, int64_t n, int32_t* bad) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -186,10 +196,16 @@ void setup_operator(Ctx<T>& c) {
   CS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_check_signs, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.signs, p.n, c.ibuf);
   CS_LAUNCH_CHECK();
+  if (p.perm) {
+    fill<int32_t>(c.pinv, p.n, -1, s);
+    hipLaunchKernelGGL(k_perm_inverse, dim3(nblk(p.n, 256)), dim3(256), 0, s, p.perm, p.n, c.pinv, c.ibuf);
+    CS_LAUNCH_CHECK();
+  }
   int32_t bad = 0;
   dev_read(s, c.ibuf, &bad, sizeof(int32_t));
   if (bad & 1) throw Error(CS_E_OP, "operator rows must be strictly ascending in [0, N)");
   if (bad & 2) throw Error(CS_E_OP, "operator signs must be +1 or -1");
+  if (bad & 4) throw Error(CS_E_OP, "operator perm must be a permutation of [0, N)");
 }
 
 // ------------------------------------------------------------------ host reads
@@ -374,27 +390,29 @@ void transform_adj(Ctx<T>& c, const T* inf, T* out, bool key_order) {
 
 template <typename T>
 __global__ void k_perm_in(const T* __restrict__ x, T* __restrict__ dense, const int8_t* __restrict__ signs,
-                          int64_t n) {
+                          const Plan pl) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  dense[vpos(j, n)] = signs[j] < 0 ? -x[j] : x[j];
+  if (j >= pl.n) return;
+  const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
+  dense[vpos(q, pl.n)] = signs[j] < 0 ? -x[j] : x[j];
 }
 template <typename T>
 __global__ void k_perm_out(const T* __restrict__ dense, T* __restrict__ x, const int8_t* __restrict__ signs,
-                           int64_t n) {
+                           const Plan pl) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const T v = dense[vpos(j, n)];
+  if (j >= pl.n) return;
+  const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
+  const T v = dense[vpos(q, pl.n)];
   x[j] = signs[j] < 0 ? -v : v;
 }
 template <typename T>
 void perm_in(Ctx<T>& c, const T* x, T* dense) {
-  hipLaunchKernelGGL(k_perm_in<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, x, dense, c.signs, c.plan.n);
+  hipLaunchKernelGGL(k_perm_in<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, x, dense, c.signs, c.plan);
   CS_LAUNCH_CHECK();
 }
 template <typename T>
 void perm_out(Ctx<T>& c, const T* dense, T* x) {
-  hipLaunchKernelGGL(k_perm_out<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, dense, x, c.signs, c.plan.n);
+  hipLaunchKernelGGL(k_perm_out<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, dense, x, c.signs, c.plan);
   CS_LAUNCH_CHECK();
 }
 

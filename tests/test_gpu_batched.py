@@ -148,3 +148,25 @@ def test_batched_workload_256_fp32_against_oracle():
         assert m["min_margin"] is not None and m["min_margin"] <= 1e-6 * scale, (i, m)
     print("exact", exact, "certified near-tie trajectories", near, flush=True)
     assert exact >= 0.8 * len(res)
+
+
+def test_batched_with_permutation_randomizer():
+    """Signals whose randomizer is a permutation (the paper's) in one batch."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    sizes = synth.batched_sizes(6, 90, (10, 13))
+    draws, ops, ys, dops = [], [], [], []
+    for sig, (n, m, k) in enumerate(sizes):
+        d = synth.draw_problem(90, sig, n, m, k, "normal", 30.0, randomizer="perm" if sig % 2 else "signed_perm")
+        op, y = build(d, "f64")
+        draws.append(d)
+        ops.append(op)
+        ys.append(y)
+        dops.append(cs.Operator.from_numpy(d.n, d.rows, d.signs, d.perm))
+    batch = cs.Batch([to_dev(y, torch.float64) for y in ys], dops, [d.k for d in draws])
+    announce("batched perm", sizes)
+    s_list, supp_list, infos = cs.cs_recover_ompr_batched(batch, 1e-10)
+    for i, d in enumerate(draws):
+        ref = oracle.ompr(ops[i], ys[i], d.k)
+        assert np.array_equal(supp_list[i].cpu().numpy(), ref.support), i
+        assert rel(s_list[i].cpu().numpy(), ref.s) <= 1e-8, i

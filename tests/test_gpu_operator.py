@@ -169,3 +169,36 @@ def test_ls_solve_absolute_tolerance(xi):
     assert np.linalg.norm(r) <= 1.01 * xi, (np.linalg.norm(r), info)
     _, info_loose = cs.cs_ls_solve(to_dev(y, torch.float64), dop, to_dev(S, torch.int32), 10 * xi, tol_abs=True)
     assert info_loose["cg_iters"] <= info["cg_iters"]
+
+
+@pytest.mark.parametrize("n,m,randomizer,dt", [(4096, 1001, "perm", "f64"), (2 ** 16, 2 ** 14, "signed_perm", "f32"),
+                                               (2 ** 20, 2 ** 18, "perm", "f32")])
+def test_apply_with_permutation_randomizer(n, m, randomizer, dt):
+    """The paper's randomizer (a permutation) through the operator entry points."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d = synth.draw_problem(73, 0, n, m, 5, "normal", None, randomizer=randomizer)
+    op = oracle.SRM(n, d.rows, d.signs, d.perm)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(n)
+    u = rng.standard_normal(m)
+    bar = 1e-13 if dt == "f64" else 3e-6
+    announce("apply perm", n, m, randomizer, dt)
+    assert rel(cs.cs_apply_A(to_dev(x, tdt), dop).cpu().numpy(), op.apply(x)) <= bar
+    assert rel(cs.cs_apply_At(to_dev(u, tdt), dop).cpu().numpy(), op.adjoint(u)) <= bar
+
+
+def test_bad_permutation_is_rejected():
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    n = 1024
+    d = synth.draw_problem(74, 0, n, 300, 5, "normal", None, randomizer="perm")
+    x = to_dev(np.ones(n), torch.float32)
+    for bad in (np.where(np.arange(n) == 7, 9, d.perm), np.where(np.arange(n) == 3, n, d.perm)):
+        dop = cs.Operator.from_numpy(n, d.rows, d.signs, bad.astype(np.int32))
+        announce("bad perm")
+        with pytest.raises(cs.CSError) as e:
+            cs.cs_apply_A(x, dop)
+        assert e.value.status == cs.CS_E_OP

@@ -33,6 +33,11 @@ RECOVER_CASES = [
     ("omprl3_small_40db_f64", 83, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10),
     ("omprl4_small_noiseless_f32", 82, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6),
     ("omprl5_ragged_f64", 85, 2 ** 12, 777, 29, "normal", 35.0, "f64", 1e-10),
+    # the paper's randomizer: a permutation (signs +1), and a signed permutation
+    ("sp_perm_40db_f64", 89, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10, "perm"),
+    ("ompr_perm_noiseless_f32", 89, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6, "perm"),
+    ("omp_perm_f64", 89, 4096, 1024, 50, "normal_min0.1", None, "f64", 1e-10, "signed_perm"),
+    ("cosamp_perm_40db_f64", 89, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10, "signed_perm"),
 ]
 
 
@@ -46,14 +51,15 @@ def _algo(name):
 
 @pytest.mark.parametrize("case", RECOVER_CASES, ids=[c[0] for c in RECOVER_CASES])
 def test_recover_matches_oracle(case):
-    name, cfg, n, m, k, values, snr, dt, tol = case
+    name, cfg, n, m, k, values, snr, dt, tol = case[:9]
+    randomizer = case[9] if len(case) > 9 else "signs"
     torch = torch_dev()
     import paper_1509_03979_amd as cs
     tdt = torch.float64 if dt == "f64" else torch.float32
-    d, op, y = problem(cfg, 0, n, m, k, values, snr, dt)
+    d, op, y = problem(cfg, 0, n, m, k, values, snr, dt, randomizer)
     algo, okw = _algo(name)
     ref = getattr(oracle, algo)(op, y, k, **okw)
-    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm)
     announce("recover", name)
     fn = getattr(cs, f"cs_recover_{algo}")
     s, supp, info = fn(to_dev(y, tdt), dop, k, tol, **({"ompr_l": okw["l"]} if okw else {}))
