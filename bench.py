@@ -67,8 +67,10 @@ def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1509_03979_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        path = os.path.join(csrc, f)
+        if os.path.isfile(path) and f.endswith((".hip", ".h", ".inc")):
+            with open(path, "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -248,7 +250,8 @@ def adjoint_leg(torch, cs, batch: int, reps: int = 3) -> dict:
 
 def xi_sweep_leg(torch, cs, ns, algos=("sp", "ompr", "omp")) -> dict:
     """The precision experiment of the paper's Tables II-IV on its problem shape
-    (M = N/4, K = M/4, N(0,1) nonzeros, noise sigma 0.01), FP64: CG run to
+    (M = N/4, K = M/4, N(0,1) nonzeros, noise sigma 0.01, R a random
+    permutation as in the paper; Psi = I), FP64: CG run to
     'exact' precision (relative 1e-12) and stopped at the absolute thresholds
     ||r|| <= 1e-10 and <= 1e-5 of Algorithm 1 line 15.  Per (algorithm, N):
     seconds per recovery and reconstruction SNR 20 log10(||s|| / ||s_hat - s||),
@@ -258,7 +261,7 @@ def xi_sweep_leg(torch, cs, ns, algos=("sp", "ompr", "omp")) -> dict:
     out = {}
     for n in ns:
         d = synth.paper_problem(n)
-        op = cs.Operator.from_numpy(d.n, d.rows, d.signs)
+        op = cs.Operator.from_numpy(d.n, d.rows, d.signs, d.perm)
         s_true = torch.as_tensor(d.s_dense(), dtype=torch.float64, device="cuda")
         y0 = cs.cs_apply_A(s_true, op).cpu().numpy()
         y = torch.as_tensor(y0 + d.noise_scale(0.0) * d.noise, dtype=torch.float64, device="cuda")

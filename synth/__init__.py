@@ -112,12 +112,13 @@ def draw_problem(cfg: int, sig: int, n: int, m: int, k: int, values: str = "norm
 
 
 # The paper's experimental set-up (Sec. IV-A): M = N/4, K = M/4, Gaussian
-# nonzeros with sigma_on = 1, additive noise with sigma = 0.01; the precision
-# experiment compares exact CG with the absolute thresholds 1e-10 and 1e-5.
-PAPER_SHAPED = dict(cfg=6, values="normal", noise_sigma=0.01, xis=(1e-10, 1e-5))
+# nonzeros with sigma_on = 1, additive noise with sigma = 0.01, R a random
+# permutation (Psi = I here); the precision experiment compares exact CG with
+# the absolute thresholds 1e-10 and 1e-5.
+PAPER_SHAPED = dict(cfg=6, values="normal", noise_sigma=0.01, xis=(1e-10, 1e-5), randomizer="perm")
 
 
-def paper_problem(n: int, sig: int = 0, randomizer: str = "signs") -> Draw:
+def paper_problem(n: int, sig: int = 0, randomizer: str = "perm") -> Draw:
     w = PAPER_SHAPED
     return draw_problem(w["cfg"], sig, n, n // 4, n // 16, w["values"], None, w["noise_sigma"], randomizer)
 
