@@ -80,6 +80,24 @@ __global__ void k_cg_bnorm(const T* __restrict__ b, int k, double* __restrict__ 
   if (threadIdx.x == 0) pbb[blockIdx.x] = acc;
 }
 
+// warm start on a superset of the previous support: with x_0 the previous
+// solution (zero on the new keys), A x_0 is the previous fit, so
+// b - H x_0 = A_S^T (y - A x_prev) = the stored correlation on S.
+// r = d = Cc[keys]; partial r^T r.
+template <typename T>
+__global__ void k_cg_init_corr(const T* __restrict__ cc, const int32_t* __restrict__ list, int k, T* __restrict__ r,
+                               T* __restrict__ d, double* __restrict__ prr) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const T v = cc[list[i]];
+    r[i] = v;
+    d[i] = v;
+    acc += (double)v * (double)v;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) prr[blockIdx.x] = acc;
+}
+
 // cold start: x = 0, r = b; partial r^T r
 template <typename T>
 __global__ void k_cg_init_cold(const T* __restrict__ b, T* __restrict__ x, T* __restrict__ r, int k,
@@ -166,7 +184,7 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
 }
 
 template <typename T>
-int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter, bool b_ready) {
+int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter, bool b_ready, bool r0_corr) {
   hipStream_t s = c.stream;
   const int k = S.k;
   const int nb = red_blocks(k);
@@ -177,7 +195,13 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   if (b_ready) hipLaunchKernelGGL(k_cg_bnorm<T>, dim3(nb), dim3(kRedThreads), 0, s, c.cb, k, pbb);
   else hipLaunchKernelGGL(k_cg_gather_b<T>, dim3(nb), dim3(kRedThreads), 0, s, c.C0, S.list, k, c.cb, pbb);
   CS_LAUNCH_CHECK();
-  if (warm) {
+  if (warm && r0_corr) {
+    hipLaunchKernelGGL(k_cg_init_corr<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.Cc, S.list, k, c.cr, c.cd,
+                       prr);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, nb, pbb, nb, tol * tol, max_iter,
+                       c.tol_abs);
+  } else if (warm) {
     // r = b - H x0, d = r through the transform, partial r^T r per column workgroup
     ColIO<T> in = col_io<T>(c, COL_X, &S);
     in.x = x;
@@ -303,7 +327,7 @@ void remap(Ctx<T>& c, const int32_t* from, const T* x, int kfrom, const int32_t*
 }
 
 #define CS_INST(T)                                                                    \
-  template int cg_solve<T>(Ctx<T>&, const Supp&, T*, bool, double, int, bool);      \
+  template int cg_solve<T>(Ctx<T>&, const Supp&, T*, bool, double, int, bool, bool); \
   template void apply_support<T>(Ctx<T>&, const Supp&, const T*, T*);               \
   template double resid_corr<T>(Ctx<T>&, const Supp&, const T*);                    \
   template void remap<T>(Ctx<T>&, const int32_t*, const T*, int, const int32_t*, T*, int);

@@ -98,7 +98,8 @@ void run_omp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32
     const Supp S{bits, c.wpre[nxt], c.list[nxt], i};
     const bool warm = prm.warm_start != 0 && i > 1;
     if (warm) remap<T>(c, c.list[cur], xc, i - 1, c.list[nxt], xn, i);
-    cg_solve<T>(c, S, xn, warm, tol, cg_cap(prm, i));      // line 06
+    // line 06; the support only grew, so the warm start's residual is the correlation of line 03
+    cg_solve<T>(c, S, xn, warm, tol, cg_cap(prm, i), false, true);
     rn = resid_corr<T>(c, S, xn);                           // line 07 (+ the next line 03's A^T r)
     std::swap(cur, nxt);
     std::swap(xc, xn);
@@ -132,7 +133,8 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
     bits_or(c.bits[iT], c.bits[iN], c.bits[iU], words, s);
     bits_to_list<T>(c, c.bits[iU], c.list[iU], 2 * K, c.wpre[iU]);
     if (warm) remap<T>(c, c.list[iT], xT, K, c.list[iU], xU, 2 * K);
-    cg_solve<T>(c, supp(iU, 2 * K), xU, warm, tol, cg_cap(prm, 2 * K));
+    // T u D contains T and Cc holds A^T r for (T, x): no transform for the warm residual
+    cg_solve<T>(c, supp(iU, 2 * K), xU, warm, tol, cg_cap(prm, 2 * K), false, true);
     topk_compact<T>(c, xU, c.list[iU], 2 * K, K, c.bits[iN]);     // T': top-K of |x~| over T u D
     bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
     if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
@@ -280,7 +282,7 @@ void run_cosamp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, in
     const Supp SU{c.bits[iU], c.wpre[iU], c.list[iU], kU};
     const bool w = warm && it > 1;
     if (w) remap<T>(c, c.list[iT], xT, K, c.list[iU], xU, kU);
-    cg_solve<T>(c, SU, xU, w, tol, cg_cap(prm, kU));
+    cg_solve<T>(c, SU, xU, w, tol, cg_cap(prm, kU), false, true);   // U contains T, Cc is A^T r of (T, x)
     topk_compact<T>(c, xU, c.list[iU], kU, K, c.bits[iN]);
     bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
     remap<T>(c, c.list[iU], xU, kU, c.list[iN], xN, K);

@@ -390,9 +390,13 @@ int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scr
 // Solves the weighted normal equations on support S; x (compact, key order,
 // sign-flipped coordinates) is the start point when `warm`, and receives the
 // solution.  The right-hand side is gathered from C0 unless `b_ready` (then
-// the caller has put it in cb).
+// the caller has put it in cb).  With `r0_corr` the warm start's residual
+// b - H x is taken from the correlation in Cc instead of a transform: valid
+// when S contains the support of the solution Cc was computed from and x is
+// that solution (zero on the new keys).
 template <typename T>
-int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter, bool b_ready = false);
+int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter, bool b_ready = false,
+             bool r0_corr = false);
 
 // outf (freq layout, N reals) = masked DCT of the compact x placed on S: the
 // forward operator on the support, before the row pick.
