@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 namespace csr {
 
@@ -238,17 +239,28 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   // After the first chunk the next is sized from the observed geometric rate
   // of r^T r so that few early-exit launches are queued.
   int it = 0;
-  int chunk = std::min(4, std::max(max_iter, 1));
+  // The first chunk: the iterations the last solve of this size took, plus
+  // one (early-exiting kernels cost far less than a host round trip), else 4.
+  int first = 4;
+  for (int h = 0; h < 2; ++h)
+    if (c.hint_k[h] == k) first = std::max(2, c.hint_it[h] + 1);
+  int chunk = std::min(first, std::max(max_iter, 1));
   CgScalars host{};
   double rr_prev = -1.0;
   int it_prev = 0;
+  // Queued iterations past convergence exit at once; their launches are taken
+  // out of the counters and the timing records once the count is known.
+  struct Queued { int rec[3]; double bytes; };
+  std::vector<Queued> queued;
   while (it < max_iter) {
     const int q = std::min(chunk, max_iter - it);
     for (int u = 0; u < q; ++u, ++it) {
       dir.it = it;
-      launch_col<T>(c, nullptr, c.W, false, dir);
-      launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done);
-      launch_col<T>(c, c.W, nullptr, true, qio);
+      Queued qd{{-1, -1, -1}, 0.0};
+      qd.bytes += launch_col<T>(c, nullptr, c.W, false, dir, &qd.rec[0]);
+      qd.bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, &qd.rec[1]);
+      qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[2]);
+      queued.push_back(qd);
       c.transforms += 2;
       hipLaunchKernelGGL(k_cg_update<T>, dim3(nb), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr, c.cg, it,
                          max_iter);
@@ -275,6 +287,17 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   if (!conv && !(host.flags & CS_F_CG_BREAKDOWN)) c.flags |= CS_F_CG_MAXITER;
   c.flags |= host.flags;
   c.cg_iters += host.iters;
+  for (size_t i = (size_t)std::max(host.iters, 0); i < queued.size(); ++i) {
+    c.transforms -= 2;
+    c.model_bytes -= queued[i].bytes;
+    for (int r : queued[i].rec) prof_discard(r);
+  }
+  if (c.hint_k[0] != k) {
+    c.hint_k[1] = c.hint_k[0];
+    c.hint_it[1] = c.hint_it[0];
+    c.hint_k[0] = k;
+  }
+  c.hint_it[0] = host.iters;
   return host.iters;
 }
 

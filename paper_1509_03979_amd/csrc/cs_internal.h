@@ -271,6 +271,10 @@ struct Ctx {
   // host-side counters
   int64_t transforms = 0;
   int64_t cg_iters = 0;
+  // iterations of the last solves by support size, to size a solve's first
+  // queued chunk of iterations (two entries, most recent first)
+  int hint_k[2] = {-1, -1};
+  int hint_it[2] = {0, 0};
   double model_bytes = 0;
   int32_t flags = 0;
 };
@@ -332,7 +336,8 @@ constexpr int kBitsPerBlockWords = 1024;  // words per block in bitmap compactio
 enum ProfClass { PC_COL_FWD = 0, PC_COL_INV, PC_ROW_HAPPLY, PC_ROW_RESID, PC_ROW_FWD, PC_ROW_ADJ, PC_COUNT };
 bool prof_on();
 int prof_begin(hipStream_t s, hipEvent_t* ev);
-void prof_end(int cls, double bytes, hipEvent_t start, hipStream_t s);
+int prof_end(int cls, double bytes, hipEvent_t start, hipStream_t s);   // record index
+void prof_discard(int idx);   // drop a recorded launch (it exited early: no work done)
 void prof_flush();
 
 // ------------------------------------------------------------------ plan/workspace
@@ -368,8 +373,12 @@ template <typename T> double norm2_host(Ctx<T>& c, const T* v, int64_t count);  
 void fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
 void sum_partials_to(const double* partial, int np, double* out, hipStream_t s);   // *out = sum (one block)
 
-template <typename T> void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<T>& io);
-template <typename T> void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done);
+// Launch a transform pass; returns its algorithmic bytes.  With `rec` the
+// profiling record index (or -1) is stored there.
+template <typename T> double launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<T>& io,
+                                        int* rec = nullptr);
+template <typename T> double launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done,
+                                        int* rec = nullptr);
 template <typename T> ColIO<T> col_io(Ctx<T>& c, int mode, const Supp* S);   // compact I/O on support S
 template <typename T> void transform_fwd(Ctx<T>& c, const T* in, T* outf); // outf = masked DCT in freq layout
 // out = F^T (freq input), in v-order or (key_order) key order

@@ -50,11 +50,17 @@ int prof_begin(hipStream_t s, hipEvent_t* ev) {
   return 0;
 }
 
-void prof_end(int cls, double bytes, hipEvent_t start, hipStream_t s) {
+int prof_end(int cls, double bytes, hipEvent_t start, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t e = get_event();
   CS_HIP(hipEventRecord(e, s));
   g_pending.push_back({cls, bytes, start, e});
+  return (int)g_pending.size() - 1;
+}
+
+void prof_discard(int idx) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (idx >= 0 && idx < (int)g_pending.size()) g_pending[idx].cls = -1;
 }
 
 void prof_flush() {
@@ -63,11 +69,12 @@ void prof_flush() {
     CS_HIP(hipEventSynchronize(p.b));
     float ms = 0.f;
     CS_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    g_free.push_back(p.a);
+    g_free.push_back(p.b);
+    if (p.cls < 0) continue;   // a launch that found its work already done
     g_stats[p.cls].launches += 1;
     g_stats[p.cls].ms += ms;
     g_stats[p.cls].bytes += p.bytes;
-    g_free.push_back(p.a);
-    g_free.push_back(p.b);
   }
   g_pending.clear();
 }

@@ -334,7 +334,7 @@ ColIO<T> col_io(Ctx<T>& c, int mode, const Supp* S) {
 }
 
 template <typename T>
-void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<T>& io) {
+double launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<T>& io, int* rec) {
   const Plan& p = c.plan;
   const KernelSet<T>& ks = kernels_plan<T>(p);
   const unsigned grid = (unsigned)(p.L2 >> p.logB);
@@ -353,12 +353,14 @@ void launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<T>
   auto fn = inv ? ks.col_inv : ks.col_fwd;
   fn<<<dim3(grid), dim3(ks.nt_col), p.lds_col, c.stream>>>(in, out, p, io, c.tw_col);
   CS_LAUNCH_CHECK();
-  if (prof) prof_end(inv ? PC_COL_INV : PC_COL_FWD, bytes, ev, c.stream);
+  const int r = prof ? prof_end(inv ? PC_COL_INV : PC_COL_FWD, bytes, ev, c.stream) : -1;
+  if (rec) *rec = r;
   c.model_bytes += bytes;
+  return bytes;
 }
 
 template <typename T>
-void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done) {
+double launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done, int* rec) {
   const Plan& p = c.plan;
   const KernelSet<T>& ks = kernels_plan<T>(p);
   const unsigned grid = (unsigned)(p.L1 >> 1);
@@ -370,8 +372,10 @@ void launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, con
   if (prof) prof_begin(c.stream, &ev);
   ks.row<<<dim3(grid), dim3(ks.nt_row), p.lds_row, c.stream>>>(c.W, p, mode, fin, fout, partial, done, c.tw_row);
   CS_LAUNCH_CHECK();
-  if (prof) prof_end(PC_ROW_HAPPLY + mode, bytes, ev, c.stream);
+  const int r = prof ? prof_end(PC_ROW_HAPPLY + mode, bytes, ev, c.stream) : -1;
+  if (rec) *rec = r;
   c.model_bytes += bytes;
+  return bytes;
 }
 
 template <typename T>
@@ -453,8 +457,8 @@ void prepare_kernels() {
   template void scatter_freq<T>(Ctx<T>&, const T*, T*);                                 \
   template void gather_freq<T>(Ctx<T>&, const T*, T*);                                  \
   template ColIO<T> col_io<T>(Ctx<T>&, int, const Supp*);                               \
-  template void launch_col<T>(Ctx<T>&, const Cx<T>*, Cx<T>*, bool, const ColIO<T>&);   \
-  template void launch_row<T>(Ctx<T>&, int, const T*, T*, double*, const int*);         \
+  template double launch_col<T>(Ctx<T>&, const Cx<T>*, Cx<T>*, bool, const ColIO<T>&, int*); \
+  template double launch_row<T>(Ctx<T>&, int, const T*, T*, double*, const int*, int*);      \
   template void transform_fwd<T>(Ctx<T>&, const T*, T*);                                \
   template void load_measurements<T>(Ctx<T>&, const T*);                                \
   template void transform_adj<T>(Ctx<T>&, const T*, T*, bool);                              \
