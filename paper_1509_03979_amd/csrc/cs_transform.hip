@@ -125,17 +125,44 @@ __global__ void k_twiddle(Cx<T>* out, int64_t count, int64_t n, int64_t step) {
   out[i] = cx<T>((T)cv, (T)(-sv));
 }
 
-// Builds the freq-layout row mask and validates the descriptor.
-// bad[0] |= 1: rows not strictly ascending or out of range; |= 2: a sign not +-1.
-__global__ void k_mask_rows(const int32_t* __restrict__ rows, int64_t m, uint32_t* __restrict__ mask,
-                            Plan p, int32_t* bad) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Row mask of D in two passes without atomics.  First the rows as a
+// natural-order bitmap: rows ascend, so the rows of one 32-bit word are
+// consecutive and the first of them writes the whole word (the bitmap is
+// cleared beforehand).  Also validates: bad |= 1 when rows are not strictly
+// ascending in [0, N).
+__global__ void k_row_bits(const int32_t* __restrict__ rows, int64_t m, int64_t n, uint32_t* __restrict__ nat,
+                           int32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  int64_t q = rows[i];
-  bool ok = (q >= 0 && q < p.n) && (i == 0 || rows[i - 1] < q);
+  const int64_t q = rows[i];
+  const bool ok = (q >= 0 && q < n) && (i == 0 || rows[i - 1] < q);
   if (!ok) { atomicOr(bad, 1); return; }
-  int64_t fp = fpos(q, p);
-  atomicOr(&mask[fp >> 5], 1u << (fp & 31));
+  const int64_t w = q >> 5;
+  if (i > 0 && (rows[i - 1] >> 5) == w) return;   // not the first row of its word
+  uint32_t word = 0;
+  for (int64_t j = i; j < m; ++j) {
+    const int64_t r = rows[j];
+    if (r < 0 || r >= n || (r >> 5) != w) break;
+    word |= 1u << (r & 31);
+  }
+  nat[w] = word;
+}
+
+// Then the freq-layout mask, one word per thread: bit 2f + h of the mask is
+// DCT output k (h = 0) or N - k (h = 1; L for k = 0) of slot f = (k mod L1) L2
+// + k / L1.
+__global__ void k_mask_from_bits(const uint32_t* __restrict__ nat, uint32_t* __restrict__ mask, const Plan p) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= p.words) return;
+  uint32_t word = 0;
+#pragma unroll 4
+  for (int b = 0; b < 32; ++b) {
+    const int64_t f = 16 * w + (b >> 1);
+    const int64_t k = (f >> p.logL2) + ((f & (p.L2 - 1)) << p.logL1);
+    const int64_t q = (b & 1) == 0 ? k : (k == 0 ? p.L : p.n - k);
+    word |= ((nat[q >> 5] >> (q & 31)) & 1u) << b;
+  }
+  mask[w] = word;
 }
 
 // Inverse of the randomizer's permutation; flags an entry out of range or a
@@ -190,9 +217,11 @@ void setup_operator(Ctx<T>& c) {
   const int64_t nhi = std::max<int64_t>(1, n4 / kTwLo);
   hipLaunchKernelGGL(k_twiddle<T>, dim3(nblk(nhi, 256)), dim3(256), 0, s, c.tw_hi, nhi, n4, (int64_t)kTwLo);
   CS_LAUNCH_CHECK();
-  fill_u32(c.mask, p.words, 0u, s);
+  fill_u32(c.nbits, p.words, 0u, s);          // scratch: the natural-order row bitmap
   fill<int32_t>(c.ibuf, 1, 0, s);
-  hipLaunchKernelGGL(k_mask_rows, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, c.mask, p, c.ibuf);
+  hipLaunchKernelGGL(k_row_bits, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, p.n, c.nbits, c.ibuf);
+  CS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_mask_from_bits, dim3(nblk(p.words, 256)), dim3(256), 0, s, (const uint32_t*)c.nbits, c.mask, p);
   CS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_check_signs, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.signs, p.n, c.ibuf);
   CS_LAUNCH_CHECK();

@@ -32,8 +32,11 @@ def cache_path() -> str:
 
 
 def _device_key(torch) -> str:
+    """Architecture (without feature flags) and compute-unit count: the marketing
+    name differs between driver versions of the same part."""
     p = torch.cuda.get_device_properties(0)
-    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|cu{p.multi_processor_count}"
+    arch = str(getattr(p, "gcnArchName", "")).split(":")[0]
+    return f"{arch}|cu{p.multi_processor_count}"
 
 
 def _read(path):
