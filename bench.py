@@ -253,7 +253,7 @@ def xi_sweep_leg(torch, cs, ns, algos=("sp", "ompr", "omp")) -> dict:
     (M = N/4, K = M/4, N(0,1) nonzeros, noise sigma 0.01, R a random
     permutation as in the paper; Psi = I), FP64: CG run to
     'exact' precision (relative 1e-12) and stopped at the absolute thresholds
-    ||r|| <= 1e-10 and <= 1e-5 of Algorithm 1 line 15.  Per (algorithm, N):
+    ||r|| <= 1e-10 and <= 1e-5 of the CG loop test of Algorithm 1.  Per (algorithm, N):
     seconds per recovery and reconstruction SNR 20 log10(||s|| / ||s_hat - s||),
     with the SNR change against exact.  OMP (K iterations) runs up to N = 2^14,
     OMPR up to 2^16."""

@@ -13,7 +13,7 @@
  * The sparsifying basis is the identity (s is sparse directly).
  *
  * Every least-squares step is the CG-based weighted least squares of
- * Sec. III-B/C (Eqs. (10)-(11), Algorithm 1 lines 11-24): CG on
+ * Sec. III-B/C (Eqs. (10)-(11), the CG function of Algorithm 1): CG on
  * W_S A^T A W_S theta = W_S A^T y, touching A only through the operator.
  *
  * Conventions for every entry point
@@ -106,8 +106,8 @@ typedef struct {
                              Single-signal calls ignore it.                          */
   double ompr_eta;        /* OMPR step eta; <= 0 -> N/M                             */
   int32_t tol_abs;        /* 1: `tol` is absolute, each CG solve stops at
-                             ||b - H theta|| <= tol (the xi of Algorithm 1 line 15
-                             as printed); 0 (default): relative, <= tol ||b||     */
+                             ||b - H theta|| <= tol (the xi of the CG loop test of
+                             Algorithm 1 as printed); 0 (default): relative, <= tol ||b||     */
   int32_t ompr_l;         /* OMPR replacement size l (indices swapped per step);
                              0 -> 1                                                 */
 } cs_params;
@@ -130,7 +130,7 @@ size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_alg
  * Recovery entry points: y [M] -> s [N] (dense, zero off the support) and
  * support [K] (int32, strictly ascending).  `tol` is the CG stopping
  * tolerance, relative: each solve stops when ||b - H theta|| <= tol ||b||
- * (Algorithm 1 line 15 with xi = tol ||b||).
+ * (the CG loop test of Algorithm 1 with xi = tol ||b||).
  *
  * cs_recover_omp:  Sec. II steps 1-4 / Algorithm 1: K iterations of
  *                  argmax |A^T r| outside S, S <- S + t, CG least squares,
@@ -166,11 +166,11 @@ cs_status cs_recover_cosamp(cs_dtype dtype, const void* y, const cs_op* op, int3
                             void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream);
 
 /*
- * The CG function of Algorithm 1 (lines 11-24) on its own: solve the weighted
+ * The CG function of Algorithm 1 on its own: solve the weighted
  * least squares of Eq. (10) through its normal equations, Eq. (11), for the
  * columns `support` [k] (device int32, strictly ascending, in [0, N)).
  * theta [k] receives the solution on the support, in support order.
- * x0 [k] (nullable) is the starting point (NULL: theta = 0, as in line 13).
+ * x0 [k] (nullable) is the starting point (NULL: theta = 0, the algorithm's own start).
  */
 cs_status cs_ls_solve(cs_dtype dtype, const void* y, const cs_op* op, const int32_t* support,
                       int32_t k, double tol, const void* x0, void* theta,

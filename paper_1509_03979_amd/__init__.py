@@ -268,7 +268,7 @@ def cs_recover_cosamp(y, op: Operator, k: int, tol: float, ws=None, stream=None,
 
 
 def cs_ls_solve(y, op: Operator, support, tol: float, x0=None, ws=None, stream=None, **kw):
-    """CG weighted least squares on `support` (Algorithm 1 lines 11-24) -> (theta [k], info)."""
+    """CG weighted least squares on `support` (the CG function of Algorithm 1) -> (theta [k], info)."""
     torch = _torch()
     dt = _dtype_code(y)
     k = int(support.numel())

@@ -66,6 +66,11 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   c.partial2 = cv.take<double>(rows);
   c.pgrid = cv.take<double>(strips);
   c.argpart = cv.take<ArgKey>(kArgBlocks);
+  const SplitLayout sl = split_layout(n);
+  c.rkey = cv.take<T>((int64_t)sl.blocks * sl.cap);
+  c.rpos = cv.take<uint32_t>((int64_t)sl.blocks * sl.cap);
+  c.rcnt = cv.take<int32_t>(2 * (int64_t)sl.blocks);
+  c.hrows = cv.take<uint32_t>(2 * (int64_t)kPassBlocks * 2048);
   c.ibuf = cv.take<int32_t>(64);
   c.blockcnt = cv.take<uint32_t>((p.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords + 2);
   c.cg = cv.take<CgScalars>(1);

@@ -5,7 +5,7 @@
 // single-signal call.  One batched step moves every unfinished signal one
 // stage along the OMPR loop of the single-signal driver:
 //   WARM    r = b - H x (warm start), r^T r, CG set-up
-//   ITER    one CG iteration (Algorithm 1 lines 16-23)
+//   ITER    one CG iteration (the CG loop body of Algorithm 1)
 //   RESID   r = y - A x, ||r||, the correlation F^T D^T r and its argmax
 //   SELECT  the stop tests, the drop step and the swap: the new support's
 //           list, prefix counts, remapped x and right-hand side

@@ -1,4 +1,4 @@
-// CG subsystem: the CG function of Algorithm 1 (lines 11-24) on the weighted
+// CG subsystem: the CG function of Algorithm 1 on the weighted
 // normal equations of Eq. (11),
 //     H theta = b,   H = W_S A^T A W_S,   b = W_S A^T y,
 // restricted to the support S (rows and columns of H off S are zero, so the

@@ -1,4 +1,4 @@
-// Greedy drivers: OMP (Sec. II steps 1-4, Algorithm 1 lines 01-10), SP and
+// Greedy drivers: OMP (Sec. II steps 1-4, the outer loop of Algorithm 1), SP and
 // OMPR (the other two greedy algorithms of Sec. IV), all built from the same
 // three steps: correlation A^T r, support selection, CG least squares.
 //
@@ -90,17 +90,17 @@ void run_omp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32
   fill_u32(bits, c.plan.words, 0u, s);
   double rn = 0.0;
   for (int i = 1; i <= K; ++i) {
-    // line 03: the first correlation is A^T r_0 = A^T y, already in C0
+    // selection: the first correlation is A^T r_0 = A^T y, already in C0
     argmax_excl<T>(c, i == 1 ? (const T*)c.C0 : (const T*)c.Cc, bits, c.ibuf);
-    hipLaunchKernelGGL(k_set_bit_dev, dim3(1), dim3(64), 0, s, bits, (const int32_t*)c.ibuf, c.plan);  // line 04
+    hipLaunchKernelGGL(k_set_bit_dev, dim3(1), dim3(64), 0, s, bits, (const int32_t*)c.ibuf, c.plan);  // S = S u {j}
     CS_LAUNCH_CHECK();
     bits_to_list<T>(c, bits, c.list[nxt], i, c.wpre[nxt]);
     const Supp S{bits, c.wpre[nxt], c.list[nxt], i};
     const bool warm = prm.warm_start != 0 && i > 1;
     if (warm) remap<T>(c, c.list[cur], xc, i - 1, c.list[nxt], xn, i);
-    // line 06; the support only grew, so the warm start's residual is the correlation of line 03
+    // least squares on S; the support only grew, so the warm start's residual is the stored correlation
     cg_solve<T>(c, S, xn, warm, tol, cg_cap(prm, i), false, true);
-    rn = resid_corr<T>(c, S, xn);                           // line 07 (+ the next line 03's A^T r)
+    rn = resid_corr<T>(c, S, xn);                           // residual update (+ the next iteration's A^T r)
     std::swap(cur, nxt);
     std::swap(xc, xn);
   }

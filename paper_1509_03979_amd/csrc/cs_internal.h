@@ -18,6 +18,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 #include <cstddef>
 #include <string>
@@ -215,16 +216,41 @@ struct CgScalars {
   int32_t pad;
 };
 
-struct SelState {          // radix select state
+struct SelHead {           // radix state between the passes of a top-K
   uint64_t prefix, pmask;  // key prefix found so far
-  int64_t need;            // how many of the keys equal to the final prefix to take
-  int64_t count_eq;        // how many keys equal the final prefix
-  uint32_t jprefix, jmask; // tie-break prefix over indices
-  int64_t jneed;
-  uint32_t hist[256];
-  int32_t tie;             // 1 if the index tie-break is active
+  int64_t need;            // how many of the keys matching the prefix to take
+  int32_t mode;            // candidate source
+  int32_t bit;             // unresolved low key bits
+  int32_t tie;             // 1 if more keys equal the threshold than are needed
+  int32_t pending;         // 1 if the previous pass left histogram rows to pick from
+};
+
+struct SelState {          // top-K selection state
+  SelHead head[2];         // double-buffered by pass parity
+  int64_t k;               // K of the current selection
+  uint64_t t_lo, t_hi;     // candidate band of the dense split
+  uint64_t tau;            // threshold key of the last selection
+  int32_t tie_out;         // whether the last selection broke a tie by index
   int32_t nonfinite;
 };
+
+// Dense top-K split: one workgroup of kSplitThreads per block of `per_block`
+// elements (a multiple of 4 kSplitThreads), each with `cap` candidate slots.
+constexpr int kSplitBlocks = 1024;
+constexpr int kSplitThreads = 512;
+struct SplitLayout {
+  int blocks;
+  int64_t per_block;
+  int cap;
+};
+inline SplitLayout split_layout(int64_t n) {
+  constexpr int64_t r = 4 * kSplitThreads;
+  int64_t g = std::min<int64_t>(kSplitBlocks, (n + r - 1) / r);
+  const int64_t eb = ((n + g - 1) / g + r - 1) / r * r;
+  g = (n + eb - 1) / eb;
+  return SplitLayout{(int)g, eb, (int)(eb / 8 + 64)};
+}
+constexpr int kPassBlocks = 32;   // workgroups of a radix pass (one histogram row each)
 
 struct ArgKey {            // argmax key: (magnitude bits + 1, ~index)
   uint64_t hi;
@@ -262,6 +288,10 @@ struct Ctx {
   double* partial2;        // row-pass partials (L1/2)
   double* pgrid;           // column-pass partials (one per column workgroup)
   ArgKey* argpart;         // kArgBlocks
+  void* rkey;              // dense top-K candidates: keys (width of T), positions and
+  uint32_t* rpos;          //   per-block (count, selected count) pairs
+  int32_t* rcnt;
+  uint32_t* hrows;         // radix histogram rows (2 x kPassBlocks x 2048)
   int32_t* ibuf;           // small int scratch (>= 64)
   uint32_t* blockcnt;      // bitmap compaction block counts
   CgScalars* cg;

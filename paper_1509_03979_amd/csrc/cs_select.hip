@@ -1,5 +1,5 @@
-// Selection subsystem: support detection (Eq. (6), Algorithm 1 line 03) and
-// the top-K selections of SP and OMPR.
+// Selection subsystem: support detection (Eq. (6), Algorithm 1) and the
+// top-K selections of SP and OMPR.
 //
 // Every selection ranks candidates by (magnitude descending, index ascending).
 // Candidates live at keys k (the key order of the column passes; natural index
@@ -9,14 +9,22 @@
 // values for non-negative numbers; a key of 0 marks an excluded candidate and
 // every admissible key is bits(|v|) + 1.
 //  * argmax: packed keys (bits + 1, ~index) reduced with wavefront shuffles.
-//  * top-K: MSB-first radix select, 8 bits per pass, on the magnitude key;
-//    if the K-th key is shared by more candidates than are still needed, a
-//    second radix select over the indices (ascending) keeps the lowest ones.
-//    Selected indices are marked in an N-bit bitmap and compacted to a sorted
-//    list with a block prefix sum, so supports come out ascending.
+//  * top-K of a dense vector: a sorted sample brackets the K-th key in a band;
+//    one streaming pass writes the bitmap of the keys above the band and
+//    collects the keys inside it; an MSB-first radix select (11-bit digits)
+//    over those candidates finds the threshold (each pass writes one
+//    histogram row per workgroup, and the next pass sums the rows to fix the
+//    digit, so there are no global atomics and no extra launches); if the K-th
+//    key is shared by more candidates than are still needed, the ones with the
+//    lowest natural indices are kept.  When the band misses (too many keys
+//    above it, too few in it, or a full segment) the same radix passes run
+//    over every key instead.  Top-K of a compact vector runs the radix passes
+//    over its entries.  Supports are compacted from the bitmaps with a block
+//    prefix sum, so they come out ascending.
 #include "cs_device.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace csr {
 
@@ -61,170 +69,622 @@ void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j
   CS_LAUNCH_CHECK();
 }
 
-// ------------------------------------------------------------------ radix select
-// Candidate sources.  Dense: key k of a key-order vector, excluded through a
-// key bitmap.  Compact: entry i of vals at key list[i].  Both report the key
-// (for marking) and the natural index (for ties).
-struct DenseSrc {};
-struct CompactSrc {};
+// ------------------------------------------------------------------ top-K
+// Candidate sources of the radix passes (SelHead::mode).
+enum : int32_t {
+  SEL_DENSE = 0,   // every key of a dense key-order vector (excluded keys count as 0)
+  SEL_SEG = 1,     // the candidate segments written by the dense split
+  SEL_LIST = 2,    // a compact vector with its key list
+  SEL_NONE = 3,    // the split already marked every selected key
+};
 
-template <typename T, typename S>
-__device__ __forceinline__ void cand(const T* __restrict__ vals, const void* __restrict__ aux, int64_t i,
-                                     const Plan& pl, uint64_t& key, uint32_t& j, uint32_t& pos, bool& bad) {
-  if constexpr (std::is_same<S, DenseSrc>::value) {
-    const uint32_t* excl = (const uint32_t*)aux;
-    pos = (uint32_t)i;
-    j = (uint32_t)nat_of_key(i, pl);
-    if (excl && bit_of(excl, i)) { key = 0; return; }
-    const T v = vals[i];
-    bad |= !finite_v(v);
-    key = mag_bits(v) + 1;
-  } else {
-    const int32_t* list = (const int32_t*)aux;
-    pos = (uint32_t)list[i];
-    j = (uint32_t)nat_of_key(pos, pl);
-    const T v = vals[i];
-    bad |= !finite_v(v);
-    key = mag_bits(v) + 1;
-  }
+constexpr int kSample = 2048;     // keys sampled to bracket the K-th key
+constexpr int kDigit = 11;        // radix digit width of the passes
+constexpr int kBins = 1 << kDigit;
+constexpr int kTieCap = 4096;     // tied candidates sorted in LDS by the final pass
+
+// Magnitude key of candidate i of a dense vector: 0 if excluded.
+template <typename T>
+__device__ __forceinline__ uint64_t dense_key(const T* __restrict__ vals, const uint32_t* __restrict__ excl,
+                                              int64_t i) {
+  if (excl && bit_of(excl, i)) return 0;
+  return mag_bits(vals[i]) + 1;
 }
 
-__global__ void k_sel_init(SelState* sel, int64_t need) {
-  if (threadIdx.x == 0) {
-    sel->prefix = 0; sel->pmask = 0; sel->need = need; sel->count_eq = 0;
-    sel->jprefix = 0; sel->jmask = 0; sel->jneed = 0; sel->tie = 0; sel->nonfinite = 0;
-  }
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) sel->hist[i] = 0;
+__device__ __forceinline__ void load4(const float* p, float (&o)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double (&o)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
 }
 
-// phase 0: histogram of key digit at `shift` among keys matching the prefix.
-// phase 1: histogram of index digit among keys equal to the threshold whose
-//          index matches the index prefix (only when the tie-break is active).
-template <typename T, typename S, int PHASE>
-__global__ void k_radix_hist(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, const Plan pl,
-                             SelState* sel, int shift) {
-  __shared__ uint32_t h[256];
-  if (PHASE == 1 && !sel->tie) return;
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) h[i] = 0;
-  __syncthreads();
-  const uint64_t prefix = sel->prefix, pmask = sel->pmask;
-  const uint32_t jprefix = sel->jprefix, jmask = sel->jmask;
-  bool bad = false;
-  const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
-    uint64_t key; uint32_t j, pos;
-    cand<T, S>(vals, aux, i, pl, key, j, pos, bad);
-    if (PHASE == 0) {
-      if ((key & pmask) == prefix) atomicAdd(&h[(key >> shift) & 255u], 1u);
-    } else {
-      if (key == prefix && (j & jmask) == jprefix) atomicAdd(&h[(j >> shift) & 255u], 1u);
+// Candidate records of the dense split store the key in the width of T.
+template <typename T> using RecKey = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+
+__device__ __forceinline__ uint64_t max_key(int keybits) { return keybits >= 64 ? ~0ull : (1ull << keybits) - 1; }
+
+// Sorts LDS keys s[0, P) (P a power of two, <= 2 * blockDim.x * 2) with a
+// bitonic network; ascending or descending.
+__device__ void lds_bitonic(uint64_t* s, int P, bool descending) {
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int str = size >> 1; str > 0; str >>= 1) {
+      for (int q = threadIdx.x; q < (P >> 1); q += blockDim.x) {
+        const int i = 2 * q - (q & (str - 1));
+        const int j = i + str;
+        const bool up = ((i & size) == 0) != descending;   // ascending run
+        const uint64_t a = s[i], b = s[j];
+        if ((a > b) == up) {
+          s[i] = b;
+          s[j] = a;
+        }
+      }
+      __syncthreads();
     }
   }
-  if (PHASE == 0 && bad) atomicOr(&sel->nonfinite, 1);
-  __syncthreads();
-  for (int i = threadIdx.x; i < 256; i += blockDim.x)
-    if (h[i]) atomicAdd(&sel->hist[i], h[i]);
 }
 
-// One block of 256 threads: the histogram is staged in LDS with one load per
-// thread and a suffix (phase 0, digits high to low) or prefix (phase 1,
-// digits low to high) scan picks the digit that holds the `need`-th candidate.
-template <int PHASE>
-__global__ void k_radix_pick(SelState* sel, int shift) {
-  __shared__ int64_t cum[256];
-  __shared__ int64_t hist[256];
+// Inclusive prefix sum over the workgroup (any size up to 1024, a multiple of
+// 64): wavefront shuffles, then the wavefront totals through LDS.
+__device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t* ws) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t a = __shfl_up((long long)v, off, 64);
+    if (lane >= off) v += a;
+  }
+  if (lane == 63) ws[wave] = v;
+  __syncthreads();
+  int64_t pre = 0;
+  for (int i = 0; i < wave; ++i) pre += ws[i];
+  __syncthreads();
+  return v + pre;
+}
+
+// One workgroup of 1024 threads, two keys each: sorts kSample keys taken at
+// hashed offsets of equal strides (all keys when N <= kSample; padding keys
+// are 0) in descending order and sets the candidate band [t_lo, t_hi] so
+// that, with high probability, fewer than K keys lie above t_hi and at least
+// K lie at or above t_lo.  The band only steers the work: the first radix
+// pass checks both counts and falls back to every key when either fails.
+// The sort runs on the top 32 key bits (all of an FP32 key); for longer keys
+// the band is widened to the edges of its 32-bit buckets.  Bitonic network;
+// pairs closer than 128 keys are exchanged with wavefront shuffles, the rest
+// through LDS.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sel_sample(const T* __restrict__ vals, const uint32_t* __restrict__ excl,
+                                                     int64_t n, int64_t k, int keybits, SelState* sel) {
+  __shared__ uint32_t s[kSample];
   const int t = threadIdx.x;
-  if (PHASE == 1 && !sel->tie) {
-    sel->hist[t] = 0;
+  const int S = (int)std::min<int64_t>(kSample, n);   // both powers of two
+  const int64_t stride = n / S;
+  const int kshift = keybits - 32;
+  int64_t pos[2];
+  T val[2];
+  uint32_t xw[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = std::min(2 * t + h, S - 1);
+    uint32_t x = (uint32_t)e * 0x9E3779B1u;
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    pos[h] = (int64_t)e * stride + (int64_t)(x & (uint32_t)(stride - 1));
+    val[h] = vals[pos[h]];
+    xw[h] = excl ? excl[pos[h] >> 5] : 0u;
+  }
+  uint32_t v[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const bool in = 2 * t + h < S && !((xw[h] >> (pos[h] & 31)) & 1u) && finite_v(val[h]);
+    v[h] = in ? (uint32_t)((mag_bits(val[h]) + 1) >> kshift) : 0u;
+  }
+#pragma unroll
+  for (int size = 2; size <= kSample; size <<= 1) {
+    const bool desc = ((2 * t) & size) == 0;
+#pragma unroll
+    for (int str = size >> 1; str > 0; str >>= 1) {
+      if (str == 1) {
+        if ((v[0] < v[1]) == desc) {
+          const uint32_t a = v[0];
+          v[0] = v[1];
+          v[1] = a;
+        }
+        continue;
+      }
+      uint32_t p0, p1;
+      if (str <= 64) {
+        p0 = __shfl_xor(v[0], str >> 1, 64);
+        p1 = __shfl_xor(v[1], str >> 1, 64);
+      } else {
+        s[2 * t] = v[0];
+        s[2 * t + 1] = v[1];
+        __syncthreads();
+        p0 = s[(2 * t) ^ str];
+        p1 = s[(2 * t + 1) ^ str];
+        __syncthreads();
+      }
+      const bool keep_max = (((2 * t) & str) == 0) == desc;
+      v[0] = keep_max ? max(v[0], p0) : min(v[0], p0);
+      v[1] = keep_max ? max(v[1], p1) : min(v[1], p1);
+    }
+  }
+  s[2 * t] = v[0];
+  s[2 * t + 1] = v[1];
+  __syncthreads();
+  if (t == 0) {
+    // expected sample rank of the K-th key and a margin of four standard
+    // deviations of a binomial count (none when the sample is every key)
+    const double r = (double)k * (double)S / (double)n;
+    const double margin = (S == n) ? 0.0 : 4.0 * sqrt(r) + 4.0;
+    const int64_t rh = (int64_t)floor(r - margin), rl = (int64_t)ceil(r + margin);
+    const uint64_t low = kshift ? (1ull << kshift) - 1 : 0ull;   // bits below the sorted ones
+    uint64_t thi = max_key(keybits), tlo = 1;
+    if (rh >= 1) thi = ((uint64_t)s[std::min<int64_t>(rh, S) - 1] << kshift) | low;
+    if (rl >= 1 && rl <= S) tlo = std::max<uint64_t>(1, (uint64_t)s[rl - 1] << kshift);
+    sel->t_lo = tlo;
+    sel->t_hi = thi;
+    sel->k = k;
+    sel->nonfinite = 0;
+  }
+}
+
+// Dense split (kSplitThreads per workgroup).  Workgroup b reads keys
+// [b E, (b+1) E), four consecutive keys per lane, and writes the output bitmap words itself (keys above t_hi set,
+// the rest clear), so no word needs clearing or atomics; keys inside the band
+// go to the workgroup's candidate segment.  Per workgroup it records
+// (candidates found, keys above the band).
+template <typename T>
+__global__ __launch_bounds__(kSplitThreads) void k_sel_split(const T* __restrict__ vals, const uint32_t* __restrict__ excl,
+                                                   int64_t n, int64_t eb, int cap, SelState* sel,
+                                                   RecKey<T>* __restrict__ rkey, uint32_t* __restrict__ rpos,
+                                                   int32_t* __restrict__ rcnt, uint32_t* __restrict__ out_bits) {
+  __shared__ uint32_t s_mid;
+  __shared__ uint32_t s_hi[kSplitThreads / 64];
+  if (threadIdx.x == 0) s_mid = 0u;
+  __syncthreads();
+  const uint64_t t_lo = sel->t_lo, t_hi = sel->t_hi;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t b0 = (int64_t)blockIdx.x * eb;
+  const int64_t end = std::min<int64_t>(n, b0 + eb);
+  RecKey<T>* bk = rkey + (int64_t)blockIdx.x * cap;
+  uint32_t* bp = rpos + (int64_t)blockIdx.x * cap;
+  uint32_t hcnt = 0;
+  bool bad = false;
+  constexpr int U = 4;                           // rounds in flight per iteration
+  constexpr int R = kSplitThreads * 4;            // keys per round
+  for (int64_t r0 = b0; r0 < end; r0 += U * R) {
+    T v[U][4];
+    uint32_t ex[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = r0 + u * R + wave * 256 + lane * 4;
+      if (p < end) {
+        load4(vals + p, v[u]);
+        ex[u] = excl ? (excl[p >> 5] >> (p & 31)) & 0xFu : 0u;
+      } else {
+        v[u][0] = v[u][1] = v[u][2] = v[u][3] = (T)0;
+        ex[u] = 0xFu;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = r0 + u * R + wave * 256 + lane * 4;
+      uint64_t key[4];
+      uint32_t hib = 0, midb = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool x = (ex[u] >> e) & 1u;
+        bad |= !x && !finite_v(v[u][e]);
+        key[e] = x ? 0 : mag_bits(v[u][e]) + 1;
+        if (key[e] > t_hi) hib |= 1u << e;
+        else if (key[e] >= t_lo) midb |= 1u << e;
+      }
+      // eight lanes hold the 32 bits of one word
+      uint32_t w = hib << ((lane & 7) * 4);
+      w |= __shfl_xor(w, 1, 64);
+      w |= __shfl_xor(w, 2, 64);
+      w |= __shfl_xor(w, 4, 64);
+      if ((lane & 7) == 0 && p < end) out_bits[p >> 5] = w;
+      hcnt += __popc(hib);
+      const uint64_t m0 = __ballot(midb & 1u), m1 = __ballot((midb >> 1) & 1u);
+      const uint64_t m2 = __ballot((midb >> 2) & 1u), m3 = __ballot((midb >> 3) & 1u);
+      const uint32_t c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
+      const uint32_t tot = c0 + c1 + c2 + c3;
+      if (tot) {
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&s_mid, tot);
+        base = __shfl(base, 0, 64);
+        const uint32_t o[4] = {base + __popcll(m0 & below), base + c0 + __popcll(m1 & below),
+                               base + c0 + c1 + __popcll(m2 & below), base + c0 + c1 + c2 + __popcll(m3 & below)};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (((midb >> e) & 1u) && o[e] < (uint32_t)cap) {
+            bk[o[e]] = (RecKey<T>)key[e];
+            bp[o[e]] = (uint32_t)(p + e);
+          }
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) hcnt += __shfl_xor(hcnt, off, 64);
+  if (lane == 0) s_hi[wave] = hcnt;
+  if (bad) atomicOr(&sel->nonfinite, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rcnt[2 * blockIdx.x] = (int32_t)s_mid;
+    uint32_t hsum = 0;
+    for (int i = 0; i < kSplitThreads / 64; ++i) hsum += s_hi[i];
+    rcnt[2 * blockIdx.x + 1] = (int32_t)hsum;
+  }
+}
+
+// Dense source: totals of the split.  Candidates come from the segments when
+// fewer than K keys lie above the band and the band holds the rest (or every
+// admissible key), and no segment overflowed; otherwise from every key.
+// Every thread of the workgroup calls it; thread 0 stores the result.
+__device__ __forceinline__ void sel_decide(const SelState* sel, const int32_t* __restrict__ rcnt, int nseg, int cap,
+                                           int keybits, SelHead* out) {
+  double mid = 0.0, hi = 0.0, over = 0.0;
+  for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
+    const int32_t m = rcnt[2 * i], h = rcnt[2 * i + 1];
+    mid += m;
+    hi += h;
+    over += (m > cap) ? 1.0 : 0.0;
+  }
+  mid = block_sum_any(mid);
+  hi = block_sum_any(hi);
+  over = block_sum_any(over);
+  if (threadIdx.x != 0) return;
+  SelHead& hd = *out;
+  const uint64_t t_lo = sel->t_lo, t_hi = sel->t_hi;
+  const int64_t K = sel->k, nh = (int64_t)hi, nm = (int64_t)mid;
+  hd.tie = 0;
+  hd.pending = 0;
+  const bool ok = over == 0.0 && nh <= K && (nh + nm >= K || t_lo == 1);
+  if (!ok) {
+    hd.mode = SEL_DENSE;
+    hd.need = K;
+    hd.prefix = 0;
+    hd.pmask = 0;
+    hd.bit = keybits;
     return;
   }
-  const int64_t h = sel->hist[t];
-  // phase 0 scans digits from 255 down: position q = 255 - digit
-  const int q = (PHASE == 0) ? 255 - t : t;
-  hist[q] = h;
-  __syncthreads();
-  // inclusive scan over q
-  int64_t v = hist[t];
-  cum[t] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int64_t a = (t >= off) ? cum[t - off] : 0;
-    __syncthreads();
-    cum[t] += a;
-    __syncthreads();
+  hd.need = std::min<int64_t>(K - nh, nm);
+  hd.mode = hd.need == 0 ? SEL_NONE : SEL_SEG;
+  hd.bit = 0;
+  hd.prefix = t_hi;
+  hd.pmask = ~0ull;
+  if (hd.need == 0) return;
+  const uint64_t x = t_lo ^ t_hi;   // bits above the highest differing one are shared by the band
+  if (x == 0) {
+    hd.tie = hd.need < nm ? 1 : 0;   // every candidate has the key t_hi
+  } else {
+    const int b = 64 - __clzll((long long)x);
+    hd.bit = b;
+    hd.pmask = b >= 64 ? 0ull : ~((1ull << b) - 1);
+    hd.prefix = t_hi & hd.pmask;
   }
-  const int64_t need = (PHASE == 0) ? sel->need : sel->jneed;
-  const int64_t incl = cum[t], excl = incl - hist[t];
-  __syncthreads();
-  if (excl < need && need <= incl) {          // exactly one q satisfies this (need >= 1)
-    const int d = (PHASE == 0) ? 255 - t : t;
-    if (PHASE == 0) {
-      sel->need = need - excl;
-      sel->prefix |= (uint64_t)d << shift;
-      sel->pmask |= (uint64_t)255 << shift;
-      if (shift == 0) {
-        sel->count_eq = hist[t];
-        sel->tie = (need - excl < hist[t]) ? 1 : 0;
-        sel->jneed = need - excl;
-      }
-    } else {
-      sel->jneed = need - excl;
-      sel->jprefix |= (uint32_t)d << shift;
-      sel->jmask |= 255u << shift;
+}
+
+// Every workgroup (1024 threads, two bins each) sums the histogram rows of the
+// previous pass and fixes the digit (high to low) that holds the need-th
+// candidate; all workgroups reach the same state.
+__device__ __forceinline__ void sel_pick(SelHead& hd, const uint32_t* __restrict__ rows, int nrows, int64_t* sc) {
+  const int w = hd.bit < kDigit ? hd.bit : kDigit, shift = hd.bit - w;
+  const int nb = 1 << w;
+  const int t = threadIdx.x;
+  int64_t c[2] = {0, 0};
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int q = 2 * t + u;
+    if (q < nb) {
+      const int d = nb - 1 - q;
+      uint32_t a[kPassBlocks];
+#pragma unroll
+      for (int r = 0; r < kPassBlocks; ++r) a[r] = r < nrows ? rows[r * kBins + d] : 0u;
+      int64_t sum = 0;
+#pragma unroll
+      for (int r = 0; r < kPassBlocks; ++r) sum += a[r];
+      c[u] = sum;
     }
   }
-  sel->hist[t] = 0;
+  const int64_t loc = c[0] + c[1];
+  const int64_t incl = block_incl_scan(loc, sc), need = hd.need;
+  int64_t run = incl - loc;
+  __syncthreads();   // every thread has read hd.need
+  if (run < need && need <= incl) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (run < need && need <= run + c[u]) {
+        const uint64_t d = (uint64_t)(nb - 1 - (2 * t + u));
+        const int64_t rest = need - run;
+        hd.need = rest;
+        hd.prefix |= d << shift;
+        hd.pmask |= (uint64_t)(nb - 1) << shift;
+        hd.bit = shift;
+        if (shift == 0) hd.tie = rest < c[u] ? 1 : 0;
+      }
+      run += c[u];
+    }
+  }
+  if (t == 0) hd.pending = 0;
+  __syncthreads();
 }
 
-template <typename T, typename S>
-__global__ void k_radix_mark(const T* __restrict__ vals, const void* __restrict__ aux, int64_t count, const Plan pl,
-                             const SelState* __restrict__ sel, uint32_t* __restrict__ bits) {
-  const uint64_t tau = sel->prefix;
-  const int tie = sel->tie;
-  const uint32_t jt = sel->jprefix;
-  bool bad = false;
+// One radix pass p (1024 threads per workgroup, at most kPassBlocks
+// workgroups).  Reads the state left by pass p-1, picks the digit its
+// histogram rows fix, and if key bits remain unresolved writes one histogram
+// row per workgroup of the next digit (up to kDigit bits) among the candidates
+// matching the prefix.  State and rows are double-buffered by pass parity.
+// init = 1 (first pass over a dense split) decides the source; init = 2
+// starts a selection over a list of k entries.  Segments are read one
+// wavefront per segment.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sel_pass(const T* __restrict__ vals, const void* __restrict__ aux,
+                                                   int64_t count, SelState* sel, const RecKey<T>* __restrict__ rkey,
+                                                   const uint32_t* __restrict__ rpos,
+                                                   const int32_t* __restrict__ rcnt, int nseg, int cap,
+                                                   uint32_t* __restrict__ hrows, int p, int init, int64_t k,
+                                                   int keybits) {
+  __shared__ uint32_t h[kBins];
+  __shared__ SelHead hd;
+  __shared__ int64_t sc[16];
+  if (init == 1) {
+    sel_decide(sel, rcnt, nseg, cap, keybits, &hd);
+  } else if (threadIdx.x == 0) {
+    if (init == 2) {
+      hd.mode = SEL_LIST; hd.need = k; hd.prefix = 0; hd.pmask = 0; hd.bit = keybits; hd.tie = 0; hd.pending = 0;
+    } else {
+      hd = sel->head[p & 1];
+    }
+  }
+  __syncthreads();
+  if (hd.pending) sel_pick(hd, hrows + (int64_t)((p - 1) & 1) * kPassBlocks * kBins, (int)gridDim.x, sc);
+  const bool active = hd.mode != SEL_NONE && hd.bit > 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    SelHead o = hd;
+    o.pending = active ? 1 : 0;
+    sel->head[(p + 1) & 1] = o;
+    if (init == 2) sel->nonfinite = 0;
+  }
+  if (!active) return;
+  const int mode = hd.mode;
+  const int w = hd.bit < kDigit ? hd.bit : kDigit, shift = hd.bit - w;
+  const uint32_t dm = (1u << w) - 1;
+  for (uint32_t i = threadIdx.x; i <= dm; i += blockDim.x) h[i] = 0u;
+  __syncthreads();
+  const uint64_t prefix = hd.prefix, pmask = hd.pmask;
+  auto add = [&](uint64_t key) {
+    if ((key & pmask) == prefix) atomicAdd(&h[(uint32_t)(key >> shift) & dm], 1u);
+  };
+  if (mode == SEL_SEG) {
+    const int lane = threadIdx.x & 63;
+    const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+    for (int sg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); sg < nseg; sg += nw) {
+      const int c = std::min(rcnt[2 * sg], cap);
+      const int64_t o = (int64_t)sg * cap;
+      for (int i = lane; i < c; i += 64) add((uint64_t)rkey[o + i]);
+    }
+  } else {
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    if (mode == SEL_DENSE) {
+      const uint32_t* excl = (const uint32_t*)aux;
+      for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st)
+        add(dense_key(vals, excl, i));
+    } else {
+      for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) add(mag_bits(vals[i]) + 1);
+    }
+  }
+  __syncthreads();
+  uint32_t* row = hrows + (int64_t)(p & 1) * kPassBlocks * kBins + (int64_t)blockIdx.x * kBins;
+  for (uint32_t i = threadIdx.x; i <= dm; i += blockDim.x) row[i] = h[i];
+}
+
+// Final pass: picks the last digit, then marks the selected candidates: every
+// key above the threshold tau, and the keys equal to tau (all of them, or, when
+// more share tau than are still needed, the ones with the lowest natural
+// indices).  Segments and lists set bits atomically; the dense source
+// rewrites every word.  Ties are resolved by workgroup 0 alone: the tied
+// candidates are collected and sorted by index in LDS, or, beyond kTieCap of
+// them, found by a radix select over their indices.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, const void* __restrict__ aux,
+                                                    int64_t count, int64_t words, const Plan pl, SelState* sel,
+                                                    const RecKey<T>* __restrict__ rkey,
+                                                    const uint32_t* __restrict__ rpos,
+                                                    const int32_t* __restrict__ rcnt, int nseg, int cap,
+                                                    const uint32_t* __restrict__ hrows, int p, int jbits,
+                                                    uint32_t* __restrict__ bits) {
+  __shared__ SelHead hd;
+  __shared__ int64_t sc[16];
+  __shared__ uint64_t tb[kTieCap];
+  __shared__ uint32_t th[kBins];
+  __shared__ uint32_t s_cnt, s_digit;
+  __shared__ int64_t s_rest;
+  if (threadIdx.x == 0) hd = sel->head[p & 1];
+  __syncthreads();
+  if (hd.pending) sel_pick(hd, hrows + (int64_t)((p - 1) & 1) * kPassBlocks * kBins, (int)gridDim.x, sc);
+  const int mode = hd.mode;
+  if (mode == SEL_NONE) return;
+  const uint64_t tau = hd.prefix;
+  const bool tie = hd.tie != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sel->tau = tau;
+    sel->tie_out = hd.tie;
+  }
+  const int lane = threadIdx.x & 63;
+  const int nw = (int)(gridDim.x * (blockDim.x >> 6));
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
-    uint64_t key; uint32_t j, pos;
-    cand<T, S>(vals, aux, i, pl, key, j, pos, bad);
-    if (key == 0) continue;
-    if (key > tau || (key == tau && (!tie || j <= jt))) atomicOr(&bits[pos >> 5], 1u << (pos & 31));
+  const uint32_t* excl = (const uint32_t*)aux;
+  const int32_t* list = (const int32_t*)aux;
+  // --- keys above tau (and equal to it without a tie)
+  if (mode == SEL_DENSE) {
+    if (tie && blockIdx.x != 0) return;   // workgroup 0 owns every word when it also resolves the tie
+    const int64_t w0 = tie ? threadIdx.x : (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ws = tie ? blockDim.x : st;
+    for (int64_t w = w0; w < words; w += ws) {
+      uint32_t word = 0;
+      for (int e = 0; e < 32; ++e) {
+        const int64_t q = w * 32 + e;
+        if (q < count) {
+          const uint64_t key = dense_key(vals, excl, q);
+          if (key != 0 && (key > tau || (key == tau && !tie))) word |= 1u << e;
+        }
+      }
+      bits[w] = word;
+    }
+  } else if (mode == SEL_SEG) {
+    for (int sg = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); sg < nseg; sg += nw) {
+      const int c = std::min(rcnt[2 * sg], cap);
+      const int64_t o = (int64_t)sg * cap;
+      for (int i = lane; i < c; i += 64) {
+        const uint64_t key = (uint64_t)rkey[o + i];
+        if (key > tau || (key == tau && !tie)) {
+          const uint32_t q = rpos[o + i];
+          atomicOr(&bits[q >> 5], 1u << (q & 31));
+        }
+      }
+    }
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
+      const uint64_t key = mag_bits(vals[i]) + 1;
+      if (key > tau || (key == tau && !tie)) {
+        const uint32_t q = (uint32_t)list[i];
+        atomicOr(&bits[q >> 5], 1u << (q & 31));
+      }
+    }
   }
+  if (!tie || blockIdx.x != 0 || tau == 0) return;   // key 0 (excluded) is never marked
+  // --- tie: the need lowest natural indices among the keys equal to tau
+  __syncthreads();
+  __threadfence_block();
+  const int64_t need = hd.need;
+  // visits every (key, key position) of the source with this workgroup alone
+  auto each = [&](auto&& f) {
+    if (mode == SEL_SEG) {
+      for (int sg = threadIdx.x >> 6; sg < nseg; sg += (int)(blockDim.x >> 6)) {
+        const int c = std::min(rcnt[2 * sg], cap);
+        const int64_t o = (int64_t)sg * cap;
+        for (int i = lane; i < c; i += 64) f((uint64_t)rkey[o + i], rpos[o + i]);
+      }
+    } else if (mode == SEL_DENSE) {
+      for (int64_t i = threadIdx.x; i < count; i += blockDim.x) f(dense_key(vals, excl, i), (uint32_t)i);
+    } else {
+      for (int64_t i = threadIdx.x; i < count; i += blockDim.x) f(mag_bits(vals[i]) + 1, (uint32_t)list[i]);
+    }
+  };
+  if (threadIdx.x == 0) s_cnt = 0u;
+  __syncthreads();
+  each([&](uint64_t key, uint32_t q) {
+    if (key == tau) {
+      const uint32_t slot = atomicAdd(&s_cnt, 1u);
+      if (slot < (uint32_t)kTieCap) tb[slot] = ((uint64_t)(uint32_t)nat_of_key(q, pl) << 32) | q;
+    }
+  });
+  __syncthreads();
+  const uint32_t nt = s_cnt;
+  if (nt <= (uint32_t)kTieCap) {
+    int P = 2;
+    while (P < (int)nt) P <<= 1;
+    for (int i = (int)nt + threadIdx.x; i < P; i += blockDim.x) tb[i] = ~0ull;
+    __syncthreads();
+    lds_bitonic(tb, P, false);
+    for (int i = threadIdx.x; i < (int)need; i += blockDim.x) {
+      const uint32_t q = (uint32_t)tb[i];
+      atomicOr(&bits[q >> 5], 1u << (q & 31));
+    }
+    return;
+  }
+  // many tied keys: radix select (low indices first) over the tied indices
+  uint32_t jprefix = 0u, jmask = 0u;
+  int64_t rest = need;
+  for (int bit = jbits; bit > 0;) {
+    const int w = bit < kDigit ? bit : kDigit, shift = bit - w;
+    const uint32_t dm = (1u << w) - 1;
+    for (uint32_t i = threadIdx.x; i <= dm; i += blockDim.x) th[i] = 0u;
+    __syncthreads();
+    each([&](uint64_t key, uint32_t q) {
+      if (key != tau) return;
+      const uint32_t j = (uint32_t)nat_of_key(q, pl);
+      if ((j & jmask) == jprefix) atomicAdd(&th[(j >> shift) & dm], 1u);
+    });
+    __syncthreads();
+    const int t = threadIdx.x;
+    int64_t c[2];
+    c[0] = 2 * t <= (int)dm ? th[2 * t] : 0;
+    c[1] = 2 * t + 1 <= (int)dm ? th[2 * t + 1] : 0;
+    const int64_t loc = c[0] + c[1];
+    const int64_t incl = block_incl_scan(loc, sc);
+    int64_t run = incl - loc;
+    if (run < rest && rest <= incl) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (run < rest && rest <= run + c[u]) {
+          s_digit = (uint32_t)(2 * t + u);
+          s_rest = rest - run;
+        }
+        run += c[u];
+      }
+    }
+    __syncthreads();
+    const uint32_t d = s_digit;
+    const int64_t nrest = s_rest;
+    __syncthreads();
+    jprefix |= d << shift;
+    jmask |= dm << shift;
+    rest = nrest;
+    bit = shift;
+  }
+  each([&](uint64_t key, uint32_t q) {
+    if (key == tau && (uint32_t)nat_of_key(q, pl) <= jprefix) atomicOr(&bits[q >> 5], 1u << (q & 31));
+  });
 }
 
-template <typename T, typename S>
-static void radix_topk(Ctx<T>& c, const T* vals, const void* aux, int64_t count, int k, uint32_t* out_bits) {
+static inline int index_bits(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << b) < n) ++b;
+  return std::max(b, 1);
+}
+
+template <typename T>
+static void sel_run(Ctx<T>& c, const T* vals, const void* aux, int64_t count, int init, int64_t k, int nseg,
+                    int cap, unsigned grid, uint32_t* out_bits) {
   hipStream_t s = c.stream;
-  const Plan& pl = c.plan;
-  const unsigned grid = (unsigned)std::min<int64_t>(1024, nblk(count, 256));
-  fill_u32(out_bits, c.plan.words, 0u, s);
-  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, c.sel, (int64_t)k);
-  CS_LAUNCH_CHECK();
-  const int width = (sizeof(T) == 4) ? 32 : 64;
-  for (int shift = width - 8; shift >= 0; shift -= 8) {
-    hipLaunchKernelGGL((k_radix_hist<T, S, 0>), dim3(grid), dim3(256), 0, s, vals, aux, count, pl, c.sel, shift);
-    CS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_radix_pick<0>, dim3(1), dim3(256), 0, s, c.sel, shift);
+  const int keybits = 8 * (int)sizeof(T);
+  const int passes = (keybits + kDigit - 1) / kDigit;
+  for (int p = 0; p < passes; ++p) {
+    hipLaunchKernelGGL((k_sel_pass<T>), dim3(grid), dim3(1024), 0, s, vals, aux, count, c.sel, (const RecKey<T>*)c.rkey, c.rpos,
+                       c.rcnt, nseg, cap, c.hrows, p, p == 0 ? init : 0, k, keybits);
     CS_LAUNCH_CHECK();
   }
-  for (int shift = 24; shift >= 0; shift -= 8) {
-    hipLaunchKernelGGL((k_radix_hist<T, S, 1>), dim3(grid), dim3(256), 0, s, vals, aux, count, pl, c.sel, shift);
-    CS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_radix_pick<1>, dim3(1), dim3(256), 0, s, c.sel, shift);
-    CS_LAUNCH_CHECK();
-  }
-  hipLaunchKernelGGL((k_radix_mark<T, S>), dim3(grid), dim3(256), 0, s, vals, aux, count, pl, c.sel, out_bits);
+  hipLaunchKernelGGL((k_sel_final<T>), dim3(grid), dim3(1024), 0, s, vals, aux, count, c.plan.words, c.plan, c.sel,
+                     (const RecKey<T>*)c.rkey, c.rpos, c.rcnt, nseg, cap, c.hrows, passes, index_bits(c.plan.n), out_bits);
   CS_LAUNCH_CHECK();
 }
 
 template <typename T>
 void topk_dense(Ctx<T>& c, const T* dense, const uint32_t* excl, int k, uint32_t* out_bits) {
-  radix_topk<T, DenseSrc>(c, dense, excl, c.plan.n, k, out_bits);
+  hipStream_t s = c.stream;
+  const int64_t n = c.plan.n;
+  const SplitLayout sl = split_layout(n);
+  hipLaunchKernelGGL((k_sel_sample<T>), dim3(1), dim3(1024), 0, s, dense, excl, n, (int64_t)k, 8 * (int)sizeof(T),
+                     c.sel);
+  CS_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_sel_split<T>), dim3(sl.blocks), dim3(kSplitThreads), 0, s, dense, excl, n, sl.per_block, sl.cap, c.sel,
+                     (RecKey<T>*)c.rkey, c.rpos, c.rcnt, out_bits);
+  CS_LAUNCH_CHECK();
+  const unsigned grid = (unsigned)std::min(kPassBlocks, sl.blocks);
+  sel_run<T>(c, dense, excl, n, 1, k, sl.blocks, sl.cap, grid, out_bits);
 }
 
 template <typename T>
 void topk_compact(Ctx<T>& c, const T* vals, const int32_t* list, int count, int k, uint32_t* out_bits) {
-  radix_topk<T, CompactSrc>(c, vals, list, count, k, out_bits);
+  fill_u32(out_bits, c.plan.words, 0u, c.stream);
+  const unsigned grid = (unsigned)std::min<int64_t>(kPassBlocks, nblk(count, 1024));
+  sel_run<T>(c, vals, list, count, 2, k, 0, 0, grid, out_bits);
 }
 
 // ------------------------------------------------------------------ bitmaps

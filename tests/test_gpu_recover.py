@@ -70,3 +70,36 @@ def test_recover_matches_oracle(case):
     assert rel(s, ref.s) <= 1e-5
     assert np.count_nonzero(s[np.setdiff1d(np.arange(n), supp)]) == 0
     assert info["flags"] & ~cs.CS_F_CG_MAXITER == 0
+
+
+ZERO_CASES = [
+    # name, n, m, k, dtype: y = 0 makes every correlation magnitude equal, so each
+    # selection is decided by the index tie-break alone.  At N = 16 all keys sit
+    # in one candidate segment; at N = 2^14 and 4096 they overflow the segments
+    # and the selection runs its passes over every key.
+    ("sp_n16_f64", "sp", 16, 9, 4, "f64"),
+    ("sp_n16_f32", "sp", 16, 9, 4, "f32"),
+    ("sp_n2p14_f32", "sp", 2 ** 14, 2 ** 12, 100, "f32"),
+    ("cosamp_n2p14_f64", "cosamp", 2 ** 14, 2 ** 12, 100, "f64"),
+    ("ompr_n2p14_f32", "ompr", 2 ** 14, 2 ** 12, 100, "f32"),
+    ("omp_n4096_f64", "omp", 4096, 1024, 20, "f64"),
+]
+
+
+@pytest.mark.parametrize("case", ZERO_CASES, ids=[c[0] for c in ZERO_CASES])
+def test_zero_measurement_matches_oracle(case):
+    name, algo, n, m, k, dt = case
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, _ = problem(80, 0, n, m, k, "normal_min0.1", None, dt)
+    y = np.zeros(m)
+    ref = getattr(oracle, algo)(op, y, k)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    announce("recover zero y", name)
+    s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, 1e-6)
+    supp = supp.cpu().numpy()
+    print(name, info, flush=True)
+    assert np.array_equal(supp, ref.support)
+    assert np.array_equal(supp, np.arange(k))
+    assert np.count_nonzero(s.cpu().numpy()) == 0
