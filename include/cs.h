@@ -9,8 +9,10 @@
  *   D  keeping the M sampled rows `rows` of an N-vector,
  *   F  the orthonormal N-point DCT-II, (F x)_k = c_k sum_n x_n cos(pi(2n+1)k/(2N)),
  *      c_0 = sqrt(1/N), c_k = sqrt(2/N),
- *   R  the diagonal sign flip diag(signs), signs in {+1,-1}.
- * The sparsifying basis is the identity (s is sparse directly).
+ *   R  the randomizer: a sign flip, optionally with a permutation.
+ * The measured signal is x = Psi s (Eq. (2)) with Psi the identity (s is
+ * sparse directly) or, as in the experiments of Sec. IV-A, the orthonormal
+ * DCT-II (the same F), so that A = D F R F; see cs_op.psi.
  *
  * Every least-squares step is the CG-based weighted least squares of
  * Sec. III-B/C (Eqs. (10)-(11), the CG function of Algorithm 1): CG on
@@ -70,7 +72,8 @@ typedef enum {
   CS_OK = 0,
   CS_E_INVALID = -1,    /* null pointer, bad dtype/algo, K < 1, tol <= 0 or not finite  */
   CS_E_SHAPE = -2,      /* N not a power of two in [16, 2^26], M > N, K > M, SP 2K > M   */
-  CS_E_OP = -3,         /* rows not strictly ascending in [0, N) or a sign not +-1       */
+  CS_E_OP = -3,         /* rows not strictly ascending in [0, N), a sign not +-1, perm
+                           not a permutation, or psi not 0 or 1                        */
   CS_E_WORKSPACE = -4,  /* workspace too small or not 256-byte aligned                   */
   CS_E_HIP = -5         /* HIP runtime error                                             */
 } cs_status;
@@ -83,17 +86,23 @@ enum {
   CS_F_NONFINITE = 8       /* a non-finite value reached a selection or a norm        */
 };
 
-/* Sensing operator A = D F R (Eq. (7)): D keeps rows, F is the orthonormal
- * DCT-II, R the randomizer: entry j of x enters the DCT at index perm[j]
- * with sign signs[j].  perm == NULL is the identity (R = diag(signs), the
- * workloads here); the paper's R is a uniform random permutation (perm with
- * all signs +1). */
+/* Sensing operator A = Phi Psi with Phi = D F R (Eq. (7)): D keeps rows, F
+ * is the orthonormal DCT-II, R the randomizer: entry j of x enters the DCT at
+ * index perm[j] with sign signs[j].  perm == NULL is the identity
+ * (R = diag(signs), the headline workloads here); the paper's R is a uniform
+ * random permutation (perm with all signs +1).  Psi is the sparsifying basis
+ * of Eq. (2): psi = 0 the identity, psi = 1 the orthonormal DCT-II, as in the
+ * experiments of Sec. IV-A (A s = D F R F s).  With psi = 1 every H-apply
+ * runs two more transforms and two reorders through R; the workspace must be
+ * sized by cs_workspace_size_op(), and the batched entry point rejects it. */
 typedef struct {
   int64_t n;              /* signal length N                                        */
   int64_t m;              /* number of sampled rows M                               */
   const int32_t* rows;    /* device [m]: sampled DCT rows, strictly ascending      */
   const int8_t* signs;    /* device [n]: sign flips, each +1 or -1                  */
   const int32_t* perm;    /* device [n] permutation of [0, N), or NULL              */
+  int32_t psi;            /* sparsifying basis: 0 identity, 1 orthonormal DCT-II    */
+  int32_t pad;            /* set to 0                                               */
 } cs_op;
 
 /* Optional knobs; pass NULL for the defaults shown. */
@@ -125,6 +134,11 @@ typedef struct {
 /* Workspace bytes needed by one call of `algo` at these sizes (0 if invalid).
  * It grows as O(N + K) (Sec. III-D: the method's memory is O(N)). */
 size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_algo algo);
+
+/* The same for a given operator (host descriptor; only n, m and psi are
+ * read): a DCT sparsifying basis (psi = 1) needs two more N-vectors.
+ * 0 if invalid. */
+size_t cs_workspace_size_op(cs_dtype dtype, const cs_op* op, int32_t k, cs_algo algo);
 
 /*
  * Recovery entry points: y [M] -> s [N] (dense, zero off the support) and

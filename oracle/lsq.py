@@ -10,7 +10,7 @@ an explicit pseudo-inverse:
 * ``ls_dense``: QR/SVD least squares (``numpy.linalg.lstsq``) on the dense
   A_S built from the cosine formula, for small M * |S|;
 * ``ls_gram``:  Cholesky of the closed-form Gram (``oracle.gram``) with the
-  right-hand side (A^T y)[S];
+  right-hand side (A^T y)[S] (Psi = I only);
 * ``ls_cg``:    only where the Gram would not fit in memory (|S| > 16384):
   plain FP64 conjugate gradients on the normal equations through the
   operator, run to a relative residual of 1e-13 and re-checked with the true
@@ -97,7 +97,7 @@ def ls(op: SRM, supp, y, g: np.ndarray | None = None, aty: np.ndarray | None = N
     if route == "auto":
         if op.m * k <= DENSE_LIMIT:
             route = "dense"
-        elif k <= GRAM_LIMIT:
+        elif k <= GRAM_LIMIT and not op.psi:   # the closed-form Gram needs Psi = I
             route = "gram"
         else:
             route = "cg"
@@ -134,7 +134,7 @@ class LSContext:
         if route == "auto":
             if self.op.m * k <= DENSE_LIMIT:
                 route = "dense"
-            elif k <= GRAM_LIMIT:
+            elif k <= GRAM_LIMIT and not self.op.psi:   # the closed-form Gram needs Psi = I
                 route = "gram"
             else:
                 route = "cg"

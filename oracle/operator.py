@@ -1,4 +1,4 @@
-"""Sensing operator of Sec. III-A, Eq. (7): Phi = D F R, with Psi = I so A = Phi.
+"""Sensing operator of Sec. III-A, Eq. (7): Phi = D F R, and A = Phi Psi (Eq. (2)).
 
 * D keeps the sampled rows ``rows`` (M of N, ascending) of an N-vector
   (the "randomly choose M indices" operator of Sec. III-D).
@@ -6,9 +6,14 @@
       (F x)_k = c_k sum_n x_n cos(pi (2n+1) k / (2N)),
       c_0 = sqrt(1/N), c_k = sqrt(2/N) for k >= 1.
   Its transpose (= inverse) is the orthonormal DCT-III.
-* R = diag(signs) with signs in {+1, -1}.
+* R = diag(signs) with signs in {+1, -1}, optionally with a permutation.
+* Psi, the sparsifying basis: the identity (``psi = 0``, s sparse directly)
+  or, as in the experiments of Sec. IV-A, the orthonormal DCT-II F itself
+  (``psi = 1``).
 
-So A x = (F (signs * x))[rows] and A^T u = signs * F^T (zero-fill_rows(u)).
+So with Psi = I, A x = (F (signs * x))[rows] and A^T u = signs * F^T
+(zero-fill_rows(u)); with Psi = F, A s = (F R F s)[rows] and
+A^T u = F^T R^T F^T zero-fill_rows(u).
 
 Two independent routes are provided: SciPy's FFT-based DCT (``apply``,
 ``adjoint``) and the dense cosine formula (``columns``, ``dense``) with the
@@ -44,14 +49,15 @@ def dct2_matrix(n: int) -> np.ndarray:
 
 
 class SRM:
-    """A = D_rows . DCT-II . R, an M x N operator (FP64).
+    """A = D_rows . DCT-II . R . Psi, an M x N operator (FP64).
 
     R is the randomizer: entry j of x goes to DCT input perm[j] with sign
     signs[j] ((R x)[perm[j]] = signs[j] x[j]); perm = None is the identity, so
     R = diag(signs).  The paper's R is a uniform random permutation (signs all
-    +1); the workloads here use the sign flip."""
+    +1); the workloads here use the sign flip.  Psi is the identity (psi = 0)
+    or the DCT-II (psi = 1, A = D F R F)."""
 
-    def __init__(self, n: int, rows, signs, perm=None):
+    def __init__(self, n: int, rows, signs, perm=None, psi: int = 0):
         rows = np.asarray(rows, dtype=np.int64)
         signs = np.asarray(signs)
         if rows.ndim != 1 or signs.shape != (n,):
@@ -64,6 +70,9 @@ class SRM:
         self.m = int(rows.size)
         self.rows = rows
         self.signs = signs.astype(np.float64)
+        if psi not in (0, 1):
+            raise ValueError("psi must be 0 or 1")
+        self.psi = int(psi)
         self.perm = None
         if perm is not None:
             perm = np.asarray(perm, dtype=np.int64)
@@ -91,8 +100,10 @@ class SRM:
 
     # ---------------------------------------------------------- FFT route
     def apply(self, x: np.ndarray) -> np.ndarray:
-        """A x for a dense N-vector x."""
+        """A x for a dense N-vector x (with psi = 1, F x enters R first)."""
         x = np.asarray(x, dtype=np.float64)
+        if self.psi:
+            x = sfft.dct(x, type=2, norm="ortho", workers=WORKERS)
         return sfft.dct(self._place(x), type=2, norm="ortho", workers=WORKERS)[self.rows]
 
     def apply_sparse(self, supp, vals) -> np.ndarray:
@@ -105,14 +116,29 @@ class SRM:
         """A^T u for an M-vector u: zero-fill, orthonormal DCT-III, sign flip."""
         full = np.zeros(self.n)
         full[self.rows] = np.asarray(u, dtype=np.float64)
-        return self._unplace(sfft.idct(full, type=2, norm="ortho", workers=WORKERS))
+        w = self._unplace(sfft.idct(full, type=2, norm="ortho", workers=WORKERS))
+        if self.psi:
+            w = sfft.idct(w, type=2, norm="ortho", workers=WORKERS)
+        return w
 
     # ---------------------------------------------------- formula route
     def columns(self, supp) -> np.ndarray:
-        """Dense A_S (M x |S|) from the cosine formula."""
+        """Dense A_S (M x |S|) from the cosine formula.
+
+        With psi = 1 each column is D F R (F e_j): F e_j from the formula, then
+        R, then F through the same formula for N <= 4096 (else SciPy's DCT)."""
         j = np.asarray(supp, dtype=np.int64)[None, :]
         k = self.rows[:, None]
-        return _dct_scale(k, self.n) * _cos_table(k, self.dct_index(j), self.n) * self.signs[j]
+        if not self.psi:
+            return _dct_scale(k, self.n) * _cos_table(k, self.dct_index(j), self.n) * self.signs[j]
+        i = np.arange(self.n)[:, None]
+        fcols = _dct_scale(i, self.n) * _cos_table(i, j, self.n)        # F e_j, N x |S|
+        placed = np.zeros_like(fcols)
+        idx = self.dct_index(np.arange(self.n))
+        placed[idx, :] = self.signs[:, None] * fcols                    # R applied to each column
+        if self.n <= 4096:
+            return (_dct_scale(k, self.n) * _cos_table(k, np.arange(self.n)[None, :], self.n)) @ placed
+        return sfft.dct(placed, type=2, norm="ortho", axis=0, workers=WORKERS)[self.rows, :]
 
     def dense(self) -> np.ndarray:
         return self.columns(np.arange(self.n))

@@ -24,7 +24,7 @@ CS_ALGO_OMP, CS_ALGO_SP, CS_ALGO_OMPR, CS_ALGO_OPERATOR, CS_ALGO_LS, CS_ALGO_COS
 CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, -3, -4, -5
 CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
 
-EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_recover_cosamp",
+EXPORTS = ("cs_workspace_size", "cs_workspace_size_op", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_recover_cosamp",
            "cs_ls_solve",
            "cs_adjoint_ls", "cs_workspace_size_batched", "cs_recover_ompr_batched", "cs_apply_A", "cs_apply_At",
            "cs_shape_candidates", "cs_set_shape", "cs_time_shape", "cs_status_str", "cs_last_error",
@@ -33,7 +33,8 @@ EXPORTS = ("cs_workspace_size", "cs_recover_omp", "cs_recover_sp", "cs_recover_o
 
 class cs_op(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("rows", ctypes.c_void_p),
-                ("signs", ctypes.c_void_p), ("perm", ctypes.c_void_p)]
+                ("signs", ctypes.c_void_p), ("perm", ctypes.c_void_p), ("psi", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class cs_params(ctypes.Structure):
@@ -86,6 +87,8 @@ def _load():
     P = ctypes.POINTER
     lib.cs_workspace_size.argtypes = [ctypes.c_int, i64, i64, i32, ctypes.c_int]
     lib.cs_workspace_size.restype = sz
+    lib.cs_workspace_size_op.argtypes = [ctypes.c_int, P(cs_op), i32, ctypes.c_int]
+    lib.cs_workspace_size_op.restype = sz
     for name in ("cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_recover_cosamp"):
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, vp, P(cs_op), i32, dbl, vp, vp, P(cs_params), vp, sz, P(cs_info), vp]
@@ -155,6 +158,13 @@ def cs_workspace_size(dtype: int, n: int, m: int, k: int, algo: int) -> int:
     return int(lib.cs_workspace_size(dtype, n, m, k, algo))
 
 
+def cs_workspace_size_op(dtype: int, op, k: int, algo: int) -> int:
+    """Workspace bytes for an operator descriptor (`Operator` or `cs_op`); a
+    DCT sparsifying basis (psi = 1) needs two more N-vectors."""
+    c = op.c if hasattr(op, "c") else op
+    return int(lib.cs_workspace_size_op(dtype, ctypes.byref(c), k, algo))
+
+
 def _check(status: int):
     if status != CS_OK:
         raise CSError(status, f"{cs_status_str(status)}: {cs_last_error()}")
@@ -186,11 +196,13 @@ def _ptr(t):
 
 
 class Operator:
-    """Sensing operator A = D F R (device descriptor): rows int32 [M] ascending,
-    signs int8 [N], and optionally perm int32 [N] (the randomizer's permutation;
-    None: R is the sign flip alone)."""
+    """Sensing operator A = D F R Psi (device descriptor): rows int32 [M]
+    ascending, signs int8 [N], optionally perm int32 [N] (the randomizer's
+    permutation; None: R is the sign flip alone), and the sparsifying basis
+    psi (0: identity, s sparse directly; 1: the orthonormal DCT-II, as in the
+    paper's experiments)."""
 
-    def __init__(self, n: int, rows, signs, perm=None):
+    def __init__(self, n: int, rows, signs, perm=None, psi: int = 0):
         torch = _torch()
         if rows.dtype != torch.int32 or signs.dtype != torch.int8:
             raise TypeError("rows must be int32 and signs int8")
@@ -203,15 +215,17 @@ class Operator:
         self.rows = rows.contiguous()
         self.signs = signs.contiguous()
         self.perm = perm.contiguous() if perm is not None else None
+        self.psi = int(psi)
         self.c = cs_op(self.n, self.m, self.rows.data_ptr(), self.signs.data_ptr(),
-                       self.perm.data_ptr() if self.perm is not None else None)
+                       self.perm.data_ptr() if self.perm is not None else None, self.psi, 0)
 
     @classmethod
-    def from_numpy(cls, n, rows, signs, perm=None, device="cuda"):
+    def from_numpy(cls, n, rows, signs, perm=None, device="cuda", psi: int = 0):
         torch = _torch()
         return cls(n, torch.as_tensor(rows, dtype=torch.int32, device=device),
                    torch.as_tensor(signs, dtype=torch.int8, device=device),
-                   torch.as_tensor(perm, dtype=torch.int32, device=device) if perm is not None else None)
+                   torch.as_tensor(perm, dtype=torch.int32, device=device) if perm is not None else None,
+                   psi=psi)
 
 
 def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0, cg_block=0, tol_abs=False, ompr_l=1):
@@ -221,7 +235,7 @@ def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0, cg_block=0, 
 
 def workspace(dtype_code: int, op: Operator, k: int, algo: int, device=None):
     torch = _torch()
-    nbytes = cs_workspace_size(dtype_code, op.n, op.m, k, algo)
+    nbytes = cs_workspace_size_op(dtype_code, op, k, algo)
     if nbytes == 0:
         raise CSError(CS_E_SHAPE, "no workspace size for these arguments")
     dev = device if device is not None else op.rows.device

@@ -27,7 +27,7 @@ struct Carver {
 };
 
 template <typename T>
-static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
+static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0) {
   Carver cv{base};
   const int64_t n = p.n;
   c.W = cv.take<Cx<T>>(p.L);
@@ -71,6 +71,10 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base) {
   c.rpos = cv.take<uint32_t>((int64_t)sl.blocks * sl.cap);
   c.rcnt = cv.take<int32_t>(2 * (int64_t)sl.blocks);
   c.hrows = cv.take<uint32_t>(2 * (int64_t)kPassBlocks * 2048);
+  if (psi) {
+    c.P1 = cv.take<T>(n);
+    c.P2 = cv.take<T>(n);
+  }
   c.ibuf = cv.take<int32_t>(64);
   c.blockcnt = cv.take<uint32_t>((p.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords + 2);
   c.cg = cv.take<CgScalars>(1);
@@ -88,12 +92,12 @@ static int kmax_for(cs_algo algo, int32_t k) {
   }
 }
 
-size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo) {
+size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo, int psi) {
   Plan p;
   if (!choose_plan(dt, n, m, p)) return 0;
-  if (dt == CS_F32) { Ctx<float> c{}; return carve(c, p, kmax_for(algo, k), nullptr); }
+  if (dt == CS_F32) { Ctx<float> c{}; return carve(c, p, kmax_for(algo, k), nullptr, psi); }
   Ctx<double> c{};
-  return carve(c, p, kmax_for(algo, k), nullptr);
+  return carve(c, p, kmax_for(algo, k), nullptr, psi);
 }
 
 template <typename T>
@@ -101,17 +105,25 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   Plan p;
   const cs_dtype dt = sizeof(T) == 4 ? CS_F32 : CS_F64;
   if (!choose_plan(dt, op->n, op->m, p, force)) throw Error(CS_E_SHAPE, "unsupported N or shape");
-  const size_t need = carve(c, p, kmax, nullptr);
+  if (op->psi != 0 && op->psi != 1) throw Error(CS_E_OP, "operator psi must be 0 or 1");
+  const int psi = op->psi;
+  const size_t need = carve(c, p, kmax, nullptr, psi);
   if (ws_bytes < need) throw Error(CS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
-  carve(c, p, kmax, (char*)ws);
+  carve(c, p, kmax, (char*)ws, psi);
   p.tw_lo = c.tw_lo;
   p.tw_hi = c.tw_hi;
   p.mask = c.mask;
-  p.perm = op->perm;
-  p.pinv = op->perm ? c.pinv : nullptr;
+  // the candidates' key order follows the transform they enter: Phi's (through
+  // the randomizer) or, with a DCT basis, Psi's (no randomizer)
+  p.perm = psi ? nullptr : op->perm;
+  p.pinv = (!psi && op->perm) ? c.pinv : nullptr;
   c.plan = p;
   c.stream = s;
-  c.signs = op->signs;
+  c.psi = psi;
+  c.rsigns = op->signs;
+  c.rperm = op->perm;
+  c.rpinv = op->perm ? c.pinv : nullptr;
+  c.signs = psi ? nullptr : op->signs;
   c.rows = op->rows;
   c.kmax = kmax;
   prepare_kernels<T>();
@@ -127,6 +139,7 @@ static void check_shape(cs_dtype dt, const cs_op* op, int32_t k, cs_algo algo) {
   const int64_t n = op->n, m = op->m;
   if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) throw Error(CS_E_SHAPE, "N must be a power of two in [16, 2^26]");
   if (m < 1 || m > n) throw Error(CS_E_SHAPE, "M must satisfy 1 <= M <= N");
+  if (op->psi != 0 && op->psi != 1) throw Error(CS_E_OP, "operator psi must be 0 or 1");
   if (algo == CS_ALGO_OPERATOR) return;
   if (k < 1) throw Error(CS_E_INVALID, "K must be >= 1");
   if (k > m) throw Error(CS_E_SHAPE, "K must not exceed M");
@@ -246,7 +259,7 @@ __global__ void k_reorder(const int32_t* __restrict__ sup, int k, const Plan pl,
   if (i >= k) return;
   const int32_t j = sup[i];
   const uint32_t slot = rank_of(bits, wpre, (uint32_t)key_of_nat(j, pl));
-  const bool neg = signs[j] < 0;
+  const bool neg = signs && signs[j] < 0;
   if (TO_KEY) xkey[slot] = neg ? -xnat[i] : xnat[i];
   else xnat[i] = neg ? -xkey[slot] : xkey[slot];
 }
@@ -311,7 +324,7 @@ __global__ void k_grad_rhs(const int32_t* __restrict__ sup, int k, const Plan pl
   if (i >= k) return;
   const int32_t j = sup[i];
   const uint32_t slot = rank_of(bits, wpre, (uint32_t)key_of_nat(j, pl));
-  b[slot] = signs[j] < 0 ? -g[j] : g[j];
+  b[slot] = (signs && signs[j] < 0) ? -g[j] : g[j];
 }
 
 // dL/dy = A_S z with (A_S^T A_S) z = (dL/ds)_S: the CG on the sign-flipped
@@ -378,13 +391,25 @@ static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, vo
   Ctx<T> c{};
   ctx_init<T>(c, op, 1, ws, ws_bytes, stream);
   setup_operator<T>(c);
+  // With a DCT basis (psi) perm_in/perm_out place s with no randomizer, and
+  // R is applied between Psi's and Phi's transforms.
   if (!adjoint) {
     perm_in<T>(c, (const T*)in, c.Dd);
-    transform_fwd<T>(c, c.Dd, c.Yf);
+    transform_fwd<T>(c, c.Dd, c.Yf, c.psi != 0);   // Psi = F: every output, unmasked
+    if (c.psi) {
+      rand_in<T>(c, c.Yf, c.P2, nullptr);
+      transform_fwd<T>(c, c.P2, c.Yf);
+    }
     gather_freq<T>(c, c.Yf, (T*)out);
   } else {
     scatter_freq<T>(c, (const T*)in, c.Yf);
-    transform_adj<T>(c, c.Yf, (T*)c.W, false);
+    if (c.psi) {
+      transform_adj<T>(c, c.Yf, c.P2, false);
+      rand_out<T>(c, c.P2, c.P1, nullptr);
+      transform_adj<T>(c, c.P1, (T*)c.W, false);
+    } else {
+      transform_adj<T>(c, c.Yf, (T*)c.W, false);
+    }
     perm_out<T>(c, (const T*)c.W, (T*)out);
   }
   CS_HIP(hipStreamSynchronize(stream));
@@ -403,7 +428,13 @@ size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_alg
   if (algo != CS_ALGO_OPERATOR && (k < 1 || k > m)) return 0;
   if (algo < CS_ALGO_OMP || algo > CS_ALGO_COSAMP) return 0;
   if (algo == CS_ALGO_COSAMP && (int64_t)3 * k > m) return 0;
-  return workspace_bytes(dtype, n, m, k, algo);
+  return workspace_bytes(dtype, n, m, k, algo, 0);
+}
+
+size_t cs_workspace_size_op(cs_dtype dtype, const cs_op* op, int32_t k, cs_algo algo) {
+  if (!op || (op->psi != 0 && op->psi != 1)) return 0;
+  if (cs_workspace_size(dtype, op->n, op->m, k, algo) == 0) return 0;
+  return workspace_bytes(dtype, op->n, op->m, k, algo, op->psi);
 }
 
 cs_status cs_recover_omp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,
@@ -475,7 +506,7 @@ size_t cs_workspace_size_batched(cs_dtype dtype, int32_t count, const cs_batch_i
   if (count < 1 || !items || algo != CS_ALGO_OMPR) return 0;
   for (int i = 0; i < count; ++i) {
     const cs_op& o = items[i].op;
-    if (cs_workspace_size(dtype, o.n, o.m, items[i].k, algo) == 0) return 0;
+    if (o.psi != 0 || cs_workspace_size(dtype, o.n, o.m, items[i].k, algo) == 0) return 0;
   }
   return batch_layout(dtype, count, items, nullptr);
 }
@@ -488,6 +519,7 @@ cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_
     if (params && params->ompr_l > 1) throw Error(CS_E_INVALID, "the batched call runs OMPR with l = 1");
     for (int i = 0; i < count; ++i) {
       check_shape(dtype, &items[i].op, items[i].k, CS_ALGO_OMPR);
+      if (items[i].op.psi != 0) throw Error(CS_E_INVALID, "the batched call takes operators with psi = 0");
       if (!items[i].y || !items[i].s || !items[i].support) throw Error(CS_E_INVALID, "null y, s or support in batch");
     }
     check_tol(tol);

@@ -207,7 +207,8 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     ColIO<T> in = col_io<T>(c, COL_X, &S);
     in.x = x;
     launch_col<T>(c, nullptr, c.W, false, in);
-    launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, nullptr);
+    if (c.psi) psi_middle<T>(c, nullptr, nullptr);
+    else launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, nullptr);
     ColIO<T> out = col_io<T>(c, COL_R, &S);
     out.r = c.cr;
     out.d = c.cd;
@@ -250,18 +251,22 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   int it_prev = 0;
   // Queued iterations past convergence exit at once; their launches are taken
   // out of the counters and the timing records once the count is known.
-  struct Queued { int rec[3]; double bytes; };
+  // With a DCT basis the H-apply runs on Psi's column passes with Phi^T Phi
+  // (and the two reorders through R) in between.
+  struct Queued { int rec[7]; double bytes; };
   std::vector<Queued> queued;
+  const int per_it = c.psi ? 4 : 2;   // transforms per iteration
   while (it < max_iter) {
     const int q = std::min(chunk, max_iter - it);
     for (int u = 0; u < q; ++u, ++it) {
       dir.it = it;
-      Queued qd{{-1, -1, -1}, 0.0};
+      Queued qd{{-1, -1, -1, -1, -1, -1, -1}, 0.0};
       qd.bytes += launch_col<T>(c, nullptr, c.W, false, dir, &qd.rec[0]);
-      qd.bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, &qd.rec[1]);
-      qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[2]);
+      if (c.psi) qd.bytes += psi_middle<T>(c, c.cg, &qd.rec[1]);
+      else qd.bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, &qd.rec[1]);
+      qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[6]);
       queued.push_back(qd);
-      c.transforms += 2;
+      c.transforms += 2;   // (psi_middle counts Phi's two)
       hipLaunchKernelGGL(k_cg_update<T>, dim3(nb), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr, c.cg, it,
                          max_iter);
       CS_LAUNCH_CHECK();
@@ -288,7 +293,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   c.flags |= host.flags;
   c.cg_iters += host.iters;
   for (size_t i = (size_t)std::max(host.iters, 0); i < queued.size(); ++i) {
-    c.transforms -= 2;
+    c.transforms -= per_it;
     c.model_bytes -= queued[i].bytes;
     for (int r : queued[i].rec) prof_discard(r);
   }
@@ -306,7 +311,8 @@ double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
   ColIO<T> in = col_io<T>(c, COL_X, &S);
   in.x = const_cast<T*>(x);
   launch_col<T>(c, nullptr, c.W, false, in);
-  launch_row<T>(c, ROW_RESID, c.Yf, nullptr, c.partial2, nullptr);
+  if (c.psi) psi_resid_middle<T>(c);
+  else launch_row<T>(c, ROW_RESID, c.Yf, nullptr, c.partial2, nullptr);
   launch_col<T>(c, c.W, (Cx<T>*)c.Cc, true, col_io<T>(c, COL_KEY, nullptr));
   c.transforms += 2;
   sum_partials_to(c.partial2, (int)(c.plan.L1 >> 1), &c.cg->resid2, c.stream);
@@ -320,6 +326,12 @@ void apply_support(Ctx<T>& c, const Supp& S, const T* x, T* outf) {
   ColIO<T> in = col_io<T>(c, COL_X, &S);
   in.x = const_cast<T*>(x);
   launch_col<T>(c, nullptr, c.W, false, in);
+  if (c.psi) {   // F s into freq layout, R, then Phi's forward transform
+    launch_row<T>(c, ROW_FWD_ALL, nullptr, c.P1, nullptr, nullptr);
+    rand_in<T>(c, c.P1, c.P2, nullptr);
+    launch_col<T>(c, (const Cx<T>*)c.P2, c.W, false, col_io<T>(c, COL_DENSE, nullptr));
+    c.transforms += 1;
+  }
   launch_row<T>(c, ROW_FWD, nullptr, outf, nullptr, nullptr);
   c.transforms += 1;
 }

@@ -61,7 +61,7 @@ __global__ void k_output(T* __restrict__ s, uint32_t* __restrict__ nbits, const 
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) {
     const uint32_t j = (uint32_t)nat_of_key(list[i], pl);
-    s[j] = signs[j] < 0 ? -x[i] : x[i];
+    s[j] = (signs && signs[j] < 0) ? -x[i] : x[i];
     atomicOr(&nbits[j >> 5], 1u << (j & 31));
   }
 }

@@ -262,7 +262,17 @@ template <typename T>
 struct Ctx {
   hipStream_t stream;
   Plan plan;
-  const int8_t* signs;     // natural order
+  const int8_t* signs;     // natural order, on the greedy candidates (null: all +1)
+  // Sparsifying basis Psi = DCT-II (psi = 1): the candidates index s, whose
+  // transform has no randomizer (plan.perm/pinv and signs are null); the
+  // randomizer R sits between Psi's output and Phi's input, applied by the
+  // reorder kernels through rsigns/rperm/rpinv.
+  int psi = 0;
+  const int8_t* rsigns = nullptr;
+  const int32_t* rperm = nullptr;
+  const int32_t* rpinv = nullptr;
+  T* P1 = nullptr;         // psi: freq-layout N-vector (Psi output / Psi^T input)
+  T* P2 = nullptr;         // psi: v-order N-vector (Phi input / output)
   const int32_t* rows;
   int kmax;                // largest support handled by the compact buffers
   // dense N-vectors (v-order unless noted)
@@ -379,14 +389,15 @@ bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p, const Shape* force 
 int shape_candidates(cs_dtype dt, int l, Shape* out, int max);
 // Installs (s != nullptr) or clears the process-wide shape for L = 2^l.
 bool set_shape_override(cs_dtype dt, int l, const Shape* s);
-size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo);
+size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo, int psi = 0);
 
 template <typename T>
 void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s,
               const Shape* force = nullptr);
 
 // ------------------------------------------------------------------ transform launchers
-enum RowMode { ROW_HAPPLY = 0, ROW_RESID = 1, ROW_FWD = 2, ROW_ADJ = 3 };
+enum RowMode { ROW_HAPPLY = 0, ROW_RESID = 1, ROW_FWD = 2, ROW_ADJ = 3,
+               ROW_FWD_ALL = 4 };   // ROW_FWD without the row mask (a full DCT-II: the DCT basis)
 
 template <typename T> void setup_operator(Ctx<T>& c);                  // twiddles, masks (+ validation)
 template <typename T> void scatter_freq(Ctx<T>& c, const T* u, T* outf); // u [M] -> freq layout
@@ -410,11 +421,17 @@ template <typename T> double launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, 
 template <typename T> double launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, const int* done,
                                         int* rec = nullptr);
 template <typename T> ColIO<T> col_io(Ctx<T>& c, int mode, const Supp* S);   // compact I/O on support S
-template <typename T> void transform_fwd(Ctx<T>& c, const T* in, T* outf); // outf = masked DCT in freq layout
+template <typename T> void transform_fwd(Ctx<T>& c, const T* in, T* outf, bool all = false); // outf = DCT in freq layout, masked unless all
 // out = F^T (freq input), in v-order or (key_order) key order
 template <typename T> void transform_adj(Ctx<T>& c, const T* inf, T* out, bool key_order);
 template <typename T> void perm_in(Ctx<T>& c, const T* x, T* dense);      // dense[vpos(perm j)] = sign_j x_j
 template <typename T> void perm_out(Ctx<T>& c, const T* dense, T* x);     // x_j = sign_j dense[vpos(perm j)]
+// DCT sparsifying basis: R from Psi's freq-layout output to Phi's v-order
+// input, R^T back; the middle of an H-apply and of a residual pass.
+template <typename T> void rand_in(Ctx<T>& c, const T* fin, T* vout, const int* done);
+template <typename T> void rand_out(Ctx<T>& c, const T* vin, T* fout, const int* done);
+template <typename T> double psi_middle(Ctx<T>& c, CgScalars* cg, int* rec);   // rec: 5 entries or null
+template <typename T> void psi_resid_middle(Ctx<T>& c);
 template <typename T> void prepare_kernels();                             // LDS limits, once per process
 
 // ------------------------------------------------------------------ selection

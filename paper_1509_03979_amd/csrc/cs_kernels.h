@@ -130,7 +130,9 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
       bufr[2 * lp((int)e) + (key & 1)] = val;
     }
   } else {
-    if (io.mode == COL_Q && io.cg && io.cg->done) return;
+    // CG-driven passes (the compact q gather, and the dense passes of an
+    // H-apply through a DCT basis) exit once the solve has converged
+    if ((io.mode == COL_Q || io.mode == COL_DENSE) && io.cg && io.cg->done) return;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
@@ -389,8 +391,9 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       xb0 = fin[2 * it.fb]; xb1 = fin[2 * it.fb + 1];
     }
     if (mode != ROW_ADJ) {
-      const uint32_t ma = mask2(p.mask, it.fa);
-      const uint32_t mb = it.zero ? 0u : mask2(p.mask, it.fb);
+      const bool all = mode == ROW_FWD_ALL;
+      const uint32_t ma = all ? 3u : mask2(p.mask, it.fa);
+      const uint32_t mb = it.zero ? 0u : (all ? 3u : mask2(p.mask, it.fb));
       if (mode == ROW_RESID) {
         xa0 = fin[2 * it.fa] - xa0;
         xa1 = fin[2 * it.fa + 1] - xa1;
@@ -407,7 +410,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         acc += (double)xa0 * xa0 + (double)xa1 * xa1;
         if (!self) acc += (double)xb0 * xb0 + (double)xb1 * xb1;
       }
-      if (mode == ROW_FWD) {
+      if (mode == ROW_FWD || all) {
         fout[2 * it.fa] = xa0; fout[2 * it.fa + 1] = xa1;
         if (!it.zero) { fout[2 * it.fb] = xb0; fout[2 * it.fb + 1] = xb1; }
         continue;
@@ -437,7 +440,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       partial[w] = s;
     }
   }
-  if (mode == ROW_FWD) return;
+  if (mode == ROW_FWD || mode == ROW_FWD_ALL) return;
   __syncthreads();
   ct_fft<T, true, NT, LOGL2, 1, false, LOGE>(lds, tw);
   if (SPLIT) {

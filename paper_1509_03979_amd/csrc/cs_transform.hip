@@ -223,11 +223,11 @@ void setup_operator(Ctx<T>& c) {
   CS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_mask_from_bits, dim3(nblk(p.words, 256)), dim3(256), 0, s, (const uint32_t*)c.nbits, c.mask, p);
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_check_signs, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.signs, p.n, c.ibuf);
+  hipLaunchKernelGGL(k_check_signs, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.rsigns, p.n, c.ibuf);
   CS_LAUNCH_CHECK();
-  if (p.perm) {
+  if (c.rperm) {
     fill<int32_t>(c.pinv, p.n, -1, s);
-    hipLaunchKernelGGL(k_perm_inverse, dim3(nblk(p.n, 256)), dim3(256), 0, s, p.perm, p.n, c.pinv, c.ibuf);
+    hipLaunchKernelGGL(k_perm_inverse, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.rperm, p.n, c.pinv, c.ibuf);
     CS_LAUNCH_CHECK();
   }
   int32_t bad = 0;
@@ -345,7 +345,14 @@ template <typename T>
 void load_measurements(Ctx<T>& c, const T* y) {
   scatter_freq<T>(c, y, c.Yf);
   c.ynorm = norm2_host<T>(c, y, c.plan.m);
-  transform_adj<T>(c, c.Yf, c.C0, true);
+  if (!c.psi) {
+    transform_adj<T>(c, c.Yf, c.C0, true);
+    return;
+  }
+  // A^T y = F^T R^T F^T D^T y: Phi^T into v-order, R^T, then Psi^T into key order
+  transform_adj<T>(c, c.Yf, c.P2, false);
+  rand_out<T>(c, c.P2, c.P1, nullptr);
+  transform_adj<T>(c, c.P1, c.C0, true);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -401,16 +408,17 @@ double launch_row(Ctx<T>& c, int mode, const T* fin, T* fout, double* partial, c
   if (prof) prof_begin(c.stream, &ev);
   ks.row<<<dim3(grid), dim3(ks.nt_row), p.lds_row, c.stream>>>(c.W, p, mode, fin, fout, partial, done, c.tw_row);
   CS_LAUNCH_CHECK();
-  const int r = prof ? prof_end(PC_ROW_HAPPLY + mode, bytes, ev, c.stream) : -1;
+  const int cls = mode == ROW_FWD_ALL ? PC_ROW_FWD : PC_ROW_HAPPLY + mode;
+  const int r = prof ? prof_end(cls, bytes, ev, c.stream) : -1;
   if (rec) *rec = r;
   c.model_bytes += bytes;
   return bytes;
 }
 
 template <typename T>
-void transform_fwd(Ctx<T>& c, const T* in, T* outf) {
+void transform_fwd(Ctx<T>& c, const T* in, T* outf, bool all) {
   launch_col<T>(c, (const Cx<T>*)in, c.W, false, col_io<T>(c, COL_DENSE, nullptr));
-  launch_row<T>(c, ROW_FWD, nullptr, outf, nullptr, nullptr);
+  launch_row<T>(c, all ? ROW_FWD_ALL : ROW_FWD, nullptr, outf, nullptr, nullptr);
   c.transforms += 1;
 }
 
@@ -427,7 +435,7 @@ __global__ void k_perm_in(const T* __restrict__ x, T* __restrict__ dense, const 
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= pl.n) return;
   const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
-  dense[vpos(q, pl.n)] = signs[j] < 0 ? -x[j] : x[j];
+  dense[vpos(q, pl.n)] = (signs && signs[j] < 0) ? -x[j] : x[j];
 }
 template <typename T>
 __global__ void k_perm_out(const T* __restrict__ dense, T* __restrict__ x, const int8_t* __restrict__ signs,
@@ -436,7 +444,7 @@ __global__ void k_perm_out(const T* __restrict__ dense, T* __restrict__ x, const
   if (j >= pl.n) return;
   const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
   const T v = dense[vpos(q, pl.n)];
-  x[j] = signs[j] < 0 ? -v : v;
+  x[j] = (signs && signs[j] < 0) ? -v : v;
 }
 template <typename T>
 void perm_in(Ctx<T>& c, const T* x, T* dense) {
@@ -447,6 +455,97 @@ template <typename T>
 void perm_out(Ctx<T>& c, const T* dense, T* x) {
   hipLaunchKernelGGL(k_perm_out<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, dense, x, c.signs, c.plan);
   CS_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ DCT sparsifying basis
+// With Psi = F the signal is x = F s: index i of x is output i of Psi's DCT
+// (freq-layout float fpos(i)) and enters Phi's DCT at input perm[i] with sign
+// signs[i] (v-order position vpos(perm[i])).  Both reorders write their
+// destination in order and gather the source.
+
+// freq-layout float position -> DCT output index (inverse of fpos)
+__device__ __forceinline__ int64_t fpos_inv(int64_t P, const Plan& p) {
+  const int64_t f = P >> 1, h = P & 1;
+  const int64_t k = (f & (p.L2 - 1)) * p.L1 + (f >> p.logL2);
+  if (!h) return k;
+  return k == 0 ? p.L : p.n - k;
+}
+
+// v-order Phi input t <- R (Psi output): DCT input q at t, x index i = pinv[q]
+template <typename T>
+__global__ void k_rand_in(const T* __restrict__ fin, T* __restrict__ vout, const int8_t* __restrict__ signs,
+                          const int32_t* __restrict__ pinv, const Plan pl, const int* __restrict__ done) {
+  if (done && *done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= pl.n) return;
+  const int64_t q = vinv(t, pl.n);
+  const int64_t i = pinv ? (int64_t)pinv[q] : q;
+  const T v = fin[fpos(i, pl)];
+  vout[t] = signs[i] < 0 ? -v : v;
+}
+
+// freq-layout Psi^T input P <- R^T (Phi^T output): x index i = fpos_inv(P),
+// read at v-order position vpos(perm[i])
+template <typename T>
+__global__ void k_rand_out(const T* __restrict__ vin, T* __restrict__ fout, const int8_t* __restrict__ signs,
+                           const int32_t* __restrict__ perm, const Plan pl, const int* __restrict__ done) {
+  if (done && *done) return;
+  const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (P >= pl.n) return;
+  const int64_t i = fpos_inv(P, pl);
+  const int64_t q = perm ? (int64_t)perm[i] : i;
+  const T v = vin[vpos(q, pl.n)];
+  fout[P] = signs[i] < 0 ? -v : v;
+}
+
+template <typename T>
+void rand_in(Ctx<T>& c, const T* fin, T* vout, const int* done) {
+  hipLaunchKernelGGL(k_rand_in<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, fin, vout, c.rsigns, c.rpinv,
+                     c.plan, done);
+  CS_LAUNCH_CHECK();
+}
+template <typename T>
+void rand_out(Ctx<T>& c, const T* vin, T* fout, const int* done) {
+  hipLaunchKernelGGL(k_rand_out<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, vin, fout, c.rsigns, c.rperm,
+                     c.plan, done);
+  CS_LAUNCH_CHECK();
+}
+
+// Between the two column passes of an H-apply on Psi's transform (W holds
+// Psi's column stage): finish F s (row pass into P1), R into Phi's input,
+// Phi^T Phi = three passes with the row mask, R^T, and Psi^T's row pass
+// back into W.  `cg` (nullable) makes every launch exit once CG is done.
+template <typename T>
+double psi_middle(Ctx<T>& c, CgScalars* cg, int* rec) {
+  const int* done = cg ? &cg->done : nullptr;
+  ColIO<T> fwd = col_io<T>(c, COL_DENSE, nullptr), inv = col_io<T>(c, COL_DENSE, nullptr);
+  fwd.cg = cg;
+  inv.cg = cg;
+  double bytes = 0.0;
+  bytes += launch_row<T>(c, ROW_FWD_ALL, nullptr, c.P1, nullptr, done, rec ? &rec[0] : nullptr);
+  rand_in<T>(c, c.P1, c.P2, done);
+  bytes += launch_col<T>(c, (const Cx<T>*)c.P2, c.W, false, fwd, rec ? &rec[1] : nullptr);
+  bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, rec ? &rec[2] : nullptr);
+  bytes += launch_col<T>(c, c.W, (Cx<T>*)c.P2, true, inv, rec ? &rec[3] : nullptr);
+  rand_out<T>(c, c.P2, c.P1, done);
+  bytes += launch_row<T>(c, ROW_ADJ, c.P1, nullptr, nullptr, done, rec ? &rec[4] : nullptr);
+  c.transforms += 2;
+  return bytes;
+}
+
+// y-side of the residual with a DCT basis: W holds Psi's column stage of x.
+// Forms r = y - A x (masked, with its norm partials) and leaves Psi^T's row
+// pass of A^T r in W for the inverse column pass.
+template <typename T>
+void psi_resid_middle(Ctx<T>& c) {
+  launch_row<T>(c, ROW_FWD_ALL, nullptr, c.P1, nullptr, nullptr);
+  rand_in<T>(c, c.P1, c.P2, nullptr);
+  launch_col<T>(c, (const Cx<T>*)c.P2, c.W, false, col_io<T>(c, COL_DENSE, nullptr));
+  launch_row<T>(c, ROW_RESID, c.Yf, nullptr, c.partial2, nullptr);
+  launch_col<T>(c, c.W, (Cx<T>*)c.P2, true, col_io<T>(c, COL_DENSE, nullptr));
+  rand_out<T>(c, c.P2, c.P1, nullptr);
+  launch_row<T>(c, ROW_ADJ, c.P1, nullptr, nullptr, nullptr);
+  c.transforms += 2;
 }
 
 template <typename T>
@@ -488,11 +587,15 @@ void prepare_kernels() {
   template ColIO<T> col_io<T>(Ctx<T>&, int, const Supp*);                               \
   template double launch_col<T>(Ctx<T>&, const Cx<T>*, Cx<T>*, bool, const ColIO<T>&, int*); \
   template double launch_row<T>(Ctx<T>&, int, const T*, T*, double*, const int*, int*);      \
-  template void transform_fwd<T>(Ctx<T>&, const T*, T*);                                \
+  template void transform_fwd<T>(Ctx<T>&, const T*, T*, bool);                                \
   template void load_measurements<T>(Ctx<T>&, const T*);                                \
   template void transform_adj<T>(Ctx<T>&, const T*, T*, bool);                              \
   template void perm_in<T>(Ctx<T>&, const T*, T*);                                      \
   template void perm_out<T>(Ctx<T>&, const T*, T*);                                     \
+  template void rand_in<T>(Ctx<T>&, const T*, T*, const int*);                          \
+  template void rand_out<T>(Ctx<T>&, const T*, T*, const int*);                         \
+  template double psi_middle<T>(Ctx<T>&, CgScalars*, int*);                             \
+  template void psi_resid_middle<T>(Ctx<T>&);                                           \
   template void prepare_kernels<T>();
 CS_INST(float)
 CS_INST(double)

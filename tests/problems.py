@@ -10,8 +10,8 @@ import oracle
 import synth
 
 
-def build(d: synth.Draw, dtype: str = "f64"):
-    op = oracle.SRM(d.n, d.rows, d.signs, d.perm)
+def build(d: synth.Draw, dtype: str = "f64", psi: int = 0):
+    op = oracle.SRM(d.n, d.rows, d.signs, d.perm, psi)
     y0 = op.apply_sparse(d.supp, d.vals)
     y = y0 + d.noise_scale(np.linalg.norm(y0)) * d.noise if d.noise is not None else y0
     if dtype == "f32":
@@ -19,7 +19,8 @@ def build(d: synth.Draw, dtype: str = "f64"):
     return op, y
 
 
-def problem(cfg, sig, n, m, k, values="normal", snr_db=None, dtype="f64", randomizer="signs"):
+def problem(cfg, sig, n, m, k, values="normal", snr_db=None, dtype="f64", randomizer="signs", psi=0):
+    """psi = 1: s is sparse in the DCT-II basis (A = D F R F)."""
     d = synth.draw_problem(cfg, sig, n, m, k, values, snr_db, randomizer=randomizer)
-    op, y = build(d, dtype)
+    op, y = build(d, dtype, psi)
     return d, op, y

@@ -49,6 +49,25 @@ def test_workspace_is_linear_in_n_and_k():
     assert cs.cs_workspace_size(cs.CS_F32, 8, 4, 1, cs.CS_ALGO_SP) == 0           # N too small
 
 
+def test_workspace_for_a_dct_basis():
+    """cs_workspace_size_op reads n, m and psi from a host descriptor: Psi = I
+    matches cs_workspace_size, the DCT basis adds two N-vectors, other psi
+    values and batched descriptors with psi = 1 have no size."""
+    for dt, esz in ((cs.CS_F32, 4), (cs.CS_F64, 8)):
+        n, m, k = 2 ** 16, 2 ** 14, 300
+        base = cs.cs_workspace_size(dt, n, m, k, cs.CS_ALGO_SP)
+        op0 = cs.cs_op(n, m, None, None, None, 0, 0)
+        op1 = cs.cs_op(n, m, None, None, None, 1, 0)
+        assert cs.cs_workspace_size_op(dt, op0, k, cs.CS_ALGO_SP) == base
+        extra = cs.cs_workspace_size_op(dt, op1, k, cs.CS_ALGO_SP) - base
+        assert 2 * esz * n <= extra <= 2 * esz * n + 1024
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, m, None, None, None, 2, 0), k, cs.CS_ALGO_SP) == 0
+        items = (cs.cs_batch_item * 1)()
+        items[0].op = op1
+        items[0].k = 10
+        assert cs.lib.cs_workspace_size_batched(dt, 1, items, cs.CS_ALGO_OMPR) == 0
+
+
 FAKE = 4096          # a 256-aligned fake device address: never dereferenced on these paths
 
 

@@ -1,0 +1,137 @@
+"""GPU parity with the DCT sparsifying basis of the paper's experiments
+(Sec. IV-A: Psi a discrete cosine transform, so A = D F R F with F the
+orthonormal DCT-II) against the FP64 oracle: the operator entry points, the
+CG least squares, the four greedy recoveries and the gradient of the
+least-squares step.  Bars: FP64 1e-13 / FP32 6e-6 relative L2 for the
+operator (two transforms per apply, twice the one-transform bound); least
+squares and recoveries as for Psi = I."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import announce, rel, to_dev, torch_dev
+from tests.problems import problem
+
+pytestmark = pytest.mark.gpu
+
+OP_CASES = [
+    # n, m, randomizer, dtype
+    (16, 9, "signs", "f64"), (256, 77, "perm", "f32"), (4096, 1001, "perm", "f64"),
+    (2 ** 14, 2 ** 12, "signs", "f32"), (2 ** 16, 2 ** 14, "signed_perm", "f32"),
+    (2 ** 20, 2 ** 18, "perm", "f32"), (2 ** 20, 2 ** 18, "signs", "f64"),
+]
+
+
+@pytest.mark.parametrize("n,m,randomizer,dt", OP_CASES)
+def test_apply_with_dct_basis(n, m, randomizer, dt):
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d = synth.draw_problem(75, 0, n, m, 5, "normal", None, randomizer=randomizer)
+    op = oracle.SRM(n, d.rows, d.signs, d.perm, psi=1)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=1)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(n)
+    u = rng.standard_normal(m)
+    bar = 1e-13 if dt == "f64" else 6e-6
+    announce("apply psi", n, m, randomizer, dt)
+    ax = cs.cs_apply_A(to_dev(x, tdt), dop).cpu().numpy()
+    assert rel(ax, op.apply(x)) <= bar
+    atu = cs.cs_apply_At(to_dev(u, tdt), dop).cpu().numpy()
+    assert rel(atu, op.adjoint(u)) <= bar
+    aatu = cs.cs_apply_A(to_dev(atu, tdt), dop).cpu().numpy()    # A A^T = I
+    assert rel(aatu, u) <= 2 * bar
+
+
+def test_bad_basis_is_rejected():
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    d = synth.draw_problem(75, 1, 1024, 300, 5, "normal", None)
+    dop = cs.Operator.from_numpy(1024, d.rows, d.signs, psi=1)
+    ws = cs.workspace(cs.CS_F32, dop, 1, cs.CS_ALGO_OPERATOR)
+    dop.c.psi = 2
+    with pytest.raises(cs.CSError) as e:
+        cs.cs_apply_A(to_dev(np.ones(1024), torch.float32), dop, ws=ws)
+    assert e.value.status == cs.CS_E_OP
+
+
+LS_CASES = [
+    # n, m, k, dtype, tol, bound, randomizer
+    (4096, 1024, 50, "f64", 1e-12, 1e-10, "perm"),
+    (4096, 1024, 50, "f32", 1e-6, 1e-5, "signs"),
+    (2 ** 16, 2 ** 14, 300, "f32", 1e-6, 1e-5, "perm"),
+]
+
+
+@pytest.mark.parametrize("n,m,k,dt,tol,bound,randomizer", LS_CASES)
+def test_ls_solve_with_dct_basis(n, m, k, dt, tol, bound, randomizer):
+    """Theorems 1-2 with Psi = F: the CG solution equals the explicit
+    least-squares solution on S; a warm start from it converges at once."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, y = problem(76, k, n, m, k, "normal", 30.0, dt, randomizer, psi=1)
+    rng = synth.rng_for(76, k, 9)
+    wrong = rng.choice(np.setdiff1d(np.arange(n), d.supp), k // 4, replace=False)
+    S = np.sort(np.concatenate([d.supp[k // 4:], wrong])).astype(np.int32)
+    ref = oracle.ls(op, S, y)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=1)
+    announce("ls_solve psi", n, m, k, dt)
+    th, info = cs.cs_ls_solve(to_dev(y, tdt), dop, to_dev(S, torch.int32), tol)
+    th = th.cpu().numpy()
+    assert rel(th, ref) <= bound, (rel(th, ref), info)
+    th2, info2 = cs.cs_ls_solve(to_dev(y, tdt), dop, to_dev(S, torch.int32), tol, x0=to_dev(th, tdt))
+    assert rel(th2.cpu().numpy(), ref) <= bound
+    assert info2["cg_iters"] <= max(2, info["cg_iters"] // 2)
+
+
+RECOVER_CASES = [
+    # name, cfg, n, m, k, values, snr, dtype, tol, randomizer
+    ("omp_n4096_f64", 77, 4096, 1024, 50, "normal_min0.1", None, "f64", 1e-10, "perm"),
+    ("sp_n2p14_f32", 78, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6, "signs"),
+    ("sp_n2p14_40db_f64", 79, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10, "perm"),
+    ("ompr_n2p14_f64", 80, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f64", 1e-10, "perm"),
+    ("ompr_n4096_40db_f32", 81, 4096, 1024, 40, "normal", 40.0, "f32", 1e-6, "signed_perm"),
+    ("cosamp_n2p14_f32", 82, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6, "perm"),
+    ("sp_n16_f64", 83, 16, 9, 3, "normal_min0.1", None, "f64", 1e-10, "signs"),
+]
+
+
+@pytest.mark.parametrize("case", RECOVER_CASES, ids=[c[0] for c in RECOVER_CASES])
+def test_recover_with_dct_basis(case):
+    name, cfg, n, m, k, values, snr, dt, tol, randomizer = case
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, y = problem(cfg, 0, n, m, k, values, snr, dt, randomizer, psi=1)
+    algo = name.split("_")[0]
+    ref = getattr(oracle, algo)(op, y, k)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=1)
+    announce("recover psi", name)
+    s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, tol)
+    s = s.cpu().numpy()
+    supp = supp.cpu().numpy()
+    print(name, info, "oracle iters", ref.iters, ref.stop, flush=True)
+    assert np.array_equal(supp, ref.support), (np.setdiff1d(supp, ref.support), np.setdiff1d(ref.support, supp))
+    assert rel(s, ref.s) <= 1e-5
+    assert info["flags"] & ~cs.CS_F_CG_MAXITER == 0
+
+
+@pytest.mark.parametrize("dt,tol,bar", [("f64", 1e-12, 1e-8), ("f32", 1e-6, 1e-3)])
+def test_adjoint_ls_with_dct_basis(dt, tol, bar):
+    """dL/dy = A_S (A_S^T A_S)^-1 (dL/ds)_S on a frozen support, Psi = F."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    n, m, k = 2 ** 12, 1001, 37
+    d, op, y = problem(84, 0, n, m, k, "normal", 30.0, dt, "perm", psi=1)
+    t = d.s_dense()
+    g_ref, s_hat = oracle.adjoint_gradient(op, d.supp, y, t)
+    gs = np.random.default_rng(7).standard_normal(n)
+    gs[d.supp] = 2.0 * (s_hat - t[d.supp])
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=1)
+    announce("adjoint_ls psi", dt)
+    gy, info = cs.cs_adjoint_ls(to_dev(gs, tdt), dop, to_dev(d.supp, torch.int32), tol)
+    assert rel(gy.cpu().numpy(), g_ref) <= bar
+    assert info["flags"] == 0

@@ -515,3 +515,70 @@ def test_p2_permutation_randomizer(randomizer):
     for f in (oracle.omp, oracle.sp, oracle.ompr, oracle.cosamp):
         r = f(o2, y, 25)
         assert np.array_equal(r.support, dd.supp), f.__name__
+
+
+# ------------------------------------------------------------------ DCT sparsifying basis
+@pytest.mark.parametrize("randomizer", ["signs", "perm"])
+def test_p2_dct_basis(randomizer):
+    """Psi = F (the paper's experiments): A = D F R F equals the product of
+    the dense cosine-formula matrices, has orthonormal rows, and its columns
+    and adjoint agree with that product; a basis taken as F^T instead of F,
+    or left out, gives a different operator."""
+    d = synth.draw_problem(105, 0, 256, 90, 8, "normal", None, randomizer=randomizer)
+    op = oracle.SRM(d.n, d.rows, d.signs, d.perm, psi=1)
+    Fm = oracle.dct2_matrix(d.n)
+    Rm = np.zeros((d.n, d.n))
+    idx = d.perm if d.perm is not None else np.arange(d.n)
+    Rm[idx, np.arange(d.n)] = d.signs
+    A = Fm[d.rows] @ Rm @ Fm
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(d.n)
+    u = rng.standard_normal(d.m)
+    assert np.allclose(op.apply(x), A @ x, atol=1e-12)
+    assert np.allclose(op.adjoint(u), A.T @ u, atol=1e-12)
+    assert np.allclose(A @ A.T, np.eye(d.m), atol=1e-12)
+    S = np.sort(rng.choice(d.n, 12, replace=False))
+    assert np.allclose(op.columns(S), A[:, S], atol=1e-12)
+    assert not np.allclose(A, Fm[d.rows] @ Rm @ Fm.T, atol=1e-3)   # Psi = F^T differs
+    assert not np.allclose(A, Fm[d.rows] @ Rm, atol=1e-3)          # Psi = I differs
+    with pytest.raises(ValueError):
+        oracle.gram_matrix(op, S)                                   # closed form is for Psi = I
+
+
+def test_p6_orthogonal_special_case_dct_basis():
+    """M = N with Psi = F: A = F R F is orthogonal, so every algorithm returns
+    hard thresholding of A^T y, and the LS routes agree on the operator."""
+    rng = np.random.default_rng(14)
+    n, k = 512, 20
+    rows, signs = synth.draw_operator(rng, n, n)
+    op = oracle.SRM(n, rows, signs, psi=1)
+    y = rng.standard_normal(n)
+    c = op.adjoint(y)
+    expect = np.sort(np.argsort(-np.abs(c), kind="stable")[:k])
+    for f in (oracle.omp, oracle.sp, oracle.cosamp):
+        r = f(op, y, k)
+        assert np.array_equal(r.support, expect), f.__name__
+        assert np.allclose(r.s[expect], c[expect], atol=1e-12)
+    q = oracle.ompr(op, y, k, eta=1.0)
+    assert np.array_equal(q.support, expect) and q.iters == 0
+
+
+def test_p4_dct_basis_ls_routes_and_recovery():
+    """Psi = F: dense QR and operator CG least squares agree and leave a
+    residual orthogonal to the columns (Theorems 1-2); a noiseless signal
+    sparse in the DCT basis is recovered exactly by all four algorithms."""
+    d = synth.draw_problem(106, 0, 2048, 512, 25, "normal_min0.1", None, randomizer="perm")
+    op = oracle.SRM(d.n, d.rows, d.signs, d.perm, psi=1)
+    y = op.apply_sparse(d.supp, d.vals)
+    rng = np.random.default_rng(8)
+    yn = y + 0.01 * rng.standard_normal(d.m)
+    S = np.sort(rng.choice(d.n, 40, replace=False))
+    v1 = oracle.ls_dense(op, S, yn)
+    v2, _ = oracle.ls_cg(op, S, yn, tol=1e-13)
+    assert np.allclose(v1, v2, atol=1e-10)
+    r = yn - op.columns(S) @ v1
+    assert np.max(np.abs(op.columns(S).T @ r)) < 1e-10
+    for f in (oracle.omp, oracle.sp, oracle.ompr, oracle.cosamp):
+        res = f(op, y, 25)
+        assert np.array_equal(res.support, d.supp), f.__name__
+        assert np.allclose(res.s[d.supp], d.vals, atol=1e-9)
