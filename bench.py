@@ -249,25 +249,25 @@ def adjoint_leg(torch, cs, batch: int, reps: int = 3) -> dict:
 
 
 def xi_sweep_leg(torch, cs, ns, algos=("sp", "ompr", "omp")) -> dict:
-    """The precision experiment of the paper's Tables II-IV on its problem shape
-    (M = N/4, K = M/4, N(0,1) nonzeros, noise sigma 0.01, R a random
-    permutation as in the paper; Psi = I), FP64: CG run to
-    'exact' precision (relative 1e-12) and stopped at the absolute thresholds
-    ||r|| <= 1e-10 and <= 1e-5 of the CG loop test of Algorithm 1.  Per (algorithm, N):
-    seconds per recovery and reconstruction SNR 20 log10(||s|| / ||s_hat - s||),
-    with the SNR change against exact.  OMP (K iterations) runs up to N = 2^14,
-    OMPR up to 2^16."""
+    """The precision experiment of the paper's Tables II-IV on its own setup:
+    M = N/4, K = M/4, N(0,1) nonzeros, noise sigma 0.01, Phi = D F R with R a
+    random permutation and the signal sparse in the DCT basis (Psi = F, so
+    A = D F R F), FP64: CG run to 'exact' precision (relative 1e-12) and
+    stopped at the absolute thresholds ||r|| <= 1e-10 and <= 1e-5 of the CG
+    loop test of Algorithm 1.  Per (algorithm, N): seconds per recovery and
+    reconstruction SNR 20 log10(||s|| / ||s_hat - s||), with the SNR change
+    against exact.  OMP (K iterations) runs up to N = 2^12, OMPR up to 2^14."""
     import synth
-    out = {}
+    out = {"operator": "A = D F R F (R a uniform random permutation, Psi = DCT-II)"}
     for n in ns:
         d = synth.paper_problem(n)
-        op = cs.Operator.from_numpy(d.n, d.rows, d.signs, d.perm)
+        op = cs.Operator.from_numpy(d.n, d.rows, d.signs, d.perm, psi=1)
         s_true = torch.as_tensor(d.s_dense(), dtype=torch.float64, device="cuda")
         y0 = cs.cs_apply_A(s_true, op).cpu().numpy()
         y = torch.as_tensor(y0 + d.noise_scale(0.0) * d.noise, dtype=torch.float64, device="cuda")
         s_np = d.s_dense()
         for algo in algos:
-            if n > {"omp": 2 ** 14, "ompr": 2 ** 16}.get(algo, 2 ** 30):
+            if n > {"omp": 2 ** 12, "ompr": 2 ** 14}.get(algo, 2 ** 30):
                 continue
             fn = getattr(cs, f"cs_recover_{algo}")
             row = {}
