@@ -92,3 +92,53 @@ def test_sp_n2p24_fp32():
     r = y - op.apply(s)
     cols = op.columns(supp[:: max(1, supp.size // 512)])
     assert np.linalg.norm(cols.T @ r) <= 1e-5 * np.linalg.norm(cols.T @ y)
+
+
+# ------------------------------------------------------------------ largest sizes the library takes
+MAX_OP_CASES = [(2 ** 26, 2 ** 23, "f32"), (2 ** 25, 2 ** 22, "f64")]
+
+
+@pytest.mark.parametrize("n,m,dt", MAX_OP_CASES)
+def test_operator_at_the_largest_sizes(n, m, dt):
+    """N = 2^26 (the largest N) in FP32 and N = 2^25 (an odd four-step split)
+    in FP64: A x and A^T u against the oracle's SciPy route, relative L2 as
+    for the smaller operator cases."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d = synth.draw_problem(85, 0, n, m, 5, "normal", None)
+    op = oracle.SRM(n, d.rows, d.signs)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(n)
+    u = rng.standard_normal(m)
+    bar = 1e-13 if dt == "f64" else 3e-6
+    announce("apply max size", n, m, dt)
+    assert rel(cs.cs_apply_A(to_dev(x, tdt), dop).cpu().numpy(), op.apply(x)) <= bar
+    announce("apply_At max size", n, m, dt)
+    assert rel(cs.cs_apply_At(to_dev(u, tdt), dop).cpu().numpy(), op.adjoint(u)) <= bar
+
+
+def test_sp_at_the_largest_size():
+    """SP at N = 2^26, M = 2^23, K = 2^13, FP32, noiseless, values
+    +-(1 + |N(0,1)|): far inside the recoverable range (K/M = 2^-10), so the
+    recovered support is the drawn one and s equals the drawn s to the CG
+    tolerance; the residual is orthogonal to the support columns
+    (Theorems 1-2).  The oracle's SP does not finish in seconds at this size;
+    these properties hold at any size."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    n, m, k = 2 ** 26, 2 ** 23, 2 ** 13
+    d = synth.draw_problem(86, 0, n, m, k, "pm_one_plus_absnormal", None)
+    op, y = build(d, "f32")
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    announce("sp max size", n, m, k)
+    s, supp, info = cs.cs_recover_sp(to_dev(y, torch.float32), dop, k, 1e-6)
+    supp = supp.cpu().numpy()
+    s = s.cpu().numpy().astype(np.float64)
+    print(info, flush=True)
+    assert np.array_equal(supp, d.supp)
+    assert rel(s, d.s_dense()) <= 1e-5
+    r = y - op.apply(s)
+    # A_S^T r = (A^T r)_S: one adjoint instead of M x K dense columns
+    assert np.linalg.norm(op.adjoint(r)[supp]) <= 1e-5 * np.linalg.norm(op.adjoint(y)[supp])
