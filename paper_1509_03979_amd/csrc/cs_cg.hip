@@ -136,7 +136,14 @@ __global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, int nr
 
 // alpha = rr / d^T q (d^T q from the inverse pass); x += alpha d; r -= alpha q;
 // per-block r^T r, and the last block to finish reduces them (fixed order) to
-// the next rr, beta and the convergence test.
+// the next rr, beta and the convergence test.  Each thread updates kUpdUnroll
+// elements with their loads issued together; a single block needs no ticket.
+constexpr int kUpdUnroll = 8;
+static inline int upd_blocks(int k) {
+  const int per = kRedThreads * kUpdUnroll;
+  return std::max(1, std::min(kRedBlocks, (k + per - 1) / per));
+}
+
 template <typename T>
 __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ d, const T* __restrict__ q,
                             int k, double* __restrict__ prr, CgScalars* cg, int it, int max_iter) {
@@ -153,25 +160,49 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
   }
   const T alpha = (T)(rr / dq);
   double acc = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-    x[i] += alpha * d[i];
-    const T rv = r[i] - alpha * q[i];
-    r[i] = rv;
-    acc += (double)rv * (double)rv;
+  const int st = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x + threadIdx.x; base < k; base += st * kUpdUnroll) {
+    T xv[kUpdUnroll], dv[kUpdUnroll], rv[kUpdUnroll], qv[kUpdUnroll];
+#pragma unroll
+    for (int u = 0; u < kUpdUnroll; ++u) {
+      const int i = base + u * st;
+      if (i < k) {
+        xv[u] = x[i];
+        dv[u] = d[i];
+        rv[u] = r[i];
+        qv[u] = q[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUpdUnroll; ++u) {
+      const int i = base + u * st;
+      if (i < k) {
+        x[i] = xv[u] + alpha * dv[u];
+        const T rn = rv[u] - alpha * qv[u];
+        r[i] = rn;
+        acc += (double)rn * (double)rn;
+      }
+    }
   }
   acc = block_sum(acc);
-  if (threadIdx.x == 0) {
+  if (gridDim.x == 1) {
+    if (threadIdx.x == 0) prr[0] = acc;
+    last = 1;
+  } else if (threadIdx.x == 0) {
     prr[blockIdx.x] = acc;
     __threadfence();
     last = atomicAdd(&cg->cnt_u, 1u) == gridDim.x - 1;
   }
   __syncthreads();
   if (last) {
-    __threadfence();
-    const volatile double* vp = prr;
-    double s = 0.0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) s += vp[i];
-    const double rr_new = block_sum(s);
+    double rr_new = acc;
+    if (gridDim.x > 1) {
+      __threadfence();
+      const volatile double* vp = prr;
+      double sum = 0.0;
+      for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) sum += vp[i];
+      rr_new = block_sum(sum);
+    }
     if (threadIdx.x == 0) {
       const bool fin = isfinite(rr_new);
       cg->rr[(it + 1) & 1] = rr_new;
@@ -267,8 +298,8 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
       qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[6]);
       queued.push_back(qd);
       c.transforms += 2;   // (psi_middle counts Phi's two)
-      hipLaunchKernelGGL(k_cg_update<T>, dim3(nb), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr, c.cg, it,
-                         max_iter);
+      hipLaunchKernelGGL(k_cg_update<T>, dim3(upd_blocks(k)), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr,
+                         c.cg, it, max_iter);
       CS_LAUNCH_CHECK();
     }
     dev_read(s, c.cg, &host, sizeof(CgScalars));
@@ -316,9 +347,11 @@ double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
   launch_col<T>(c, c.W, (Cx<T>*)c.Cc, true, col_io<T>(c, COL_KEY, nullptr));
   c.transforms += 2;
   sum_partials_to(c.partial2, (int)(c.plan.L1 >> 1), &c.cg->resid2, c.stream);
-  double r2 = 0.0;
-  dev_read(c.stream, &c.cg->resid2, &r2, sizeof(double));
-  return std::sqrt(r2);
+  // one host read brings ||r||^2 and the support-comparison flag queued before it
+  struct { double r2; int32_t differ, pad; } h{};
+  dev_read(c.stream, &c.cg->resid2, &h, sizeof(h));
+  c.last_differ = h.differ;
+  return std::sqrt(h.r2);
 }
 
 template <typename T>

@@ -139,8 +139,9 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
     bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
     if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
     cg_solve<T>(c, supp(iN, K), xN, warm, tol, cg_cap(prm, K));
-    const bool same = bits_equal(c.bits[iN], c.bits[iT], words, c.ibuf + 8, s);
-    const double rn2 = resid_corr<T>(c, supp(iN, K), xN);
+    bits_differ(c.bits[iN], c.bits[iT], words, &c.cg->differ, s);
+    const double rn2 = resid_corr<T>(c, supp(iN, K), xN);     // also reads the flag back
+    const bool same = c.last_differ == 0;
     if (same) {
       std::swap(iT, iN);
       std::swap(xT, xN);
@@ -286,9 +287,10 @@ void run_cosamp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, in
     topk_compact<T>(c, xU, c.list[iU], kU, K, c.bits[iN]);
     bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
     remap<T>(c, c.list[iU], xU, kU, c.list[iN], xN, K);
-    const bool same = it > 1 && bits_equal(c.bits[iN], c.bits[iT], words, c.ibuf + 8, s);
+    if (it > 1) bits_differ(c.bits[iN], c.bits[iT], words, &c.cg->differ, s);
     const Supp SN{c.bits[iN], c.wpre[iN], c.list[iN], K};
-    const double rn2 = resid_corr<T>(c, SN, xN);
+    const double rn2 = resid_corr<T>(c, SN, xN);               // also reads the flag back
+    const bool same = it > 1 && c.last_differ == 0;
     if (same) {
       std::swap(iT, iN);
       std::swap(xT, xN);

@@ -205,6 +205,8 @@ struct CgScalars {
   double bb;              // b^T b
   double tol2;            // tol^2
   double resid2;          // ||y - A x||^2 of the last residual pass
+  int32_t differ;         // set by bits_differ; read back with resid2
+  int32_t pad0;
   double dq;              // d^T H d of the current iteration
   double beta;            // next direction update coefficient
   double ref;             // the stopping test is r^T r <= tol2 * ref: ref = b^T b (relative) or 1 (absolute)
@@ -307,6 +309,7 @@ struct Ctx {
   CgScalars* cg;
   SelState* sel;
   double ynorm = 0;        // ||y||, FP64 accumulation
+  int32_t last_differ = 0; // CgScalars::differ as read back by the last resid_corr
   int tol_abs = 0;         // CG tolerance absolute (||r|| <= tol) instead of relative
   // host-side counters
   int64_t transforms = 0;
@@ -441,6 +444,8 @@ template <typename T> void topk_compact(Ctx<T>& c, const T* vals, const int32_t*
 template <typename T> int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uint32_t* wpre);
 void bits_or(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t words, hipStream_t s);
 int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, hipStream_t s);
+// *flag = 1 if the bitmaps differ, else 0 (no host read)
+void bits_differ(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* flag, hipStream_t s);
 
 // ------------------------------------------------------------------ CG
 // Solves the weighted normal equations on support S; x (compact, key order,

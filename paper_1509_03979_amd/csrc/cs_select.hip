@@ -716,6 +716,12 @@ __global__ void k_bits_diff(const uint32_t* __restrict__ a, const uint32_t* __re
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < words && a[i] != b[i]) *flag = 1;
 }
+void bits_differ(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* flag, hipStream_t s) {
+  fill<int32_t>(flag, 1, 0, s);
+  hipLaunchKernelGGL(k_bits_diff, dim3(nblk(words, 256)), dim3(256), 0, s, a, b, words, flag);
+  CS_LAUNCH_CHECK();
+}
+
 int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, hipStream_t s) {
   fill<int32_t>(scratch, 1, 0, s);
   hipLaunchKernelGGL(k_bits_diff, dim3(nblk(words, 256)), dim3(256), 0, s, a, b, words, scratch);
