@@ -9,7 +9,8 @@
 * R = diag(signs) with signs in {+1, -1}, optionally with a permutation.
 * Psi, the sparsifying basis: the identity (``psi = 0``, s sparse directly)
   or, as in the experiments of Sec. IV-A, the orthonormal DCT-II F itself
-  (``psi = 1``).
+  (``psi = 1``), or the separable 2-D DCT of Sec. III-E on an n x n image,
+  N = n^2 (``psi = 2``): x = vec(F_n S F_n^T), row-major vec.
 
 So with Psi = I, A x = (F (signs * x))[rows] and A^T u = signs * F^T
 (zero-fill_rows(u)); with Psi = F, A s = (F R F s)[rows] and
@@ -54,8 +55,9 @@ class SRM:
     R is the randomizer: entry j of x goes to DCT input perm[j] with sign
     signs[j] ((R x)[perm[j]] = signs[j] x[j]); perm = None is the identity, so
     R = diag(signs).  The paper's R is a uniform random permutation (signs all
-    +1); the workloads here use the sign flip.  Psi is the identity (psi = 0)
-    or the DCT-II (psi = 1, A = D F R F)."""
+    +1); the workloads here use the sign flip.  Psi is the identity (psi = 0),
+    the DCT-II (psi = 1, A = D F R F) or the 2-D DCT (psi = 2,
+    A = D F R (F_n (x) F_n))."""
 
     def __init__(self, n: int, rows, signs, perm=None, psi: int = 0):
         rows = np.asarray(rows, dtype=np.int64)
@@ -70,9 +72,15 @@ class SRM:
         self.m = int(rows.size)
         self.rows = rows
         self.signs = signs.astype(np.float64)
-        if psi not in (0, 1):
-            raise ValueError("psi must be 0 or 1")
+        if psi not in (0, 1, 2):
+            raise ValueError("psi must be 0, 1 or 2")
         self.psi = int(psi)
+        self.side = 0
+        if psi == 2:
+            side = int(round(np.sqrt(n)))
+            if side * side != n:
+                raise ValueError("psi = 2 needs N = n^2")
+            self.side = side
         self.perm = None
         if perm is not None:
             perm = np.asarray(perm, dtype=np.int64)
@@ -102,8 +110,10 @@ class SRM:
     def apply(self, x: np.ndarray) -> np.ndarray:
         """A x for a dense N-vector x (with psi = 1, F x enters R first)."""
         x = np.asarray(x, dtype=np.float64)
-        if self.psi:
+        if self.psi == 1:
             x = sfft.dct(x, type=2, norm="ortho", workers=WORKERS)
+        elif self.psi == 2:
+            x = sfft.dctn(x.reshape(self.side, self.side), type=2, norm="ortho", workers=WORKERS).reshape(-1)
         return sfft.dct(self._place(x), type=2, norm="ortho", workers=WORKERS)[self.rows]
 
     def apply_sparse(self, supp, vals) -> np.ndarray:
@@ -117,22 +127,30 @@ class SRM:
         full = np.zeros(self.n)
         full[self.rows] = np.asarray(u, dtype=np.float64)
         w = self._unplace(sfft.idct(full, type=2, norm="ortho", workers=WORKERS))
-        if self.psi:
+        if self.psi == 1:
             w = sfft.idct(w, type=2, norm="ortho", workers=WORKERS)
+        elif self.psi == 2:
+            w = sfft.idctn(w.reshape(self.side, self.side), type=2, norm="ortho", workers=WORKERS).reshape(-1)
         return w
 
     # ---------------------------------------------------- formula route
     def columns(self, supp) -> np.ndarray:
         """Dense A_S (M x |S|) from the cosine formula.
 
-        With psi = 1 each column is D F R (F e_j): F e_j from the formula, then
-        R, then F through the same formula for N <= 4096 (else SciPy's DCT)."""
+        With psi = 1 each column is D F R (F e_j), with psi = 2 D F R (Psi e_j)
+        for the 2-D basis: Psi's columns from the formula, then R, then F
+        through the same formula for N <= 4096 (else SciPy's DCT)."""
         j = np.asarray(supp, dtype=np.int64)[None, :]
         k = self.rows[:, None]
         if not self.psi:
             return _dct_scale(k, self.n) * _cos_table(k, self.dct_index(j), self.n) * self.signs[j]
-        i = np.arange(self.n)[:, None]
-        fcols = _dct_scale(i, self.n) * _cos_table(i, j, self.n)        # F e_j, N x |S|
+        if self.psi == 1:
+            i = np.arange(self.n)[:, None]
+            fcols = _dct_scale(i, self.n) * _cos_table(i, j, self.n)    # F e_j, N x |S|
+        else:                                                           # vec(F_n E_ab F_n^T) = F_n[:, a] (x) F_n[:, b]
+            fs = dct2_matrix(self.side)
+            a, b = j[0] // self.side, j[0] % self.side
+            fcols = (fs[:, a][:, None, :] * fs[:, b][None, :, :]).reshape(self.n, -1)
         placed = np.zeros_like(fcols)
         idx = self.dct_index(np.arange(self.n))
         placed[idx, :] = self.signs[:, None] * fcols                    # R applied to each column

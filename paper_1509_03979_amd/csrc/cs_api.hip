@@ -75,6 +75,11 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0)
     c.P1 = cv.take<T>(n);
     c.P2 = cv.take<T>(n);
   }
+  if (psi == 2) {
+    c.P3 = cv.take<T>(n);
+    c.P4 = cv.take<T>(n);
+    c.tw_dct = cv.take<Cx<T>>(kTwStage);
+  }
   c.ibuf = cv.take<int32_t>(64);
   c.blockcnt = cv.take<uint32_t>((p.words + kBitsPerBlockWords - 1) / kBitsPerBlockWords + 2);
   c.cg = cv.take<CgScalars>(1);
@@ -105,8 +110,10 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   Plan p;
   const cs_dtype dt = sizeof(T) == 4 ? CS_F32 : CS_F64;
   if (!choose_plan(dt, op->n, op->m, p, force)) throw Error(CS_E_SHAPE, "unsupported N or shape");
-  if (op->psi != 0 && op->psi != 1) throw Error(CS_E_OP, "operator psi must be 0 or 1");
+  if (op->psi < 0 || op->psi > 2) throw Error(CS_E_OP, "operator psi must be 0, 1 or 2");
   const int psi = op->psi;
+  const int dlog = psi == 2 ? dct2d_side_log(dt, op->n) : 0;
+  if (dlog < 0) throw Error(CS_E_SHAPE, "the 2-D DCT basis needs N = n^2 with n a power of two in [8, 8192] (FP64: 4096)");
   const size_t need = carve(c, p, kmax, nullptr, psi);
   if (ws_bytes < need) throw Error(CS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   carve(c, p, kmax, (char*)ws, psi);
@@ -117,9 +124,11 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   // the randomizer) or, with a DCT basis, Psi's (no randomizer)
   p.perm = psi ? nullptr : op->perm;
   p.pinv = (!psi && op->perm) ? c.pinv : nullptr;
+  p.keynat = psi == 2 ? 1 : 0;
   c.plan = p;
   c.stream = s;
   c.psi = psi;
+  c.dct_log = dlog;
   c.rsigns = op->signs;
   c.rperm = op->perm;
   c.rpinv = op->perm ? c.pinv : nullptr;
@@ -139,7 +148,9 @@ static void check_shape(cs_dtype dt, const cs_op* op, int32_t k, cs_algo algo) {
   const int64_t n = op->n, m = op->m;
   if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) throw Error(CS_E_SHAPE, "N must be a power of two in [16, 2^26]");
   if (m < 1 || m > n) throw Error(CS_E_SHAPE, "M must satisfy 1 <= M <= N");
-  if (op->psi != 0 && op->psi != 1) throw Error(CS_E_OP, "operator psi must be 0 or 1");
+  if (op->psi < 0 || op->psi > 2) throw Error(CS_E_OP, "operator psi must be 0, 1 or 2");
+  if (op->psi == 2 && dct2d_side_log(dt, n) < 0)
+    throw Error(CS_E_SHAPE, "the 2-D DCT basis needs N = n^2 with n a power of two in [8, 8192] (FP64: 4096)");
   if (algo == CS_ALGO_OPERATOR) return;
   if (k < 1) throw Error(CS_E_INVALID, "K must be >= 1");
   if (k > m) throw Error(CS_E_SHAPE, "K must not exceed M");
@@ -393,7 +404,15 @@ static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, vo
   setup_operator<T>(c);
   // With a DCT basis (psi) perm_in/perm_out place s with no randomizer, and
   // R is applied between Psi's and Phi's transforms.
-  if (!adjoint) {
+  if (c.psi == 2) {   // natural order on the s side: no placement pass
+    if (!adjoint) {
+      psi2_forward<T>(c, (const T*)in, c.Yf);
+      gather_freq<T>(c, c.Yf, (T*)out);
+    } else {
+      scatter_freq<T>(c, (const T*)in, c.Yf);
+      psi2_adjoint<T>(c, c.Yf, (T*)out);
+    }
+  } else if (!adjoint) {
     perm_in<T>(c, (const T*)in, c.Dd);
     transform_fwd<T>(c, c.Dd, c.Yf, c.psi != 0);   // Psi = F: every output, unmasked
     if (c.psi) {
@@ -432,7 +451,8 @@ size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_alg
 }
 
 size_t cs_workspace_size_op(cs_dtype dtype, const cs_op* op, int32_t k, cs_algo algo) {
-  if (!op || (op->psi != 0 && op->psi != 1)) return 0;
+  if (!op || op->psi < 0 || op->psi > 2) return 0;
+  if (op->psi == 2 && dct2d_side_log(dtype, op->n) < 0) return 0;
   if (cs_workspace_size(dtype, op->n, op->m, k, algo) == 0) return 0;
   return workspace_bytes(dtype, op->n, op->m, k, algo, op->psi);
 }

@@ -215,6 +215,88 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
   }
 }
 
+// ---- separable 2-D DCT basis: compact vectors <-> the support of the
+// zero-padded image P3 (keys are natural indices; the support is fixed within
+// a solve, so P3 is cleared once per solve)
+template <typename T>
+__global__ void k_s2_scatter(const T* __restrict__ v, const int32_t* __restrict__ list, int k, T* __restrict__ img) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) img[list[i]] = v[i];
+}
+
+// d = r (iteration 0) or r + beta d on the support, scattered into the image
+template <typename T>
+__global__ void k_s2_dir(const T* __restrict__ r, T* __restrict__ d, const int32_t* __restrict__ list, int k,
+                         T* __restrict__ img, const CgScalars* __restrict__ cg, int it) {
+  if (cg->done) return;
+  const T beta = it == 0 ? (T)0 : (T)cg->beta;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const T v = it == 0 ? r[i] : r[i] + beta * d[i];
+    d[i] = v;
+    img[list[i]] = v;
+  }
+}
+
+// q = (H d)_S gathered from the transformed image, and d^T q: per-block
+// partials, the last block to finish sums them in index order.
+template <typename T>
+__global__ void k_s2_q(const T* __restrict__ sout, const int32_t* __restrict__ list, int k, const T* __restrict__ d,
+                       T* __restrict__ q, double* __restrict__ pdq, CgScalars* cg) {
+  __shared__ int last;
+  if (cg->done) return;
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const T v = sout[list[i]];
+    q[i] = v;
+    acc += (double)d[i] * (double)v;
+  }
+  acc = block_sum(acc);
+  if (gridDim.x == 1) {
+    last = 1;
+  } else if (threadIdx.x == 0) {
+    pdq[blockIdx.x] = acc;
+    __threadfence();
+    last = atomicAdd(&cg->cnt_q, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) {
+    double sdq = acc;
+    if (gridDim.x > 1) {
+      __threadfence();
+      const volatile double* vp = pdq;
+      double sum = 0.0;
+      for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) sum += vp[i];
+      sdq = block_sum(sum);
+    }
+    if (threadIdx.x == 0) {
+      cg->dq = sdq;
+      cg->cnt_q = 0u;
+    }
+  }
+}
+
+// warm start: r = b - (H x0)_S, d = r, partial r^T r per block
+template <typename T>
+__global__ void k_s2_r(const T* __restrict__ sout, const int32_t* __restrict__ list, int k, const T* __restrict__ b,
+                       T* __restrict__ r, T* __restrict__ d, double* __restrict__ prr) {
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const T v = b[i] - sout[list[i]];
+    r[i] = v;
+    d[i] = v;
+    acc += (double)v * (double)v;
+  }
+  acc = block_sum(acc);
+  if (threadIdx.x == 0) prr[blockIdx.x] = acc;
+}
+
+template <typename T>
+static void s2_scatter(Ctx<T>& c, const Supp& S, const T* v) {
+  hipLaunchKernelGGL(k_s2_scatter<T>, dim3(std::max(1, (S.k + 255) / 256)), dim3(256), 0, c.stream, v, S.list, S.k,
+                     c.P3);
+  CS_LAUNCH_CHECK();
+}
+
 template <typename T>
 int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter, bool b_ready, bool r0_corr) {
   hipStream_t s = c.stream;
@@ -230,6 +312,15 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   if (warm && r0_corr) {
     hipLaunchKernelGGL(k_cg_init_corr<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.Cc, S.list, k, c.cr, c.cd,
                        prr);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, nb, pbb, nb, tol * tol, max_iter,
+                       c.tol_abs);
+  } else if (warm && c.psi == 2) {
+    fill<T>(c.P3, c.plan.n, (T)0, s);
+    s2_scatter<T>(c, S, x);
+    psi2_happly<T>(c, nullptr, c.P1);
+    hipLaunchKernelGGL(k_s2_r<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.P1, S.list, k, (const T*)c.cb, c.cr,
+                       c.cd, prr);
     CS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, nb, pbb, nb, tol * tol, max_iter,
                        c.tol_abs);
@@ -287,11 +378,26 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   struct Queued { int rec[7]; double bytes; };
   std::vector<Queued> queued;
   const int per_it = c.psi ? 4 : 2;   // transforms per iteration
+  if (c.psi == 2 && !(warm && !r0_corr)) fill<T>(c.P3, c.plan.n, (T)0, s);   // (cleared above otherwise)
   while (it < max_iter) {
     const int q = std::min(chunk, max_iter - it);
     for (int u = 0; u < q; ++u, ++it) {
       dir.it = it;
       Queued qd{{-1, -1, -1, -1, -1, -1, -1}, 0.0};
+      if (c.psi == 2) {
+        hipLaunchKernelGGL(k_s2_dir<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.cr, c.cd, S.list, k, c.P3,
+                           (const CgScalars*)c.cg, it);
+        CS_LAUNCH_CHECK();
+        psi2_happly<T>(c, c.cg, c.P1);
+        hipLaunchKernelGGL(k_s2_q<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.P1, S.list, k, (const T*)c.cd,
+                           c.cq, pdq, c.cg);
+        CS_LAUNCH_CHECK();
+        queued.push_back(qd);
+        hipLaunchKernelGGL(k_cg_update<T>, dim3(upd_blocks(k)), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr,
+                           c.cg, it, max_iter);
+        CS_LAUNCH_CHECK();
+        continue;
+      }
       qd.bytes += launch_col<T>(c, nullptr, c.W, false, dir, &qd.rec[0]);
       if (c.psi) qd.bytes += psi_middle<T>(c, c.cg, &qd.rec[1]);
       else qd.bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, &qd.rec[1]);
@@ -339,6 +445,11 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
 
 template <typename T>
 double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
+  if (c.psi == 2) {
+    fill<T>(c.P3, c.plan.n, (T)0, c.stream);
+    s2_scatter<T>(c, S, x);
+    psi2_resid<T>(c, c.Cc);
+  } else {
   ColIO<T> in = col_io<T>(c, COL_X, &S);
   in.x = const_cast<T*>(x);
   launch_col<T>(c, nullptr, c.W, false, in);
@@ -346,6 +457,7 @@ double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
   else launch_row<T>(c, ROW_RESID, c.Yf, nullptr, c.partial2, nullptr);
   launch_col<T>(c, c.W, (Cx<T>*)c.Cc, true, col_io<T>(c, COL_KEY, nullptr));
   c.transforms += 2;
+  }
   sum_partials_to(c.partial2, (int)(c.plan.L1 >> 1), &c.cg->resid2, c.stream);
   // one host read brings ||r||^2 and the support-comparison flag queued before it
   struct { double r2; int32_t differ, pad; } h{};
@@ -356,6 +468,12 @@ double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
 
 template <typename T>
 void apply_support(Ctx<T>& c, const Supp& S, const T* x, T* outf) {
+  if (c.psi == 2) {
+    fill<T>(c.P3, c.plan.n, (T)0, c.stream);
+    s2_scatter<T>(c, S, x);
+    psi2_forward<T>(c, c.P3, outf);
+    return;
+  }
   ColIO<T> in = col_io<T>(c, COL_X, &S);
   in.x = const_cast<T*>(x);
   launch_col<T>(c, nullptr, c.W, false, in);

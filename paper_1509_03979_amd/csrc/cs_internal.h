@@ -91,6 +91,7 @@ struct Plan {
   const uint32_t* mask;   // N bits in freq-layout: bit 2f+h = row sampled
   const int32_t* perm;    // randomizer permutation: entry j enters the DCT at perm[j] (null: identity)
   const int32_t* pinv;    // its inverse (null with perm)
+  int keynat;             // 1: candidates are keyed by their natural index (2-D DCT basis)
 };
 
 constexpr int kTwStage = 8192;   // entries reserved for one stage-twiddle table (size 2^13 needs 8176)
@@ -137,10 +138,12 @@ __host__ __device__ __forceinline__ int64_t pos_of_key(int64_t k, const Plan& pl
 // Natural index j of x <-> DCT input index (through the randomizer's
 // permutation, device tables) <-> key.
 __device__ __forceinline__ int64_t nat_of_key(int64_t k, const Plan& pl) {
+  if (pl.keynat) return k;
   const int64_t q = vinv(pos_of_key(k, pl), pl.n);
   return pl.pinv ? (int64_t)pl.pinv[q] : q;
 }
 __device__ __forceinline__ int64_t key_of_nat(int64_t j, const Plan& pl) {
+  if (pl.keynat) return j;
   const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
   return key_of_pos(vpos(q, pl.n), pl);
 }
@@ -273,8 +276,13 @@ struct Ctx {
   const int8_t* rsigns = nullptr;
   const int32_t* rperm = nullptr;
   const int32_t* rpinv = nullptr;
-  T* P1 = nullptr;         // psi: freq-layout N-vector (Psi output / Psi^T input)
+  T* P1 = nullptr;         // psi: freq-layout N-vector (Psi output / Psi^T input); psi 2: x in natural order
   T* P2 = nullptr;         // psi: v-order N-vector (Phi input / output)
+  // psi = 2, the separable 2-D DCT basis on an n x n image (n = 2^dct_log):
+  T* P3 = nullptr;         // the support scattered into a zero image (fixed within a CG solve)
+  T* P4 = nullptr;         // row-pass intermediate
+  Cx<T>* tw_dct = nullptr; // stage twiddles of the n/2-point row FFTs
+  int dct_log = 0;
   const int32_t* rows;
   int kmax;                // largest support handled by the compact buffers
   // dense N-vectors (v-order unless noted)
@@ -435,6 +443,20 @@ template <typename T> void rand_in(Ctx<T>& c, const T* fin, T* vout, const int* 
 template <typename T> void rand_out(Ctx<T>& c, const T* vin, T* fout, const int* done);
 template <typename T> double psi_middle(Ctx<T>& c, CgScalars* cg, int* rec);   // rec: 5 entries or null
 template <typename T> void psi_resid_middle(Ctx<T>& c);
+// psi = 2: natural-order x (instead of freq layout) through R and back
+template <typename T> void rand_in_nat(Ctx<T>& c, const T* xin, T* vout, const int* done);
+template <typename T> void rand_out_nat(Ctx<T>& c, const T* vin, T* xout, const int* done);
+// separable 2-D DCT basis: out = vec(F S F^T) (inv: vec(F^T S F)); tmp an N-vector
+constexpr int kDct2dMinLog = 3;      // image sides 8 ..
+constexpr int kDct2dMaxLog32 = 13;   // .. 8192 (FP32)
+constexpr int kDct2dMaxLog64 = 12;   // .. 4096 (FP64)
+int dct2d_side_log(cs_dtype dt, int64_t n);   // log2 of the side, or -1 if N is not a supported square
+template <typename T> void dct2d(Ctx<T>& c, bool inv, const T* in, T* tmp, T* out, const int* done);
+template <typename T> void dct2d_setup(Ctx<T>& c);
+template <typename T> void psi2_happly(Ctx<T>& c, CgScalars* cg, T* sout);   // image in P3 -> F^T(...)F into sout
+template <typename T> void psi2_resid(Ctx<T>& c, T* cout);                  // image in P3 -> A^T (y - A x)
+template <typename T> void psi2_forward(Ctx<T>& c, const T* img, T* outf);
+template <typename T> void psi2_adjoint(Ctx<T>& c, const T* inf, T* out);
 template <typename T> void prepare_kernels();                             // LDS limits, once per process
 
 // ------------------------------------------------------------------ selection

@@ -225,6 +225,7 @@ void setup_operator(Ctx<T>& c) {
   CS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_check_signs, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.rsigns, p.n, c.ibuf);
   CS_LAUNCH_CHECK();
+  if (c.psi == 2) dct2d_setup<T>(c);
   if (c.rperm) {
     fill<int32_t>(c.pinv, p.n, -1, s);
     hipLaunchKernelGGL(k_perm_inverse, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.rperm, p.n, c.pinv, c.ibuf);
@@ -347,6 +348,10 @@ void load_measurements(Ctx<T>& c, const T* y) {
   c.ynorm = norm2_host<T>(c, y, c.plan.m);
   if (!c.psi) {
     transform_adj<T>(c, c.Yf, c.C0, true);
+    return;
+  }
+  if (c.psi == 2) {
+    psi2_adjoint<T>(c, c.Yf, c.C0);
     return;
   }
   // A^T y = F^T R^T F^T D^T y: Phi^T into v-order, R^T, then Psi^T into key order
@@ -472,15 +477,17 @@ __device__ __forceinline__ int64_t fpos_inv(int64_t P, const Plan& p) {
 }
 
 // v-order Phi input t <- R (Psi output): DCT input q at t, x index i = pinv[q]
+// nat = 1: the source holds x in natural order (the 2-D DCT basis) instead of
+// Psi's freq layout.
 template <typename T>
 __global__ void k_rand_in(const T* __restrict__ fin, T* __restrict__ vout, const int8_t* __restrict__ signs,
-                          const int32_t* __restrict__ pinv, const Plan pl, const int* __restrict__ done) {
+                          const int32_t* __restrict__ pinv, const Plan pl, const int* __restrict__ done, int nat) {
   if (done && *done) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= pl.n) return;
   const int64_t q = vinv(t, pl.n);
   const int64_t i = pinv ? (int64_t)pinv[q] : q;
-  const T v = fin[fpos(i, pl)];
+  const T v = fin[nat ? i : fpos(i, pl)];
   vout[t] = signs[i] < 0 ? -v : v;
 }
 
@@ -488,11 +495,11 @@ __global__ void k_rand_in(const T* __restrict__ fin, T* __restrict__ vout, const
 // read at v-order position vpos(perm[i])
 template <typename T>
 __global__ void k_rand_out(const T* __restrict__ vin, T* __restrict__ fout, const int8_t* __restrict__ signs,
-                           const int32_t* __restrict__ perm, const Plan pl, const int* __restrict__ done) {
+                           const int32_t* __restrict__ perm, const Plan pl, const int* __restrict__ done, int nat) {
   if (done && *done) return;
   const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (P >= pl.n) return;
-  const int64_t i = fpos_inv(P, pl);
+  const int64_t i = nat ? P : fpos_inv(P, pl);
   const int64_t q = perm ? (int64_t)perm[i] : i;
   const T v = vin[vpos(q, pl.n)];
   fout[P] = signs[i] < 0 ? -v : v;
@@ -501,13 +508,25 @@ __global__ void k_rand_out(const T* __restrict__ vin, T* __restrict__ fout, cons
 template <typename T>
 void rand_in(Ctx<T>& c, const T* fin, T* vout, const int* done) {
   hipLaunchKernelGGL(k_rand_in<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, fin, vout, c.rsigns, c.rpinv,
-                     c.plan, done);
+                     c.plan, done, 0);
+  CS_LAUNCH_CHECK();
+}
+template <typename T>
+void rand_in_nat(Ctx<T>& c, const T* xin, T* vout, const int* done) {
+  hipLaunchKernelGGL(k_rand_in<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, xin, vout, c.rsigns, c.rpinv,
+                     c.plan, done, 1);
   CS_LAUNCH_CHECK();
 }
 template <typename T>
 void rand_out(Ctx<T>& c, const T* vin, T* fout, const int* done) {
   hipLaunchKernelGGL(k_rand_out<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, vin, fout, c.rsigns, c.rperm,
-                     c.plan, done);
+                     c.plan, done, 0);
+  CS_LAUNCH_CHECK();
+}
+template <typename T>
+void rand_out_nat(Ctx<T>& c, const T* vin, T* xout, const int* done) {
+  hipLaunchKernelGGL(k_rand_out<T>, dim3(nblk(c.plan.n, 256)), dim3(256), 0, c.stream, vin, xout, c.rsigns, c.rperm,
+                     c.plan, done, 1);
   CS_LAUNCH_CHECK();
 }
 
@@ -531,6 +550,60 @@ double psi_middle(Ctx<T>& c, CgScalars* cg, int* rec) {
   bytes += launch_row<T>(c, ROW_ADJ, c.P1, nullptr, nullptr, done, rec ? &rec[4] : nullptr);
   c.transforms += 2;
   return bytes;
+}
+
+// ---- separable 2-D DCT basis (psi = 2): the s-space image lives in natural
+// order, so the 2-D transform runs as two row passes on either side of Phi.
+
+// H-apply on the image in P3 (the support's values, zero elsewhere): x = F S F^T,
+// R, Phi^T Phi with the row mask, R^T, and F^T X F into `sout` (an N-vector,
+// natural order).  `cg` (nullable) makes every launch exit once CG is done.
+template <typename T>
+void psi2_happly(Ctx<T>& c, CgScalars* cg, T* sout) {
+  const int* done = cg ? &cg->done : nullptr;
+  ColIO<T> fwd = col_io<T>(c, COL_DENSE, nullptr), inv = col_io<T>(c, COL_DENSE, nullptr);
+  fwd.cg = cg;
+  inv.cg = cg;
+  dct2d<T>(c, false, c.P3, c.P4, c.P1, done);
+  rand_in_nat<T>(c, c.P1, c.P2, done);
+  launch_col<T>(c, (const Cx<T>*)c.P2, c.W, false, fwd);
+  launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done);
+  launch_col<T>(c, c.W, (Cx<T>*)c.P2, true, inv);
+  rand_out_nat<T>(c, c.P2, c.P1, done);
+  dct2d<T>(c, true, c.P1, c.P4, sout, done);
+  c.transforms += 4;
+}
+
+// Residual on the image in P3: r = y - A x masked (norm partials into
+// partial2) and A^T r into `cout` (natural order).
+template <typename T>
+void psi2_resid(Ctx<T>& c, T* cout) {
+  dct2d<T>(c, false, c.P3, c.P4, c.P1, nullptr);
+  rand_in_nat<T>(c, c.P1, c.P2, nullptr);
+  launch_col<T>(c, (const Cx<T>*)c.P2, c.W, false, col_io<T>(c, COL_DENSE, nullptr));
+  launch_row<T>(c, ROW_RESID, c.Yf, nullptr, c.partial2, nullptr);
+  launch_col<T>(c, c.W, (Cx<T>*)c.P2, true, col_io<T>(c, COL_DENSE, nullptr));
+  rand_out_nat<T>(c, c.P2, c.P1, nullptr);
+  dct2d<T>(c, true, c.P1, c.P4, cout, nullptr);
+  c.transforms += 4;
+}
+
+// A s for an image `img` (natural order) into freq layout (masked).
+template <typename T>
+void psi2_forward(Ctx<T>& c, const T* img, T* outf) {
+  dct2d<T>(c, false, img, c.P4, c.P1, nullptr);
+  rand_in_nat<T>(c, c.P1, c.P2, nullptr);
+  transform_fwd<T>(c, c.P2, outf);
+  c.transforms += 1;
+}
+
+// A^T u for u in freq layout (zero off the rows) into `out` (natural order).
+template <typename T>
+void psi2_adjoint(Ctx<T>& c, const T* inf, T* out) {
+  transform_adj<T>(c, inf, c.P2, false);
+  rand_out_nat<T>(c, c.P2, c.P1, nullptr);
+  dct2d<T>(c, true, c.P1, c.P4, out, nullptr);
+  c.transforms += 1;
 }
 
 // y-side of the residual with a DCT basis: W holds Psi's column stage of x.
@@ -594,8 +667,14 @@ void prepare_kernels() {
   template void perm_out<T>(Ctx<T>&, const T*, T*);                                     \
   template void rand_in<T>(Ctx<T>&, const T*, T*, const int*);                          \
   template void rand_out<T>(Ctx<T>&, const T*, T*, const int*);                         \
+  template void rand_in_nat<T>(Ctx<T>&, const T*, T*, const int*);                      \
+  template void rand_out_nat<T>(Ctx<T>&, const T*, T*, const int*);                     \
   template double psi_middle<T>(Ctx<T>&, CgScalars*, int*);                             \
   template void psi_resid_middle<T>(Ctx<T>&);                                           \
+  template void psi2_happly<T>(Ctx<T>&, CgScalars*, T*);                                \
+  template void psi2_resid<T>(Ctx<T>&, T*);                                             \
+  template void psi2_forward<T>(Ctx<T>&, const T*, T*);                                 \
+  template void psi2_adjoint<T>(Ctx<T>&, const T*, T*);                                 \
   template void prepare_kernels<T>();
 CS_INST(float)
 CS_INST(double)

@@ -51,8 +51,9 @@ def test_workspace_is_linear_in_n_and_k():
 
 def test_workspace_for_a_dct_basis():
     """cs_workspace_size_op reads n, m and psi from a host descriptor: Psi = I
-    matches cs_workspace_size, the DCT basis adds two N-vectors, other psi
-    values and batched descriptors with psi = 1 have no size."""
+    matches cs_workspace_size, the DCT basis adds two N-vectors, the 2-D DCT
+    basis four and a stage table (and needs a square N), other psi values and
+    batched descriptors with psi = 1 have no size."""
     for dt, esz in ((cs.CS_F32, 4), (cs.CS_F64, 8)):
         n, m, k = 2 ** 16, 2 ** 14, 300
         base = cs.cs_workspace_size(dt, n, m, k, cs.CS_ALGO_SP)
@@ -61,7 +62,10 @@ def test_workspace_for_a_dct_basis():
         assert cs.cs_workspace_size_op(dt, op0, k, cs.CS_ALGO_SP) == base
         extra = cs.cs_workspace_size_op(dt, op1, k, cs.CS_ALGO_SP) - base
         assert 2 * esz * n <= extra <= 2 * esz * n + 1024
-        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, m, None, None, None, 2, 0), k, cs.CS_ALGO_SP) == 0
+        extra2 = cs.cs_workspace_size_op(dt, cs.cs_op(n, m, None, None, None, 2, 0), k, cs.CS_ALGO_SP) - base
+        assert 4 * esz * n <= extra2 <= 4 * esz * n + 2 * esz * 8192 + 2048
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(2 * n, m, None, None, None, 2, 0), k, cs.CS_ALGO_SP) == 0
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, m, None, None, None, 3, 0), k, cs.CS_ALGO_SP) == 0
         items = (cs.cs_batch_item * 1)()
         items[0].op = op1
         items[0].k = 10

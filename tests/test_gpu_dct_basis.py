@@ -50,7 +50,7 @@ def test_bad_basis_is_rejected():
     d = synth.draw_problem(75, 1, 1024, 300, 5, "normal", None)
     dop = cs.Operator.from_numpy(1024, d.rows, d.signs, psi=1)
     ws = cs.workspace(cs.CS_F32, dop, 1, cs.CS_ALGO_OPERATOR)
-    dop.c.psi = 2
+    dop.c.psi = 3
     with pytest.raises(cs.CSError) as e:
         cs.cs_apply_A(to_dev(np.ones(1024), torch.float32), dop, ws=ws)
     assert e.value.status == cs.CS_E_OP
@@ -132,6 +132,118 @@ def test_adjoint_ls_with_dct_basis(dt, tol, bar):
     gs[d.supp] = 2.0 * (s_hat - t[d.supp])
     dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=1)
     announce("adjoint_ls psi", dt)
+    gy, info = cs.cs_adjoint_ls(to_dev(gs, tdt), dop, to_dev(d.supp, torch.int32), tol)
+    assert rel(gy.cpu().numpy(), g_ref) <= bar
+    assert info["flags"] == 0
+
+
+# ------------------------------------------------------------------ separable 2-D DCT basis (psi = 2)
+OP2_CASES = [
+    # n (= side^2), m, randomizer, dtype; sides 8 .. 8192 (FP32) and .. 4096 (FP64)
+    (64, 20, "signs", "f64"), (256, 77, "perm", "f32"), (1024, 301, "perm", "f32"), (4096, 1001, "perm", "f64"),
+    (2 ** 14, 2 ** 12, "signs", "f32"), (2 ** 16, 2 ** 14, "signed_perm", "f32"), (2 ** 18, 2 ** 16, "perm", "f64"),
+    (2 ** 20, 2 ** 18, "perm", "f32"), (2 ** 22, 2 ** 20, "signs", "f32"), (2 ** 24, 2 ** 21, "perm", "f32"),
+    (2 ** 24, 2 ** 21, "signs", "f64"), (2 ** 26, 2 ** 23, "perm", "f32"),
+]
+
+
+@pytest.mark.parametrize("n,m,randomizer,dt", OP2_CASES)
+def test_apply_with_2d_dct_basis(n, m, randomizer, dt):
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d = synth.draw_problem(88, 0, n, m, 5, "normal", None, randomizer=randomizer)
+    op = oracle.SRM(n, d.rows, d.signs, d.perm, psi=2)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=2)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(n)
+    u = rng.standard_normal(m)
+    bar = 1e-13 if dt == "f64" else 6e-6
+    announce("apply psi2", n, m, randomizer, dt)
+    ax = cs.cs_apply_A(to_dev(x, tdt), dop).cpu().numpy()
+    assert rel(ax, op.apply(x)) <= bar
+    atu = cs.cs_apply_At(to_dev(u, tdt), dop).cpu().numpy()
+    assert rel(atu, op.adjoint(u)) <= bar
+    aatu = cs.cs_apply_A(to_dev(atu, tdt), dop).cpu().numpy()    # A A^T = I
+    assert rel(aatu, u) <= 2 * bar
+
+
+def test_2d_basis_needs_a_square_size():
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    d = synth.draw_problem(88, 1, 2 ** 13, 2000, 5, "normal", None)
+    dop = cs.Operator.from_numpy(2 ** 13, d.rows, d.signs, psi=2)
+    assert cs.cs_workspace_size_op(cs.CS_F32, dop, 10, cs.CS_ALGO_SP) == 0
+    ws = cs.workspace(cs.CS_F32, cs.Operator.from_numpy(2 ** 13, d.rows, d.signs), 10, cs.CS_ALGO_SP)
+    with pytest.raises(cs.CSError) as e:
+        cs.cs_recover_sp(to_dev(np.ones(2000), torch.float32), dop, 10, 1e-6, ws=ws)
+    assert e.value.status == cs.CS_E_SHAPE
+
+
+@pytest.mark.parametrize("n,m,k,dt,tol,bound,randomizer", [
+    (4096, 1024, 50, "f64", 1e-12, 1e-10, "perm"), (2 ** 16, 2 ** 14, 300, "f32", 1e-6, 1e-5, "signs")])
+def test_ls_solve_with_2d_dct_basis(n, m, k, dt, tol, bound, randomizer):
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, y = problem(89, k, n, m, k, "normal", 30.0, dt, randomizer, psi=2)
+    rng = synth.rng_for(89, k, 9)
+    wrong = rng.choice(np.setdiff1d(np.arange(n), d.supp), k // 4, replace=False)
+    S = np.sort(np.concatenate([d.supp[k // 4:], wrong])).astype(np.int32)
+    ref = oracle.ls(op, S, y)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=2)
+    announce("ls_solve psi2", n, m, k, dt)
+    th, info = cs.cs_ls_solve(to_dev(y, tdt), dop, to_dev(S, torch.int32), tol)
+    th = th.cpu().numpy()
+    assert rel(th, ref) <= bound, (rel(th, ref), info)
+    th2, info2 = cs.cs_ls_solve(to_dev(y, tdt), dop, to_dev(S, torch.int32), tol, x0=to_dev(th, tdt))
+    assert rel(th2.cpu().numpy(), ref) <= bound
+    assert info2["cg_iters"] <= max(2, info["cg_iters"] // 2)
+
+
+RECOVER2_CASES = [
+    ("omp_n4096_f64", 90, 4096, 1024, 50, "normal_min0.1", None, "f64", 1e-10, "perm"),
+    ("sp_n2p14_f32", 91, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6, "signs"),
+    ("sp_n2p14_40db_f64", 92, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10, "perm"),
+    ("ompr_n2p14_f64", 93, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f64", 1e-10, "perm"),
+    ("cosamp_n2p14_f32", 94, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6, "perm"),
+    ("sp_n64_f64", 95, 64, 30, 4, "normal_min0.1", None, "f64", 1e-10, "signs"),
+]
+
+
+@pytest.mark.parametrize("case", RECOVER2_CASES, ids=[c[0] for c in RECOVER2_CASES])
+def test_recover_with_2d_dct_basis(case):
+    name, cfg, n, m, k, values, snr, dt, tol, randomizer = case
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, y = problem(cfg, 0, n, m, k, values, snr, dt, randomizer, psi=2)
+    algo = name.split("_")[0]
+    ref = getattr(oracle, algo)(op, y, k)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=2)
+    announce("recover psi2", name)
+    s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, tol)
+    s = s.cpu().numpy()
+    supp = supp.cpu().numpy()
+    print(name, info, "oracle iters", ref.iters, ref.stop, flush=True)
+    assert np.array_equal(supp, ref.support), (np.setdiff1d(supp, ref.support), np.setdiff1d(ref.support, supp))
+    assert rel(s, ref.s) <= 1e-5
+    assert info["flags"] & ~cs.CS_F_CG_MAXITER == 0
+
+
+@pytest.mark.parametrize("dt,tol,bar", [("f64", 1e-12, 1e-8), ("f32", 1e-6, 1e-3)])
+def test_adjoint_ls_with_2d_dct_basis(dt, tol, bar):
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    n, m, k = 4096, 1001, 37
+    d, op, y = problem(96, 0, n, m, k, "normal", 30.0, dt, "perm", psi=2)
+    t = d.s_dense()
+    g_ref, s_hat = oracle.adjoint_gradient(op, d.supp, y, t)
+    gs = np.random.default_rng(7).standard_normal(n)
+    gs[d.supp] = 2.0 * (s_hat - t[d.supp])
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs, d.perm, psi=2)
+    announce("adjoint_ls psi2", dt)
     gy, info = cs.cs_adjoint_ls(to_dev(gs, tdt), dop, to_dev(d.supp, torch.int32), tol)
     assert rel(gy.cpu().numpy(), g_ref) <= bar
     assert info["flags"] == 0

@@ -103,3 +103,30 @@ def test_zero_measurement_matches_oracle(case):
     assert np.array_equal(supp, ref.support)
     assert np.array_equal(supp, np.arange(k))
     assert np.count_nonzero(s.cpu().numpy()) == 0
+
+
+@pytest.mark.parametrize("psi", [0, 1])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_orthogonal_operator_is_hard_thresholding(psi, dt):
+    """M = N makes A orthogonal (A^T A = I), so the least squares on any S is
+    (A^T y)_S and OMP, SP, OMPR (eta = 1) and CoSaMP all return hard
+    thresholding of A^T y: the K largest |A^T y| with those values."""
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    n, k = 4096, 60
+    rng = synth.rng_for(87, psi, 0)
+    rows, signs = synth.draw_operator(rng, n, n)
+    op = oracle.SRM(n, rows, signs, psi=psi)
+    y = rng.standard_normal(n)
+    if dt == "f32":
+        y = y.astype(np.float32).astype(np.float64)
+    c = op.adjoint(y)
+    expect = np.sort(np.argsort(-np.abs(c), kind="stable")[:k])
+    dop = cs.Operator.from_numpy(n, rows, signs, psi=psi)
+    bar = 1e-12 if dt == "f64" else 1e-5
+    for algo, kw in (("omp", {}), ("sp", {}), ("ompr", {"ompr_eta": 1.0}), ("cosamp", {})):
+        announce("orthogonal", algo, dt, psi)
+        s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, 1e-12 if dt == "f64" else 1e-6, **kw)
+        assert np.array_equal(supp.cpu().numpy(), expect), algo
+        assert rel(s.cpu().numpy()[expect], c[expect]) <= bar, algo

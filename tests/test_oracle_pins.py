@@ -582,3 +582,57 @@ def test_p4_dct_basis_ls_routes_and_recovery():
         res = f(op, y, 25)
         assert np.array_equal(res.support, d.supp), f.__name__
         assert np.allclose(res.s[d.supp], d.vals, atol=1e-9)
+
+
+@pytest.mark.parametrize("side,randomizer", [(8, "signs"), (16, "perm")])
+def test_p2_dct2d_basis(side, randomizer):
+    """Psi = F_n (x) F_n on an n x n image (Sec. III-E with fixed DCT factors):
+    A = D F R (F_n (x) F_n) equals the product of dense cosine-formula
+    matrices (the Kronecker product written out), has orthonormal rows, and
+    its columns and adjoint agree with that product; Psi = F_N (1-D) gives a
+    different operator."""
+    n = side * side
+    d = synth.draw_problem(107, 0, n, n // 3, 5, "normal", None, randomizer=randomizer)
+    op = oracle.SRM(n, d.rows, d.signs, d.perm, psi=2)
+    Fn = oracle.dct2_matrix(n)
+    Fs = oracle.dct2_matrix(side)
+    Rm = np.zeros((n, n))
+    idx = d.perm if d.perm is not None else np.arange(n)
+    Rm[idx, np.arange(n)] = d.signs
+    A = Fn[d.rows] @ Rm @ np.kron(Fs, Fs)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(n)
+    u = rng.standard_normal(d.m)
+    assert np.allclose(op.apply(x), A @ x, atol=1e-12)
+    assert np.allclose(op.adjoint(u), A.T @ u, atol=1e-12)
+    assert np.allclose(A @ A.T, np.eye(d.m), atol=1e-12)
+    S = np.sort(rng.choice(n, 9, replace=False))
+    assert np.allclose(op.columns(S), A[:, S], atol=1e-12)
+    assert not np.allclose(A, Fn[d.rows] @ Rm @ Fn, atol=1e-3)                   # the 1-D basis differs
+    assert not np.allclose(A, Fn[d.rows] @ Rm @ np.kron(Fs, Fs).T, atol=1e-3)    # so does its transpose
+
+
+def test_p6_dct2d_orthogonal_and_recovery():
+    """Psi = F_n (x) F_n: with M = N every algorithm returns hard thresholding
+    of A^T y; with M = N/4 the dense and CG least-squares routes agree, and a
+    noiseless image sparse in the 2-D DCT basis is recovered exactly."""
+    rng = np.random.default_rng(15)
+    n, k = 256, 12
+    rows, signs = synth.draw_operator(rng, n, n)
+    op = oracle.SRM(n, rows, signs, psi=2)
+    y = rng.standard_normal(n)
+    c = op.adjoint(y)
+    expect = np.sort(np.argsort(-np.abs(c), kind="stable")[:k])
+    for f in (oracle.omp, oracle.sp, oracle.cosamp):
+        r = f(op, y, k)
+        assert np.array_equal(r.support, expect), f.__name__
+    d = synth.draw_problem(108, 0, 4096, 1024, 25, "normal_min0.1", None, randomizer="perm")
+    o2 = oracle.SRM(d.n, d.rows, d.signs, d.perm, psi=2)
+    y2 = o2.apply_sparse(d.supp, d.vals)
+    S = np.sort(rng.choice(d.n, 40, replace=False))
+    v1 = oracle.ls_dense(o2, S, y2)
+    v2, _ = oracle.ls_cg(o2, S, y2, tol=1e-13)
+    assert np.allclose(v1, v2, atol=1e-10)
+    for f in (oracle.omp, oracle.sp, oracle.ompr, oracle.cosamp):
+        res = f(o2, y2, 25)
+        assert np.array_equal(res.support, d.supp), f.__name__
