@@ -11,8 +11,9 @@
  *      c_0 = sqrt(1/N), c_k = sqrt(2/N),
  *   R  the randomizer: a sign flip, optionally with a permutation.
  * The measured signal is x = Psi s (Eq. (2)) with Psi the identity (s is
- * sparse directly) or, as in the experiments of Sec. IV-A, the orthonormal
- * DCT-II (the same F), so that A = D F R F; see cs_op.psi.
+ * sparse directly), the orthonormal DCT-II (the same F) as in the
+ * experiments of Sec. IV-A, so that A = D F R F, or the separable 2-D DCT of
+ * Sec. III-E on an n x n image; see cs_op.psi.
  *
  * Every least-squares step is the CG-based weighted least squares of
  * Sec. III-B/C (Eqs. (10)-(11), the CG function of Algorithm 1): CG on
@@ -73,7 +74,7 @@ typedef enum {
   CS_E_INVALID = -1,    /* null pointer, bad dtype/algo, K < 1, tol <= 0 or not finite  */
   CS_E_SHAPE = -2,      /* N not a power of two in [16, 2^26], M > N, K > M, SP 2K > M   */
   CS_E_OP = -3,         /* rows not strictly ascending in [0, N), a sign not +-1, perm
-                           not a permutation, or psi not 0 or 1                        */
+                           not a permutation, or psi not 0, 1 or 2                     */
   CS_E_WORKSPACE = -4,  /* workspace too small or not 256-byte aligned                   */
   CS_E_HIP = -5         /* HIP runtime error                                             */
 } cs_status;
@@ -91,17 +92,22 @@ enum {
  * index perm[j] with sign signs[j].  perm == NULL is the identity
  * (R = diag(signs), the headline workloads here); the paper's R is a uniform
  * random permutation (perm with all signs +1).  Psi is the sparsifying basis
- * of Eq. (2): psi = 0 the identity, psi = 1 the orthonormal DCT-II, as in the
- * experiments of Sec. IV-A (A s = D F R F s).  With psi = 1 every H-apply
- * runs two more transforms and two reorders through R; the workspace must be
- * sized by cs_workspace_size_op(), and the batched entry point rejects it. */
+ * of Eq. (2): psi = 0 the identity; psi = 1 the orthonormal DCT-II, as in the
+ * experiments of Sec. IV-A (A s = D F R F s); psi = 2 the separable 2-D DCT
+ * of Sec. III-E with both factors the orthonormal DCT-II F_n of the side
+ * n = sqrt(N) (x = vec(F_n S F_n^T), s = vec(S) row-major; N = n^2 with n a
+ * power of two in [8, 8192], FP64 [8, 4096], else CS_E_SHAPE).  With psi != 0
+ * every H-apply runs two more transforms and two reorders through R; the
+ * workspace must be sized by cs_workspace_size_op(), and the batched entry
+ * point rejects it. */
 typedef struct {
   int64_t n;              /* signal length N                                        */
   int64_t m;              /* number of sampled rows M                               */
   const int32_t* rows;    /* device [m]: sampled DCT rows, strictly ascending      */
   const int8_t* signs;    /* device [n]: sign flips, each +1 or -1                  */
   const int32_t* perm;    /* device [n] permutation of [0, N), or NULL              */
-  int32_t psi;            /* sparsifying basis: 0 identity, 1 orthonormal DCT-II    */
+  int32_t psi;            /* sparsifying basis: 0 identity, 1 orthonormal DCT-II,
+                             2 separable 2-D DCT-II on an n x n image             */
   int32_t pad;            /* set to 0                                               */
 } cs_op;
 
@@ -136,8 +142,8 @@ typedef struct {
 size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_algo algo);
 
 /* The same for a given operator (host descriptor; only n, m and psi are
- * read): a DCT sparsifying basis (psi = 1) needs two more N-vectors.
- * 0 if invalid. */
+ * read): a DCT sparsifying basis needs two more N-vectors (psi = 1) or four
+ * and a twiddle table (psi = 2).  0 if invalid. */
 size_t cs_workspace_size_op(cs_dtype dtype, const cs_op* op, int32_t k, cs_algo algo);
 
 /*

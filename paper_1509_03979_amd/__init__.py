@@ -160,7 +160,7 @@ def cs_workspace_size(dtype: int, n: int, m: int, k: int, algo: int) -> int:
 
 def cs_workspace_size_op(dtype: int, op, k: int, algo: int) -> int:
     """Workspace bytes for an operator descriptor (`Operator` or `cs_op`); a
-    DCT sparsifying basis (psi = 1) needs two more N-vectors."""
+    DCT sparsifying basis needs two (psi = 1) or four (psi = 2) more N-vectors."""
     c = op.c if hasattr(op, "c") else op
     return int(lib.cs_workspace_size_op(dtype, ctypes.byref(c), k, algo))
 
@@ -200,7 +200,8 @@ class Operator:
     ascending, signs int8 [N], optionally perm int32 [N] (the randomizer's
     permutation; None: R is the sign flip alone), and the sparsifying basis
     psi (0: identity, s sparse directly; 1: the orthonormal DCT-II, as in the
-    paper's experiments)."""
+    paper's experiments; 2: the separable 2-D DCT on an n x n image, N = n^2,
+    s the row-major image of coefficients)."""
 
     def __init__(self, n: int, rows, signs, perm=None, psi: int = 0):
         torch = _torch()
