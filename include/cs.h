@@ -106,9 +106,10 @@ typedef struct {
   const int32_t* rows;    /* device [m]: sampled DCT rows, strictly ascending      */
   const int8_t* signs;    /* device [n]: sign flips, each +1 or -1                  */
   const int32_t* perm;    /* device [n] permutation of [0, N), or NULL              */
-  int32_t psi;            /* sparsifying basis: 0 identity, 1 orthonormal DCT-II,
+  int32_t psi;            /* sparsifying basis: 0 identity, 1 the transform F,
                              2 separable 2-D DCT-II on an n x n image             */
-  int32_t pad;            /* set to 0                                               */
+  int32_t xform;          /* F: 0 orthonormal DCT-II; 1 orthonormal real Fourier
+                             basis (partial Fourier sensing, see above)           */
 } cs_op;
 
 /* Optional knobs; pass NULL for the defaults shown. */

@@ -33,7 +33,7 @@ paper prints no values: those are "parity unpinned" beyond the invariants
 (residual orthogonality on the returned support, exact recovery of
 noiseless well-separated inputs, the M = N special case).
 """
-from .operator import SRM, dct2_matrix  # noqa: F401
+from .operator import SRM, dct2_matrix, rdft_matrix  # noqa: F401
 from .gram import gram_generator, gram_matrix  # noqa: F401
 from .lsq import ls, ls_dense, ls_gram, ls_cg  # noqa: F401
 from .greedy import omp, sp, ompr, cosamp, topk_order, argmax_excluding  # noqa: F401

@@ -35,8 +35,8 @@ def gram_generator(op: SRM) -> np.ndarray:
 
 def gram_matrix(op: SRM, supp, g: np.ndarray | None = None) -> np.ndarray:
     """A_S^T A_S (|S| x |S|) in closed form."""
-    if op.psi:
-        raise ValueError("the closed-form Gram holds for Psi = I only")
+    if op.psi or op.xform:
+        raise ValueError("the closed-form Gram holds for the DCT-II with Psi = I only")
     if g is None:
         g = gram_generator(op)
     s = np.asarray(supp, dtype=np.int64)

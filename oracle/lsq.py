@@ -97,7 +97,7 @@ def ls(op: SRM, supp, y, g: np.ndarray | None = None, aty: np.ndarray | None = N
     if route == "auto":
         if op.m * k <= DENSE_LIMIT:
             route = "dense"
-        elif k <= GRAM_LIMIT and not op.psi:   # the closed-form Gram needs Psi = I
+        elif k <= GRAM_LIMIT and not op.psi and not op.xform:   # the closed-form Gram: DCT-II, Psi = I
             route = "gram"
         else:
             route = "cg"
@@ -134,7 +134,7 @@ class LSContext:
         if route == "auto":
             if self.op.m * k <= DENSE_LIMIT:
                 route = "dense"
-            elif k <= GRAM_LIMIT and not self.op.psi:   # the closed-form Gram needs Psi = I
+            elif k <= GRAM_LIMIT and not self.op.psi and not self.op.xform:   # closed-form Gram: DCT-II, Psi = I
                 route = "gram"
             else:
                 route = "cg"

@@ -42,6 +42,54 @@ def _cos_table(k: np.ndarray, j: np.ndarray, n: int) -> np.ndarray:
     return np.cos(np.pi * a.astype(np.float64) / (2.0 * n))
 
 
+def _rdft_table(q: np.ndarray, t: np.ndarray, n: int) -> np.ndarray:
+    """Orthonormal real Fourier basis (partial Fourier sensing of a real
+    signal): row q at input t is 1/sqrt(n) (q = 0), (-1)^t / sqrt(n) (q = n/2),
+    sqrt(2/n) cos(2 pi q t / n) (0 < q < n/2) and sqrt(2/n) sin(2 pi (n-q) t / n)
+    (q > n/2); the angle is reduced exactly in integers."""
+    q = q.astype(np.int64)
+    t = t.astype(np.int64)
+    half = n // 2
+    kq = np.where(q > half, n - q, q)
+    a = (kq * t) % n
+    ang = 2.0 * np.pi * a.astype(np.float64) / n
+    val = np.where(q > half, np.sin(ang), np.cos(ang)) * np.sqrt(2.0 / n)
+    return np.where((q == 0) | (q == half), np.cos(ang) / np.sqrt(n), val)
+
+
+def rdft_matrix(n: int) -> np.ndarray:
+    """Dense orthonormal real Fourier basis (n x n) from the formula."""
+    return _rdft_table(np.arange(n)[:, None], np.arange(n)[None, :], n)
+
+
+def _rdft(x: np.ndarray, axis: int = 0) -> np.ndarray:
+    """The real Fourier basis applied along `axis` through NumPy's real FFT."""
+    x = np.moveaxis(np.asarray(x, dtype=np.float64), axis, 0)
+    n = x.shape[0]
+    half = n // 2
+    X = np.fft.rfft(x, axis=0)
+    out = np.empty_like(x)
+    out[0] = X[0].real / np.sqrt(n)
+    out[half] = X[half].real / np.sqrt(n)
+    k = np.arange(1, half)
+    out[k] = np.sqrt(2.0 / n) * X[k].real
+    out[n - k] = -np.sqrt(2.0 / n) * X[k].imag
+    return np.moveaxis(out, 0, axis)
+
+
+def _irdft(u: np.ndarray) -> np.ndarray:
+    """Inverse (= transpose) of the real Fourier basis through NumPy's inverse real FFT."""
+    u = np.asarray(u, dtype=np.float64)
+    n = u.size
+    half = n // 2
+    X = np.zeros(half + 1, dtype=complex)
+    X[0] = u[0] * np.sqrt(n)
+    X[half] = u[half] * np.sqrt(n)
+    k = np.arange(1, half)
+    X[k] = np.sqrt(n / 2.0) * (u[k] - 1j * u[n - k])
+    return np.fft.irfft(X, n=n)
+
+
 def dct2_matrix(n: int) -> np.ndarray:
     """Dense orthonormal DCT-II matrix F (n x n) from the cosine formula."""
     k = np.arange(n)[:, None]
@@ -59,7 +107,7 @@ class SRM:
     the DCT-II (psi = 1, A = D F R F) or the 2-D DCT (psi = 2,
     A = D F R (F_n (x) F_n))."""
 
-    def __init__(self, n: int, rows, signs, perm=None, psi: int = 0):
+    def __init__(self, n: int, rows, signs, perm=None, psi: int = 0, xform: int = 0):
         rows = np.asarray(rows, dtype=np.int64)
         signs = np.asarray(signs)
         if rows.ndim != 1 or signs.shape != (n,):
@@ -74,6 +122,9 @@ class SRM:
         self.signs = signs.astype(np.float64)
         if psi not in (0, 1, 2):
             raise ValueError("psi must be 0, 1 or 2")
+        if xform not in (0, 1):
+            raise ValueError("xform must be 0 (DCT-II) or 1 (real Fourier)")
+        self.xform = int(xform)
         self.psi = int(psi)
         self.side = 0
         if psi == 2:
@@ -106,15 +157,26 @@ class SRM:
         j = np.asarray(j, dtype=np.int64)
         return j if self.perm is None else self.perm[j]
 
+    def _F(self, v: np.ndarray) -> np.ndarray:
+        """The orthonormal transform F: DCT-II, or the real Fourier basis."""
+        if self.xform:
+            return _rdft(v)
+        return sfft.dct(v, type=2, norm="ortho", workers=WORKERS)
+
+    def _Ft(self, w: np.ndarray) -> np.ndarray:
+        if self.xform:
+            return _irdft(w)
+        return sfft.idct(w, type=2, norm="ortho", workers=WORKERS)
+
     # ---------------------------------------------------------- FFT route
     def apply(self, x: np.ndarray) -> np.ndarray:
         """A x for a dense N-vector x (with psi = 1, F x enters R first)."""
         x = np.asarray(x, dtype=np.float64)
         if self.psi == 1:
-            x = sfft.dct(x, type=2, norm="ortho", workers=WORKERS)
+            x = self._F(x)
         elif self.psi == 2:
             x = sfft.dctn(x.reshape(self.side, self.side), type=2, norm="ortho", workers=WORKERS).reshape(-1)
-        return sfft.dct(self._place(x), type=2, norm="ortho", workers=WORKERS)[self.rows]
+        return self._F(self._place(x))[self.rows]
 
     def apply_sparse(self, supp, vals) -> np.ndarray:
         """A x where x is zero off ``supp`` and equals ``vals`` on it."""
@@ -126,9 +188,9 @@ class SRM:
         """A^T u for an M-vector u: zero-fill, orthonormal DCT-III, sign flip."""
         full = np.zeros(self.n)
         full[self.rows] = np.asarray(u, dtype=np.float64)
-        w = self._unplace(sfft.idct(full, type=2, norm="ortho", workers=WORKERS))
+        w = self._unplace(self._Ft(full))
         if self.psi == 1:
-            w = sfft.idct(w, type=2, norm="ortho", workers=WORKERS)
+            w = self._Ft(w)
         elif self.psi == 2:
             w = sfft.idctn(w.reshape(self.side, self.side), type=2, norm="ortho", workers=WORKERS).reshape(-1)
         return w
@@ -142,11 +204,13 @@ class SRM:
         through the same formula for N <= 4096 (else SciPy's DCT)."""
         j = np.asarray(supp, dtype=np.int64)[None, :]
         k = self.rows[:, None]
+        table = (lambda q, t: _rdft_table(q, t, self.n)) if self.xform else \
+            (lambda q, t: _dct_scale(q, self.n) * _cos_table(q, t, self.n))
         if not self.psi:
-            return _dct_scale(k, self.n) * _cos_table(k, self.dct_index(j), self.n) * self.signs[j]
+            return table(k, self.dct_index(j)) * self.signs[j]
         if self.psi == 1:
             i = np.arange(self.n)[:, None]
-            fcols = _dct_scale(i, self.n) * _cos_table(i, j, self.n)    # F e_j, N x |S|
+            fcols = table(i, j)                                         # F e_j, N x |S|
         else:                                                           # vec(F_n E_ab F_n^T) = F_n[:, a] (x) F_n[:, b]
             fs = dct2_matrix(self.side)
             a, b = j[0] // self.side, j[0] % self.side
@@ -155,7 +219,9 @@ class SRM:
         idx = self.dct_index(np.arange(self.n))
         placed[idx, :] = self.signs[:, None] * fcols                    # R applied to each column
         if self.n <= 4096:
-            return (_dct_scale(k, self.n) * _cos_table(k, np.arange(self.n)[None, :], self.n)) @ placed
+            return table(k, np.arange(self.n)[None, :]) @ placed
+        if self.xform:
+            return _rdft(placed, axis=0)[self.rows, :]
         return sfft.dct(placed, type=2, norm="ortho", axis=0, workers=WORKERS)[self.rows, :]
 
     def dense(self) -> np.ndarray:

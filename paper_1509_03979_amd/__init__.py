@@ -34,7 +34,7 @@ EXPORTS = ("cs_workspace_size", "cs_workspace_size_op", "cs_recover_omp", "cs_re
 class cs_op(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("rows", ctypes.c_void_p),
                 ("signs", ctypes.c_void_p), ("perm", ctypes.c_void_p), ("psi", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("xform", ctypes.c_int32)]
 
 
 class cs_params(ctypes.Structure):
@@ -201,9 +201,12 @@ class Operator:
     permutation; None: R is the sign flip alone), and the sparsifying basis
     psi (0: identity, s sparse directly; 1: the orthonormal DCT-II, as in the
     paper's experiments; 2: the separable 2-D DCT on an n x n image, N = n^2,
-    s the row-major image of coefficients)."""
+    s the row-major image of coefficients), and the transform F (xform 0: the
+    orthonormal DCT-II; 1: the orthonormal real Fourier basis, partial
+    Fourier sensing, where rows k and N-k hold the real and imaginary parts
+    of Fourier coefficient k)."""
 
-    def __init__(self, n: int, rows, signs, perm=None, psi: int = 0):
+    def __init__(self, n: int, rows, signs, perm=None, psi: int = 0, xform: int = 0):
         torch = _torch()
         if rows.dtype != torch.int32 or signs.dtype != torch.int8:
             raise TypeError("rows must be int32 and signs int8")
@@ -217,16 +220,17 @@ class Operator:
         self.signs = signs.contiguous()
         self.perm = perm.contiguous() if perm is not None else None
         self.psi = int(psi)
+        self.xform = int(xform)
         self.c = cs_op(self.n, self.m, self.rows.data_ptr(), self.signs.data_ptr(),
-                       self.perm.data_ptr() if self.perm is not None else None, self.psi, 0)
+                       self.perm.data_ptr() if self.perm is not None else None, self.psi, self.xform)
 
     @classmethod
-    def from_numpy(cls, n, rows, signs, perm=None, device="cuda", psi: int = 0):
+    def from_numpy(cls, n, rows, signs, perm=None, device="cuda", psi: int = 0, xform: int = 0):
         torch = _torch()
         return cls(n, torch.as_tensor(rows, dtype=torch.int32, device=device),
                    torch.as_tensor(signs, dtype=torch.int8, device=device),
                    torch.as_tensor(perm, dtype=torch.int32, device=device) if perm is not None else None,
-                   psi=psi)
+                   psi=psi, xform=xform)
 
 
 def _params(cg_max_iter=0, max_outer=0, warm_start=1, ompr_eta=0.0, cg_block=0, tol_abs=False, ompr_l=1):

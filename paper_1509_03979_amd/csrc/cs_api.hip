@@ -111,6 +111,7 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   const cs_dtype dt = sizeof(T) == 4 ? CS_F32 : CS_F64;
   if (!choose_plan(dt, op->n, op->m, p, force)) throw Error(CS_E_SHAPE, "unsupported N or shape");
   if (op->psi < 0 || op->psi > 2) throw Error(CS_E_OP, "operator psi must be 0, 1 or 2");
+  if (op->xform != 0 && op->xform != 1) throw Error(CS_E_OP, "operator xform must be 0 or 1");
   const int psi = op->psi;
   const int dlog = psi == 2 ? dct2d_side_log(dt, op->n) : 0;
   if (dlog < 0) throw Error(CS_E_SHAPE, "the 2-D DCT basis needs N = n^2 with n a power of two in [8, 8192] (FP64: 4096)");
@@ -125,6 +126,7 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   p.perm = psi ? nullptr : op->perm;
   p.pinv = (!psi && op->perm) ? c.pinv : nullptr;
   p.keynat = psi == 2 ? 1 : 0;
+  p.fourier = op->xform;
   c.plan = p;
   c.stream = s;
   c.psi = psi;
@@ -149,6 +151,7 @@ static void check_shape(cs_dtype dt, const cs_op* op, int32_t k, cs_algo algo) {
   if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) throw Error(CS_E_SHAPE, "N must be a power of two in [16, 2^26]");
   if (m < 1 || m > n) throw Error(CS_E_SHAPE, "M must satisfy 1 <= M <= N");
   if (op->psi < 0 || op->psi > 2) throw Error(CS_E_OP, "operator psi must be 0, 1 or 2");
+  if (op->xform != 0 && op->xform != 1) throw Error(CS_E_OP, "operator xform must be 0 or 1");
   if (op->psi == 2 && dct2d_side_log(dt, n) < 0)
     throw Error(CS_E_SHAPE, "the 2-D DCT basis needs N = n^2 with n a power of two in [8, 8192] (FP64: 4096)");
   if (algo == CS_ALGO_OPERATOR) return;

@@ -92,6 +92,7 @@ struct Plan {
   const int32_t* perm;    // randomizer permutation: entry j enters the DCT at perm[j] (null: identity)
   const int32_t* pinv;    // its inverse (null with perm)
   int keynat;             // 1: candidates are keyed by their natural index (2-D DCT basis)
+  int fourier;            // 1: F is the orthonormal real Fourier basis instead of the DCT-II
 };
 
 constexpr int kTwStage = 8192;   // entries reserved for one stage-twiddle table (size 2^13 needs 8176)
@@ -104,6 +105,14 @@ __host__ __device__ __forceinline__ int64_t vpos(int64_t j, int64_t n) {
 }
 __host__ __device__ __forceinline__ int64_t vinv(int64_t p, int64_t n) {
   return (p < (n >> 1)) ? (2 * p) : (2 * (n - 1 - p) + 1);
+}
+// Position of transform input q in the packed N-vector: v-order for the DCT
+// (Makhoul's reordering), natural for the real Fourier basis.
+__host__ __device__ __forceinline__ int64_t xpos(int64_t q, const Plan& pl) {
+  return pl.fourier ? q : vpos(q, pl.n);
+}
+__host__ __device__ __forceinline__ int64_t xinv(int64_t p, const Plan& pl) {
+  return pl.fourier ? p : vinv(p, pl.n);
 }
 // freq-layout float position of DCT output index q.
 __host__ __device__ __forceinline__ int64_t fpos(int64_t q, const Plan& p) {
@@ -139,13 +148,13 @@ __host__ __device__ __forceinline__ int64_t pos_of_key(int64_t k, const Plan& pl
 // permutation, device tables) <-> key.
 __device__ __forceinline__ int64_t nat_of_key(int64_t k, const Plan& pl) {
   if (pl.keynat) return k;
-  const int64_t q = vinv(pos_of_key(k, pl), pl.n);
+  const int64_t q = xinv(pos_of_key(k, pl), pl);
   return pl.pinv ? (int64_t)pl.pinv[q] : q;
 }
 __device__ __forceinline__ int64_t key_of_nat(int64_t j, const Plan& pl) {
   if (pl.keynat) return j;
   const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
-  return key_of_pos(vpos(q, pl.n), pl);
+  return key_of_pos(xpos(q, pl), pl);
 }
 
 // W_{4N}^idx = exp(-2 pi i idx / (4N)), idx in [0, 4N), from the two-level table.

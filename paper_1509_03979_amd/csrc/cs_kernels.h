@@ -366,6 +366,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         wk = tw4n<T>(p, (uint32_t)it.k);
         WN = tw4n<T>(p, (uint32_t)(4 * it.k));
       }
+      if (p.fourier) wk = cx((T)1, (T)0);   // the real Fourier basis: no Makhoul rotation
     }
     if (mode != ROW_ADJ) {
       const Cx<T> Zk = lds[sa];
@@ -381,7 +382,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         const Cx<T> WO = cmul(WN, O);
         const Cx<T> Vk = E + WO;
         const Cx<T> Vm = conj(E - WO);
-        const Cx<T> wm = cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));  // e^{-i pi/4} conj(wk)
+        const Cx<T> wm = p.fourier ? cx((T)1, (T)0) : cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));  // e^{-i pi/4} conj(wk)
         const Cx<T> a = cmul(wk, Vk), b = cmul(wm, Vm);
         xa0 = c * a.re; xa1 = -c * a.im;
         xb0 = c * b.re; xb1 = -c * b.im;
@@ -420,7 +421,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
     if (it.zero) {
       lds[sa] = cx((xa0 + xa1) * rsn, (xa0 - xa1) * rsn);
     } else {
-      const Cx<T> wm = cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));
+      const Cx<T> wm = p.fourier ? cx((T)1, (T)0) : cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));
       const Cx<T> Vk = scale(cmulc(cx(xa0, -xa1), wk), c);    // conj(wk) (Xk - i X_{N-k}) c
       const Cx<T> Vm = scale(cmulc(cx(xb0, -xb1), wm), c);
       const Cx<T> E = scale(Vk + conj(Vm), (T)0.5);

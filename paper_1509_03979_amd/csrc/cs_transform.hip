@@ -440,7 +440,7 @@ __global__ void k_perm_in(const T* __restrict__ x, T* __restrict__ dense, const 
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= pl.n) return;
   const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
-  dense[vpos(q, pl.n)] = (signs && signs[j] < 0) ? -x[j] : x[j];
+  dense[xpos(q, pl)] = (signs && signs[j] < 0) ? -x[j] : x[j];
 }
 template <typename T>
 __global__ void k_perm_out(const T* __restrict__ dense, T* __restrict__ x, const int8_t* __restrict__ signs,
@@ -448,7 +448,7 @@ __global__ void k_perm_out(const T* __restrict__ dense, T* __restrict__ x, const
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= pl.n) return;
   const int64_t q = pl.perm ? (int64_t)pl.perm[j] : j;
-  const T v = dense[vpos(q, pl.n)];
+  const T v = dense[xpos(q, pl)];
   x[j] = (signs && signs[j] < 0) ? -v : v;
 }
 template <typename T>
@@ -485,7 +485,7 @@ __global__ void k_rand_in(const T* __restrict__ fin, T* __restrict__ vout, const
   if (done && *done) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= pl.n) return;
-  const int64_t q = vinv(t, pl.n);
+  const int64_t q = xinv(t, pl);
   const int64_t i = pinv ? (int64_t)pinv[q] : q;
   const T v = fin[nat ? i : fpos(i, pl)];
   vout[t] = signs[i] < 0 ? -v : v;
@@ -501,7 +501,7 @@ __global__ void k_rand_out(const T* __restrict__ vin, T* __restrict__ fout, cons
   if (P >= pl.n) return;
   const int64_t i = nat ? P : fpos_inv(P, pl);
   const int64_t q = perm ? (int64_t)perm[i] : i;
-  const T v = vin[vpos(q, pl.n)];
+  const T v = vin[xpos(q, pl)];
   fout[P] = signs[i] < 0 ? -v : v;
 }
 

@@ -10,8 +10,8 @@ import oracle
 import synth
 
 
-def build(d: synth.Draw, dtype: str = "f64", psi: int = 0):
-    op = oracle.SRM(d.n, d.rows, d.signs, d.perm, psi)
+def build(d: synth.Draw, dtype: str = "f64", psi: int = 0, xform: int = 0):
+    op = oracle.SRM(d.n, d.rows, d.signs, d.perm, psi, xform)
     y0 = op.apply_sparse(d.supp, d.vals)
     y = y0 + d.noise_scale(np.linalg.norm(y0)) * d.noise if d.noise is not None else y0
     if dtype == "f32":
@@ -19,8 +19,9 @@ def build(d: synth.Draw, dtype: str = "f64", psi: int = 0):
     return op, y
 
 
-def problem(cfg, sig, n, m, k, values="normal", snr_db=None, dtype="f64", randomizer="signs", psi=0):
-    """psi = 1: s is sparse in the DCT-II basis (A = D F R F)."""
+def problem(cfg, sig, n, m, k, values="normal", snr_db=None, dtype="f64", randomizer="signs", psi=0, xform=0):
+    """psi = 1: s is sparse in the basis F (A = D F R F), psi = 2: in the 2-D
+    DCT basis; xform = 1: F is the real Fourier basis (partial Fourier)."""
     d = synth.draw_problem(cfg, sig, n, m, k, values, snr_db, randomizer=randomizer)
-    op, y = build(d, dtype, psi)
+    op, y = build(d, dtype, psi, xform)
     return d, op, y

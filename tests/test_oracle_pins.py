@@ -636,3 +636,60 @@ def test_p6_dct2d_orthogonal_and_recovery():
     for f in (oracle.omp, oracle.sp, oracle.ompr, oracle.cosamp):
         res = f(o2, y2, 25)
         assert np.array_equal(res.support, d.supp), f.__name__
+
+
+# ------------------------------------------------------------------ partial Fourier sensing
+@pytest.mark.parametrize("psi,randomizer", [(0, "signs"), (0, "perm"), (1, "perm")])
+def test_p2_real_fourier_basis(psi, randomizer):
+    """F = the orthonormal real Fourier basis: the FFT route equals the dense
+    cosine/sine formula (D Rf R, and D Rf R Rf with Psi = F), the rows are
+    orthonormal, and sampling rows k and N-k measures the complex Fourier
+    coefficient of R x: y_k - i y_{N-k} = sqrt(2/N) FFT(R x)_k (D(FFT(x)) of
+    Sec. II), checked against NumPy's complex FFT."""
+    n = 256
+    d = synth.draw_problem(109, 0, n, 90, 5, "normal", None, randomizer=randomizer)
+    op = oracle.SRM(n, d.rows, d.signs, d.perm, psi=psi, xform=1)
+    Rf = oracle.rdft_matrix(n)
+    Rm = np.zeros((n, n))
+    idx = d.perm if d.perm is not None else np.arange(n)
+    Rm[idx, np.arange(n)] = d.signs
+    A = Rf[d.rows] @ Rm @ (Rf if psi else np.eye(n))
+    rng = np.random.default_rng(10)
+    x = rng.standard_normal(n)
+    u = rng.standard_normal(d.m)
+    assert np.allclose(op.apply(x), A @ x, atol=1e-12)
+    assert np.allclose(op.adjoint(u), A.T @ u, atol=1e-12)
+    assert np.allclose(A @ A.T, np.eye(d.m), atol=1e-12)
+    S = np.sort(rng.choice(n, 9, replace=False))
+    assert np.allclose(op.columns(S), A[:, S], atol=1e-12)
+    with pytest.raises(ValueError):
+        oracle.gram_matrix(op, S)
+    if psi == 0:
+        full = oracle.SRM(n, np.arange(n), d.signs, d.perm, xform=1)
+        yf = full.apply(x)
+        X = np.fft.fft(Rm @ x)
+        k = np.arange(1, n // 2)
+        assert np.allclose(yf[k] - 1j * yf[n - k], np.sqrt(2.0 / n) * X[k], atol=1e-12)
+        assert np.isclose(yf[0], X[0].real / np.sqrt(n)) and np.isclose(yf[n // 2], X[n // 2].real / np.sqrt(n))
+
+
+def test_p6_real_fourier_orthogonal_and_recovery():
+    """Real Fourier basis: M = N reduces every algorithm to hard thresholding;
+    with M = N/4 a noiseless sparse signal is recovered exactly and the dense
+    and CG least-squares routes agree."""
+    rng = np.random.default_rng(16)
+    n, k = 512, 20
+    rows, signs = synth.draw_operator(rng, n, n)
+    op = oracle.SRM(n, rows, signs, xform=1)
+    y = rng.standard_normal(n)
+    c = op.adjoint(y)
+    expect = np.sort(np.argsort(-np.abs(c), kind="stable")[:k])
+    for f in (oracle.omp, oracle.sp, oracle.cosamp):
+        assert np.array_equal(f(op, y, k).support, expect), f.__name__
+    d = synth.draw_problem(110, 0, 4096, 1024, 25, "normal_min0.1", None, randomizer="perm")
+    o2 = oracle.SRM(d.n, d.rows, d.signs, d.perm, xform=1)
+    y2 = o2.apply_sparse(d.supp, d.vals)
+    S = np.sort(rng.choice(d.n, 40, replace=False))
+    assert np.allclose(oracle.ls_dense(o2, S, y2), oracle.ls_cg(o2, S, y2, tol=1e-13)[0], atol=1e-10)
+    for f in (oracle.omp, oracle.sp, oracle.ompr, oracle.cosamp):
+        assert np.array_equal(f(o2, y2, 25).support, d.supp), f.__name__
