@@ -8,7 +8,11 @@
  * Eq. (7), A = D F R with
  *   D  keeping the M sampled rows `rows` of an N-vector,
  *   F  the orthonormal N-point DCT-II, (F x)_k = c_k sum_n x_n cos(pi(2n+1)k/(2N)),
- *      c_0 = sqrt(1/N), c_k = sqrt(2/N),
+ *      c_0 = sqrt(1/N), c_k = sqrt(2/N); or (cs_op.xform = 1, partial Fourier
+ *      sensing of a real signal, Sec. II) the orthonormal real Fourier basis:
+ *      row k < N/2 sqrt(2/N) Re X_k, row N-k -sqrt(2/N) Im X_k, rows 0 and N/2
+ *      X_0 / sqrt(N) and X_{N/2} / sqrt(N), with X the N-point DFT, so that
+ *      sampling rows k and N-k measures the complex coefficient X_k,
  *   R  the randomizer: a sign flip, optionally with a permutation.
  * The measured signal is x = Psi s (Eq. (2)) with Psi the identity (s is
  * sparse directly), the orthonormal DCT-II (the same F) as in the
