@@ -133,9 +133,6 @@ __global__ __launch_bounds__((dct2d_nt<T, LOGC>())) void k_dct_rows(const T* __r
 }
 
 // ------------------------------------------------------------------ host
-template <typename T>
-using DctFn = void (*)(const T*, T*, const Plan, const Cx<T>*, const int*);
-
 template <typename T, int LOGC>
 static void dct_launch(bool inv, const T* in, T* out, const Plan& p, const Cx<T>* tw, const int* done,
                        hipStream_t s) {

@@ -24,6 +24,7 @@
 #include "cs_device.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 namespace csr {
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(kSplitThreads) void k_sel_split(const T* __restrict
 // admissible key), and no segment overflowed; otherwise from every key.
 // Every thread of the workgroup calls it; thread 0 stores the result.
 __device__ __forceinline__ void sel_decide(const SelState* sel, const int32_t* __restrict__ rcnt, int nseg, int cap,
-                                           int keybits, SelHead* out) {
+                                           int keybits, bool force_dense, SelHead* out) {
   double mid = 0.0, hi = 0.0, over = 0.0;
   for (int i = threadIdx.x; i < nseg; i += blockDim.x) {
     const int32_t m = rcnt[2 * i], h = rcnt[2 * i + 1];
@@ -343,7 +344,7 @@ __device__ __forceinline__ void sel_decide(const SelState* sel, const int32_t* _
   const int64_t K = sel->k, nh = (int64_t)hi, nm = (int64_t)mid;
   hd.tie = 0;
   hd.pending = 0;
-  const bool ok = over == 0.0 && nh <= K && (nh + nm >= K || t_lo == 1);
+  const bool ok = !force_dense && over == 0.0 && nh <= K && (nh + nm >= K || t_lo == 1);
   if (!ok) {
     hd.mode = SEL_DENSE;
     hd.need = K;
@@ -419,21 +420,21 @@ __device__ __forceinline__ void sel_pick(SelHead& hd, const uint32_t* __restrict
 // histogram rows fix, and if key bits remain unresolved writes one histogram
 // row per workgroup of the next digit (up to kDigit bits) among the candidates
 // matching the prefix.  State and rows are double-buffered by pass parity.
-// init = 1 (first pass over a dense split) decides the source; init = 2
-// starts a selection over a list of k entries.  Segments are read one
+// init = 1 (first pass over a dense split) decides the source (init = 3: the
+// same, but always every key: the fallback, for tests); init = 2 starts a
+// selection over a list of k entries.  Segments are read one
 // wavefront per segment.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_sel_pass(const T* __restrict__ vals, const void* __restrict__ aux,
                                                    int64_t count, SelState* sel, const RecKey<T>* __restrict__ rkey,
-                                                   const uint32_t* __restrict__ rpos,
                                                    const int32_t* __restrict__ rcnt, int nseg, int cap,
                                                    uint32_t* __restrict__ hrows, int p, int init, int64_t k,
                                                    int keybits) {
   __shared__ uint32_t h[kBins];
   __shared__ SelHead hd;
   __shared__ int64_t sc[16];
-  if (init == 1) {
-    sel_decide(sel, rcnt, nseg, cap, keybits, &hd);
+  if (init == 1 || init == 3) {
+    sel_decide(sel, rcnt, nseg, cap, keybits, init == 3, &hd);
   } else if (threadIdx.x == 0) {
     if (init == 2) {
       hd.mode = SEL_LIST; hd.need = k; hd.prefix = 0; hd.pmask = 0; hd.bit = keybits; hd.tie = 0; hd.pending = 0;
@@ -656,8 +657,8 @@ static void sel_run(Ctx<T>& c, const T* vals, const void* aux, int64_t count, in
   const int keybits = 8 * (int)sizeof(T);
   const int passes = (keybits + kDigit - 1) / kDigit;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_sel_pass<T>), dim3(grid), dim3(1024), 0, s, vals, aux, count, c.sel, (const RecKey<T>*)c.rkey, c.rpos,
-                       c.rcnt, nseg, cap, c.hrows, p, p == 0 ? init : 0, k, keybits);
+    hipLaunchKernelGGL((k_sel_pass<T>), dim3(grid), dim3(1024), 0, s, vals, aux, count, c.sel,
+                       (const RecKey<T>*)c.rkey, c.rcnt, nseg, cap, c.hrows, p, p == 0 ? init : 0, k, keybits);
     CS_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL((k_sel_final<T>), dim3(grid), dim3(1024), 0, s, vals, aux, count, c.plan.words, c.plan, c.sel,
@@ -677,7 +678,10 @@ void topk_dense(Ctx<T>& c, const T* dense, const uint32_t* excl, int k, uint32_t
                      (RecKey<T>*)c.rkey, c.rpos, c.rcnt, out_bits);
   CS_LAUNCH_CHECK();
   const unsigned grid = (unsigned)std::min(kPassBlocks, sl.blocks);
-  sel_run<T>(c, dense, excl, n, 1, k, sl.blocks, sl.cap, grid, out_bits);
+  // CS_SELECT_DENSE set: take the every-key fallback regardless of the band
+  // (a test hook; the band's own checks make the fallback rare)
+  const bool force = std::getenv("CS_SELECT_DENSE") != nullptr;
+  sel_run<T>(c, dense, excl, n, force ? 3 : 1, k, sl.blocks, sl.cap, grid, out_bits);
 }
 
 template <typename T>

@@ -130,3 +130,31 @@ def test_orthogonal_operator_is_hard_thresholding(psi, dt):
         s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, 1e-12 if dt == "f64" else 1e-6, **kw)
         assert np.array_equal(supp.cpu().numpy(), expect), algo
         assert rel(s.cpu().numpy()[expect], c[expect]) <= bar, algo
+
+
+DENSE_FALLBACK_CASES = [
+    ("sp_small_noiseless_f32", 80, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6),
+    ("cosamp_small_40db_f64", 81, 2 ** 14, 2 ** 12, 100, "normal", 40.0, "f64", 1e-10),
+    ("ompr_small_noiseless_f32", 82, 2 ** 14, 2 ** 12, 100, "normal_min0.1", None, "f32", 1e-6),
+    ("sp_n2p16_40db_f32", 84, 2 ** 16, 2 ** 14, 300, "normal", 40.0, "f32", 1e-6),
+]
+
+
+@pytest.mark.parametrize("case", DENSE_FALLBACK_CASES, ids=[c[0] for c in DENSE_FALLBACK_CASES])
+def test_top_k_dense_fallback_matches_oracle(case, monkeypatch):
+    """Every dense top-K taken through its fallback (radix passes over every
+    key, the output bitmap rewritten word by word) instead of the sampled
+    band, which the band's checks select only when the sample misleads."""
+    name, cfg, n, m, k, values, snr, dt, tol = case
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, y = problem(cfg, 0, n, m, k, values, snr, dt)
+    algo = name.split("_")[0]
+    ref = getattr(oracle, algo)(op, y, k)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    monkeypatch.setenv("CS_SELECT_DENSE", "1")
+    announce("recover dense fallback", name)
+    s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, tol)
+    assert np.array_equal(supp.cpu().numpy(), ref.support)
+    assert rel(s.cpu().numpy(), ref.s) <= 1e-5
