@@ -158,3 +158,25 @@ def test_top_k_dense_fallback_matches_oracle(case, monkeypatch):
     s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, tol)
     assert np.array_equal(supp.cpu().numpy(), ref.support)
     assert rel(s.cpu().numpy(), ref.s) <= 1e-5
+
+
+EDGE_CASES = [
+    # algo, n, m, k: one measurement; K = M = N; the smallest SP / OMPR / CoSaMP shapes; M = N
+    ("omp", 16, 1, 1), ("omp", 16, 16, 16), ("sp", 16, 2, 1), ("ompr", 32, 4, 2), ("cosamp", 64, 3, 1),
+    ("sp", 16, 16, 8), ("ompr", 16, 16, 5),
+]
+
+
+@pytest.mark.parametrize("algo,n,m,k", EDGE_CASES, ids=[f"{a}_n{n}_m{m}_k{k}" for a, n, m, k in EDGE_CASES])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_tiny_edge_shapes(algo, n, m, k, dt):
+    torch = torch_dev()
+    import paper_1509_03979_amd as cs
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    d, op, y = problem(120, 0, n, m, k, "normal_min0.1", None, dt)
+    ref = getattr(oracle, algo)(op, y, k)
+    dop = cs.Operator.from_numpy(n, d.rows, d.signs)
+    announce("edge", algo, n, m, k, dt)
+    s, supp, info = getattr(cs, f"cs_recover_{algo}")(to_dev(y, tdt), dop, k, 1e-12 if dt == "f64" else 1e-6)
+    assert np.array_equal(supp.cpu().numpy(), ref.support)
+    assert rel(s.cpu().numpy(), ref.s) <= (1e-9 if dt == "f64" else 1e-5)
