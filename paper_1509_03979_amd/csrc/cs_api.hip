@@ -64,7 +64,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0)
   }
   c.partial = cv.take<double>(4 * kRedBlocks);
   c.partial2 = cv.take<double>(rows);
-  c.pgrid = cv.take<double>(strips);
+  c.pgrid = cv.take<double>(4 * strips);   // fused CG step: four partials per strip
   c.argpart = cv.take<ArgKey>(kArgBlocks);
   const SplitLayout sl = split_layout(n);
   c.rkey = cv.take<T>((int64_t)sl.blocks * sl.cap);

@@ -128,6 +128,7 @@ __global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, int nr
     cg->flags = 0;
     cg->cnt_q = 0u;
     cg->cnt_u = 0u;
+    cg->alpha = 0.0;
     const bool fin = isfinite(rr) && isfinite(bb);
     if (!fin) cg->flags |= CS_F_NONFINITE;
     cg->done = (!fin || rr <= tol2 * cg->ref || max_iter <= 0) ? 1 : 0;
@@ -198,7 +199,7 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
     double rr_new = acc;
     if (gridDim.x > 1) {
       __threadfence();
-      const volatile double* vp = prr;
+      const double* vp = prr;
       double sum = 0.0;
       for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) sum += vp[i];
       rr_new = block_sum(sum);
@@ -212,6 +213,21 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
       if (!fin) cg->flags |= CS_F_NONFINITE;
       if (!fin || rr_new <= cg->tol2 * cg->ref || it + 1 >= max_iter) cg->done = 1;
     }
+  }
+}
+
+// The last iteration's x += alpha d, r -= alpha q when the column passes carry
+// the CG update (they apply each iteration's step at the start of the next
+// one, and no pass runs after the solve has stopped).  alpha = 0 when no step
+// is pending (no iteration, or a breakdown).
+template <typename T>
+__global__ void k_cg_finish(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ d, const T* __restrict__ q,
+                            int k, const CgScalars* __restrict__ cg) {
+  const T alpha = (T)cg->alpha;
+  if (alpha == (T)0) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    x[i] = x[i] + alpha * d[i];
+    r[i] = r[i] - alpha * q[i];
   }
 }
 
@@ -263,7 +279,7 @@ __global__ void k_s2_q(const T* __restrict__ sout, const int32_t* __restrict__ l
     double sdq = acc;
     if (gridDim.x > 1) {
       __threadfence();
-      const volatile double* vp = pdq;
+      const double* vp = pdq;
       double sum = 0.0;
       for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) sum += vp[i];
       sdq = block_sum(sum);
@@ -347,15 +363,25 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   }
   CS_LAUNCH_CHECK();
 
+  // Through the four-step column passes the CG update is fused into them:
+  // the inverse pass's last workgroup takes the scalar step, the next forward
+  // pass moves x, r and d (no update launch per iteration).
+  const bool fused = c.psi != 2;
   ColIO<T> dir = col_io<T>(c, COL_DIR, &S);
   dir.r = c.cr;
   dir.d = c.cd;
   dir.cg = c.cg;
+  dir.fused = fused;
+  dir.x = x;
+  dir.q = c.cq;
   ColIO<T> qio = col_io<T>(c, COL_Q, &S);
   qio.q = c.cq;
   qio.d = c.cd;
+  qio.r = c.cr;
   qio.pout = pdq;
   qio.cg = c.cg;
+  qio.fused = fused;
+  qio.max_iter = max_iter;
   const int* done = &c.cg->done;
 
   // Iterations are queued in chunks; the host reads the flags between chunks.
@@ -383,6 +409,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     const int q = std::min(chunk, max_iter - it);
     for (int u = 0; u < q; ++u, ++it) {
       dir.it = it;
+      qio.it = it;
       Queued qd{{-1, -1, -1, -1, -1, -1, -1}, 0.0};
       if (c.psi == 2) {
         hipLaunchKernelGGL(k_s2_dir<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.cr, c.cd, S.list, k, c.P3,
@@ -404,9 +431,6 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
       qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[6]);
       queued.push_back(qd);
       c.transforms += 2;   // (psi_middle counts Phi's two)
-      hipLaunchKernelGGL(k_cg_update<T>, dim3(upd_blocks(k)), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr,
-                         c.cg, it, max_iter);
-      CS_LAUNCH_CHECK();
     }
     dev_read(s, c.cg, &host, sizeof(CgScalars));
     if (host.done) break;
@@ -425,6 +449,11 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     it_prev = host.iters;
   }
   if (!host.done) dev_read(s, c.cg, &host, sizeof(CgScalars));
+  if (fused && host.iters > 0) {
+    hipLaunchKernelGGL(k_cg_finish<T>, dim3(upd_blocks(k)), dim3(kRedThreads), 0, s, x, c.cr, (const T*)c.cd,
+                       (const T*)c.cq, k, (const CgScalars*)c.cg);
+    CS_LAUNCH_CHECK();
+  }
   const bool conv = host.rr[host.iters & 1] <= host.tol2 * host.ref;
   if (!conv && !(host.flags & CS_F_CG_BREAKDOWN)) c.flags |= CS_F_CG_MAXITER;
   c.flags |= host.flags;

@@ -185,7 +185,9 @@ enum ColMode {
   COL_DENSE = 0,   // forward: read a dense v-order input; inverse: write dense v-order output
   COL_X = 1,       // forward: input = x on the support
   COL_DIR = 2,     // forward: d = r + beta d (d = r at iteration 0), input = d
-  COL_Q = 3,       // inverse: q = output on the support, d^T q (last workgroup reduces)
+                   //   (fused: first x += alpha d, r -= alpha q of the previous iteration)
+  COL_Q = 3,       // inverse: q = output on the support, d^T q (last workgroup reduces;
+                   //   fused: also r^T r, r^T q, q^T q, and the scalar CG step)
   COL_R = 4,       // inverse: r = b - output, d = r, partial r^T r per workgroup
   COL_KEY = 5      // inverse: write dense key-order output
 };
@@ -193,9 +195,9 @@ enum ColMode {
 template <typename T>
 struct ColIO {
   int mode;
-  int it;                  // COL_DIR: iteration index
-  int max_iter;            // COL_DIR: iteration cap
-  int npin;                // COL_DIR: number of r^T r partials in pin
+  int it;                  // COL_DIR / COL_Q: iteration index
+  int max_iter;            // COL_Q (fused): iteration cap
+  int fused;               // COL_DIR / COL_Q: the CG vector and scalar updates ride on the passes
   int kcap;                // compact length; slots at or beyond it are ignored
   const uint32_t* sbits;   // support bitmap over keys
   const uint32_t* wpre;    // per-word exclusive prefix counts of sbits
@@ -205,8 +207,7 @@ struct ColIO {
   T* d;
   T* q;
   const T* b;
-  const double* pin;       // COL_DIR: r^T r partials of the previous update
-  double* pout;            // COL_Q / COL_R: one partial per workgroup
+  double* pout;            // COL_Q / COL_R: one partial per workgroup (fused COL_Q: four)
   struct CgScalars* cg;    // nullable: no early exit, no scalar updates
 };
 
@@ -221,6 +222,7 @@ struct CgScalars {
   int32_t pad0;
   double dq;              // d^T H d of the current iteration
   double beta;            // next direction update coefficient
+  double alpha;           // step of the last iteration (fused passes: applied by the next one)
   double ref;             // the stopping test is r^T r <= tol2 * ref: ref = b^T b (relative) or 1 (absolute)
   int32_t done;
   int32_t iters;

@@ -382,11 +382,13 @@ double launch_col(Ctx<T>& c, const Cx<T>* in, Cx<T>* out, bool inv, const ColIO<
   // A dense pass reads and writes one N-vector.  A compact side replaces one
   // of them by the k support keys and the compact vectors it moves: x read
   // (COL_X); r, d read and d written (COL_DIR); d read and q written (COL_Q);
-  // b read, r and d written (COL_R).
+  // b read, r and d written (COL_R).  With the CG update fused, COL_DIR also
+  // reads x and q and writes x and r, and COL_Q also reads r.
   double bytes = 2.0 * (double)p.n * sizeof(T);
   if (io.mode != COL_DENSE && io.mode != COL_KEY) {
     static const int vec[6] = {0, 1, 3, 2, 3, 0};
-    bytes = (double)p.n * sizeof(T) + (double)io.kcap * (4.0 + vec[io.mode] * (double)sizeof(T));
+    const int nv = io.fused ? (io.mode == COL_DIR ? 7 : (io.mode == COL_Q ? 3 : vec[io.mode])) : vec[io.mode];
+    bytes = (double)p.n * sizeof(T) + (double)io.kcap * (4.0 + nv * (double)sizeof(T));
   }
   hipEvent_t ev = nullptr;
   const bool prof = prof_on();
