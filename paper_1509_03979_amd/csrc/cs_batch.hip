@@ -120,7 +120,12 @@ __global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __rest
     }
   } else if (phase == BP_ITER) {
     const int it = st->it;
-    const double dq = cg->dq;
+    // d^T q from the inverse pass's per-workgroup partials (fixed order)
+    const int ncol = (int)(p.L2 >> p.logB);
+    double dqs = 0.0;
+    for (int i = tid; i < ncol; i += blockDim.x) dqs += s.pgrid[i];
+    const double dq = block_sum_any(dqs);
+    if (tid == 0) cg->dq = dq;
     const double rr = cg->rr[it & 1];
     if (tid == 0) {
       st->transforms += 2;

@@ -23,7 +23,7 @@
 // results are deterministic and consumers read one scalar.  Scalars stay on the device; every kernel of an iteration
 // exits early once `done` is set, and the host reads the flags between chunks
 // of queued iterations.
-#include "cs_internal.h"
+#include "cs_device.h"
 
 #include <algorithm>
 #include <cmath>
@@ -216,6 +216,21 @@ __global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __res
   }
 }
 
+// The scalar CG step from the inverse pass's four partials per workgroup,
+// summed in a fixed order (the kernel boundary makes them visible).
+template <typename T>
+__global__ void k_cg_step(CgScalars* cg, const double* __restrict__ part, int g, int it, int max_iter) {
+  if (cg->done) return;
+  __shared__ double red4[4][kRedThreads / 64];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < g; i += blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] += part[j * g + i];
+  }
+  const double4 t = wg_sum4<kRedThreads / 64>(v[0], v[1], v[2], v[3], red4);
+  if (threadIdx.x == 0) cg_step_fused(cg, t, it, max_iter, (T)0);
+}
+
 // The last iteration's x += alpha d, r -= alpha q when the column passes carry
 // the CG update (they apply each iteration's step at the start of the next
 // one, and no pass runs after the solve has stopped).  alpha = 0 when no step
@@ -364,8 +379,8 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   CS_LAUNCH_CHECK();
 
   // Through the four-step column passes the CG update is fused into them:
-  // the inverse pass's last workgroup takes the scalar step, the next forward
-  // pass moves x, r and d (no update launch per iteration).
+  // the inverse pass writes per-workgroup partials, a one-workgroup step
+  // kernel takes the scalar step, and the next forward pass moves x, r and d.
   const bool fused = c.psi != 2;
   ColIO<T> dir = col_io<T>(c, COL_DIR, &S);
   dir.r = c.cr;
@@ -382,6 +397,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   qio.cg = c.cg;
   qio.fused = fused;
   qio.max_iter = max_iter;
+
   const int* done = &c.cg->done;
 
   // Iterations are queued in chunks; the host reads the flags between chunks.
@@ -429,6 +445,11 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
       if (c.psi) qd.bytes += psi_middle<T>(c, c.cg, &qd.rec[1]);
       else qd.bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, &qd.rec[1]);
       qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[6]);
+      if (fused) {
+        hipLaunchKernelGGL(k_cg_step<T>, dim3(1), dim3(kRedThreads), 0, s, c.cg, (const double*)pdq, ncol, it,
+                           max_iter);
+        CS_LAUNCH_CHECK();
+      }
       queued.push_back(qd);
       c.transforms += 2;   // (psi_middle counts Phi's two)
     }

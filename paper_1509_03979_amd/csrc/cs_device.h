@@ -195,4 +195,73 @@ __device__ __forceinline__ void bits_write_body(const uint32_t* __restrict__ bit
   }
 }
 
+// ------------------------------------------------------------------ fused CG step
+// Four workgroup sums at once, valid in thread 0: shuffle trees within each
+// wave, then across the waves' totals in wave 0 (NW <= 16 waves).
+// A wave that holds no data (`wave_has` false, uniform per wave) skips its
+// shuffles and contributes zeros.
+template <int NW>
+__device__ __forceinline__ double4 wg_sum4(double a, double b, double c, double d, double (&red)[4][NW],
+                                           bool wave_has = true) {
+  if (wave_has) {
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_down(a, off, 64);
+      b += __shfl_down(b, off, 64);
+      c += __shfl_down(c, off, 64);
+      d += __shfl_down(d, off, 64);
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = a;
+    red[1][w] = b;
+    red[2][w] = c;
+    red[3][w] = d;
+  }
+  __syncthreads();
+  double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (w == 0) {
+    if (lane < NW) s = make_double4(red[0][lane], red[1][lane], red[2][lane], red[3][lane]);
+    for (int off = 8; off > 0; off >>= 1) {
+      s.x += __shfl_down(s.x, off, 64);
+      s.y += __shfl_down(s.y, off, 64);
+      s.z += __shfl_down(s.z, off, 64);
+      s.w += __shfl_down(s.w, off, 64);
+    }
+  }
+  __syncthreads();
+  return s;
+}
+
+// The scalar CG step of iteration `it` from the inner products of its current
+// residual r and direction d with q = H d (sum = {d^T q, r^T r, r^T q, q^T q}):
+// alpha = r^T r / d^T q, and the next residual's norm without a second pass,
+// |r - alpha q|^2 = r^T r - 2 alpha r^T q + alpha^2 q^T q.  r^T r is summed
+// afresh every iteration, so the expansion's rounding never accumulates.
+// alpha is rounded to the vector precision first, since that is the step the
+// vectors take.  Breakdown (d^T q not positive) stops with alpha = 0.
+template <typename T>
+__device__ __forceinline__ void cg_step_fused(CgScalars* cg, double4 sum, int it, int max_iter, T) {
+  const double dq = sum.x, rr = sum.y;
+  cg->dq = dq;
+  cg->cnt_q = 0u;
+  cg->rr[it & 1] = rr;
+  if (!(dq > 0.0) || !isfinite(dq)) {            // H not positive on d (Theorem 3's condition fails)
+    cg->alpha = 0.0;
+    cg->flags |= CS_F_CG_BREAKDOWN;
+    cg->done = 1;
+    return;
+  }
+  const double alpha = (double)(T)(rr / dq);
+  double rr_new = rr - 2.0 * alpha * sum.z + alpha * alpha * sum.w;
+  if (rr_new < 0.0) rr_new = 0.0;                // rounding below an exact zero residual
+  const bool fin = isfinite(rr_new);
+  cg->alpha = alpha;
+  cg->rr[(it + 1) & 1] = rr_new;
+  cg->beta = rr > 0.0 ? rr_new / rr : 0.0;
+  cg->iters = it + 1;
+  if (!fin) cg->flags |= CS_F_NONFINITE;
+  if (!fin || rr_new <= cg->tol2 * cg->ref || it + 1 >= max_iter) cg->done = 1;
+}
+
 }  // namespace csr

@@ -186,8 +186,8 @@ enum ColMode {
   COL_X = 1,       // forward: input = x on the support
   COL_DIR = 2,     // forward: d = r + beta d (d = r at iteration 0), input = d
                    //   (fused: first x += alpha d, r -= alpha q of the previous iteration)
-  COL_Q = 3,       // inverse: q = output on the support, d^T q (last workgroup reduces;
-                   //   fused: also r^T r, r^T q, q^T q, and the scalar CG step)
+  COL_Q = 3,       // inverse: q = output on the support, partial d^T q per workgroup
+                   //   (fused: partials of d^T q, r^T r, r^T q, q^T q for the step kernel)
   COL_R = 4,       // inverse: r = b - output, d = r, partial r^T r per workgroup
   COL_KEY = 5      // inverse: write dense key-order output
 };
@@ -207,7 +207,7 @@ struct ColIO {
   T* d;
   T* q;
   const T* b;
-  double* pout;            // COL_Q / COL_R: one partial per workgroup (fused COL_Q: four)
+  double* pout;            // COL_Q / COL_R: one partial per workgroup (fused COL_Q: four, by rows of G)
   struct CgScalars* cg;    // nullable: no early exit, no scalar updates
 };
 

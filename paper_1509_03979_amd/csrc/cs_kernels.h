@@ -12,6 +12,7 @@
 // residual, forward-only, adjoint-only) is a uniform argument.
 #pragma once
 
+#include "cs_device.h"
 #include "cs_fft.h"
 
 namespace csr {
@@ -61,74 +62,6 @@ __device__ __forceinline__ double wg_sum(double v, double* red, int nwaves) {
   for (int i = 0; i < nwaves; ++i) s += red[i];
   __syncthreads();
   return s;
-}
-
-// Four workgroup sums at once, valid in thread 0: shuffle trees within each
-// wave, then across the waves' totals in wave 0 (NW <= 16 waves).
-// A wave that holds no data (`wave_has` false, uniform per wave) skips its
-// shuffles and contributes zeros.
-template <int NW>
-__device__ __forceinline__ double4 wg_sum4(double a, double b, double c, double d, double (&red)[4][NW],
-                                           bool wave_has = true) {
-  if (wave_has) {
-    for (int off = 32; off > 0; off >>= 1) {
-      a += __shfl_down(a, off, 64);
-      b += __shfl_down(b, off, 64);
-      c += __shfl_down(c, off, 64);
-      d += __shfl_down(d, off, 64);
-    }
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[0][w] = a;
-    red[1][w] = b;
-    red[2][w] = c;
-    red[3][w] = d;
-  }
-  __syncthreads();
-  double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (w == 0) {
-    if (lane < NW) s = make_double4(red[0][lane], red[1][lane], red[2][lane], red[3][lane]);
-    for (int off = 8; off > 0; off >>= 1) {
-      s.x += __shfl_down(s.x, off, 64);
-      s.y += __shfl_down(s.y, off, 64);
-      s.z += __shfl_down(s.z, off, 64);
-      s.w += __shfl_down(s.w, off, 64);
-    }
-  }
-  __syncthreads();
-  return s;
-}
-
-// The scalar CG step of iteration `it` from the inner products of its current
-// residual r and direction d with q = H d (sum = {d^T q, r^T r, r^T q, q^T q}):
-// alpha = r^T r / d^T q, and the next residual's norm without a second pass,
-// |r - alpha q|^2 = r^T r - 2 alpha r^T q + alpha^2 q^T q.  r^T r is summed
-// afresh every iteration, so the expansion's rounding never accumulates.
-// alpha is rounded to the vector precision first, since that is the step the
-// vectors take.  Breakdown (d^T q not positive) stops with alpha = 0.
-template <typename T>
-__device__ __forceinline__ void cg_step_fused(CgScalars* cg, double4 sum, int it, int max_iter, T) {
-  const double dq = sum.x, rr = sum.y;
-  cg->dq = dq;
-  cg->cnt_q = 0u;
-  cg->rr[it & 1] = rr;
-  if (!(dq > 0.0) || !isfinite(dq)) {            // H not positive on d (Theorem 3's condition fails)
-    cg->alpha = 0.0;
-    cg->flags |= CS_F_CG_BREAKDOWN;
-    cg->done = 1;
-    return;
-  }
-  const double alpha = (double)(T)(rr / dq);
-  double rr_new = rr - 2.0 * alpha * sum.z + alpha * alpha * sum.w;
-  if (rr_new < 0.0) rr_new = 0.0;                // rounding below an exact zero residual
-  const bool fin = isfinite(rr_new);
-  cg->alpha = alpha;
-  cg->rr[(it + 1) & 1] = rr_new;
-  cg->beta = rr > 0.0 ? rr_new / rr : 0.0;
-  cg->iters = it + 1;
-  if (!fin) cg->flags |= CS_F_NONFINITE;
-  if (!fin || rr_new <= cg->tol2 * cg->ref || it + 1 >= max_iter) cg->done = 1;
 }
 
 // First compact slot at or after key `key`: the support keys below it.
@@ -223,8 +156,11 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
   __syncthreads();
   ct_fft<T, INV, NT, LOGL1, LOGB, true, LOGE>(buf, tw);
   if (INV && compact && io.mode == COL_Q && io.fused) {
-    // q = H d on the strip's slots with the four inner products of the CG
-    // step (r is the current residual, already updated by the forward pass)
+    // q = H d on the strip's slots with the partials of the four inner
+    // products of the CG step (r is the current residual, already updated by
+    // the forward pass).  No ticket: a device-scope release in every one of
+    // the pass's workgroups costs more than the separate step launch that
+    // reduces the partials after the kernel boundary.
     double a_dq = 0.0, a_rr = 0.0, a_rq = 0.0, a_qq = 0.0;
     for (uint32_t sl = s0 + tid; sl < s1; sl += NT) {
       const uint32_t key = (uint32_t)io.list[sl];
@@ -240,31 +176,13 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
     }
     const int G = (int)gridDim.x;
     __shared__ double red4[4][NW];
-    __shared__ int last;
     // the strip's few slots sit in the first waves; the others skip the tree
-    double4 t = wg_sum4<NW>(a_dq, a_rr, a_rq, a_qq, red4, s0 + (uint32_t)(tid & ~63) < s1);
+    const double4 t = wg_sum4<NW>(a_dq, a_rr, a_rq, a_qq, red4, s0 + (uint32_t)(tid & ~63) < s1);
     if (tid == 0) {
       io.pout[blockIdx.x] = t.x;
       io.pout[G + blockIdx.x] = t.y;
       io.pout[2 * G + blockIdx.x] = t.z;
       io.pout[3 * G + blockIdx.x] = t.w;
-      __threadfence();
-      last = atomicAdd(&io.cg->cnt_q, 1u) == (unsigned)G - 1;
-    }
-    __syncthreads();
-    if (last) {
-      // The other workgroups' partials: their release fences and this
-      // acquire fence around the ticket order them, so plain loads (issued
-      // together, unlike volatile ones) see them.
-      __threadfence();
-      const double* vp = io.pout;
-      double v[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int i = tid; i < G; i += NT) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] += vp[j * G + i];
-      }
-      t = wg_sum4<NW>(v[0], v[1], v[2], v[3], red4);
-      if (tid == 0) cg_step_fused(io.cg, t, io.it, io.max_iter, (T)0);
     }
   } else if (INV && compact) {
     const bool qm = io.mode == COL_Q;
@@ -284,29 +202,9 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
         acc += (double)rv * (double)rv;
       }
     }
+    // one partial per workgroup (d^T q or r^T r), summed by the next kernel
     const double tot = wg_sum(acc, red, NW);
-    // COL_Q: the last workgroup to finish reduces all partials (fixed order) to d^T H d
-    __shared__ int last;
-    if (tid == 0) {
-      io.pout[blockIdx.x] = tot;
-      last = 0;
-      if (qm && io.cg) {
-        __threadfence();
-        last = atomicAdd(&io.cg->cnt_q, 1u) == gridDim.x - 1;
-      }
-    }
-    __syncthreads();
-    if (last) {
-      __threadfence();
-      const double* vp = io.pout;
-      double sdq = 0.0;
-      for (unsigned i = tid; i < gridDim.x; i += NT) sdq += vp[i];
-      sdq = wg_sum(sdq, red, NW);
-      if (tid == 0) {
-        io.cg->dq = sdq;
-        io.cg->cnt_q = 0u;
-      }
-    }
+    if (tid == 0) io.pout[blockIdx.x] = tot;
   } else if (INV && io.mode == COL_KEY) {
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
