@@ -10,8 +10,11 @@ second: a step counts when its support equals the FP64 oracle's and its
 coefficients agree to relative L2 <= 1e-5.
 
 Default workload: SP on one signal with N = 2^20, M = 2^18, K = 4096, FP32,
-40 dB noise, CG tol 1e-6 with warm starts.  The OMPR recovery of the same
-signal is reported under "extra".
+40 dB noise, CG tol 1e-6 with warm starts.  Under "extra": the OMPR recovery of
+the same signal; SP on the one large signal (N = 2^24, M = 2^21, K = 2^16,
+noiseless) with the roofline of its transform passes (the dominant one, and
+all of them together); the batched 256-signal OMPR; the differentiated
+64-signal SP; the precision sweep on the paper's own operator.
 
 Prints ONE JSON line.  Besides the driver's fields it carries
   roofline      the dominant transform pass: algorithmic bytes per launch over
@@ -50,6 +53,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled replay (roofline)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched OMPR leg (256 signals)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large-signal SP leg (N = 2^24, transform-pass roofline)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the differentiated SP leg (64 signals)")
     ap.add_argument("--no-single-loop", action="store_true", help="batched leg: skip the single-signal loop")
     ap.add_argument("--no-tune", action="store_true", help="keep the default transform shape (no autotuner)")
@@ -107,6 +112,76 @@ def load_inputs(name: str, torch, cs):
     dt = torch.float32 if w["dtype"] == "f32" else torch.float64
     y_dev = torch.as_tensor(y32 if w["dtype"] == "f32" else y32.astype(np.float64), dtype=dt, device="cuda")
     return w, d, op, y_dev, y32, expect, y_src
+
+
+def profiled_roofline(torch, cs, step, steps: int, traffic_file: str, shape_in_use):
+    """Replay `steps` recoveries with per-launch HIP events on the library's
+    stream (timing-only events: no system-scope cache flush around the launch)
+    and return the roofline of the transform pass class with the largest share
+    of transform time, plus the per-class totals.  Launches that exited at once
+    because CG had converged are not counted."""
+    cs.cs_prof_reset()
+    cs.cs_prof_enable(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    prof = cs.cs_prof_read()
+    cs.cs_prof_enable(False)
+    live = {k: v for k, v in prof.items() if v["launches"] > 0}
+    if not live:
+        return None, prof
+    dom = max(live, key=lambda k: live[k]["total_ms"])
+    st = live[dom]
+    per_launch_bytes = st["bytes"] / st["launches"]
+    avg_us = 1e3 * st["total_ms"] / st["launches"]
+    achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", traffic_file)
+    if os.path.exists(tpath):
+        t = json.load(open(tpath))
+        cls = t.get("classes", {}).get(dom)
+        if t.get("source_hash") == source_hash() and list(t.get("shape", [])) == list(shape_in_use) and cls:
+            traffic = cls.get("hbm_bytes_per_launch")
+    tot_bytes = sum(v["bytes"] for v in live.values())
+    tot_ms = sum(v["total_ms"] for v in live.values())
+    loop = tot_bytes / (tot_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "avg_launch_us": round(avg_us, 3), "algorithmic_bytes_per_launch": per_launch_bytes,
+            "launches_per_step": st["launches"] / steps,
+            "share_of_transform_time": round(st["total_ms"] / tot_ms, 3),
+            "all_transform_passes": {"achieved": round(loop, 1), "frac": round(loop / HBM_PEAK_GBS, 4)}}
+    return roof, prof
+
+
+def large_signal_leg(torch, cs, steps: int) -> dict:
+    """SP on the one large signal (N = 2^24, M = 2^21, K = 2^16, FP32,
+    noiseless): recovered signals/s and the HBM roofline of its transform
+    passes, measured as for the headline workload."""
+    name = "sp_n2p24"
+    w, d, op, y, y32, expect, y_src = load_inputs(name, torch, cs)
+    import paper_1509_03979_amd.tune as tune
+    ent = tune.load(w["dtype"], tune.SHIPPED).get("shapes", {}).get(str(d.n))
+    shape = list(ent["shape"]) if ent else cs.cs_shape_candidates(cs.CS_F32, d.n)[0]
+    ws = cs.workspace(cs.CS_F32, op, d.k, cs.CS_ALGO_SP)
+    step = lambda: cs.cs_recover_sp(y, op, d.k, w["tol"], ws=ws)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ok = 0
+    err = 0.0
+    for s_t, supp_t, _ in outs:
+        good, e = recovered(s_t.cpu().numpy().astype(np.float64), supp_t.cpu().numpy(), expect.get("sp"))
+        ok += int(good)
+        err = max(err, e) if good else float("nan")
+    roof, _ = profiled_roofline(torch, cs, step, steps, f"traffic_{name}_sp.json", shape)
+    return {"workload": name, "n": d.n, "m": d.m, "k": d.k, "tol": w["tol"], "y_source": y_src,
+            "signals_per_s": round(ok / el, 3), "ms_per_signal": round(1e3 * el / steps, 4),
+            "recovered": ok, "of": steps, "max_rel_err": err, "info": outs[-1][2], "shape": shape,
+            "roofline": roof}
 
 
 def recovered(s, supp, exp) -> tuple[bool, float]:
@@ -365,33 +440,9 @@ def main():
     roof = None
     prof = {}
     if not args.no_profile:
-        cs.cs_prof_reset()
-        cs.cs_prof_enable(True)
-        for _ in range(args.steps):
-            fn(y, op, d.k, tol, ws=ws)
-        torch.cuda.synchronize()
-        prof = cs.cs_prof_read()
-        cs.cs_prof_enable(False)
-        live = {k: v for k, v in prof.items() if v["launches"] > 0}
-        if live:
-            dom = max(live, key=lambda k: live[k]["total_ms"])
-            st = live[dom]
-            per_launch_bytes = st["bytes"] / st["launches"]
-            avg_us = 1e3 * st["total_ms"] / st["launches"]
-            achieved = st["bytes"] / (st["total_ms"] * 1e-3) / 1e9
-            traffic = None
-            tpath = os.path.join(ROOT, "profiles", f"traffic_{args.workload}_{algo}.json")
-            if os.path.exists(tpath):
-                t = json.load(open(tpath))
-                in_use = tuned["shape"] if tuned else cs.cs_shape_candidates(dtc, d.n)[0]
-                cls = t.get("classes", {}).get(dom)
-                if t.get("source_hash") == source_hash() and list(t.get("shape", [])) == list(in_use) and cls:
-                    traffic = cls.get("hbm_bytes_per_launch")
-            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                    "avg_launch_us": round(avg_us, 3), "algorithmic_bytes_per_launch": per_launch_bytes,
-                    "launches_per_step": st["launches"] / args.steps,
-                    "share_of_transform_time": round(st["total_ms"] / sum(v["total_ms"] for v in live.values()), 3)}
+        in_use = tuned["shape"] if tuned else cs.cs_shape_candidates(dtc, d.n)[0]
+        roof, prof = profiled_roofline(torch, cs, lambda: fn(y, op, d.k, tol, ws=ws), args.steps,
+                                       f"traffic_{args.workload}_{algo}.json", in_use)
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     cpu = None
@@ -428,6 +479,8 @@ def main():
             extra[other] = {"signals_per_s": round((1.0 if ok else 0.0) / to, 3), "ms_per_signal": round(1e3 * to, 3),
                             "recovered": ok, "rel_err": err, "info": info_o}
 
+    if not args.no_large and args.workload != "sp_n2p24":
+        extra["sp_n2p24"] = large_signal_leg(torch, cs, 5)
     if not args.no_batched:
         extra["ompr_batched_256"] = batched_leg(torch, cs, 256, not args.no_single_loop)
     if not args.no_adjoint:

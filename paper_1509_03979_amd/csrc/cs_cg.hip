@@ -404,11 +404,19 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   // After the first chunk the next is sized from the observed geometric rate
   // of r^T r so that few early-exit launches are queued.
   int it = 0;
-  // The first chunk: the iterations the last solve of this size took, plus
-  // one (early-exiting kernels cost far less than a host round trip), else 4.
-  int first = 4;
-  for (int h = 0; h < 2; ++h)
-    if (c.hint_k[h] == k) first = std::max(2, c.hint_it[h] + 1);
+  // The first chunk: the iterations the last solve of this size and start
+  // took, plus one (early-exiting kernels cost less than a host round trip);
+  // else 4 from a cold start and 2 from a warm one.  A warm start is capped
+  // by the most recent warm solve plus two: once the greedy support settles,
+  // warm starts converge in few iterations (or none), whatever the same-size
+  // solve of an earlier round took, and queued iterations would all exit.
+  int first = warm ? 2 : 4;
+  for (int h = 0; h < 4; ++h)
+    if (c.hint[h].k == k && c.hint[h].warm == (int)warm) {
+      first = std::max(1, c.hint[h].it + 1);
+      break;
+    }
+  if (warm && c.last_warm_it >= 0) first = std::min(first, c.last_warm_it + 2);
   int chunk = std::min(first, std::max(max_iter, 1));
   CgScalars host{};
   double rr_prev = -1.0;
@@ -484,12 +492,13 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     c.model_bytes -= queued[i].bytes;
     for (int r : queued[i].rec) prof_discard(r);
   }
-  if (c.hint_k[0] != k) {
-    c.hint_k[1] = c.hint_k[0];
-    c.hint_it[1] = c.hint_it[0];
-    c.hint_k[0] = k;
-  }
-  c.hint_it[0] = host.iters;
+  int h = 0;
+  while (h < 3 && !(c.hint[h].k == k && c.hint[h].warm == (int)warm)) ++h;
+  for (; h > 0; --h) c.hint[h] = c.hint[h - 1];   // move (or insert) to the front
+  c.hint[0].k = k;
+  c.hint[0].warm = warm;
+  c.hint[0].it = host.iters;
+  if (warm) c.last_warm_it = host.iters;
   return host.iters;
 }
 

@@ -333,10 +333,14 @@ struct Ctx {
   // host-side counters
   int64_t transforms = 0;
   int64_t cg_iters = 0;
-  // iterations of the last solves by support size, to size a solve's first
-  // queued chunk of iterations (two entries, most recent first)
-  int hint_k[2] = {-1, -1};
-  int hint_it[2] = {0, 0};
+  // iterations of the last solves by support size and start (cold or warm),
+  // to size a solve's first queued chunk of iterations (most recent first)
+  struct CgHint {
+    int k = -1;
+    int warm = 0;
+    int it = 0;
+  } hint[4];
+  int last_warm_it = -1;   // iterations of the most recent warm-started solve
   double model_bytes = 0;
   int32_t flags = 0;
 };
