@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <mutex>
 #include <cmath>
 #include <cstdio>
@@ -239,29 +240,60 @@ void setup_operator(Ctx<T>& c) {
 }
 
 // ------------------------------------------------------------------ host reads
-__global__ void k_post(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int words) {
-  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+// A pinned, coherent host mailbox per host thread: word 0 is a sequence
+// number, the payload follows from word 2.  k_post copies the payload, makes
+// it visible system-wide, then publishes the sequence number; the host spins
+// on that word instead of waiting for the stream (a stream wait adds the
+// runtime's completion signalling to every read of the greedy and CG loops).
+// A read that does not arrive within a bound falls back to a stream wait,
+// which also reports any error of the queued work.
+constexpr int kBoxWords = 1024;
+constexpr int kBoxHead = 2;
+
+__global__ void k_post(const uint32_t* __restrict__ src, uint32_t* __restrict__ box, int words, uint32_t seq) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) box[kBoxHead + i] = src[i];
   __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(box, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 namespace {
 struct HostBox {
-  void* h = nullptr;
-  void* d = nullptr;
+  uint32_t* h = nullptr;
+  uint32_t* d = nullptr;
+  uint32_t seq = 0;
 };
 thread_local HostBox g_box;
 }  // namespace
 
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
-  if (bytes % 4 || bytes > 4096) throw Error(CS_E_INVALID, "dev_read size");
+  if (bytes % 4 || bytes > 4 * (kBoxWords - kBoxHead)) throw Error(CS_E_INVALID, "dev_read size");
   if (!g_box.h) {
-    CS_HIP(hipHostMalloc(&g_box.h, 4096, hipHostMallocMapped | hipHostMallocCoherent));
-    CS_HIP(hipHostGetDevicePointer(&g_box.d, g_box.h, 0));
+    void* h = nullptr;
+    CS_HIP(hipHostMalloc(&h, 4 * kBoxWords, hipHostMallocMapped | hipHostMallocCoherent));
+    void* d = nullptr;
+    CS_HIP(hipHostGetDevicePointer(&d, h, 0));
+    g_box.h = (uint32_t*)h;
+    g_box.d = (uint32_t*)d;
+    __atomic_store_n(g_box.h, 0u, __ATOMIC_RELEASE);
   }
-  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, (uint32_t*)g_box.d, (int)(bytes / 4));
+  const uint32_t want = ++g_box.seq == 0 ? ++g_box.seq : g_box.seq;   // never 0 (the initial word)
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, g_box.d, (int)(bytes / 4), want);
   CS_LAUNCH_CHECK();
-  CS_HIP(hipStreamSynchronize(s));
-  std::memcpy(host, g_box.h, bytes);
+  bool arrived = false;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t spin = 0;; ++spin) {
+    if (__atomic_load_n(g_box.h, __ATOMIC_ACQUIRE) == want) {
+      arrived = true;
+      break;
+    }
+    if ((spin & 1023u) == 1023u && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(20)) break;
+  }
+  if (!arrived) {
+    CS_HIP(hipStreamSynchronize(s));
+    if (__atomic_load_n(g_box.h, __ATOMIC_ACQUIRE) != want) throw Error(CS_E_HIP, "device read did not arrive");
+  }
+  std::memcpy(host, g_box.h + kBoxHead, bytes);
 }
 
 // ------------------------------------------------------------------ freq-layout scatter / gather
