@@ -100,10 +100,51 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
   const size_t kb = (size_t)g * E;      // first key-order complex slot of the strip
   const size_t L2 = (size_t)p.L2;
   const bool compact = io.mode != COL_DENSE && io.mode != COL_KEY;
+  // CG-driven passes (the compact CG passes, and the dense passes of an
+  // H-apply through a DCT basis) exit once the solve has converged
+  if ((io.mode == COL_DIR || io.mode == COL_Q || io.mode == COL_DENSE) && io.cg && io.cg->done) return;
   uint32_t s0 = 0, s1 = 0;
   if (compact) {
-    s0 = slot_at(io, 2 * kb, p.words);
-    s1 = slot_at(io, 2 * (kb + E), p.words);
+    if constexpr (E >= 16) {
+      // the strip starts and ends on bitmap word boundaries: its slot range is
+      // two prefix counts
+      const int64_t w0 = (int64_t)((2 * kb) >> 5), w1 = (int64_t)((2 * (kb + E)) >> 5);
+      s0 = w0 < p.words ? min(io.wpre[w0], (uint32_t)io.kcap) : (uint32_t)io.kcap;
+      s1 = w1 < p.words ? min(io.wpre[w1], (uint32_t)io.kcap) : (uint32_t)io.kcap;
+    } else {
+      s0 = slot_at(io, 2 * kb, p.words);
+      s1 = slot_at(io, 2 * (kb + E), p.words);
+    }
+  }
+  // The compact side of a thread's first slot is loaded up front (key and
+  // vector values together, ahead of the LDS fill or the dense loads and the
+  // FFT), so its latency overlaps the rest; a strip with more slots than
+  // threads takes the others in a loop afterwards.
+  const uint32_t sl0 = s0 + (uint32_t)tid;
+  const bool has0 = compact && sl0 < s1;
+  uint32_t key0 = 0;
+  T v_x = (T)0, v_r = (T)0, v_d = (T)0, v_q = (T)0, v_b = (T)0;
+  const bool dir = io.mode == COL_DIR, first = io.it == 0;
+  const bool upd = dir && io.fused && !first;
+  if (has0) {
+    key0 = (uint32_t)io.list[sl0];
+    if (!INV) {
+      if (dir) {
+        v_r = io.r[sl0];
+        if (!first) v_d = io.d[sl0];
+        if (upd) {
+          v_x = io.x[sl0];
+          v_q = io.q[sl0];
+        }
+      } else {
+        v_x = io.x[sl0];
+      }
+    } else if (io.mode == COL_Q) {
+      v_d = io.d[sl0];
+      if (io.fused) v_r = io.r[sl0];
+    } else {
+      v_b = io.b[sl0];
+    }
   }
   // thread tid handles e = tid + q NT: row n1 = e >> LOGB, column b = e & (B-1),
   // v-order complex element n1 L2 + c0 + b, keys 2 (kb + e) and 2 (kb + e) + 1
@@ -113,40 +154,38 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
       const int e = tid + q * NT;
       if (E % NT == 0 || e < E) buf[lp(e)] = cx((T)0, (T)0);
     }
-    const bool dir = io.mode == COL_DIR, first = io.it == 0;
-    if (dir && io.cg && io.cg->done) return;
     const T beta = (dir && !first) ? (T)io.cg->beta : (T)0;
     // fused: the previous iteration's x += alpha d, r -= alpha q lands here,
     // each compact slot updated by the one workgroup whose strip holds its key
-    const bool upd = dir && io.fused && !first;
     const T alpha = upd ? (T)io.cg->alpha : (T)0;
-    __syncthreads();
-    for (uint32_t sl = s0 + tid; sl < s1; sl += NT) {
-      const uint32_t key = (uint32_t)io.list[sl];
+    // one slot: the new direction (and the fused update) or x
+    auto slot = [&](uint32_t sl, uint32_t key, T xv, T rv, T dv, T qv) {
       const int64_t e = (int64_t)(key >> 1) - (int64_t)kb;
-      if (e < 0 || e >= E) continue;   // only a list shorter than kcap leaves stale entries here
+      if (e < 0 || e >= E) return;   // only a list shorter than kcap leaves stale entries here
       T val;
       if (dir) {
-        T rv = io.r[sl];
         if (upd) {
-          const T dv = io.d[sl];
-          io.x[sl] = io.x[sl] + alpha * dv;
-          rv = rv - alpha * io.q[sl];
+          io.x[sl] = xv + alpha * dv;
+          rv = rv - alpha * qv;
           io.r[sl] = rv;
           val = rv + beta * dv;
         } else {
-          val = first ? rv : rv + beta * io.d[sl];
+          val = first ? rv : rv + beta * dv;
         }
         io.d[sl] = val;
       } else {
-        val = io.x[sl];
+        val = xv;
       }
       bufr[2 * lp((int)e) + (key & 1)] = val;
+    };
+    __syncthreads();
+    if (has0) slot(sl0, key0, v_x, v_r, v_d, v_q);
+    for (uint32_t sl = sl0 + NT; sl < s1; sl += NT) {
+      const bool need_d = dir && !first;
+      slot(sl, (uint32_t)io.list[sl], (!dir || upd) ? io.x[sl] : (T)0, dir ? io.r[sl] : (T)0,
+           need_d ? io.d[sl] : (T)0, upd ? io.q[sl] : (T)0);
     }
   } else {
-    // CG-driven passes (the compact q gather, and the dense passes of an
-    // H-apply through a DCT basis) exit once the solve has converged
-    if ((io.mode == COL_Q || io.mode == COL_DENSE) && io.cg && io.cg->done) return;
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
@@ -162,18 +201,19 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
     // the pass's workgroups costs more than the separate step launch that
     // reduces the partials after the kernel boundary.
     double a_dq = 0.0, a_rr = 0.0, a_rq = 0.0, a_qq = 0.0;
-    for (uint32_t sl = s0 + tid; sl < s1; sl += NT) {
-      const uint32_t key = (uint32_t)io.list[sl];
+    auto slot = [&](uint32_t sl, uint32_t key, T dvv, T rvv) {
       const int64_t e = (int64_t)(key >> 1) - (int64_t)kb;
-      if (e < 0 || e >= E) continue;
+      if (e < 0 || e >= E) return;
       const T val = bufr[2 * lp((int)e) + (key & 1)];
       io.q[sl] = val;
-      const double qv = (double)val, dv = (double)io.d[sl], rv = (double)io.r[sl];
+      const double qv = (double)val, dv = (double)dvv, rv = (double)rvv;
       a_dq += dv * qv;
       a_rr += rv * rv;
       a_rq += rv * qv;
       a_qq += qv * qv;
-    }
+    };
+    if (has0) slot(sl0, key0, v_d, v_r);
+    for (uint32_t sl = sl0 + NT; sl < s1; sl += NT) slot(sl, (uint32_t)io.list[sl], io.d[sl], io.r[sl]);
     const int G = (int)gridDim.x;
     __shared__ double red4[4][NW];
     // the strip's few slots sit in the first waves; the others skip the tree
@@ -187,21 +227,23 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
   } else if (INV && compact) {
     const bool qm = io.mode == COL_Q;
     double acc = 0.0;
-    for (uint32_t sl = s0 + tid; sl < s1; sl += NT) {
-      const uint32_t key = (uint32_t)io.list[sl];
+    auto slot = [&](uint32_t sl, uint32_t key, T dv, T bv) {
       const int64_t e = (int64_t)(key >> 1) - (int64_t)kb;
-      if (e < 0 || e >= E) continue;
+      if (e < 0 || e >= E) return;
       const T val = bufr[2 * lp((int)e) + (key & 1)];
       if (qm) {
         io.q[sl] = val;
-        acc += (double)io.d[sl] * (double)val;
+        acc += (double)dv * (double)val;
       } else {
-        const T rv = io.b[sl] - val;
+        const T rv = bv - val;
         io.r[sl] = rv;
         io.d[sl] = rv;
         acc += (double)rv * (double)rv;
       }
-    }
+    };
+    if (has0) slot(sl0, key0, v_d, v_b);
+    for (uint32_t sl = sl0 + NT; sl < s1; sl += NT)
+      slot(sl, (uint32_t)io.list[sl], qm ? io.d[sl] : (T)0, qm ? (T)0 : io.b[sl]);
     // one partial per workgroup (d^T q or r^T r), summed by the next kernel
     const double tot = wg_sum(acc, red, NW);
     if (tid == 0) io.pout[blockIdx.x] = tot;
