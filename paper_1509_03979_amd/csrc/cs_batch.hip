@@ -105,8 +105,6 @@ __global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __rest
       cg->tol2 = st->tol2;
       cg->iters = 0;
       cg->flags = 0;
-      cg->cnt_q = 0u;
-      cg->cnt_u = 0u;
       const bool fin = isfinite(rr) && isfinite(bb);
       const bool conv = rr <= st->tol2 * cg->ref;
       const bool done = !fin || conv || st->cg_cap <= 0;

@@ -126,8 +126,6 @@ __global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, int nr
     cg->tol2 = tol2;
     cg->iters = 0;
     cg->flags = 0;
-    cg->cnt_q = 0u;
-    cg->cnt_u = 0u;
     cg->alpha = 0.0;
     const bool fin = isfinite(rr) && isfinite(bb);
     if (!fin) cg->flags |= CS_F_NONFINITE;
@@ -135,85 +133,11 @@ __global__ void k_cg_start(CgScalars* cg, const double* __restrict__ prr, int nr
   }
 }
 
-// alpha = rr / d^T q (d^T q from the inverse pass); x += alpha d; r -= alpha q;
-// per-block r^T r, and the last block to finish reduces them (fixed order) to
-// the next rr, beta and the convergence test.  Each thread updates kUpdUnroll
-// elements with their loads issued together; a single block needs no ticket.
+// Blocks of the compact element-wise kernels: kUpdUnroll elements per thread.
 constexpr int kUpdUnroll = 8;
 static inline int upd_blocks(int k) {
   const int per = kRedThreads * kUpdUnroll;
   return std::max(1, std::min(kRedBlocks, (k + per - 1) / per));
-}
-
-template <typename T>
-__global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ d, const T* __restrict__ q,
-                            int k, double* __restrict__ prr, CgScalars* cg, int it, int max_iter) {
-  __shared__ int last;
-  if (cg->done) return;
-  const double dq = cg->dq;
-  const double rr = cg->rr[it & 1];
-  if (!(dq > 0.0) || !isfinite(dq)) {           // H not positive on d (Theorem 3's condition fails)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      cg->flags |= CS_F_CG_BREAKDOWN;
-      cg->done = 1;
-    }
-    return;
-  }
-  const T alpha = (T)(rr / dq);
-  double acc = 0.0;
-  const int st = gridDim.x * blockDim.x;
-  for (int base = blockIdx.x * blockDim.x + threadIdx.x; base < k; base += st * kUpdUnroll) {
-    T xv[kUpdUnroll], dv[kUpdUnroll], rv[kUpdUnroll], qv[kUpdUnroll];
-#pragma unroll
-    for (int u = 0; u < kUpdUnroll; ++u) {
-      const int i = base + u * st;
-      if (i < k) {
-        xv[u] = x[i];
-        dv[u] = d[i];
-        rv[u] = r[i];
-        qv[u] = q[i];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kUpdUnroll; ++u) {
-      const int i = base + u * st;
-      if (i < k) {
-        x[i] = xv[u] + alpha * dv[u];
-        const T rn = rv[u] - alpha * qv[u];
-        r[i] = rn;
-        acc += (double)rn * (double)rn;
-      }
-    }
-  }
-  acc = block_sum(acc);
-  if (gridDim.x == 1) {
-    if (threadIdx.x == 0) prr[0] = acc;
-    last = 1;
-  } else if (threadIdx.x == 0) {
-    prr[blockIdx.x] = acc;
-    __threadfence();
-    last = atomicAdd(&cg->cnt_u, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (last) {
-    double rr_new = acc;
-    if (gridDim.x > 1) {
-      __threadfence();
-      const double* vp = prr;
-      double sum = 0.0;
-      for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) sum += vp[i];
-      rr_new = block_sum(sum);
-    }
-    if (threadIdx.x == 0) {
-      const bool fin = isfinite(rr_new);
-      cg->rr[(it + 1) & 1] = rr_new;
-      cg->beta = rr_new / rr;
-      cg->iters = it + 1;
-      cg->cnt_u = 0u;
-      if (!fin) cg->flags |= CS_F_NONFINITE;
-      if (!fin || rr_new <= cg->tol2 * cg->ref || it + 1 >= max_iter) cg->done = 1;
-    }
-  }
 }
 
 // The scalar CG step from the inverse pass's four partials per workgroup,
@@ -255,54 +179,55 @@ __global__ void k_s2_scatter(const T* __restrict__ v, const int32_t* __restrict_
   if (i < k) img[list[i]] = v[i];
 }
 
-// d = r (iteration 0) or r + beta d on the support, scattered into the image
+// d = r (iteration 0) or r + beta d on the support, scattered into the image;
+// from iteration 1 on, first the previous step x += alpha d, r -= alpha q (as
+// the forward column pass does for the four-step operator)
 template <typename T>
-__global__ void k_s2_dir(const T* __restrict__ r, T* __restrict__ d, const int32_t* __restrict__ list, int k,
-                         T* __restrict__ img, const CgScalars* __restrict__ cg, int it) {
+__global__ void k_s2_dir(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d, const T* __restrict__ q,
+                         const int32_t* __restrict__ list, int k, T* __restrict__ img,
+                         const CgScalars* __restrict__ cg, int it) {
   if (cg->done) return;
   const T beta = it == 0 ? (T)0 : (T)cg->beta;
+  const T alpha = it == 0 ? (T)0 : (T)cg->alpha;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
-    const T v = it == 0 ? r[i] : r[i] + beta * d[i];
+    T v = r[i];
+    if (it > 0) {
+      const T dv = d[i];
+      x[i] = x[i] + alpha * dv;
+      v = v - alpha * q[i];
+      r[i] = v;
+      v = v + beta * dv;
+    }
     d[i] = v;
     img[list[i]] = v;
   }
 }
 
-// q = (H d)_S gathered from the transformed image, and d^T q: per-block
-// partials, the last block to finish sums them in index order.
+// q = (H d)_S gathered from the transformed image, with per-block partials of
+// d^T q, r^T r, r^T q and q^T q (rows of gridDim.x) for the step kernel.
 template <typename T>
 __global__ void k_s2_q(const T* __restrict__ sout, const int32_t* __restrict__ list, int k, const T* __restrict__ d,
-                       T* __restrict__ q, double* __restrict__ pdq, CgScalars* cg) {
-  __shared__ int last;
+                       const T* __restrict__ r, T* __restrict__ q, double* __restrict__ part,
+                       const CgScalars* __restrict__ cg) {
   if (cg->done) return;
-  double acc = 0.0;
+  double a_dq = 0.0, a_rr = 0.0, a_rq = 0.0, a_qq = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
     const T v = sout[list[i]];
     q[i] = v;
-    acc += (double)d[i] * (double)v;
+    const double qv = (double)v, dv = (double)d[i], rv = (double)r[i];
+    a_dq += dv * qv;
+    a_rr += rv * rv;
+    a_rq += rv * qv;
+    a_qq += qv * qv;
   }
-  acc = block_sum(acc);
-  if (gridDim.x == 1) {
-    last = 1;
-  } else if (threadIdx.x == 0) {
-    pdq[blockIdx.x] = acc;
-    __threadfence();
-    last = atomicAdd(&cg->cnt_q, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (last) {
-    double sdq = acc;
-    if (gridDim.x > 1) {
-      __threadfence();
-      const double* vp = pdq;
-      double sum = 0.0;
-      for (unsigned i = threadIdx.x; i < gridDim.x; i += blockDim.x) sum += vp[i];
-      sdq = block_sum(sum);
-    }
-    if (threadIdx.x == 0) {
-      cg->dq = sdq;
-      cg->cnt_q = 0u;
-    }
+  __shared__ double red4[4][kRedThreads / 64];
+  const double4 t = wg_sum4<kRedThreads / 64>(a_dq, a_rr, a_rq, a_qq, red4);
+  if (threadIdx.x == 0) {
+    const int g = (int)gridDim.x;
+    part[blockIdx.x] = t.x;
+    part[g + blockIdx.x] = t.y;
+    part[2 * g + blockIdx.x] = t.z;
+    part[3 * g + blockIdx.x] = t.w;
   }
 }
 
@@ -378,10 +303,12 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   }
   CS_LAUNCH_CHECK();
 
-  // Through the four-step column passes the CG update is fused into them:
-  // the inverse pass writes per-workgroup partials, a one-workgroup step
-  // kernel takes the scalar step, and the next forward pass moves x, r and d.
-  const bool fused = c.psi != 2;
+  // The CG update is fused into the passes around each H-apply: the inverse
+  // pass (or the gather from the 2-D basis image) writes per-workgroup
+  // partials, a one-workgroup step kernel takes the scalar step, and the next
+  // forward pass (or scatter) moves x, r and d; a finish kernel applies the
+  // last step once the solve has stopped.
+  const bool fused = c.psi != 2;   // (the column-pass I/O below; the 2-D basis has its own kernels)
   ColIO<T> dir = col_io<T>(c, COL_DIR, &S);
   dir.r = c.cr;
   dir.d = c.cd;
@@ -435,30 +362,27 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
       dir.it = it;
       qio.it = it;
       Queued qd{{-1, -1, -1, -1, -1, -1, -1}, 0.0};
+      int nparts = ncol;
       if (c.psi == 2) {
-        hipLaunchKernelGGL(k_s2_dir<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.cr, c.cd, S.list, k, c.P3,
-                           (const CgScalars*)c.cg, it);
+        hipLaunchKernelGGL(k_s2_dir<T>, dim3(nb), dim3(kRedThreads), 0, s, x, c.cr, c.cd, (const T*)c.cq, S.list, k,
+                           c.P3, (const CgScalars*)c.cg, it);
         CS_LAUNCH_CHECK();
         psi2_happly<T>(c, c.cg, c.P1);
         hipLaunchKernelGGL(k_s2_q<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.P1, S.list, k, (const T*)c.cd,
-                           c.cq, pdq, c.cg);
+                           (const T*)c.cr, c.cq, pdq, (const CgScalars*)c.cg);
         CS_LAUNCH_CHECK();
-        queued.push_back(qd);
-        hipLaunchKernelGGL(k_cg_update<T>, dim3(upd_blocks(k)), dim3(kRedThreads), 0, s, x, c.cr, c.cd, c.cq, k, prr,
-                           c.cg, it, max_iter);
-        CS_LAUNCH_CHECK();
-        continue;
+        nparts = nb;
+      } else {
+        qd.bytes += launch_col<T>(c, nullptr, c.W, false, dir, &qd.rec[0]);
+        if (c.psi) qd.bytes += psi_middle<T>(c, c.cg, &qd.rec[1]);
+        else qd.bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, &qd.rec[1]);
+        qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[6]);
       }
-      qd.bytes += launch_col<T>(c, nullptr, c.W, false, dir, &qd.rec[0]);
-      if (c.psi) qd.bytes += psi_middle<T>(c, c.cg, &qd.rec[1]);
-      else qd.bytes += launch_row<T>(c, ROW_HAPPLY, nullptr, nullptr, nullptr, done, &qd.rec[1]);
-      qd.bytes += launch_col<T>(c, c.W, nullptr, true, qio, &qd.rec[6]);
-      if (fused) {
-        hipLaunchKernelGGL(k_cg_step<T>, dim3(1), dim3(kRedThreads), 0, s, c.cg, (const double*)pdq, ncol, it,
-                           max_iter);
-        CS_LAUNCH_CHECK();
-      }
+      hipLaunchKernelGGL(k_cg_step<T>, dim3(1), dim3(kRedThreads), 0, s, c.cg, (const double*)pdq, nparts, it,
+                         max_iter);
+      CS_LAUNCH_CHECK();
       queued.push_back(qd);
+      if (c.psi == 2) continue;
       c.transforms += 2;   // (psi_middle counts Phi's two)
     }
     dev_read(s, c.cg, &host, sizeof(CgScalars));
@@ -478,7 +402,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     it_prev = host.iters;
   }
   if (!host.done) dev_read(s, c.cg, &host, sizeof(CgScalars));
-  if (fused && host.iters > 0) {
+  if (host.iters > 0) {
     hipLaunchKernelGGL(k_cg_finish<T>, dim3(upd_blocks(k)), dim3(kRedThreads), 0, s, x, c.cr, (const T*)c.cd,
                        (const T*)c.cq, k, (const CgScalars*)c.cg);
     CS_LAUNCH_CHECK();

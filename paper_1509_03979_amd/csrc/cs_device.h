@@ -244,7 +244,6 @@ template <typename T>
 __device__ __forceinline__ void cg_step_fused(CgScalars* cg, double4 sum, int it, int max_iter, T) {
   const double dq = sum.x, rr = sum.y;
   cg->dq = dq;
-  cg->cnt_q = 0u;
   cg->rr[it & 1] = rr;
   if (!(dq > 0.0) || !isfinite(dq)) {            // H not positive on d (Theorem 3's condition fails)
     cg->alpha = 0.0;

@@ -227,9 +227,7 @@ struct CgScalars {
   int32_t done;
   int32_t iters;
   int32_t flags;
-  uint32_t cnt_q;         // workgroups finished in the current d^T H d pass
-  uint32_t cnt_u;         // blocks finished in the current update
-  int32_t pad;
+  int32_t pad1;
 };
 
 struct SelHead {           // radix state between the passes of a top-K
