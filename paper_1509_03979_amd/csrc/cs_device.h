@@ -133,38 +133,16 @@ __device__ __forceinline__ void bits_count_body(const uint32_t* __restrict__ bit
   if (threadIdx.x == 0) cnt[b] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Exclusive scan of cnt[0..nb) in place (one block of 1024 threads); total -> cnt[nb].
-__device__ __forceinline__ void bits_scan_body(uint32_t* cnt, int nb) {
-  __shared__ uint32_t sh[1024];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < nb; base += 1024) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = (i < nb) ? cnt[i] : 0u;
-    sh[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-      uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
-      __syncthreads();
-      sh[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < nb) cnt[i] = carry + sh[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += sh[1023];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) cnt[nb] = carry;
-}
-
 // Block b (256 threads, 4 words each) writes the indices of its set bits at
 // their ranks (at most `limit` of them) and, per word, the number of set bits
-// in all earlier words (wpre, nullable).
+// in all earlier words (wpre, nullable).  The block's first rank is the sum of
+// the earlier blocks' counts cnt[0..b), taken here rather than by a scan pass;
+// the last block (b = nb - 1) also stores the total in cnt[nb].
 __device__ __forceinline__ void bits_write_body(const uint32_t* __restrict__ bits, int64_t words,
-                                                const uint32_t* __restrict__ cnt, int32_t* __restrict__ list,
-                                                int limit, uint32_t* __restrict__ wpre, int b) {
+                                                uint32_t* __restrict__ cnt, int32_t* __restrict__ list,
+                                                int limit, uint32_t* __restrict__ wpre, int b, int nb) {
   __shared__ uint32_t sh[256];
+  __shared__ uint32_t wsum[4];
   const int64_t w0 = (int64_t)b * kBitsPerBlockWords + threadIdx.x * 4;
   uint32_t wv[4];
   uint32_t mine = 0;
@@ -173,15 +151,21 @@ __device__ __forceinline__ void bits_write_body(const uint32_t* __restrict__ bit
     wv[q] = (w0 + q < words) ? bits[w0 + q] : 0u;
     mine += __popc(wv[q]);
   }
+  uint32_t pre = 0;
+  for (int i = threadIdx.x; i < b; i += blockDim.x) pre += cnt[i];
+  for (int off = 32; off > 0; off >>= 1) pre += __shfl_down(pre, off, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = pre;
   sh[threadIdx.x] = mine;
   __syncthreads();
+  const uint32_t base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
   for (int off = 1; off < 256; off <<= 1) {
     uint32_t t = (threadIdx.x >= (unsigned)off) ? sh[threadIdx.x - off] : 0u;
     __syncthreads();
     sh[threadIdx.x] += t;
     __syncthreads();
   }
-  uint32_t pos = cnt[b] + sh[threadIdx.x] - mine;
+  if (b == nb - 1 && threadIdx.x == 255) cnt[nb] = base + sh[255];
+  uint32_t pos = base + sh[threadIdx.x] - mine;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (wpre && w0 + q < words) wpre[w0 + q] = pos;

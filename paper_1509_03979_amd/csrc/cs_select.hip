@@ -738,10 +738,9 @@ int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scr
 __global__ void k_bits_count(const uint32_t* __restrict__ bits, int64_t words, uint32_t* __restrict__ cnt) {
   bits_count_body(bits, words, cnt, blockIdx.x);
 }
-__global__ void k_bits_scan(uint32_t* cnt, int nb) { bits_scan_body(cnt, nb); }
-__global__ void k_bits_write(const uint32_t* __restrict__ bits, int64_t words, const uint32_t* __restrict__ cnt,
+__global__ void k_bits_write(const uint32_t* __restrict__ bits, int64_t words, uint32_t* __restrict__ cnt,
                              int32_t* __restrict__ list, int limit, uint32_t* __restrict__ wpre) {
-  bits_write_body(bits, words, cnt, list, limit, wpre, blockIdx.x);
+  bits_write_body(bits, words, cnt, list, limit, wpre, blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -750,8 +749,6 @@ int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uin
   const int nb = (int)((words + kBitsPerBlockWords - 1) / kBitsPerBlockWords);
   hipStream_t s = c.stream;
   hipLaunchKernelGGL(k_bits_count, dim3(nb), dim3(256), 0, s, bits, words, c.blockcnt);
-  CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bits_scan, dim3(1), dim3(1024), 0, s, c.blockcnt, nb);
   CS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_bits_write, dim3(nb), dim3(256), 0, s, bits, words, c.blockcnt, list, expect, wpre);
   CS_LAUNCH_CHECK();
