@@ -357,7 +357,15 @@ __device__ __forceinline__ Cx<T> row_tw(const Plan& p, uint32_t r, uint32_t n2) 
   return tw4n<T>(p, ((r * n2) & (uint32_t)(p.L - 1)) << 3);
 }
 
-template <typename T, int LOGL2, int LOGE>
+// the four-step twiddles a row workgroup keeps in registers (none: formed twice)
+template <typename T, int N>
+struct TwKeep {
+  Cx<T> v[N];
+};
+template <typename T>
+struct TwKeep<T, 0> {};
+
+template <typename T, int LOGL2, int LOGE, bool KEEPTW = true>
 __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p, int mode,
                                          const T* __restrict__ fin, T* __restrict__ fout,
                                          double* __restrict__ partial, const Cx<T>* __restrict__ tw, int w) {
@@ -371,15 +379,27 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
   const int L1 = p.L1;
   const int ra = w, rb = (w == 0) ? (L1 >> 1) : (L1 - w);
   const int tid = threadIdx.x;
-  const T c = (T)sqrt(2.0 / (double)p.n);
+  const T hc = (T)(0.5 * sqrt(2.0 / (double)p.n));
   const T rsn = (T)(1.0 / sqrt((double)p.n));
   const T h = (T)0.70710678118654752440;
 
   // four-step twiddle W_L^{r n2}: for n2 = tid + NT qq it is W_L^{r tid} W_L^{r NT qq}
+  // (the second factor is the same for the whole workgroup); formed once and
+  // kept in registers for the load and the store (KEEPTW), or formed again
+  // for the store where registers are short (the batched pass on long rows)
   Cx<T> tb0 = cx((T)1, (T)0), tb1 = cx((T)1, (T)0);
+  constexpr bool KEEP = SPLIT && KEEPTW;
+  TwKeep<T, KEEP ? 2 * PER_ROW : 0> twk;
   if (SPLIT) {
     tb0 = row_tw<T>(p, (uint32_t)ra, (uint32_t)tid);
     tb1 = row_tw<T>(p, (uint32_t)rb, (uint32_t)tid);
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int q = 0; q < 2 * PER_ROW; ++q) {
+        const int rs = q >= PER_ROW;
+        twk.v[q] = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)(rs ? rb : ra), (uint32_t)(NT * (q - rs * PER_ROW))));
+      }
+    }
   }
 
   if (mode != ROW_ADJ) {
@@ -390,7 +410,9 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         const int qq = q - rs * PER_ROW;
         const int n2 = tid + NT * qq;
         const int r = rs ? rb : ra;
-        const Cx<T> twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
+        Cx<T> twv;
+        if constexpr (KEEP) twv = twk.v[q];
+        else twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
         lds[lp(rs * L2 + n2)] = cmul(buf[(size_t)r * L2 + n2], twv);
       }
     } else {
@@ -433,6 +455,10 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       }
       if (p.fourier) wk = cx((T)1, (T)0);   // the real Fourier basis: no Makhoul rotation
     }
+    // the DCT scale c and the halves of E and O folded into the two rotations:
+    // wkc = (c/2) wk, wmc = (c/2) e^{-i pi/4} conj(wk) (the partner's)
+    const Cx<T> wkc = scale(wk, hc);
+    const Cx<T> wmc = p.fourier ? cx(hc, (T)0) : cx(h * (wkc.re - wkc.im), -h * (wkc.re + wkc.im));
     if (mode != ROW_ADJ) {
       const Cx<T> Zk = lds[sa];
       if (it.zero) {
@@ -441,16 +467,13 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         xb0 = xb1 = (T)0;
       } else {
         const Cx<T> Zm = lds[sb];
-        const Cx<T> E = scale(Zk + conj(Zm), (T)0.5);
+        // 2E = Zk + conj Zm, 2O = (Zk - conj Zm) / i; X from (c/2)-scaled rotations
+        const Cx<T> E2 = Zk + conj(Zm);
         const Cx<T> D = Zk - conj(Zm);
-        const Cx<T> O = cx(D.im * (T)0.5, -D.re * (T)0.5);   // D / (2i)
-        const Cx<T> WO = cmul(WN, O);
-        const Cx<T> Vk = E + WO;
-        const Cx<T> Vm = conj(E - WO);
-        const Cx<T> wm = p.fourier ? cx((T)1, (T)0) : cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));  // e^{-i pi/4} conj(wk)
-        const Cx<T> a = cmul(wk, Vk), b = cmul(wm, Vm);
-        xa0 = c * a.re; xa1 = -c * a.im;
-        xb0 = c * b.re; xb1 = -c * b.im;
+        const Cx<T> WO2 = cmul(WN, cx(D.im, -D.re));
+        const Cx<T> a = cmul(wkc, E2 + WO2), b = cmul(wmc, conj(E2 - WO2));
+        xa0 = a.re; xa1 = -a.im;
+        xb0 = b.re; xb1 = -b.im;
       }
     } else {
       xa0 = fin[2 * it.fa]; xa1 = fin[2 * it.fa + 1];
@@ -486,11 +509,10 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
     if (it.zero) {
       lds[sa] = cx((xa0 + xa1) * rsn, (xa0 - xa1) * rsn);
     } else {
-      const Cx<T> wm = p.fourier ? cx((T)1, (T)0) : cx(h * (wk.re - wk.im), -h * (wk.re + wk.im));
-      const Cx<T> Vk = scale(cmulc(cx(xa0, -xa1), wk), c);    // conj(wk) (Xk - i X_{N-k}) c
-      const Cx<T> Vm = scale(cmulc(cx(xb0, -xb1), wm), c);
-      const Cx<T> E = scale(Vk + conj(Vm), (T)0.5);
-      const Cx<T> O = scale(cmulc(Vk - conj(Vm), WN), (T)0.5);
+      const Cx<T> Vk = cmulc(cx(xa0, -xa1), wkc);   // conj(wk) (Xk - i X_{N-k}) c / 2
+      const Cx<T> Vm = cmulc(cx(xb0, -xb1), wmc);
+      const Cx<T> E = Vk + conj(Vm);
+      const Cx<T> O = cmulc(Vk - conj(Vm), WN);
       lds[sa] = cx(E.re - O.im, E.im + O.re);               // E + i O
       lds[sb] = cx(E.re + O.im, -E.im + O.re);              // conj(E) + i conj(O)
     }
@@ -516,7 +538,9 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       const int qq = q - rs * PER_ROW;
       const int n2 = tid + NT * qq;
       const int r = rs ? rb : ra;
-      const Cx<T> twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
+      Cx<T> twv;
+      if constexpr (KEEP) twv = twk.v[q];
+      else twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
       buf[(size_t)r * L2 + n2] = cmulc(lds[lp(rs * L2 + n2)], twv);
     }
   } else {
@@ -546,7 +570,7 @@ __global__ __launch_bounds__(nt_for(2 << LOGL2, LOGE)) void k_row_b(const BSig<T
   const int phase = uniform_i32(s.st->phase);
   if (phase > BP_RESID) return;
   const bool res = phase == BP_RESID;
-  row_body<T, LOGL2, LOGE>(s.W, s.plan, res ? ROW_RESID : ROW_HAPPLY, res ? s.Yf : nullptr, nullptr,
+  row_body<T, LOGL2, LOGE, true>(s.W, s.plan, res ? ROW_RESID : ROW_HAPPLY, res ? s.Yf : nullptr, nullptr,
                            res ? s.prow : nullptr, s.tw_row, blockIdx.x);
 }
 
