@@ -7,22 +7,24 @@
 //   r_0 = b - H x_0 (x_0 = 0: r_0 = b), d_0 = r_0
 //   alpha = r^T r / d^T H d;  x += alpha d;  r -= alpha H d
 //   beta = r_new^T r_new / r^T r;  d = r_new + beta d
-// until ||r|| <= tol ||b|| (relative form of the line-15 test).
+// until ||r|| <= tol ||b|| (relative form of the CG loop test of Algorithm 1).
 //
 // Compact vectors are ordered by key (the order of the column passes) and
 // hold sign-flipped coordinates theta' = R theta, R = diag(+-1) the sign flip
 // of the operator: H' = R H R and b' = R b give the same inner products, so the
 // iterates are those of the plain CG, and the column passes move raw values.
-// One iteration is four launches:
-//   1. forward column pass in COL_DIR mode: d = r + beta d on the support;
+// One iteration is four launches, the vector update riding on the passes:
+//   1. forward column pass in COL_DIR mode: the previous iteration's
+//      x += alpha d, r -= alpha q, then d = r + beta d on the support;
 //   2. row pass (DCT post-processing, row mask of D, pre-processing);
-//   3. inverse column pass in COL_Q mode: q = (H d)_S and d^T q;
-//   4. update: alpha, x += alpha d, r -= alpha q, r^T r, beta, convergence.
-// Inner products accumulate in FP64 as per-workgroup partials that the last
-// workgroup to finish reduces in index order (a ticket counter picks it), so
-// results are deterministic and consumers read one scalar.  Scalars stay on the device; every kernel of an iteration
-// exits early once `done` is set, and the host reads the flags between chunks
-// of queued iterations.
+//   3. inverse column pass in COL_Q mode: q = (H d)_S and per-workgroup FP64
+//      partials of d^T q, r^T r, r^T q, q^T q;
+//   4. one-workgroup step kernel: the partials summed in index order, alpha,
+//      the next r^T r by expansion, beta and the stopping test.
+// A finish kernel applies the last step once the solve has stopped.  Results
+// are deterministic (fixed summation order).  Scalars stay on the device;
+// every kernel of an iteration exits early once `done` is set, and the host
+// reads the flags between chunks of queued iterations.
 #include "cs_device.h"
 
 #include <algorithm>
