@@ -71,6 +71,30 @@ __global__ void k_cg_gather_b(const T* __restrict__ C0, const int32_t* __restric
   if (threadIdx.x == 0) pbb[blockIdx.x] = acc;
 }
 
+// Both of the above in one pass when a warm start on a grown support also
+// gathers b: b'_i = C0[k_i] (partial b^T b) and r = d = Cc[k_i] (partial r^T r).
+template <typename T>
+__global__ void k_cg_gather_b_corr(const T* __restrict__ C0, const T* __restrict__ cc,
+                                   const int32_t* __restrict__ list, int k, T* __restrict__ b, T* __restrict__ r,
+                                   T* __restrict__ d, double* __restrict__ pbb, double* __restrict__ prr) {
+  double ab = 0.0, ar = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gridDim.x * blockDim.x) {
+    const int32_t key = list[i];
+    const T v = C0[key], w = cc[key];
+    b[i] = v;
+    r[i] = w;
+    d[i] = w;
+    ab += (double)v * (double)v;
+    ar += (double)w * (double)w;
+  }
+  ab = block_sum(ab);
+  ar = block_sum(ar);
+  if (threadIdx.x == 0) {
+    pbb[blockIdx.x] = ab;
+    prr[blockIdx.x] = ar;
+  }
+}
+
 // partial b^T b of a right-hand side already in place
 template <typename T>
 __global__ void k_cg_bnorm(const T* __restrict__ b, int k, double* __restrict__ pbb) {
@@ -264,13 +288,19 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   double* prr = c.partial;
   double* pbb = c.partial + kRedBlocks;
   double* pdq = c.pgrid;
+  const bool corr = warm && r0_corr;
   if (b_ready) hipLaunchKernelGGL(k_cg_bnorm<T>, dim3(nb), dim3(kRedThreads), 0, s, c.cb, k, pbb);
+  else if (corr)
+    hipLaunchKernelGGL(k_cg_gather_b_corr<T>, dim3(nb), dim3(kRedThreads), 0, s, c.C0, (const T*)c.Cc, S.list, k,
+                       c.cb, c.cr, c.cd, pbb, prr);
   else hipLaunchKernelGGL(k_cg_gather_b<T>, dim3(nb), dim3(kRedThreads), 0, s, c.C0, S.list, k, c.cb, pbb);
   CS_LAUNCH_CHECK();
-  if (warm && r0_corr) {
-    hipLaunchKernelGGL(k_cg_init_corr<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.Cc, S.list, k, c.cr, c.cd,
-                       prr);
-    CS_LAUNCH_CHECK();
+  if (corr) {
+    if (b_ready) {
+      hipLaunchKernelGGL(k_cg_init_corr<T>, dim3(nb), dim3(kRedThreads), 0, s, (const T*)c.Cc, S.list, k, c.cr,
+                         c.cd, prr);
+      CS_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(kRedThreads), 0, s, c.cg, prr, nb, pbb, nb, tol * tol, max_iter,
                        c.tol_abs);
   } else if (warm && c.psi == 2) {
@@ -443,12 +473,12 @@ double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
   launch_col<T>(c, c.W, (Cx<T>*)c.Cc, true, col_io<T>(c, COL_KEY, nullptr));
   c.transforms += 2;
   }
-  sum_partials_to(c.partial2, (int)(c.plan.L1 >> 1), &c.cg->resid2, c.stream);
-  // one host read brings ||r||^2 and the support-comparison flag queued before it
-  struct { double r2; int32_t differ, pad; } h{};
-  dev_read(c.stream, &c.cg->resid2, &h, sizeof(h));
-  c.last_differ = h.differ;
-  return std::sqrt(h.r2);
+  // one launch sums ||r||^2 and posts it with the support-comparison flag queued before it
+  double r2 = 0.0;
+  int32_t differ = 0;
+  dev_read_resid(c.stream, c.partial2, (int)(c.plan.L1 >> 1), &c.cg->resid2, &c.cg->differ, &r2, &differ);
+  c.last_differ = differ;
+  return std::sqrt(r2);
 }
 
 template <typename T>

@@ -434,6 +434,8 @@ template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
 // (one per calling thread, kept for the life of the process), then the stream
 // is synchronised.  Cheaper than a pageable device-to-host copy.
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes);
+void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, const int32_t* flag, double* r2_host,
+                    int32_t* flag_host);
 template <typename T> double norm2_host(Ctx<T>& c, const T* v, int64_t count);   // ||v||, synchronises
 void fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s);
 void sum_partials_to(const double* partial, int np, double* out, hipStream_t s);   // *out = sum (one block)

@@ -266,8 +266,32 @@ struct HostBox {
 thread_local HostBox g_box;
 }  // namespace
 
-void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
-  if (bytes % 4 || bytes > 4 * (kBoxWords - kBoxHead)) throw Error(CS_E_INVALID, "dev_read size");
+// The residual read: sums the row pass's partials of ||y - A x||^2 (fixed
+// order), stores the sum at `r2` on the device, and posts {r2, *flag} to the
+// mailbox in the same launch.
+__global__ void k_post_resid(const double* __restrict__ partial, int np, double* __restrict__ r2,
+                             const int32_t* __restrict__ flag, uint32_t* __restrict__ box, uint32_t seq) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) s += partial[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    *r2 = t;
+    const uint64_t bits = (uint64_t)__double_as_longlong(t);
+    box[kBoxHead] = (uint32_t)bits;
+    box[kBoxHead + 1] = (uint32_t)(bits >> 32);
+    box[kBoxHead + 2] = (uint32_t)*flag;
+    __threadfence_system();
+    __hip_atomic_store(box, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+namespace {
+void box_init() {
   if (!g_box.h) {
     void* h = nullptr;
     CS_HIP(hipHostMalloc(&h, 4 * kBoxWords, hipHostMallocMapped | hipHostMallocCoherent));
@@ -277,9 +301,11 @@ void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
     g_box.d = (uint32_t*)d;
     __atomic_store_n(g_box.h, 0u, __ATOMIC_RELEASE);
   }
-  const uint32_t want = ++g_box.seq == 0 ? ++g_box.seq : g_box.seq;   // never 0 (the initial word)
-  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, g_box.d, (int)(bytes / 4), want);
-  CS_LAUNCH_CHECK();
+}
+uint32_t box_next() { return ++g_box.seq == 0 ? ++g_box.seq : g_box.seq; }   // never 0 (the initial word)
+// spin until the sequence word shows `want` (bounded; then a stream wait, which
+// also reports any error of the queued work), and copy the payload out
+void box_wait(hipStream_t s, uint32_t want, void* host, size_t bytes) {
   bool arrived = false;
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t spin = 0;; ++spin) {
@@ -294,6 +320,28 @@ void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
     if (__atomic_load_n(g_box.h, __ATOMIC_ACQUIRE) != want) throw Error(CS_E_HIP, "device read did not arrive");
   }
   std::memcpy(host, g_box.h + kBoxHead, bytes);
+}
+}  // namespace
+
+void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, const int32_t* flag, double* r2_host,
+                    int32_t* flag_host) {
+  box_init();
+  const uint32_t want = box_next();
+  hipLaunchKernelGGL(k_post_resid, dim3(1), dim3(1024), 0, s, partial, np, r2, flag, g_box.d, want);
+  CS_LAUNCH_CHECK();
+  struct { double r2; int32_t flag, pad; } h{};
+  box_wait(s, want, &h, sizeof(h));
+  *r2_host = h.r2;
+  *flag_host = h.flag;
+}
+
+void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
+  if (bytes % 4 || bytes > 4 * (kBoxWords - kBoxHead)) throw Error(CS_E_INVALID, "dev_read size");
+  box_init();
+  const uint32_t want = box_next();
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, g_box.d, (int)(bytes / 4), want);
+  CS_LAUNCH_CHECK();
+  box_wait(s, want, host, bytes);
 }
 
 // ------------------------------------------------------------------ freq-layout scatter / gather
