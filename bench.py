@@ -16,7 +16,7 @@ noiseless) with the roofline of its transform passes (the dominant one, and
 all of them together); the batched 256-signal OMPR; the differentiated
 64-signal SP; the precision sweep on the paper's own operator.
 
-Prints ONE JSON line.  Besides the driver's fields it carries
+Prints ONE JSON line.  Besides metric, value, unit, timing and config it carries
   roofline      the dominant transform pass: algorithmic bytes per launch over
                 its average launch time, from HIP events recorded by the
                 library on its stream during a profiled replay of the timed
@@ -366,8 +366,8 @@ def xi_sweep_leg(torch, cs, ns, algos=("sp", "ompr", "omp")) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              f"(signals are independent, so more GPUs would shard them; see DESIGN.md).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(signals are independent: more GPUs would each take a share of them).", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1509_03979_amd as cs

@@ -345,7 +345,7 @@ def test_cosamp_first_round_from_its_definition():
     assert not np.allclose(r.s[T], np.linalg.lstsq(op.columns(T), y, rcond=None)[0], atol=1e-6)
 
 
-# ------------------------------------------------------------------ exact recovery (the benchmark spec)
+# ------------------------------------------------------------------ exact recovery of well-separated signals
 @pytest.mark.parametrize("algo", ["omp", "sp", "ompr", "cosamp", "ompr_l3"])
 def test_exact_recovery_well_separated(algo):
     d, op, y = problem(97, 0, 4096, 1024, 50, "normal_min0.1")
