@@ -126,44 +126,22 @@ __global__ void k_twiddle(Cx<T>* out, int64_t count, int64_t n, int64_t step) {
   out[i] = cx<T>((T)cv, (T)(-sv));
 }
 
-// Row mask of D in two passes without atomics.  First the rows as a
-// natural-order bitmap: rows ascend, so the rows of one 32-bit word are
-// consecutive and the first of them writes the whole word (the bitmap is
-// cleared beforehand).  Also validates: bad |= 1 when rows are not strictly
-// ascending in [0, N).
-__global__ void k_row_bits(const int32_t* __restrict__ rows, int64_t m, int64_t n, uint32_t* __restrict__ nat,
-                           int32_t* bad) {
+// The freq-layout mask of D straight from the sampled rows: row q sets bit
+// fpos(q) (slot f = (k mod L1) L2 + k / L1, half h: DCT output k or N - k, or
+// L for k = 0); the mask starts clear.  Flags rows out of range or not
+// strictly ascending.
+__global__ void k_mask_from_rows(const int32_t* __restrict__ rows, int64_t m, const Plan p,
+                                 uint32_t* __restrict__ mask, int32_t* bad) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   const int64_t q = rows[i];
-  const bool ok = (q >= 0 && q < n) && (i == 0 || rows[i - 1] < q);
-  if (!ok) { atomicOr(bad, 1); return; }
-  const int64_t w = q >> 5;
-  if (i > 0 && (rows[i - 1] >> 5) == w) return;   // not the first row of its word
-  uint32_t word = 0;
-  for (int64_t j = i; j < m; ++j) {
-    const int64_t r = rows[j];
-    if (r < 0 || r >= n || (r >> 5) != w) break;
-    word |= 1u << (r & 31);
+  const bool ok = (q >= 0 && q < p.n) && (i == 0 || rows[i - 1] < q);
+  if (!ok) {
+    atomicOr(bad, 1);
+    return;
   }
-  nat[w] = word;
-}
-
-// Then the freq-layout mask, one word per thread: bit 2f + h of the mask is
-// DCT output k (h = 0) or N - k (h = 1; L for k = 0) of slot f = (k mod L1) L2
-// + k / L1.
-__global__ void k_mask_from_bits(const uint32_t* __restrict__ nat, uint32_t* __restrict__ mask, const Plan p) {
-  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= p.words) return;
-  uint32_t word = 0;
-#pragma unroll 4
-  for (int b = 0; b < 32; ++b) {
-    const int64_t f = 16 * w + (b >> 1);
-    const int64_t k = (f >> p.logL2) + ((f & (p.L2 - 1)) << p.logL1);
-    const int64_t q = (b & 1) == 0 ? k : (k == 0 ? p.L : p.n - k);
-    word |= ((nat[q >> 5] >> (q & 31)) & 1u) << b;
-  }
-  mask[w] = word;
+  const int64_t b = fpos(q, p);
+  atomicOr(&mask[b >> 5], 1u << (b & 31));
 }
 
 // Inverse of the randomizer's permutation; flags an entry out of range or a
@@ -176,11 +154,28 @@ __global__ void k_perm_inverse(const int32_t* __restrict__ perm, int64_t n, int3
   if (atomicCAS(&pinv[q], -1, (int32_t)j) != -1) atomicOr(bad, 4);
 }
 
-__global__ void k_check_signs(const int8_t* __restrict__ s, int64_t n, int32_t* bad) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Sixteen signs per thread (N is a multiple of 16; the array 16-byte aligned),
+// or one per thread for an unaligned array.
+__global__ void k_check_signs1(const int8_t* __restrict__ s, int64_t n, int32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int8_t v = s[i];
+  const int8_t v = s[i];
   if (v != 1 && v != -1) atomicOr(bad, 2);
+}
+__global__ void k_check_signs(const int8_t* __restrict__ s, int64_t n, int32_t* bad) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+  if (i >= n) return;
+  const uint4 w = *reinterpret_cast<const uint4*>(s + i);
+  const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+  bool okall = true;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint32_t c = (v[j] >> (8 * b)) & 0xFFu;   // +1 = 0x01, -1 = 0xFF
+      okall &= (c == 0x01u || c == 0xFFu);
+    }
+  if (!okall) atomicOr(bad, 2);
 }
 
 template <typename T>
@@ -218,13 +213,13 @@ void setup_operator(Ctx<T>& c) {
   const int64_t nhi = std::max<int64_t>(1, n4 / kTwLo);
   hipLaunchKernelGGL(k_twiddle<T>, dim3(nblk(nhi, 256)), dim3(256), 0, s, c.tw_hi, nhi, n4, (int64_t)kTwLo);
   CS_LAUNCH_CHECK();
-  fill_u32(c.nbits, p.words, 0u, s);          // scratch: the natural-order row bitmap
+  fill_u32(c.mask, p.words, 0u, s);
   fill<int32_t>(c.ibuf, 1, 0, s);
-  hipLaunchKernelGGL(k_row_bits, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, p.n, c.nbits, c.ibuf);
+  hipLaunchKernelGGL(k_mask_from_rows, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, p, c.mask, c.ibuf);
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_mask_from_bits, dim3(nblk(p.words, 256)), dim3(256), 0, s, (const uint32_t*)c.nbits, c.mask, p);
-  CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_check_signs, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.rsigns, p.n, c.ibuf);
+  if (((uintptr_t)c.rsigns & 15u) == 0)
+    hipLaunchKernelGGL(k_check_signs, dim3(nblk((p.n + 15) / 16, 256)), dim3(256), 0, s, c.rsigns, p.n, c.ibuf);
+  else hipLaunchKernelGGL(k_check_signs1, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.rsigns, p.n, c.ibuf);
   CS_LAUNCH_CHECK();
   if (c.psi == 2) dct2d_setup<T>(c);
   if (c.rperm) {
