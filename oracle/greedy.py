@@ -88,6 +88,7 @@ class Result:
     trace: list                   # (step, kind, margin)
     stop: str = ""
     supports: list = dataclasses.field(default_factory=list)  # per-iteration support history
+    moves: list = dataclasses.field(default_factory=list)     # OMPR: (entered, dropped) index arrays per swap
 
 
 def _dense(n, supp, vals):
@@ -173,6 +174,7 @@ def ompr(op: SRM, y, K: int, eta: float | None = None, max_iter: int | None = No
     stop = "max_iter"
     t = 0
     swaps = 0
+    moves = []
     for t in range(1, max_iter + 1):
         if np.linalg.norm(r) <= 1e-12 * ynorm:
             stop = "residual zero"
@@ -196,12 +198,13 @@ def ompr(op: SRM, y, K: int, eta: float | None = None, max_iter: int | None = No
         if not np.isin(J, keep).any():
             stop = "no replacement"
             break
+        moves.append((np.setdiff1d(keep, I), np.setdiff1d(I, keep)))
         I = keep
         x = ctx.solve(I)
         r = y - op.apply_sparse(I, x)
         swaps += 1
     return Result(_dense(op.n, I, x), np.asarray(I, dtype=np.int64), swaps,
-                  float(np.linalg.norm(r)), trace, stop)
+                  float(np.linalg.norm(r)), trace, stop, moves=moves)
 
 
 def cosamp(op: SRM, y, K: int, max_iter: int = 100, ls_route: str = "auto") -> Result:

@@ -78,7 +78,14 @@ def _batched_one(args):
     meta = {"sig": sig, "n": d.n, "m": d.m, "k": d.k, "stop": r.stop, "iters": int(r.iters),
             "resid_norm": r.resid_norm, "min_margin": float(min(margins)) if margins else None, "seconds": dt,
             "y_norm": float(np.linalg.norm(y.astype(np.float64))), "y_sum": float(np.sum(y.astype(np.float64)))}
-    np.savez(path + ".tmp.npz", meta=json.dumps(meta), support=r.support.astype(np.int32), values=r.s[r.support])
+    # the trajectory: the index entering and the index leaving at each swap,
+    # and the FP64 margins of each step's two decisions (entering argmax, drop)
+    m_enter = np.array([m for (_, kind, m) in r.trace if kind == "argmax"])
+    m_drop = np.array([m for (_, kind, m) in r.trace if kind == "drop"])
+    np.savez(path + ".tmp.npz", meta=json.dumps(meta), support=r.support.astype(np.int32), values=r.s[r.support],
+             moves_in=np.array([mv[0][0] for mv in r.moves], dtype=np.int32),
+             moves_out=np.array([mv[1][0] for mv in r.moves], dtype=np.int32),
+             margin_enter=m_enter, margin_drop=m_drop, margin_init=np.array([r.trace[0][2]]))
     os.replace(path + ".tmp.npz", path)
     print("batched sig", sig, meta, flush=True)
     return sig
@@ -89,7 +96,7 @@ def run_batched(count: int = 256, cfg: int = 4, procs: int = 6, part_dir: str | 
     processes; per-signal parts are kept in part_dir so a run can resume, then
     packed into one file (concatenated supports and values + per-signal meta)."""
     import multiprocessing as mp
-    part_dir = part_dir or os.path.join(ROOT, "_work", "golden_batched_parts")
+    part_dir = part_dir or os.path.join(OUT, ".parts_ompr_batched")
     os.makedirs(part_dir, exist_ok=True)
     sizes = synth.batched_sizes(count, cfg)
     order = sorted(range(count), key=lambda i: -sizes[i][0] * sizes[i][2])
@@ -97,15 +104,27 @@ def run_batched(count: int = 256, cfg: int = 4, procs: int = 6, part_dir: str | 
         for _ in pool.imap_unordered(_batched_one, [(cfg, i, part_dir) for i in order]):
             pass
     metas, supps, vals = [], [], []
+    traj = {"moves_in": [], "moves_out": [], "margin_enter": [], "margin_drop": []}
     for sig in range(count):
         z = np.load(os.path.join(part_dir, f"sig{sig:03d}.npz"), allow_pickle=False)
-        metas.append(json.loads(str(z["meta"])))
+        meta = json.loads(str(z["meta"]))
+        meta["margin_init"] = float(z["margin_init"][0])
+        metas.append(meta)
         supps.append(z["support"])
         vals.append(z["values"])
+        for key in traj:
+            traj[key].append(z[key])
     offs = np.cumsum([0] + [s.size for s in supps]).astype(np.int64)
+    # swaps of signal i: moves_in[moff[i]:moff[i+1]]; decisions of signal i
+    # (one more than its swaps when it stopped by declining a replacement):
+    # margin_enter / margin_drop[doff[i]:doff[i+1]]
+    moff = np.cumsum([0] + [a.size for a in traj["moves_in"]]).astype(np.int64)
+    doff = np.cumsum([0] + [a.size for a in traj["margin_enter"]]).astype(np.int64)
     path = os.path.join(OUT, f"ompr_batched_{count}.npz")
     np.savez_compressed(path, meta=json.dumps({"cfg": cfg, "count": count, "ls_route": "cg", "signals": metas}),
-                        offsets=offs, support=np.concatenate(supps), values=np.concatenate(vals))
+                        offsets=offs, support=np.concatenate(supps), values=np.concatenate(vals),
+                        move_offsets=moff, decision_offsets=doff,
+                        **{key: np.concatenate(v) for key, v in traj.items()})
     print("wrote", path)
 
 

@@ -387,6 +387,135 @@ def test_p8_selection_ties():
     assert sel.tolist() == [1, 3, 4]
 
 
+# ------------------------------------------------------------------ decision margins
+def test_margins_from_their_definition():
+    """The logged margin of a selection is the key of the last chosen
+    candidate minus the key of the first rejected one, ranked by (key desc,
+    index asc): hand-made keys with known gaps, ties (margin 0) and
+    exclusions."""
+    keys = np.array([5.0, 3.0, 3.0, 1.0])
+    idx = np.arange(4)
+    assert ogreedy._margin(keys, idx, 1) == 2.0
+    assert ogreedy._margin(keys, idx, 2) == 0.0
+    assert ogreedy._margin(keys, idx, 3) == 2.0
+    assert ogreedy._margin(keys, idx, 4) == float("inf")       # nothing rejected
+    c = np.array([9.0, -4.0, 7.0, -7.0, 1.0])
+    excl = np.array([True, False, False, False, False])
+    assert oracle.argmax_excluding(c, excl) == (2, 0.0)        # |7| twice: lowest index, margin 0
+    assert oracle.argmax_excluding(np.array([9.0, 4.0, -7.0, 6.0]), excl[:4]) == (2, 1.0)
+    sel, m = ogreedy.topk_excluding(np.array([0.5, -2.0, 1.5, 0.25, -3.0]), excl, 2)
+    assert sel.tolist() == [1, 4] and m == 0.5                  # 2.0 kept, 1.5 rejected
+
+
+def _sorted_gaps(c):
+    a = np.sort(np.abs(c))[::-1]
+    return a[:-1] - a[1:]
+
+
+def test_trace_margins_in_the_orthogonal_case():
+    """M = N (A orthogonal): A^T y is computed here from the cosine formula
+    written out, independently of the oracle's operator.  Every decision of
+    the three algorithms then reduces to a ranking of |A^T y| (the LS on S
+    is (A^T y)_S and A^T r is A^T y with S zeroed), so each logged margin
+    is a gap of the sorted magnitudes: OMP's i-th argmax the gap after the
+    i-th largest, SP's initial top-K and its prune the gap after the K-th,
+    its expansion the gap after the 2K-th, and OMPR's (eta = 1) entering
+    argmax and drop the gaps after the (K+1)-th and the K-th."""
+    rng = np.random.default_rng(41)
+    n, k = 256, 12
+    rows, signs = synth.draw_operator(rng, n, n)
+    op = oracle.SRM(n, rows, signs)
+    y = rng.standard_normal(n)
+    kk = np.arange(n)[:, None]
+    jj = np.arange(n)[None, :]
+    F = np.where(kk == 0, np.sqrt(1.0 / n), np.sqrt(2.0 / n)) * np.cos(np.pi * (2 * jj + 1) * kk / (2 * n))
+    c = signs * (F.T @ y)
+    gap = _sorted_gaps(c)
+    r = oracle.omp(op, y, k)
+    got = np.array([m for (_, kind, m) in r.trace if kind == "argmax"])
+    assert np.allclose(got, gap[:k], rtol=0, atol=1e-12)
+    r = oracle.sp(op, y, k)
+    tr = {kind: m for (_, kind, m) in r.trace}
+    assert abs(tr["init_topk"] - gap[k - 1]) <= 1e-12
+    assert abs(tr["expand_topk"] - gap[2 * k - 1]) <= 1e-12      # top-K outside T: ranks K+1..2K
+    assert abs(tr["prune_topk"] - gap[k - 1]) <= 1e-12
+    r = oracle.ompr(op, y, k, eta=1.0)
+    tr = {kind: m for (_, kind, m) in r.trace}
+    assert abs(tr["argmax"] - gap[k]) <= 1e-12
+    assert abs(tr["drop"] - gap[k - 1]) <= 1e-12
+    assert r.stop == "no replacement" and r.moves == []
+
+
+def _ompr_first_step(A, y, K, eta):
+    """One OMPR step written out with dense algebra: the support after it,
+    or None if the step declines to swap."""
+    n = A.shape[1]
+    c0 = A.T @ y
+    I = np.sort(sorted(range(n), key=lambda j: (-abs(c0[j]), j))[:K])
+    x, *_ = np.linalg.lstsq(A[:, I], y, rcond=None)
+    c = A.T @ (y - A[:, I] @ x)
+    out = [j for j in range(n) if j not in set(I.tolist())]
+    j = sorted(out, key=lambda q: (-abs(c[q]), q))[0]
+    cand = list(I) + [j]
+    z = dict(zip(I.tolist(), (x + eta * c[I]).tolist()))
+    z[j] = eta * c[j]
+    keep = sorted(sorted(cand, key=lambda q: (-abs(z[q]), q))[:K])
+    return None if j not in keep else np.array(keep)
+
+
+def test_ompr_default_step_is_n_over_m():
+    """OMPR's step eta defaults to N/M (the reading: ||a_j||^2 = M/N on
+    average, so eta a_j^T r is on a coefficient's scale).  On tiny problems
+    whose first step decides differently for eta = N/M, 1 and M/N (a dense
+    sensing matrix from the cosine formula, LS by lstsq), the oracle's first
+    step with its default must follow eta = N/M."""
+    n, m, K = 32, 8, 2
+    kk = np.arange(n)[:, None]
+    jj = np.arange(n)[None, :]
+    F = np.where(kk == 0, np.sqrt(1.0 / n), np.sqrt(2.0 / n)) * np.cos(np.pi * (2 * jj + 1) * kk / (2 * n))
+    found = 0
+    for seed in range(400):
+        rng = np.random.default_rng([77, seed])
+        rows, signs = synth.draw_operator(rng, n, m)
+        A = F[rows, :] * signs[None, :]
+        y = rng.standard_normal(m)
+        outcomes = {e: _ompr_first_step(A, y, K, e) for e in (n / m, 1.0, m / n)}
+        key = lambda v: None if v is None else tuple(v.tolist())
+        if key(outcomes[n / m]) == key(outcomes[1.0]) or key(outcomes[n / m]) == key(outcomes[m / n]):
+            continue
+        r = oracle.ompr(oracle.SRM(n, rows, signs), y, K, max_iter=1)
+        if outcomes[n / m] is None:
+            assert r.stop == "no replacement" and r.moves == [], seed
+        else:
+            assert r.iters == 1 and np.array_equal(r.support, outcomes[n / m]), seed
+        found += 1
+        if found == 5:
+            break
+    assert found == 5
+
+
+def test_margin_and_step_pins_catch_planted_mistakes(monkeypatch):
+    """A margin taken one rank too far, and OMPR's step inverted (M/N) or
+    left at 1, each fail the pins above."""
+    real_margin = ogreedy._margin
+
+    def margin_off_by_one(keys, idx, k):
+        return real_margin(keys, idx, k + 1) if keys.size > k + 1 else real_margin(keys, idx, k)
+
+    with monkeypatch.context() as mp:
+        mp.setattr(ogreedy, "_margin", margin_off_by_one)
+        with pytest.raises(AssertionError):
+            test_margins_from_their_definition()
+    real_ompr = ogreedy.ompr
+    for wrong in (lambda op: op.m / op.n, lambda op: 1.0):
+        def ompr_wrong_eta(op, y, K, eta=None, *a, _w=wrong, **kw):
+            return real_ompr(op, y, K, _w(op) if eta is None else eta, *a, **kw)
+        with monkeypatch.context() as mp:
+            mp.setattr(oracle, "ompr", ompr_wrong_eta)
+            with pytest.raises(AssertionError):
+                test_ompr_default_step_is_n_over_m()
+
+
 # ------------------------------------------------------------------ P9 adjoint
 def test_p9_adjoint_matches_central_differences():
     d, op, y = problem(99, 0, 1024, 256, 12, "normal", 30.0)
