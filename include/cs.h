@@ -191,6 +191,30 @@ cs_status cs_recover_cosamp(cs_dtype dtype, const void* y, const cs_op* op, int3
                             void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream);
 
 /*
+ * cs_recover_sp_static: cs_recover_sp without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The workspace is a
+ * static device array of CS_STATIC_WS_BYTES bytes inside the library, one per
+ * GPU, held from the library's first use on that GPU until the process ends;
+ * its device address is looked up on the first call on each device (with that
+ * device current).  The call itself allocates nothing: no hipMalloc, hipFree
+ * or pinned host buffer (host reads of loop flags are stream-ordered copies
+ * into the call's own stack followed by a wait on `stream`), and kernel
+ * timing (cs_prof_*) is not recorded for it.  Arguments, results, cs_info and
+ * errors are those of cs_recover_sp; sizes whose cs_workspace_size_op(...,
+ * CS_ALGO_SP) exceeds CS_STATIC_WS_BYTES (FP32: N up to 2^21 at M = N/4,
+ * K = M/64; FP64: N up to 2^20) return CS_E_WORKSPACE with nothing written.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (each call initialises what it reads): calls that overlap on one
+ * GPU, from several threads or on several streams, race and must be
+ * serialised by the caller.
+ */
+#define CS_STATIC_WS_BYTES (64u << 20)
+cs_status cs_recover_sp_static(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol,
+                               void* s, int32_t* support, const cs_params* params, cs_info* info,
+                               hipStream_t stream);
+
+/*
  * The CG function of Algorithm 1 on its own: solve the weighted
  * least squares of Eq. (10) through its normal equations, Eq. (11), for the
  * columns `support` [k] (device int32, strictly ascending, in [0, N)).

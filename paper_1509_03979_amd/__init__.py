@@ -24,7 +24,10 @@ CS_ALGO_OMP, CS_ALGO_SP, CS_ALGO_OMPR, CS_ALGO_OPERATOR, CS_ALGO_LS, CS_ALGO_COS
 CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, -3, -4, -5
 CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
 
+CS_STATIC_WS_BYTES = 64 << 20
+
 EXPORTS = ("cs_workspace_size", "cs_workspace_size_op", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_recover_cosamp",
+           "cs_recover_sp_static",
            "cs_ls_solve",
            "cs_adjoint_ls", "cs_workspace_size_batched", "cs_recover_ompr_batched", "cs_apply_A", "cs_apply_At",
            "cs_shape_candidates", "cs_set_shape", "cs_time_shape", "cs_status_str", "cs_last_error",
@@ -93,6 +96,8 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, vp, P(cs_op), i32, dbl, vp, vp, P(cs_params), vp, sz, P(cs_info), vp]
         f.restype = ctypes.c_int
+    lib.cs_recover_sp_static.argtypes = [ctypes.c_int, vp, P(cs_op), i32, dbl, vp, vp, P(cs_params), P(cs_info), vp]
+    lib.cs_recover_sp_static.restype = ctypes.c_int
     lib.cs_ls_solve.argtypes = [ctypes.c_int, vp, P(cs_op), vp, i32, dbl, vp, vp, P(cs_params), vp, sz,
                                 P(cs_info), vp]
     lib.cs_ls_solve.restype = ctypes.c_int
@@ -274,6 +279,30 @@ def cs_recover_omp(y, op: Operator, k: int, tol: float, ws=None, stream=None, **
 def cs_recover_sp(y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
     """Subspace Pursuit with CG least squares -> (s, support, info)."""
     return _recover(lib.cs_recover_sp, CS_ALGO_SP, y, op, k, tol, ws, stream, **kw)
+
+
+def cs_recover_sp_static(y, op: Operator, k: int, tol: float, s=None, support=None, stream=None, **kw):
+    """Subspace Pursuit on the library's static device workspace (no workspace
+    argument; the call allocates nothing) -> (s, support, info).  Pass `s` [N]
+    and `support` [K] to reuse output tensors; sizes beyond CS_STATIC_WS_BYTES
+    of workspace raise with status CS_E_WORKSPACE."""
+    torch = _torch()
+    dt = _dtype_code(y)
+    y = y.contiguous()
+    if y.numel() != op.m or not y.is_cuda:
+        raise ValueError("y must be a device vector of length M")
+    if s is None:
+        s = torch.empty(op.n, dtype=y.dtype, device=y.device)
+    if support is None:
+        support = torch.empty(k, dtype=torch.int32, device=y.device)
+    if s.numel() != op.n or s.dtype != y.dtype or support.numel() != k or support.dtype != torch.int32:
+        raise ValueError("s must be [N] in y's dtype and support [K] int32")
+    info = cs_info()
+    prm = _params(**kw)
+    st = lib.cs_recover_sp_static(dt, _ptr(y), ctypes.byref(op.c), int(k), float(tol), _ptr(s), _ptr(support),
+                                  ctypes.byref(prm), ctypes.byref(info), _stream_ptr(stream))
+    _check(st)
+    return s, support, info.as_dict()
 
 
 def cs_recover_ompr(y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):

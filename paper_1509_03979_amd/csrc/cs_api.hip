@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 namespace csr {
@@ -438,6 +439,32 @@ static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, vo
   if (prof_on()) prof_flush();
 }
 
+// ------------------------------------------------------------------ static workspace
+// The workspace of cs_recover_sp_static: a file-scope device array, one copy
+// per GPU, held from the load of the code object on that GPU until the
+// process ends.  In host code the array's name is a host-side stand-in, not a
+// device address; its device address is looked up once per device (with
+// that device current) and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CS_STATIC_WS_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+static void* scratch_ptr() {
+  int dev = 0;
+  CS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error(CS_E_HIP, "device ordinal out of range for the static workspace");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    CS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256) throw Error(CS_E_HIP, "static workspace address unusable");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace csr
 
 using namespace csr;
@@ -470,6 +497,34 @@ cs_status cs_recover_sp(cs_dtype dtype, const void* y, const cs_op* op, int32_t 
                         int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
                         hipStream_t stream) {
   return recover(CS_ALGO_SP, dtype, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+}
+
+cs_status cs_recover_sp_static(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,
+                               int32_t* support, const cs_params* params, cs_info* info, hipStream_t stream) {
+  try {
+    check_shape(dtype, op, k, CS_ALGO_SP);
+    if (!y || !s || !support) throw Error(CS_E_INVALID, "null y, s or support");
+    check_tol(tol);
+    const size_t need = workspace_bytes(dtype, op->n, op->m, k, CS_ALGO_SP, op->psi);
+    if (need == 0) throw Error(CS_E_SHAPE, "unsupported N or shape");
+    if (need > (size_t)CS_STATIC_WS_BYTES)
+      throw Error(CS_E_WORKSPACE, "these sizes need " + std::to_string(need) +
+                                      " bytes of workspace; the static workspace holds " +
+                                      std::to_string((size_t)CS_STATIC_WS_BYTES));
+    void* ws = scratch_ptr();
+    NoAllocScope scope;
+    if (dtype == CS_F32)
+      recover_t<float>(CS_ALGO_SP, y, op, k, tol, s, support, params, ws, CS_STATIC_WS_BYTES, info, stream);
+    else
+      recover_t<double>(CS_ALGO_SP, y, op, k, tol, s, support, params, ws, CS_STATIC_WS_BYTES, info, stream);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
 }
 
 cs_status cs_recover_ompr(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,

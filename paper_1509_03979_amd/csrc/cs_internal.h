@@ -434,6 +434,16 @@ template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
 // (one per calling thread, kept for the life of the process), then the stream
 // is synchronised.  Cheaper than a pageable device-to-host copy.
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes);
+// While a NoAllocScope lives on the calling thread, host reads are
+// stream-ordered copies into the caller's host memory followed by a stream
+// wait (the pinned mailbox allocates on its first use), and kernel timing is
+// not recorded (its events are created on demand): the library then makes no
+// allocation of its own.
+bool no_alloc_mode();
+struct NoAllocScope {
+  NoAllocScope();
+  ~NoAllocScope();
+};
 void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, const int32_t* flag, double* r2_host,
                     int32_t* flag_host);
 template <typename T> double norm2_host(Ctx<T>& c, const T* v, int64_t count);   // ||v||, synchronises

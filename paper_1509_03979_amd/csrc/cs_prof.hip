@@ -44,7 +44,7 @@ hipEvent_t get_event() {
 }
 }  // namespace
 
-bool prof_on() { return g_on.load(std::memory_order_relaxed) != 0; }
+bool prof_on() { return g_on.load(std::memory_order_relaxed) != 0 && !no_alloc_mode(); }
 
 int prof_begin(hipStream_t s, hipEvent_t* ev) {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -277,11 +277,15 @@ __global__ void k_post_resid(const double* __restrict__ partial, int np, double*
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
     *r2 = t;
     const uint64_t bits = (uint64_t)__double_as_longlong(t);
-    box[kBoxHead] = (uint32_t)bits;
-    box[kBoxHead + 1] = (uint32_t)(bits >> 32);
-    box[kBoxHead + 2] = (uint32_t)*flag;
-    __threadfence_system();
-    __hip_atomic_store(box, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (box) {
+      box[kBoxHead] = (uint32_t)bits;
+      box[kBoxHead + 1] = (uint32_t)(bits >> 32);
+    }
+    if (box) {   // null: the caller copies r2 and the flag itself
+      box[kBoxHead + 2] = (uint32_t)*flag;
+      __threadfence_system();
+      __hip_atomic_store(box, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -318,8 +322,24 @@ void box_wait(hipStream_t s, uint32_t want, void* host, size_t bytes) {
 }
 }  // namespace
 
+namespace {
+thread_local int g_no_alloc = 0;
+}  // namespace
+
+bool no_alloc_mode() { return g_no_alloc != 0; }
+NoAllocScope::NoAllocScope() { ++g_no_alloc; }
+NoAllocScope::~NoAllocScope() { --g_no_alloc; }
+
 void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, const int32_t* flag, double* r2_host,
                     int32_t* flag_host) {
+  if (no_alloc_mode()) {
+    hipLaunchKernelGGL(k_post_resid, dim3(1), dim3(1024), 0, s, partial, np, r2, flag, nullptr, 0u);
+    CS_LAUNCH_CHECK();
+    CS_HIP(hipMemcpyAsync(r2_host, r2, sizeof(double), hipMemcpyDeviceToHost, s));
+    CS_HIP(hipMemcpyAsync(flag_host, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CS_HIP(hipStreamSynchronize(s));
+    return;
+  }
   box_init();
   const uint32_t want = box_next();
   hipLaunchKernelGGL(k_post_resid, dim3(1), dim3(1024), 0, s, partial, np, r2, flag, g_box.d, want);
@@ -332,6 +352,11 @@ void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, co
 
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
   if (bytes % 4 || bytes > 4 * (kBoxWords - kBoxHead)) throw Error(CS_E_INVALID, "dev_read size");
+  if (no_alloc_mode()) {
+    CS_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+    CS_HIP(hipStreamSynchronize(s));
+    return;
+  }
   box_init();
   const uint32_t want = box_next();
   hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, g_box.d, (int)(bytes / 4), want);

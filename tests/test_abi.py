@@ -218,3 +218,22 @@ def test_batched_validation():
     items[1].op = cs.cs_op(1024, 256, FAKE, FAKE)
     items[0].y = None
     assert f(cs.CS_F32, 2, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_INVALID
+
+
+def test_static_workspace_entry_validates_on_the_host():
+    """cs_recover_sp_static checks its arguments and the static workspace's
+    capacity before any device work (fake device addresses are never read)."""
+    def call(dt=cs.CS_F32, n=1024, m=256, k=10, tol=1e-6, y=FAKE, s=FAKE, supp=FAKE):
+        o = cs.cs_op(n, m, FAKE, FAKE)
+        return cs.lib.cs_recover_sp_static(dt, ctypes.c_void_p(y) if y else None, ctypes.byref(o), k, tol,
+                                           ctypes.c_void_p(s) if s else None,
+                                           ctypes.c_void_p(supp) if supp else None, None, None, None)
+    assert call(dt=5) == cs.CS_E_INVALID
+    assert call(y=0) == cs.CS_E_INVALID
+    assert call(tol=0.0) == cs.CS_E_INVALID
+    assert call(m=256, k=129) == cs.CS_E_SHAPE                   # SP: 2K <= M
+    assert call(n=2 ** 22, m=2 ** 20, k=16384) == cs.CS_E_WORKSPACE
+    assert call(dt=cs.CS_F64, n=2 ** 21, m=2 ** 19, k=8192) == cs.CS_E_WORKSPACE
+    assert "static workspace" in cs.cs_last_error()
+    for dt, n in ((cs.CS_F32, 2 ** 21), (cs.CS_F64, 2 ** 20)):   # the largest sizes the header promises
+        assert cs.cs_workspace_size(dt, n, n // 4, n // 256, cs.CS_ALGO_SP) <= cs.CS_STATIC_WS_BYTES
