@@ -263,7 +263,12 @@ typedef struct {
   void* s;                /* device [N] output, dense                               */
   int32_t* support;       /* device [K] output, strictly ascending                  */
   int32_t k;              /* sparsity K                                             */
-  int32_t pad;
+  int32_t moves_cap;      /* swaps `moves` can hold (0: none are recorded)          */
+  int32_t* moves;         /* device [2 moves_cap] output or NULL: swap i writes the
+                             natural index that entered the support at 2i and the
+                             one that left at 2i+1, in order, for the first
+                             moves_cap swaps (the trajectory, e.g. to compare a
+                             recovery's decisions with a reference's)           */
 } cs_batch_item;
 
 size_t cs_workspace_size_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, cs_algo algo);

@@ -57,7 +57,7 @@ class cs_info(ctypes.Structure):
 
 class cs_batch_item(ctypes.Structure):
     _fields_ = [("op", cs_op), ("y", ctypes.c_void_p), ("s", ctypes.c_void_p), ("support", ctypes.c_void_p),
-                ("k", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("k", ctypes.c_int32), ("moves_cap", ctypes.c_int32), ("moves", ctypes.c_void_p)]
 
 
 class cs_shape(ctypes.Structure):
@@ -398,7 +398,10 @@ class Batch:
     """Outputs, descriptors and workspace of one batched call, reusable across
     calls with the same signals (the measurements may change in place)."""
 
-    def __init__(self, ys, ops, ks, device=None):
+    def __init__(self, ys, ops, ks, device=None, moves_cap: int = 0):
+        """moves_cap > 0 records each signal's first moves_cap swaps in
+        self.moves[i] (int32 [moves_cap, 2]: entered, left; rows past the
+        signal's swap count are left at -1)."""
         torch = _torch()
         if not (len(ys) == len(ops) == len(ks)) or len(ys) == 0:
             raise ValueError("ys, ops and ks must be non-empty and of equal length")
@@ -413,6 +416,8 @@ class Batch:
         self.ks = [int(k) for k in ks]
         self.s = [torch.empty(op.n, dtype=self.dtype, device=dev) for op in self.ops]
         self.supp = [torch.empty(k, dtype=torch.int32, device=dev) for k in self.ks]
+        self.moves = [torch.full((int(moves_cap), 2), -1, dtype=torch.int32, device=dev) for _ in self.ks] \
+            if moves_cap > 0 else None
         n = len(self.ys)
         self.items = (cs_batch_item * n)()
         for i in range(n):
@@ -422,6 +427,9 @@ class Batch:
             it.s = _ptr(self.s[i])
             it.support = _ptr(self.supp[i])
             it.k = self.ks[i]
+            if self.moves is not None:
+                it.moves_cap = int(moves_cap)
+                it.moves = _ptr(self.moves[i])
         nbytes = lib.cs_workspace_size_batched(self.dt, n, self.items, CS_ALGO_OMPR)
         if nbytes == 0:
             raise CSError(CS_E_SHAPE, "no batched workspace size for these signals")

@@ -40,6 +40,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0)
   c.tw_row = cv.take<Cx<T>>(kTwStage);
   c.tw_lo = cv.take<Cx<T>>(kTwLo);
   c.tw_hi = cv.take<Cx<T>>(std::max<int64_t>(1, 4 * n / kTwLo));
+  c.tw_step = cv.take<Cx<T>>(2 * kTwStepHalf);
   c.mask = cv.take<uint32_t>(p.words);
   c.pinv = cv.take<int32_t>(n);
   for (int i = 0; i < 3; ++i) c.bits[i] = cv.take<uint32_t>(p.words);
@@ -121,6 +122,7 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   carve(c, p, kmax, (char*)ws, psi);
   p.tw_lo = c.tw_lo;
   p.tw_hi = c.tw_hi;
+  p.tw_step = c.tw_step;
   p.mask = c.mask;
   // the candidates' key order follows the transform they enter: Phi's (through
   // the randomizer) or, with a DCT basis, Psi's (no randomizer)
@@ -599,6 +601,8 @@ cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_
       check_shape(dtype, &items[i].op, items[i].k, CS_ALGO_OMPR);
       if (items[i].op.psi != 0) throw Error(CS_E_INVALID, "the batched call takes operators with psi = 0");
       if (!items[i].y || !items[i].s || !items[i].support) throw Error(CS_E_INVALID, "null y, s or support in batch");
+      if (items[i].moves_cap < 0 || (items[i].moves_cap > 0 && !items[i].moves))
+        throw Error(CS_E_INVALID, "moves_cap must be >= 0, with a non-null moves array when positive");
     }
     check_tol(tol);
     check_ws(ws);

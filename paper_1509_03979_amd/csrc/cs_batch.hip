@@ -269,6 +269,10 @@ __global__ void k_b_select(const BSig<T>* __restrict__ sigs, const int32_t* __re
   if (tid == 0) {
     s.bits[kd >> 5] &= ~(1u << (kd & 31));
     s.bits[kj >> 5] |= 1u << (kj & 31);
+    if (st->swaps < s.moves_cap) {
+      s.moves[2 * st->swaps] = sj;
+      s.moves[2 * st->swaps + 1] = sd;
+    }
     st->swaps += 1;
     st->cur = nxt;
     st->bb = bb;
@@ -379,6 +383,8 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
     h.argpart = c.argpart; h.blockcnt = c.blockcnt;
     h.cg = c.cg;
     h.st = d_st + i;
+    h.moves = it.moves_cap > 0 ? it.moves : nullptr;
+    h.moves_cap = it.moves_cap > 0 ? it.moves_cap : 0;
     BState& b = hst[i];
     std::memset(&b, 0, sizeof(BState));
     b.phase = BP_WARM;

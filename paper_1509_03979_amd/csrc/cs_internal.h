@@ -88,6 +88,8 @@ struct Plan {
   size_t lds_col, lds_row;
   const void* tw_lo;      // W_{4N}^i, i in [0, 4096)          (Cx<T>)
   const void* tw_hi;      // W_{4N}^{4096 h}, h in [0, 4N/4096) (Cx<T>)
+  const void* tw_step;    // W_{4N}^{i L1 nt_row} (i < 16), then W_{4N}^{4 i L1 nt_row}: the row pass's
+                          // per-item Makhoul twiddle steps (Cx<T>, 2 kTwStepHalf entries)
   const uint32_t* mask;   // N bits in freq-layout: bit 2f+h = row sampled
   const int32_t* perm;    // randomizer permutation: entry j enters the DCT at perm[j] (null: identity)
   const int32_t* pinv;    // its inverse (null with perm)
@@ -97,6 +99,7 @@ struct Plan {
 
 constexpr int kTwStage = 8192;   // entries reserved for one stage-twiddle table (size 2^13 needs 8176)
 constexpr int kTwLo = 4096;
+constexpr int kTwStepHalf = 16;
 constexpr int kTwLoLog = 12;
 
 // v-order position of natural index j, and its inverse.
@@ -303,6 +306,7 @@ struct Ctx {
   // twiddles, masks
   Cx<T>* tw_col; Cx<T>* tw_row;   // stage twiddles of the L1- and L2-point FFTs
   Cx<T>* tw_lo; Cx<T>* tw_hi;
+  Cx<T>* tw_step;
   uint32_t* mask;          // row mask of D, freq-layout bits
   int32_t* pinv;           // inverse of the randomizer's permutation (N entries)
   // supports: key bitmaps, ascending key lists and per-word prefix counts
@@ -381,6 +385,8 @@ struct BSig {              // device-side view of one signal of a batch
   uint32_t* blockcnt;
   CgScalars* cg;
   BState* st;
+  int32_t* moves;          // swap log (entered, left) per swap, or null
+  int32_t moves_cap;
 };
 
 // A support as the CG sees it.

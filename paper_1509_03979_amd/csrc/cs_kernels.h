@@ -15,6 +15,8 @@
 #include "cs_device.h"
 #include "cs_fft.h"
 
+#include <type_traits>
+
 namespace csr {
 
 // ------------------------------------------------------------------ shapes
@@ -366,9 +368,10 @@ template <typename T>
 struct TwKeep<T, 0> {};
 
 template <typename T, int LOGL2, int LOGE, bool KEEPTW = true>
-__device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p, int mode,
+__device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p, int mode_rt,
                                          const T* __restrict__ fin, T* __restrict__ fout,
                                          double* __restrict__ partial, const Cx<T>* __restrict__ tw, int w) {
+  const int mode = mode_rt;
   constexpr int L2 = 1 << LOGL2;
   constexpr int NT = nt_for(2 * L2, LOGE);
   constexpr bool SPLIT = NT <= L2;                 // threads tile each row exactly
@@ -402,18 +405,21 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
     }
   }
 
+  // the two rows (uniform base pointers; 32-bit offsets within a row)
+  Cx<T>* const rowa = buf + (size_t)ra * L2;
+  Cx<T>* const rowb = buf + (size_t)rb * L2;
   if (mode != ROW_ADJ) {
     if (SPLIT) {
 #pragma unroll
       for (int q = 0; q < 2 * PER_ROW; ++q) {
         const int rs = q >= PER_ROW;
         const int qq = q - rs * PER_ROW;
-        const int n2 = tid + NT * qq;
+        const uint32_t n2 = (uint32_t)(tid + NT * qq);
         const int r = rs ? rb : ra;
         Cx<T> twv;
         if constexpr (KEEP) twv = twk.v[q];
         else twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
-        lds[lp(rs * L2 + n2)] = cmul(buf[(size_t)r * L2 + n2], twv);
+        lds[lp(rs * L2 + n2)] = cmul((rs ? rowb : rowa)[n2], twv);
       }
     } else {
       for (int e = tid; e < 2 * L2; e += NT) {
@@ -426,42 +432,21 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
     ct_fft<T, false, NT, LOGL2, 1, false, LOGE>(lds, tw);
   }
 
-  // Makhoul twiddles for item t = tid + NT qi (rows w >= 1): k = ra + L1 t, so
-  // W_4N^k = W_4N^{ra + L1 tid} W_4N^{L1 NT qi}, and W_4N^{4k} likewise.
-  Cx<T> kb1 = cx((T)1, (T)0), kb4 = cx((T)1, (T)0);
-  const bool fast_items = SPLIT && w > 0;
-  if (fast_items) {
-    const uint32_t k0 = (uint32_t)ra + (uint32_t)L1 * (uint32_t)tid;
-    kb1 = tw4n<T>(p, k0);
-    kb4 = tw4n<T>(p, 4u * k0);
-  }
-
+  // One item: self slot (LDS sa, freq-layout fa, bin k) and its partner
+  // (sb, fb, bin L - k).  Returns after the store in the forward-only modes.
   double acc = 0.0;
-  const int nitems = (w > 0) ? L2 : (L2 + 1);
-  int qi = 0;
-  for (int t = tid; t < nitems; t += NT, ++qi) {
-    const RowItem it = row_item(t, w, ra, rb, L1, L2);
-    const int sa = lp(it.sa), sb = lp(it.sb);
+  auto item = [&](auto md_tag, int sa, int sb, uint32_t fa, uint32_t fb, bool zero, bool self, Cx<T> wk,
+                  Cx<T> WN) {
+    constexpr int MD = decltype(md_tag)::value;   // the mode when fixed at compile time, else -1
+    const int mode = MD >= 0 ? MD : mode_rt;
     T xa0, xa1, xb0, xb1;   // X_k, X_{N-k} (self slot) and X_{L-k}, X_{L+k} (partner slot)
-    Cx<T> wk = cx((T)1, (T)0), WN = cx((T)1, (T)0);
-    if (!it.zero) {
-      if (fast_items) {
-        const uint32_t st = (uint32_t)L1 * (uint32_t)NT * (uint32_t)qi;
-        wk = cmul(kb1, tw4n<T>(p, st));
-        WN = cmul(kb4, tw4n<T>(p, 4u * st));
-      } else {
-        wk = tw4n<T>(p, (uint32_t)it.k);
-        WN = tw4n<T>(p, (uint32_t)(4 * it.k));
-      }
-      if (p.fourier) wk = cx((T)1, (T)0);   // the real Fourier basis: no Makhoul rotation
-    }
     // the DCT scale c and the halves of E and O folded into the two rotations:
     // wkc = (c/2) wk, wmc = (c/2) e^{-i pi/4} conj(wk) (the partner's)
     const Cx<T> wkc = scale(wk, hc);
     const Cx<T> wmc = p.fourier ? cx(hc, (T)0) : cx(h * (wkc.re - wkc.im), -h * (wkc.re + wkc.im));
     if (mode != ROW_ADJ) {
       const Cx<T> Zk = lds[sa];
-      if (it.zero) {
+      if (zero) {
         xa0 = (Zk.re + Zk.im) * rsn;
         xa1 = (Zk.re - Zk.im) * rsn;
         xb0 = xb1 = (T)0;
@@ -476,18 +461,18 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         xb0 = b.re; xb1 = -b.im;
       }
     } else {
-      xa0 = fin[2 * it.fa]; xa1 = fin[2 * it.fa + 1];
-      xb0 = fin[2 * it.fb]; xb1 = fin[2 * it.fb + 1];
+      xa0 = fin[2u * fa]; xa1 = fin[2u * fa + 1u];
+      xb0 = fin[2u * fb]; xb1 = fin[2u * fb + 1u];
     }
     if (mode != ROW_ADJ) {
       const bool all = mode == ROW_FWD_ALL;
-      const uint32_t ma = all ? 3u : mask2(p.mask, it.fa);
-      const uint32_t mb = it.zero ? 0u : (all ? 3u : mask2(p.mask, it.fb));
+      const uint32_t ma = all ? 3u : mask2(p.mask, fa);
+      const uint32_t mb = zero ? 0u : (all ? 3u : mask2(p.mask, fb));
       if (mode == ROW_RESID) {
-        xa0 = fin[2 * it.fa] - xa0;
-        xa1 = fin[2 * it.fa + 1] - xa1;
-        xb0 = it.zero ? (T)0 : fin[2 * it.fb] - xb0;
-        xb1 = it.zero ? (T)0 : fin[2 * it.fb + 1] - xb1;
+        xa0 = fin[2u * fa] - xa0;
+        xa1 = fin[2u * fa + 1u] - xa1;
+        xb0 = zero ? (T)0 : fin[2u * fb] - xb0;
+        xb1 = zero ? (T)0 : fin[2u * fb + 1u] - xb1;
       }
       xa0 = (ma & 1u) ? xa0 : (T)0;
       xa1 = (ma & 2u) ? xa1 : (T)0;
@@ -495,18 +480,17 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       xb1 = (mb & 2u) ? xb1 : (T)0;
       if (mode == ROW_RESID) {
         // a self-paired bin (k = L/2) has fa == fb: count its two outputs once
-        const bool self = (!it.zero) && (it.fa == it.fb);
         acc += (double)xa0 * xa0 + (double)xa1 * xa1;
         if (!self) acc += (double)xb0 * xb0 + (double)xb1 * xb1;
       }
       if (mode == ROW_FWD || all) {
-        fout[2 * it.fa] = xa0; fout[2 * it.fa + 1] = xa1;
-        if (!it.zero) { fout[2 * it.fb] = xb0; fout[2 * it.fb + 1] = xb1; }
-        continue;
+        fout[2u * fa] = xa0; fout[2u * fa + 1u] = xa1;
+        if (!zero) { fout[2u * fb] = xb0; fout[2u * fb + 1u] = xb1; }
+        return;
       }
     }
     // pre-process for the inverse
-    if (it.zero) {
+    if (zero) {
       lds[sa] = cx((xa0 + xa1) * rsn, (xa0 - xa1) * rsn);
     } else {
       const Cx<T> Vk = cmulc(cx(xa0, -xa1), wkc);   // conj(wk) (Xk - i X_{N-k}) c / 2
@@ -515,6 +499,49 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       const Cx<T> O = cmulc(Vk - conj(Vm), WN);
       lds[sa] = cx(E.re - O.im, E.im + O.re);               // E + i O
       lds[sb] = cx(E.re + O.im, -E.im + O.re);              // conj(E) + i conj(O)
+    }
+  };
+
+  if (SPLIT && w > 0) {
+    // Rows w >= 1, threads tiling the row: item t = tid + NT qi pairs (ra, t)
+    // with (rb, L2-1-t), bin k = ra + L1 t.  Its Makhoul twiddles are
+    // W_4N^k = W_4N^{ra + L1 tid} W_4N^{L1 NT qi} and W_4N^{4k} likewise; the
+    // second factors are the same for every workgroup (p.tw_step).  The two
+    // modes of the CG and greedy loops get the item code with the mode fixed.
+    constexpr int PER_ITEM = SPLIT ? L2 / NT : 1;
+    const uint32_t k0 = (uint32_t)ra + (uint32_t)L1 * (uint32_t)tid;
+    const Cx<T> kb1 = tw4n<T>(p, k0), kb4 = tw4n<T>(p, 4u * k0);
+    const Cx<T>* __restrict__ step = (const Cx<T>*)p.tw_step;
+    const uint32_t fa0 = (uint32_t)ra * L2 + (uint32_t)tid;
+    const uint32_t fb0 = (uint32_t)rb * L2 + (uint32_t)(L2 - 1 - tid);
+    auto items = [&](auto md_tag) {
+#pragma unroll 1
+      for (int qi = 0; qi < PER_ITEM; ++qi) {
+        Cx<T> wk = qi ? cmul(kb1, step[qi]) : kb1;
+        const Cx<T> WN = qi ? cmul(kb4, step[kTwStepHalf + qi]) : kb4;
+        if (p.fourier) wk = cx((T)1, (T)0);   // the real Fourier basis: no Makhoul rotation
+        // LDS slots t and 2 L2 - 1 - t; NT qi is a multiple of 16, so the padded
+        // index is a per-thread base plus an immediate
+        const int dq = NT * qi + ((NT * qi) >> 4);
+        item(md_tag, lp(tid) + dq, lp(2 * L2 - 1 - tid) - dq, fa0 + (uint32_t)(NT * qi),
+             fb0 - (uint32_t)(NT * qi), false, false, wk, WN);
+      }
+    };
+    if (mode_rt == ROW_HAPPLY) items(std::integral_constant<int, ROW_HAPPLY>{});
+    else if (mode_rt == ROW_RESID) items(std::integral_constant<int, ROW_RESID>{});
+    else items(std::integral_constant<int, -1>{});
+  } else {
+    const int nitems = (w > 0) ? L2 : (L2 + 1);
+    for (int t = tid; t < nitems; t += NT) {
+      const RowItem it = row_item(t, w, ra, rb, L1, L2);
+      Cx<T> wk = cx((T)1, (T)0), WN = cx((T)1, (T)0);
+      if (!it.zero) {
+        wk = tw4n<T>(p, (uint32_t)it.k);
+        WN = tw4n<T>(p, (uint32_t)(4 * it.k));
+        if (p.fourier) wk = cx((T)1, (T)0);
+      }
+      item(std::integral_constant<int, -1>{}, lp(it.sa), lp(it.sb), (uint32_t)it.fa, (uint32_t)it.fb, it.zero,
+           !it.zero && it.fa == it.fb, wk, WN);
     }
   }
   if (mode == ROW_RESID) {
@@ -541,7 +568,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       Cx<T> twv;
       if constexpr (KEEP) twv = twk.v[q];
       else twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
-      buf[(size_t)r * L2 + n2] = cmulc(lds[lp(rs * L2 + n2)], twv);
+      (rs ? rowb : rowa)[(uint32_t)n2] = cmulc(lds[lp(rs * L2 + n2)], twv);
     }
   } else {
     for (int e = tid; e < 2 * L2; e += NT) {

@@ -213,6 +213,12 @@ void setup_operator(Ctx<T>& c) {
   const int64_t nhi = std::max<int64_t>(1, n4 / kTwLo);
   hipLaunchKernelGGL(k_twiddle<T>, dim3(nblk(nhi, 256)), dim3(256), 0, s, c.tw_hi, nhi, n4, (int64_t)kTwLo);
   CS_LAUNCH_CHECK();
+  const int64_t st = (int64_t)p.L1 * p.nt_row;   // the row pass's item stride in bins
+  hipLaunchKernelGGL(k_twiddle<T>, dim3(1), dim3(kTwStepHalf), 0, s, c.tw_step, (int64_t)kTwStepHalf, n4, st);
+  CS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_twiddle<T>, dim3(1), dim3(kTwStepHalf), 0, s, c.tw_step + kTwStepHalf, (int64_t)kTwStepHalf,
+                     n4, 4 * st);
+  CS_LAUNCH_CHECK();
   fill_u32(c.mask, p.words, 0u, s);
   fill<int32_t>(c.ibuf, 1, 0, s);
   hipLaunchKernelGGL(k_mask_from_rows, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, p, c.mask, c.ibuf);

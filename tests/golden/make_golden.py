@@ -2,6 +2,7 @@
 
     python tests/golden/make_golden.py sp_ompr_n2p20      # SP and OMPR, N = 2^20
     python tests/golden/make_golden.py sp_n2p24           # SP, N = 2^24 (noiseless)
+    python tests/golden/make_golden.py sp_ompr_n2p20:3:sp # signal 3, SP only
     python tests/golden/make_golden.py ompr_batched_256 6 # batched OMPR, 256 signals, 6 processes
 
 Each file holds the measurements the GPU consumes (float32 y, from the
@@ -38,12 +39,31 @@ def measurements(name: str, sig: int = 0):
     return w, d, op, y32
 
 
-def run(name: str, sig: int = 0, store_y: bool = True):
+def count_transforms(op):
+    """Counts the N-point transforms the oracle operator runs (wraps its F, F^T)."""
+    box = [0]
+    f, ft = op._F, op._Ft
+
+    def cf(v):
+        box[0] += 1
+        return f(v)
+
+    def cft(w):
+        box[0] += 1
+        return ft(w)
+
+    op._F, op._Ft = cf, cft
+    return box
+
+
+def run(name: str, sig: int = 0, store_y: bool = True, algos=None):
     w, d, op, y32 = measurements(name, sig)
     y = y32.astype(np.float64)
     out = {"y": y32} if store_y else {}
     meta = {"workload": name, "sig": sig, "n": d.n, "m": d.m, "k": d.k}
-    for algo in w["algos"]:
+    counter = count_transforms(op)
+    for algo in (algos or w["algos"]):
+        counter[0] = 0
         t = time.perf_counter()
         r = getattr(oracle, algo)(op, y, d.k)
         dt = time.perf_counter() - t
@@ -52,7 +72,7 @@ def run(name: str, sig: int = 0, store_y: bool = True):
         out[f"{algo}_values"] = r.s[r.support]
         meta[algo] = {"stop": r.stop, "iters": int(r.iters), "resid_norm": r.resid_norm,
                       "min_margin": float(min(margins)) if margins else None, "seconds": dt,
-                      "true_support_match": bool(np.array_equal(r.support, d.supp))}
+                      "transforms": int(counter[0]), "true_support_match": bool(np.array_equal(r.support, d.supp))}
         print(name, algo, meta[algo], flush=True)
     path = os.path.join(OUT, f"{name}_sig{sig}.npz")
     np.savez_compressed(path, meta=json.dumps(meta), **out)
@@ -133,6 +153,10 @@ if __name__ == "__main__":
         run_batched(256, 4, int(sys.argv[2]) if len(sys.argv) > 2 else 6)
         sys.exit(0)
     # y is stored for workloads small enough to keep in the repository (N <= 2^20);
-    # larger ones recompute it with the oracle (measurements()).
-    for nm in sys.argv[1:]:
-        run(nm, store_y=synth.WORKLOADS[nm]["n"] <= 2 ** 20)
+    # larger ones recompute it with the oracle (measurements()).  NAME[:SIG[:ALGO]]
+    # picks a signal other than 0 and one of the workload's algorithms.
+    for arg in sys.argv[1:]:
+        parts = arg.split(":")
+        nm = parts[0]
+        sg = int(parts[1]) if len(parts) > 1 else 0
+        run(nm, sg, store_y=synth.WORKLOADS[nm]["n"] <= 2 ** 20, algos=parts[2:3] or None)
