@@ -409,8 +409,10 @@ def batched_leg(torch, cs, count: int, loop_single: bool) -> dict:
 
 def adjoint_leg(torch, cs, batch: int, reps: int = 3, check: int = 4) -> dict:
     """Differentiated SP on the 64-signal workload (N = 2^16, M = 2^14, K = 300):
-    forward recovery, and forward + backward of L = sum_b ||s_b - t_b||^2 with
-    respect to y through the adjoint CG, beside the forward alone.  The first
+    forward recovery of the batch through cs_recover_sp_batched, and forward +
+    backward of L = sum_b ||s_b - t_b||^2 with respect to y through the adjoint
+    CG, beside the forward alone and beside the single-signal call looped over
+    the batch.  The first
     `check` signals are checked against the oracle: its SP support and
     coefficients, and its dense gradient on that support."""
     import oracle
@@ -429,29 +431,33 @@ def adjoint_leg(torch, cs, batch: int, reps: int = 3, check: int = 4) -> dict:
         draws.append(d)
     k, tol = w["k"], w["tol"]
 
-    def fwd():
+    bt = cs.Batch(ys, ops, [k] * batch, algo=cs.CS_ALGO_SP)
+
+    def fwd_loop():
         return [cs.SPRecover.apply(ys[b], ops[b], k, tol)[0] for b in range(batch)]
+
+    def fwd():
+        return cs.cs_recover_sp_batched(bt, tol)
 
     def fwd_bwd():
         yl = [y.detach().requires_grad_(True) for y in ys]
-        outs = [cs.SPRecover.apply(yl[b], ops[b], k, tol) for b in range(batch)]
-        loss = sum(((o[0] - ts[b]) ** 2).sum() for b, o in enumerate(outs))
+        s, supp = cs.SPRecoverBatched.apply(yl, ops, k, tol, batch=bt)
+        loss = sum(((s[b] - ts[b]) ** 2).sum() for b in range(batch))
         loss.backward()
-        return yl, outs
+        return yl, list(zip(s, supp))
 
-    fwd()
-    fwd_bwd()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        fwd()
-    torch.cuda.synchronize()
-    tf = (time.perf_counter() - t0) / reps
-    t1 = time.perf_counter()
-    for _ in range(reps):
-        yl, outs = fwd_bwd()
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t1) / reps
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    tl, _ = timed(fwd_loop)
+    tf, _ = timed(fwd)
+    tb, (yl, outs) = timed(fwd_bwd)
     supp_ok, s_err, g_err = 0, 0.0, 0.0
     for b in range(min(check, batch)):
         ref = oracle.sp(oops[b], y64s[b], k)
@@ -466,6 +472,7 @@ def adjoint_leg(torch, cs, batch: int, reps: int = 3, check: int = 4) -> dict:
     return {"batch": batch, "forward_s": round(tf, 4), "forward_backward_s": round(tb, 4),
             "forward_signals_per_s": round(batch / tf, 1), "forward_backward_signals_per_s": round(batch / tb, 1),
             "backward_over_forward": round((tb - tf) / tf, 3),
+            "forward_single_call_loop_s": round(tl, 4), "batched_forward_speedup": round(tl / tf, 2),
             "checked_signals": min(check, batch), "support_matches_oracle": supp_ok,
             "max_rel_err_s": s_err, "max_rel_err_grad_vs_oracle_dense": g_err}
 

@@ -88,7 +88,11 @@ enum {
   CS_F_CG_MAXITER = 1,     /* a CG solve hit its iteration cap before the tolerance   */
   CS_F_CG_BREAKDOWN = 2,   /* d^T H d <= 0 or not finite (rank-deficient A_S, Thm. 3) */
   CS_F_OUTER_MAXITER = 4,  /* SP/OMPR stopped at max_outer                            */
-  CS_F_NONFINITE = 8       /* a non-finite value reached a selection or a norm        */
+  CS_F_NONFINITE = 8,      /* a non-finite value reached a selection or a norm        */
+  CS_F_NEAR_TIE = 16       /* some selection's margin (cs_info.min_margin) was within
+                              4 (tol + u log2 N) of its chosen key (u the unit roundoff
+                              of the working precision): a different but equally
+                              valid trajectory was within the keys' resolution     */
 };
 
 /* Sensing operator A = Phi Psi with Phi = D F R (Eq. (7)): D keeps rows, F
@@ -140,6 +144,13 @@ typedef struct {
   int64_t transforms;     /* N-point transforms applied (forward + inverse)         */
   double resid_norm;      /* ||y - A s|| of the returned s (FP64 accumulation)      */
   double model_bytes;     /* algorithmic HBM bytes of the transform passes          */
+  double min_margin;      /* smallest decision margin of the call, in the working
+                             precision: over every selection (argmax, top-K, OMPR
+                             drop) the key of the last chosen candidate minus the
+                             key of the first rejected one (a lower bound of it
+                             where a top-K's rejected keys were not all seen);
+                             0 for a tie broken by index; -1 with no selection
+                             (cs_ls_solve, cs_adjoint_ls)                          */
 } cs_info;
 
 /* Workspace bytes needed by one call of `algo` at these sizes (0 if invalid).
@@ -272,6 +283,28 @@ typedef struct {
 } cs_batch_item;
 
 size_t cs_workspace_size_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, cs_algo algo);
+
+/*
+ * cs_recover_sp_batched: Subspace Pursuit (as cs_recover_sp) on `count`
+ * independent signals in one call, for example the forward of a batch being
+ * differentiated.  Each signal runs the single-signal driver on its own slice
+ * of the workspace (cs_workspace_size_batched(..., CS_ALGO_SP); operators may
+ * use any psi), with results identical to cs_recover_sp on that signal; the
+ * signals run concurrently on a pool of host threads, each with its own HIP
+ * stream (default priority), that the library creates on the first batched
+ * call on a device and keeps until the process ends.  Work queued on `stream`
+ * before the call completes before any signal starts; the call returns with
+ * every output complete and does not use `stream` afterwards.  The moves
+ * fields of the items are ignored.  Not capturable in a HIP graph: the SP
+ * loop decides on the host between steps (support repeated, residual grown),
+ * reading small device words, as the single-signal call does.  A failing
+ * signal makes the call return its status (text: cs_last_error()), other
+ * signals' outputs complete.
+ */
+cs_status cs_recover_sp_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, double tol,
+                                const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                                hipStream_t stream);
+
 cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, double tol,
                                   const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
                                   hipStream_t stream);

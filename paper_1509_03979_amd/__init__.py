@@ -22,14 +22,15 @@ LIB_PATH = os.path.join(HERE, "libcsrecover.so")
 CS_F32, CS_F64 = 0, 1
 CS_ALGO_OMP, CS_ALGO_SP, CS_ALGO_OMPR, CS_ALGO_OPERATOR, CS_ALGO_LS, CS_ALGO_COSAMP = 0, 1, 2, 3, 4, 5
 CS_OK, CS_E_INVALID, CS_E_SHAPE, CS_E_OP, CS_E_WORKSPACE, CS_E_HIP = 0, -1, -2, -3, -4, -5
-CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE = 1, 2, 4, 8
+CS_F_CG_MAXITER, CS_F_CG_BREAKDOWN, CS_F_OUTER_MAXITER, CS_F_NONFINITE, CS_F_NEAR_TIE = 1, 2, 4, 8, 16
 
 CS_STATIC_WS_BYTES = 64 << 20
 
 EXPORTS = ("cs_workspace_size", "cs_workspace_size_op", "cs_recover_omp", "cs_recover_sp", "cs_recover_ompr", "cs_recover_cosamp",
            "cs_recover_sp_static",
            "cs_ls_solve",
-           "cs_adjoint_ls", "cs_workspace_size_batched", "cs_recover_ompr_batched", "cs_apply_A", "cs_apply_At",
+           "cs_adjoint_ls", "cs_workspace_size_batched", "cs_recover_ompr_batched", "cs_recover_sp_batched",
+           "cs_apply_A", "cs_apply_At",
            "cs_shape_candidates", "cs_set_shape", "cs_time_shape", "cs_status_str", "cs_last_error",
            "cs_prof_enable", "cs_prof_reset", "cs_prof_read")
 
@@ -49,7 +50,7 @@ class cs_params(ctypes.Structure):
 class cs_info(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int32), ("flags", ctypes.c_int32), ("cg_iters", ctypes.c_int64),
                 ("transforms", ctypes.c_int64), ("resid_norm", ctypes.c_double),
-                ("model_bytes", ctypes.c_double)]
+                ("model_bytes", ctypes.c_double), ("min_margin", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -108,6 +109,9 @@ def _load():
     lib.cs_recover_ompr_batched.argtypes = [ctypes.c_int, i32, P(cs_batch_item), dbl, P(cs_params), vp, sz,
                                             P(cs_info), vp]
     lib.cs_recover_ompr_batched.restype = ctypes.c_int
+    lib.cs_recover_sp_batched.argtypes = [ctypes.c_int, i32, P(cs_batch_item), dbl, P(cs_params), vp, sz,
+                                          P(cs_info), vp]
+    lib.cs_recover_sp_batched.restype = ctypes.c_int
     for name in ("cs_apply_A", "cs_apply_At"):
         f = getattr(lib, name)
         f.argtypes = [ctypes.c_int, P(cs_op), vp, vp, vp, sz, vp]
@@ -352,17 +356,35 @@ def cs_adjoint_ls(grad_s, op: Operator, support, tol: float, ws=None, stream=Non
     return grad_y, info.as_dict()
 
 
+def _flag_check(info: dict, what: str):
+    """Errors for results that cannot be trusted, warnings for capped iterations."""
+    f = info["flags"]
+    if f & (CS_F_NONFINITE | CS_F_CG_BREAKDOWN):
+        raise CSError(CS_E_HIP if f & CS_F_NONFINITE else CS_E_INVALID,
+                      f"{what}: " + ("a non-finite value" if f & CS_F_NONFINITE else
+                                     "CG breakdown (d^T H d <= 0: the support's columns are dependent)"))
+    if f & (CS_F_CG_MAXITER | CS_F_OUTER_MAXITER):
+        import warnings
+        warnings.warn(f"{what}: an iteration cap was reached (flags {f})", RuntimeWarning, stacklevel=3)
+
+
 def _recover_fn(name: str):
     import torch
 
     fwd = {"omp": cs_recover_omp, "sp": cs_recover_sp, "ompr": cs_recover_ompr}[name]
 
     class _Recover(torch.autograd.Function):
-        """s = recover(y); the backward is cs_adjoint_ls on the frozen final support."""
+        """s = recover(y); the backward is cs_adjoint_ls on the frozen final support.
+        The forward's and the backward's cs_info are kept on the function's
+        context (``info_fwd``, ``info_bwd``); a non-finite value or a CG
+        breakdown (Theorem 3's condition failing) raises, an iteration cap
+        warns."""
 
         @staticmethod
         def forward(ctx, y, op, k, tol, adj_tol=None):
-            s, supp, _ = fwd(y, op, k, tol)
+            s, supp, info = fwd(y, op, k, tol)
+            _flag_check(info, name + " forward")
+            ctx.info_fwd = info
             ctx.save_for_backward(supp)
             ctx.op = op
             ctx.tol = tol if adj_tol is None else adj_tol
@@ -372,7 +394,9 @@ def _recover_fn(name: str):
         @staticmethod
         def backward(ctx, grad_s, grad_supp):
             (supp,) = ctx.saved_tensors
-            grad_y, _ = cs_adjoint_ls(grad_s, ctx.op, supp, ctx.tol)
+            grad_y, info = cs_adjoint_ls(grad_s, ctx.op, supp, ctx.tol)
+            _flag_check(info, name + " backward")
+            ctx.info_bwd = info
             return grad_y, None, None, None, None
 
     _Recover.__name__ = name.upper() + "Recover"
@@ -398,10 +422,12 @@ class Batch:
     """Outputs, descriptors and workspace of one batched call, reusable across
     calls with the same signals (the measurements may change in place)."""
 
-    def __init__(self, ys, ops, ks, device=None, moves_cap: int = 0):
-        """moves_cap > 0 records each signal's first moves_cap swaps in
-        self.moves[i] (int32 [moves_cap, 2]: entered, left; rows past the
-        signal's swap count are left at -1)."""
+    def __init__(self, ys, ops, ks, device=None, moves_cap: int = 0, algo: int = CS_ALGO_OMPR):
+        """algo: CS_ALGO_OMPR (cs_recover_ompr_batched) or CS_ALGO_SP
+        (cs_recover_sp_batched); it sizes the workspace.  moves_cap > 0
+        records each OMPR signal's first moves_cap swaps in self.moves[i]
+        (int32 [moves_cap, 2]: entered, left; rows past the signal's swap
+        count are left at -1)."""
         torch = _torch()
         if not (len(ys) == len(ops) == len(ks)) or len(ys) == 0:
             raise ValueError("ys, ops and ks must be non-empty and of equal length")
@@ -430,7 +456,8 @@ class Batch:
             if self.moves is not None:
                 it.moves_cap = int(moves_cap)
                 it.moves = _ptr(self.moves[i])
-        nbytes = lib.cs_workspace_size_batched(self.dt, n, self.items, CS_ALGO_OMPR)
+        self.algo = algo
+        nbytes = lib.cs_workspace_size_batched(self.dt, n, self.items, algo)
         if nbytes == 0:
             raise CSError(CS_E_SHAPE, "no batched workspace size for these signals")
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -445,6 +472,64 @@ def cs_recover_ompr_batched(batch: "Batch", tol: float, stream=None, **kw):
                                      batch.ws.numel(), infos, _stream_ptr(stream))
     _check(st)
     return batch.s, batch.supp, [infos[i].as_dict() for i in range(n)]
+
+
+def cs_recover_sp_batched(batch: "Batch", tol: float, stream=None, **kw):
+    """SP on every signal of `batch` (built with algo=CS_ALGO_SP) in one call,
+    the signals run concurrently -> (s list, support list, info list)."""
+    if batch.algo != CS_ALGO_SP:
+        raise ValueError("the batch's workspace was sized for another algorithm (use algo=CS_ALGO_SP)")
+    n = len(batch.ys)
+    infos = (cs_info * n)()
+    prm = _params(**kw)
+    st = lib.cs_recover_sp_batched(batch.dt, n, batch.items, float(tol), ctypes.byref(prm), _ptr(batch.ws),
+                                   batch.ws.numel(), infos, _stream_ptr(stream))
+    _check(st)
+    return batch.s, batch.supp, [infos[i].as_dict() for i in range(n)]
+
+
+class SPRecoverBatched:
+    """s_b = SP(y_b) for a list of signals through one cs_recover_sp_batched
+    call; differentiable with respect to every y_b (the backward is
+    cs_adjoint_ls on each frozen final support).  Reuses the Batch's output
+    tensors, so the returned s are views the next call overwrites unless the
+    caller clones them."""
+
+    @staticmethod
+    def apply(ys, ops, k, tol, batch: "Batch" = None, adj_tol=None):
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, *yv):
+                b = batch if batch is not None else Batch(list(yv), ops, [k] * len(yv), algo=CS_ALGO_SP)
+                for i, y in enumerate(yv):
+                    if b.ys[i].data_ptr() != y.data_ptr():
+                        b.ys[i].copy_(y)
+                s, supp, infos = cs_recover_sp_batched(b, tol)
+                for info in infos:
+                    _flag_check(info, "SP batched forward")
+                ctx.supps = [p.clone() for p in supp]
+                ctx.mark_non_differentiable(*ctx.supps)
+                return tuple(x.clone() for x in s) + tuple(ctx.supps)
+
+            @staticmethod
+            def backward(ctx, *grads):
+                n = len(ctx.supps)
+                out = []
+                for i in range(n):
+                    g = grads[i]
+                    if g is None:
+                        out.append(None)
+                        continue
+                    gy, info = cs_adjoint_ls(g, ops[i], ctx.supps[i], tol if adj_tol is None else adj_tol)
+                    _flag_check(info, "SP batched backward")
+                    out.append(gy)
+                return tuple(out)
+
+        res = _Fn.apply(*ys)
+        n = len(ys)
+        return list(res[:n]), list(res[n:])
 
 
 def cs_shape_candidates(dtype_code: int, n: int) -> list:

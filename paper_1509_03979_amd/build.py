@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcsrecover.so")
 SOURCES = ["cs_inst_f32.hip", "cs_inst_f64.hip", "cs_transform.hip", "cs_select.hip", "cs_cg.hip", "cs_greedy.hip",
            "cs_dct2d.hip",
-           "cs_api.hip", "cs_prof.hip", "cs_batch.hip"]
+           "cs_api.hip", "cs_prof.hip", "cs_batch.hip", "cs_pool.hip"]
 ARCH = os.environ.get("CS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

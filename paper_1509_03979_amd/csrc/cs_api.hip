@@ -67,7 +67,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0)
   c.partial = cv.take<double>(4 * kRedBlocks);
   c.partial2 = cv.take<double>(rows);
   c.pgrid = cv.take<double>(4 * strips);   // fused CG step: four partials per strip
-  c.argpart = cv.take<ArgKey>(kArgBlocks);
+  c.argpart = cv.take<ArgKey>(2 * kArgBlocks);   // best two per workgroup
   const SplitLayout sl = split_layout(n);
   c.rkey = cv.take<T>((int64_t)sl.blocks * sl.cap);
   c.rpos = cv.take<uint32_t>((int64_t)sl.blocks * sl.cap);
@@ -202,12 +202,24 @@ static void fill_info(Ctx<T>& c, cs_info* info) {
   info->model_bytes = c.model_bytes;
 }
 
+// The call's smallest decision margin into cs_info, and CS_F_NEAR_TIE (an
+// absolute CG tolerance enters scaled by 1/||y||).
+template <typename T>
+static void read_margins(Ctx<T>& c, double tol, cs_info* info) {
+  double mm = 0.0, mr = 0.0;
+  margins_read<T>(c, &mm, &mr);
+  const double trel = c.tol_abs ? tol / std::max(c.ynorm, 1e-300) : tol;
+  if (near_tie(mr, trel, sizeof(T) == 4, c.plan.logn)) c.flags |= CS_F_NEAR_TIE;
+  info->min_margin = std::isfinite(mm) ? mm : -1.0;
+}
+
 template <typename T>
 static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, double tol, void* s, int32_t* support,
                       const cs_params* params, void* ws, size_t ws_bytes, cs_info* info, hipStream_t stream) {
   Ctx<T> c{};
   ctx_init<T>(c, op, kmax_for(algo, k), ws, ws_bytes, stream);
   setup_operator<T>(c);
+  margins_reset<T>(c);
   load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
   c.tol_abs = prm.tol_abs != 0;
@@ -218,9 +230,18 @@ static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, d
   else if (algo == CS_ALGO_SP) run_sp<T>(c, k, tol, prm, (T*)s, support, inf);
   else if (algo == CS_ALGO_COSAMP) run_cosamp<T>(c, k, tol, prm, (T*)s, support, inf);
   else run_ompr<T>(c, k, tol, prm, (T*)s, support, inf);
+  read_margins<T>(c, tol, inf);
   CS_HIP(hipStreamSynchronize(stream));
   if (prof_on()) prof_flush();
   fill_info<T>(c, inf);
+}
+
+// One recovery of a batch (run by a pool worker on its own stream).
+static void recover_one(cs_algo algo, cs_dtype dt, const void* y, const cs_op* op, int32_t k, double tol, void* s,
+                        int32_t* support, const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                        hipStream_t stream) {
+  if (dt == CS_F32) recover_t<float>(algo, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
+  else recover_t<double>(algo, y, op, k, tol, s, support, params, ws, ws_bytes, info, stream);
 }
 
 static cs_status recover(cs_algo algo, cs_dtype dt, const void* y, const cs_op* op, int32_t k, double tol, void* s,
@@ -327,6 +348,7 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   if (info) {
     std::memset(info, 0, sizeof(cs_info));
     info->resid_norm = rn;
+    info->min_margin = -1.0;   // no selection
     fill_info<T>(c, info);
   }
 }
@@ -367,6 +389,7 @@ static void adj_t(const cs_op* op, const int32_t* support, int32_t k, const void
   if (prof_on()) prof_flush();
   if (info) {
     std::memset(info, 0, sizeof(cs_info));
+    info->min_margin = -1.0;   // no selection
     fill_info<T>(c, info);
   }
 }
@@ -583,12 +606,37 @@ cs_status cs_adjoint_ls(cs_dtype dtype, const cs_op* op, const int32_t* support,
 
 size_t cs_workspace_size_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, cs_algo algo) {
   if (dtype != CS_F32 && dtype != CS_F64) return 0;
-  if (count < 1 || !items || algo != CS_ALGO_OMPR) return 0;
+  if (count < 1 || !items || (algo != CS_ALGO_OMPR && algo != CS_ALGO_SP)) return 0;
   for (int i = 0; i < count; ++i) {
     const cs_op& o = items[i].op;
-    if (o.psi != 0 || cs_workspace_size(dtype, o.n, o.m, items[i].k, algo) == 0) return 0;
+    if (algo == CS_ALGO_OMPR && o.psi != 0) return 0;
+    if (algo == CS_ALGO_SP && (int64_t)2 * items[i].k > o.m) return 0;
+    if (cs_workspace_size_op(dtype, &o, items[i].k, algo) == 0) return 0;
   }
-  return batch_layout(dtype, count, items, nullptr);
+  return algo == CS_ALGO_OMPR ? batch_layout(dtype, count, items, nullptr)
+                              : batch_layout_algo(dtype, count, items, algo, nullptr);
+}
+
+cs_status cs_recover_sp_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, double tol,
+                                const cs_params* params, void* ws, size_t ws_bytes, cs_info* info,
+                                hipStream_t stream) {
+  try {
+    if (count < 1 || !items) throw Error(CS_E_INVALID, "count must be >= 1 with a non-null item array");
+    for (int i = 0; i < count; ++i) {
+      check_shape(dtype, &items[i].op, items[i].k, CS_ALGO_SP);
+      if (!items[i].y || !items[i].s || !items[i].support) throw Error(CS_E_INVALID, "null y, s or support in batch");
+    }
+    check_tol(tol);
+    check_ws(ws);
+    recover_batched_pool(CS_ALGO_SP, dtype, count, items, tol, params, ws, ws_bytes, info, stream, recover_one);
+    return CS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CS_E_HIP;
+  }
 }
 
 cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_item* items, double tol,

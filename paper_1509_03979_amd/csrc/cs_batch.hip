@@ -76,16 +76,18 @@ __global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __rest
   const int tid = threadIdx.x;
   const int nab = arg_blocks(p.n);
   if (phase == BP_RESID && (int)blockIdx.x < nab) {
-    ArgKey best{0, 0, 0};
+    K2 t;   // best and runner-up (the runner-up gives the decision's margin)
     const int64_t stp = (int64_t)nab * blockDim.x;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + tid; q < p.n; q += stp) {
       if (bit_of(s.bits, q)) continue;
       const int64_t j = nat_of_key(q, p);
-      ArgKey kk{mag_bits(s.Cc[q]) + 1, 0xFFFFFFFFu - (uint32_t)j, 0};
-      if (key_gt(kk, best)) best = kk;
+      t.add(mag_bits(s.Cc[q]) + 1, 0xFFFFFFFFu - (uint32_t)j);
     }
-    best = block_max_key(best);
-    if (tid == 0) s.argpart[blockIdx.x] = best;
+    block_max_key2(t);
+    if (tid == 0) {
+      s.argpart[2 * blockIdx.x] = t.best();
+      s.argpart[2 * blockIdx.x + 1] = t.second();
+    }
   }
   if (blockIdx.x != 0) return;
   CgScalars* cg = s.cg;
@@ -189,13 +191,19 @@ __global__ void k_b_select(const BSig<T>* __restrict__ sigs, const int32_t* __re
   __shared__ int32_t sj, sd, spd, spj;
   __shared__ int go;
   const int tid = threadIdx.x;
-  ArgKey best{0, 0, 0};
+  K2 t;
   const int nab = arg_blocks(s.plan.n);
-  for (int i = tid; i < nab; i += blockDim.x)
-    if (key_gt(s.argpart[i], best)) best = s.argpart[i];
-  best = block_max_key(best);
+  for (int i = tid; i < nab; i += blockDim.x) {
+    const ArgKey a = s.argpart[2 * i], b = s.argpart[2 * i + 1];
+    t.add(a.hi, a.lo, b.hi, b.lo);
+  }
+  block_max_key2(t);
   if (tid == 0) {
-    const int32_t j = best.hi ? (int32_t)(0xFFFFFFFFu - best.lo) : -1;
+    const int32_t j = t.bh ? (int32_t)(0xFFFFFFFFu - t.bl) : -1;
+    if (t.bh && t.sh && st->swaps < st->max_outer) {
+      const double vb = key_value<T>(t.bh);
+      note_margin(&st->mmin, &st->mrel, vb - key_value<T>(t.sh), vb);
+    }
     go = 0;
     if (st->swaps >= st->max_outer) {
       st->flags |= CS_F_OUTER_MAXITER;
@@ -210,8 +218,10 @@ __global__ void k_b_select(const BSig<T>* __restrict__ sigs, const int32_t* __re
   __syncthreads();
   if (!go) return;
   const int cur = st->cur, nxt = cur ^ 1, k = st->k;
-  const int32_t d = ompr_drop_body<T>(s.cx[cur], s.list[cur], k, s.Cc, s.plan, (T)st->eta, sj);
+  double m = -1.0, mk = 0.0;
+  const int32_t d = ompr_drop_body<T>(s.cx[cur], s.list[cur], k, s.Cc, s.plan, (T)st->eta, sj, &m, &mk);
   if (tid == 0) {
+    note_margin(&st->mmin, &st->mrel, m, mk);
     sd = d;
     go = d != sj;
     st->jd[0] = sj;
@@ -368,6 +378,7 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
     ctx_init<T>(c, &it.op, it.k, base + offs[i], ws_bytes - offs[i], stream);
     setup_operator<T>(c);
     load_measurements<T>(c, (const T*)it.y);
+    margins_reset<T>(c);
     topk_dense<T>(c, c.C0, nullptr, it.k, c.bits[0]);
     bits_to_list<T>(c, c.bits[0], c.list[0], it.k, c.wpre[0]);
     BSig<T>& h = hs[i];
@@ -398,6 +409,8 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
     b.ynorm = c.ynorm;
     b.model_bytes = c.model_bytes;
     b.transforms = c.transforms;
+    b.mmin = __builtin_huge_val();   // the initial top-K's margin is in the signal's selection state
+    b.mrel = __builtin_huge_val();
   }
   // size classes: signals with the same N share the transform kernels
   std::map<int, int> cls_index;
@@ -515,6 +528,13 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
       inf.transforms = b.transforms;
       inf.resid_norm = b.rn;
       inf.model_bytes = b.model_bytes;
+      double mm = 0.0, mr = 0.0;
+      margins_read<T>(c, &mm, &mr);   // the initial top-K
+      mm = std::min(mm, b.mmin);
+      mr = std::min(mr, b.mrel);
+      const double trel = b.tol_abs ? tol / std::max(b.ynorm, 1e-300) : tol;
+      if (near_tie(mr, trel, sizeof(T) == 4, c.plan.logn)) inf.flags |= CS_F_NEAR_TIE;
+      inf.min_margin = std::isfinite(mm) ? mm : -1.0;
     }
   }
   CS_HIP(hipStreamSynchronize(stream));

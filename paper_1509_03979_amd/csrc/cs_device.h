@@ -48,6 +48,70 @@ __device__ __forceinline__ ArgKey block_max_key(ArgKey best) {
   return best;
 }
 
+// The best two (hi, lo) keys, held as scalars so they stay in registers (keys
+// are distinct: the index part differs).  K2::add merges the pair (oh, ol) >=
+// (o2h, o2l) into (best, second).
+__device__ __forceinline__ bool kgt(uint64_t ah, uint32_t al, uint64_t bh, uint32_t bl) {
+  return ah > bh || (ah == bh && al > bl);
+}
+struct K2 {
+  uint64_t bh = 0, sh = 0;
+  uint32_t bl = 0, sl = 0;
+  __device__ __forceinline__ void add(uint64_t oh, uint32_t ol, uint64_t o2h = 0, uint32_t o2l = 0) {
+    const bool gt = kgt(oh, ol, bh, bl);
+    // new second: max(old best, o2) when o wins, else max(old second, o)
+    const uint64_t ch = gt ? bh : sh, dh = gt ? o2h : oh;
+    const uint32_t cl = gt ? bl : sl, dl = gt ? o2l : ol;
+    const bool c = kgt(ch, cl, dh, dl);
+    sh = c ? ch : dh;
+    sl = c ? cl : dl;
+    bh = gt ? oh : bh;
+    bl = gt ? ol : bl;
+  }
+  __device__ __forceinline__ ArgKey best() const { return ArgKey{bh, bl, 0}; }
+  __device__ __forceinline__ ArgKey second() const { return ArgKey{sh, sl, 0}; }
+};
+
+// Block-wide best two (any block size up to 1024); valid in thread 0.
+__device__ __forceinline__ void block_max_key2(K2& t) {
+  __shared__ uint64_t sbh[16], ssh[16];
+  __shared__ uint32_t sbl[16], ssl[16];
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t oh = __shfl_down((unsigned long long)t.bh, off, 64);
+    const uint32_t ol = __shfl_down(t.bl, off, 64);
+    const uint64_t o2h = __shfl_down((unsigned long long)t.sh, off, 64);
+    const uint32_t o2l = __shfl_down(t.sl, off, 64);
+    t.add(oh, ol, o2h, o2l);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sbh[wave] = t.bh; sbl[wave] = t.bl;
+    ssh[wave] = t.sh; ssl[wave] = t.sl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) t.add(sbh[i], sbl[i], ssh[i], ssl[i]);
+  __syncthreads();
+}
+
+// Value of a magnitude key (bits(|v|) + 1, 0: none) in the precision of T.
+template <typename T> __device__ __forceinline__ double key_value(uint64_t key);
+template <> __device__ __forceinline__ double key_value<float>(uint64_t key) {
+  return key ? (double)__uint_as_float((uint32_t)(key - 1)) : 0.0;
+}
+template <> __device__ __forceinline__ double key_value<double>(uint64_t key) {
+  return key ? __longlong_as_double((long long)(key - 1)) : 0.0;
+}
+
+// Records a decision margin (gap between the last chosen and the first
+// rejected key) and its size relative to the chosen key (one thread).
+__device__ __forceinline__ void note_margin(double* mmin, double* mrel, double margin, double key) {
+  if (!(margin >= 0.0)) return;
+  if (margin < *mmin) *mmin = margin;
+  const double rel = key > 0.0 ? margin / key : (margin == 0.0 ? 0.0 : __builtin_huge_val());   // a tie is 0
+  if (rel < *mrel) *mrel = rel;
+}
+
 // Block sum in a fixed order, broadcast to every thread (any block size up to
 // 1024, a multiple of 64).
 __device__ __forceinline__ double block_sum_any(double v) {
@@ -78,13 +142,14 @@ __device__ __forceinline__ bool dkey_gt(uint64_t ah, uint32_t al, uint64_t bh, u
   return ah > bh || (ah == bh && al > bl);
 }
 
+// With margin/mkey non-null, thread 0 also stores the gap between the
+// smallest and the next smallest |z| (the drop decision's margin) and that
+// next smallest |z|.
 template <typename T>
 __device__ __forceinline__ int32_t ompr_drop_body(const T* __restrict__ x, const int32_t* __restrict__ list, int k,
-                                                  const T* __restrict__ cc, const Plan& pl, T eta, int32_t jn) {
-  __shared__ uint64_t sh_h[16];
-  __shared__ uint32_t sh_l[16];
-  uint64_t bh = 0;
-  uint32_t bl = 0;
+                                                  const T* __restrict__ cc, const Plan& pl, T eta, int32_t jn,
+                                                  double* margin = nullptr, double* mkey = nullptr) {
+  K2 t;   // best two of (~bits(|z|), index): the smallest |z|, then the next
   for (int i = threadIdx.x; i <= k; i += blockDim.x) {
     int64_t j, key;
     if (i < k) {
@@ -97,22 +162,22 @@ __device__ __forceinline__ int32_t ompr_drop_body(const T* __restrict__ x, const
     }
     const T cv = cc[key];   // sign_j (A^T r)_j
     const T z = (i < k) ? x[i] + eta * cv : eta * cv;
-    const uint64_t h = ~mag_bits(z);
-    const uint32_t l = (uint32_t)j;
-    if (dkey_gt(h, l, bh, bl)) { bh = h; bl = l; }
+    t.add(~mag_bits(z), (uint32_t)j);
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const uint64_t oh = __shfl_down((unsigned long long)bh, off, 64);
-    const uint32_t ol = __shfl_down(bl, off, 64);
-    if (dkey_gt(oh, ol, bh, bl)) { bh = oh; bl = ol; }
-  }
-  if ((threadIdx.x & 63) == 0) { sh_h[threadIdx.x >> 6] = bh; sh_l[threadIdx.x >> 6] = bl; }
-  __syncthreads();
+  block_max_key2(t);
+  __shared__ uint32_t s_drop;
   if (threadIdx.x == 0) {
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-      if (dkey_gt(sh_h[w], sh_l[w], bh, bl)) { bh = sh_h[w]; bl = sh_l[w]; }
+    s_drop = t.bl;
+    if (margin && t.sh != 0) {   // a second candidate exists (0 is never a real ~bits key)
+      const double zmin = key_value<T>(~t.bh + 1), z2 = key_value<T>(~t.sh + 1);
+      *margin = z2 - zmin;
+      *mkey = z2;
+    } else if (margin) {
+      *margin = -1.0;
+    }
   }
   __syncthreads();
+  const uint32_t bl = s_drop;
   return (int32_t)bl;
 }
 

@@ -199,12 +199,72 @@ __device__ __forceinline__ void ct_stage(Cx<T>* buf, const Cx<T>* __restrict__ t
   __syncthreads();
 }
 
-template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGE, int LOGNS = 0>
+template <typename T, bool INV, int NT, int LOGN, int LOGCNT, bool CM, int LOGE, int LOGNS = 0, int LOGEND = LOGN>
 __device__ __forceinline__ void ct_fft(Cx<T>* buf, const Cx<T>* __restrict__ tw) {
-  if constexpr (LOGNS < LOGN) {
+  if constexpr (LOGNS < LOGEND) {
     ct_stage<T, INV, NT, LOGN, LOGCNT, CM, LOGE, LOGNS>(buf, tw);
-    ct_fft<T, INV, NT, LOGN, LOGCNT, CM, LOGE, LOGNS + stage_lr(LOGN, LOGNS, LOGE)>(buf, tw);
+    ct_fft<T, INV, NT, LOGN, LOGCNT, CM, LOGE, LOGNS + stage_lr(LOGN, LOGNS, LOGE), LOGEND>(buf, tw);
   }
+}
+
+// Register-resident first and last stages, for row-major sets of FFTs where
+// every stage is radix R = 2^LOGE and each thread owns exactly one butterfly
+// per stage (NT butterflies: CNT N / R == NT).  Thread tid owns FFT
+// f = tid / (N/R) and butterfly j = tid mod (N/R); its first stage reads
+// elements j + r N/R (r < R) of FFT f, and its last stage produces elements
+// j + r N/R as well.  So the caller can load the input straight from global
+// memory into v[] (in that order) and store the output from v[], saving an
+// LDS round trip and a barrier at each end.
+template <int LOGN, int LOGCNT, int LOGE, int NT>
+struct RegIO {
+  static constexpr int R = 1 << LOGE;
+  static constexpr bool ok = (LOGN % LOGE == 0) && LOGN >= 2 * LOGE && ((1 << (LOGN + LOGCNT)) >> LOGE) == NT;
+};
+
+// v holds the inputs of the first stage; runs every stage, output in LDS (natural order).
+template <typename T, bool INV, int NT, int LOGN, int LOGCNT, int LOGE>
+__device__ __forceinline__ void ct_fft_from_regs(Cx<T>* buf, const Cx<T>* __restrict__ tw, Cx<T> (&v)[1 << LOGE]) {
+  constexpr int R = 1 << LOGE, N = 1 << LOGN;
+  dft_r<T, R, INV>(v);
+  // first stage (span 1): butterfly j writes output r to j R + r of its FFT
+  const int tid = threadIdx.x;
+  const int j = tid & ((N >> LOGE) - 1), f = tid >> (LOGN - LOGE);
+  const int base = j * R + f * N;          // a multiple of 16 (R >= 16) or, below, generic
+  if constexpr (R == 16) {
+    const int pb = lp(base);
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[pb + r] = v[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[lp(base + r)] = v[r];
+  }
+  __syncthreads();
+  ct_fft<T, INV, NT, LOGN, LOGCNT, false, LOGE, LOGE>(buf, tw);
+}
+
+// Runs every stage of the FFTs held in LDS but keeps the last stage's outputs
+// in v (element j + r N/R of FFT f in v[r]); the LDS is free on return.
+template <typename T, bool INV, int NT, int LOGN, int LOGCNT, int LOGE>
+__device__ __forceinline__ void ct_fft_to_regs(Cx<T>* buf, const Cx<T>* __restrict__ tw, Cx<T> (&v)[1 << LOGE]) {
+  constexpr int R = 1 << LOGE, N = 1 << LOGN;
+  constexpr int LAST = LOGN - LOGE;            // span of the last stage
+  ct_fft<T, INV, NT, LOGN, LOGCNT, false, LOGE, 0, LAST>(buf, tw);
+  constexpr int NB = N >> LOGE, NS = 1 << LAST;
+  constexpr int TWOFF = tw_stage_offset(LOGN, LAST, LOGE);
+  const int tid = threadIdx.x;
+  const int j = tid & (NB - 1), f = tid >> (LOGN - LOGE);
+  const int pb = lp(j + f * N);
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = buf[pb + r * NB + ((r * NB) >> 4)];
+  const int k = j & (NS - 1);
+  const Cx<T>* tp = tw + TWOFF + k * (R - 1);
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    const Cx<T> t = tp[r - 1];
+    v[r] = INV ? cmulc(v[r], t) : cmul(v[r], t);
+  }
+  dft_r<T, R, INV>(v);
+  __syncthreads();
 }
 
 }  // namespace csr

@@ -28,9 +28,13 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_
 template <typename T>
 __global__ void k_ompr_drop(const T* __restrict__ x, const int32_t* __restrict__ list, int k,
                             const T* __restrict__ cc, const Plan pl, T eta, const int32_t* __restrict__ jptr,
-                            int32_t* __restrict__ out) {
-  const int32_t d = ompr_drop_body<T>(x, list, k, cc, pl, eta, *jptr);
-  if (threadIdx.x == 0) out[0] = d;
+                            int32_t* __restrict__ out, SelState* sel) {
+  double m = -1.0, mk = 0.0;
+  const int32_t d = ompr_drop_body<T>(x, list, k, cc, pl, eta, *jptr, &m, &mk);
+  if (threadIdx.x == 0) {
+    out[0] = d;
+    note_margin(&sel->mmin, &sel->mrel, m, mk);
+  }
 }
 
 // key bitmap update for a swap: jd[0] = index to add, jd[1] = index to drop (natural)
@@ -234,7 +238,7 @@ void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int3
     }
     argmax_excl<T>(c, (const T*)c.Cc, bits, c.ibuf);
     hipLaunchKernelGGL(k_ompr_drop<T>, dim3(1), dim3(1024), 0, s, xI, c.list[cur], K, (const T*)c.Cc, c.plan,
-                       (T)eta, (const int32_t*)c.ibuf, c.ibuf + 1);
+                       (T)eta, (const int32_t*)c.ibuf, c.ibuf + 1, c.sel);
     CS_LAUNCH_CHECK();
     dev_read(s, c.ibuf, jd, 2 * sizeof(int32_t));
     if (jd[0] < 0 || jd[1] == jd[0]) { stopped = true; break; }

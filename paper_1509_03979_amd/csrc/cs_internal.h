@@ -249,6 +249,9 @@ struct SelState {          // top-K selection state
   uint64_t tau;            // threshold key of the last selection
   int32_t tie_out;         // whether the last selection broke a tie by index
   int32_t nonfinite;
+  uint64_t below;          // largest key below the threshold seen by the final pass (0: none)
+  double mmin;             // smallest decision margin of the call so far (+inf: none)
+  double mrel;             // the smallest margin relative to its decision's key
 };
 
 // Dense top-K split: one workgroup of kSplitThreads per block of `per_block`
@@ -362,6 +365,7 @@ struct BState {
   int32_t warm, jd[2], tol_abs;
   int64_t cg_iters, transforms;
   double rn, bb, tol2, eta, ynorm, model_bytes;
+  double mmin, mrel;      // decision margins (as SelState's)
 };
 
 template <typename T>
@@ -492,6 +496,19 @@ template <typename T> void prepare_kernels();                             // LDS
 
 // ------------------------------------------------------------------ selection
 template <typename T> void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j);
+// A decision is a near-tie when its margin is within the resolution its keys
+// are computed to: relative to the chosen key, kNearTie (tol + u log2 N), with
+// tol the CG tolerance relative to ||b|| and u the working precision's unit
+// roundoff.
+constexpr double kNearTie = 4.0;
+inline bool near_tie(double mrel, double tol_rel, bool f32, int logn) {
+  const double u = f32 ? 0x1p-24 : 0x1p-53;
+  return mrel <= kNearTie * (tol_rel + u * (double)logn);   // false for +inf (no decision)
+}
+// Decision margins: cleared per call; read back as (smallest margin, smallest
+// margin relative to its key).
+template <typename T> void margins_reset(Ctx<T>& c);
+template <typename T> void margins_read(Ctx<T>& c, double* mmin, double* mrel);
 template <typename T> void topk_dense(Ctx<T>& c, const T* dense, const uint32_t* excl, int k, uint32_t* out_bits);
 template <typename T> void topk_compact(Ctx<T>& c, const T* vals, const int32_t* list, int count, int k, uint32_t* out_bits);
 template <typename T> int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uint32_t* wpre);
@@ -541,6 +558,15 @@ void write_output(Ctx<T>& c, const int32_t* list, const T* x, int k, T* s_out, i
 // Batched OMPR: workspace layout (per-signal offsets appended to offs when
 // non-null; returns the total bytes, 0 if a size is unsupported) and driver.
 size_t batch_layout(cs_dtype dt, int count, const cs_batch_item* items, std::vector<size_t>* offs);
+// Concurrent batches (cs_pool.hip): per-signal workspace slices for `algo`
+// (offsets appended to offs), and the run of `one` (a single-signal
+// recovery) over every signal on the per-device worker pool.
+size_t batch_layout_algo(cs_dtype dt, int count, const cs_batch_item* items, cs_algo algo,
+                         std::vector<size_t>* offs);
+void recover_batched_pool(cs_algo algo, cs_dtype dt, int count, const cs_batch_item* items, double tol,
+                          const cs_params* params, void* ws, size_t ws_bytes, cs_info* infos, hipStream_t stream,
+                          void (*one)(cs_algo, cs_dtype, const void*, const cs_op*, int32_t, double, void*,
+                                      int32_t*, const cs_params*, void*, size_t, cs_info*, hipStream_t));
 template <typename T>
 void run_ompr_batched(int count, const cs_batch_item* items, double tol, const cs_params& prm, int cg_threads,
                       void* ws, size_t ws_bytes, cs_info* infos, hipStream_t stream);

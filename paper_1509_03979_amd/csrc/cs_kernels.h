@@ -358,6 +358,18 @@ template <typename T>
 __device__ __forceinline__ Cx<T> row_tw(const Plan& p, uint32_t r, uint32_t n2) {
   return tw4n<T>(p, ((r * n2) & (uint32_t)(p.L - 1)) << 3);
 }
+// The same for n2 a multiple of S (a compile-time power of two): with 8 S a
+// multiple of the low table's length the index has no low part, and the
+// twiddle is one entry of the high table.
+template <typename T, int S>
+__device__ __forceinline__ Cx<T> row_tw_step(const Plan& p, uint32_t r, uint32_t n2) {
+  if constexpr ((8 * S) % kTwLo == 0) {
+    const uint32_t idx = ((r * n2) & (uint32_t)(p.L - 1)) << 3;
+    return ((const Cx<T>*)p.tw_hi)[idx >> kTwLoLog];
+  } else {
+    return row_tw<T>(p, r, n2);
+  }
+}
 
 // the four-step twiddles a row workgroup keeps in registers (none: formed twice)
 template <typename T, int N>
@@ -391,16 +403,33 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
   // kept in registers for the load and the store (KEEPTW), or formed again
   // for the store where registers are short (the batched pass on long rows)
   Cx<T> tb0 = cx((T)1, (T)0), tb1 = cx((T)1, (T)0);
-  constexpr bool KEEP = SPLIT && KEEPTW;
+  // Register-resident ends (the large shapes: every stage radix 16, one
+  // butterfly per thread): thread tid owns row rs = tid / (L2/16) of the pair
+  // and its elements j + (L2/16) r, r < 16 (j = tid mod L2/16), loaded
+  // straight into the first FFT stage and stored from the last one.
+  constexpr bool REGIO = RegIO<LOGL2, 1, LOGE, NT>::ok && KEEPTW;
+  constexpr bool KEEP = SPLIT && KEEPTW && !REGIO;
   TwKeep<T, KEEP ? 2 * PER_ROW : 0> twk;
-  if (SPLIT) {
+  constexpr int RR = 1 << LOGE, NBR = L2 >> LOGE;
+  const int rs_own = REGIO ? (tid >> (LOGL2 - LOGE)) : 0;
+  const int j_own = tid & (NBR - 1);
+  TwKeep<T, REGIO ? RR : 0> twr;      // W_L^{row (j + NBR r)} for the thread's own elements
+  Cx<T> vr[REGIO ? RR : 1];
+  if constexpr (REGIO) {
+    const uint32_t row = (uint32_t)(rs_own ? rb : ra);
+    const Cx<T> tj = row_tw<T>(p, row, (uint32_t)j_own);
+#pragma unroll
+    for (int r = 0; r < RR; ++r) twr.v[r] = r ? cmul(tj, row_tw_step<T, NBR>(p, row, (uint32_t)(NBR * r))) : tj;
+  }
+  if (SPLIT && !REGIO) {
     tb0 = row_tw<T>(p, (uint32_t)ra, (uint32_t)tid);
     tb1 = row_tw<T>(p, (uint32_t)rb, (uint32_t)tid);
     if constexpr (KEEP) {
 #pragma unroll
       for (int q = 0; q < 2 * PER_ROW; ++q) {
         const int rs = q >= PER_ROW;
-        twk.v[q] = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)(rs ? rb : ra), (uint32_t)(NT * (q - rs * PER_ROW))));
+        twk.v[q] = cmul(rs ? tb1 : tb0, row_tw_step<T, NT>(p, (uint32_t)(rs ? rb : ra),
+                                                            (uint32_t)(NT * (q - rs * PER_ROW))));
       }
     }
   }
@@ -408,7 +437,14 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
   // the two rows (uniform base pointers; 32-bit offsets within a row)
   Cx<T>* const rowa = buf + (size_t)ra * L2;
   Cx<T>* const rowb = buf + (size_t)rb * L2;
-  if (mode != ROW_ADJ) {
+  if (mode != ROW_ADJ && REGIO) {
+    if constexpr (REGIO) {
+      const Cx<T>* __restrict__ rowp = rs_own ? rowb : rowa;
+#pragma unroll
+      for (int r = 0; r < RR; ++r) vr[r] = cmul(rowp[(uint32_t)(j_own + NBR * r)], twr.v[r]);
+      ct_fft_from_regs<T, false, NT, LOGL2, 1, LOGE>(lds, tw, vr);
+    }
+  } else if (mode != ROW_ADJ) {
     if (SPLIT) {
 #pragma unroll
       for (int q = 0; q < 2 * PER_ROW; ++q) {
@@ -418,7 +454,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         const int r = rs ? rb : ra;
         Cx<T> twv;
         if constexpr (KEEP) twv = twk.v[q];
-        else twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
+        else twv = cmul(rs ? tb1 : tb0, row_tw_step<T, NT>(p, (uint32_t)r, (uint32_t)(NT * qq)));
         lds[lp(rs * L2 + n2)] = cmul((rs ? rowb : rowa)[n2], twv);
       }
     } else {
@@ -435,14 +471,14 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
   // One item: self slot (LDS sa, freq-layout fa, bin k) and its partner
   // (sb, fb, bin L - k).  Returns after the store in the forward-only modes.
   double acc = 0.0;
-  auto item = [&](auto md_tag, int sa, int sb, uint32_t fa, uint32_t fb, bool zero, bool self, Cx<T> wk,
+  // wkc = (c/2) W_4N^k: the DCT scale c and the halves of E and O folded into
+  // the rotation (c/2 alone for the real Fourier basis); the partner's is
+  // wmc = (c/2) e^{-i pi/4} conj(W_4N^k).
+  auto item = [&](auto md_tag, int sa, int sb, uint32_t fa, uint32_t fb, bool zero, bool self, Cx<T> wkc,
                   Cx<T> WN) {
     constexpr int MD = decltype(md_tag)::value;   // the mode when fixed at compile time, else -1
     const int mode = MD >= 0 ? MD : mode_rt;
     T xa0, xa1, xb0, xb1;   // X_k, X_{N-k} (self slot) and X_{L-k}, X_{L+k} (partner slot)
-    // the DCT scale c and the halves of E and O folded into the two rotations:
-    // wkc = (c/2) wk, wmc = (c/2) e^{-i pi/4} conj(wk) (the partner's)
-    const Cx<T> wkc = scale(wk, hc);
     const Cx<T> wmc = p.fourier ? cx(hc, (T)0) : cx(h * (wkc.re - wkc.im), -h * (wkc.re + wkc.im));
     if (mode != ROW_ADJ) {
       const Cx<T> Zk = lds[sa];
@@ -510,21 +546,23 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
     // modes of the CG and greedy loops get the item code with the mode fixed.
     constexpr int PER_ITEM = SPLIT ? L2 / NT : 1;
     const uint32_t k0 = (uint32_t)ra + (uint32_t)L1 * (uint32_t)tid;
-    const Cx<T> kb1 = tw4n<T>(p, k0), kb4 = tw4n<T>(p, 4u * k0);
+    const Cx<T> kb4 = tw4n<T>(p, 4u * k0);
+    // (c/2) W_4N^{k0}: the item's wkc is this times the step, no per-item scale
+    const Cx<T> kb1c = p.fourier ? cx(hc, (T)0) : scale(tw4n<T>(p, k0), hc);
     const Cx<T>* __restrict__ step = (const Cx<T>*)p.tw_step;
     const uint32_t fa0 = (uint32_t)ra * L2 + (uint32_t)tid;
     const uint32_t fb0 = (uint32_t)rb * L2 + (uint32_t)(L2 - 1 - tid);
     auto items = [&](auto md_tag) {
 #pragma unroll 1
       for (int qi = 0; qi < PER_ITEM; ++qi) {
-        Cx<T> wk = qi ? cmul(kb1, step[qi]) : kb1;
+        // the real Fourier basis has no Makhoul rotation: wkc stays c/2
+        const Cx<T> wkc = (qi && !p.fourier) ? cmul(kb1c, step[qi]) : kb1c;
         const Cx<T> WN = qi ? cmul(kb4, step[kTwStepHalf + qi]) : kb4;
-        if (p.fourier) wk = cx((T)1, (T)0);   // the real Fourier basis: no Makhoul rotation
         // LDS slots t and 2 L2 - 1 - t; NT qi is a multiple of 16, so the padded
         // index is a per-thread base plus an immediate
         const int dq = NT * qi + ((NT * qi) >> 4);
         item(md_tag, lp(tid) + dq, lp(2 * L2 - 1 - tid) - dq, fa0 + (uint32_t)(NT * qi),
-             fb0 - (uint32_t)(NT * qi), false, false, wk, WN);
+             fb0 - (uint32_t)(NT * qi), false, false, wkc, WN);
       }
     };
     if (mode_rt == ROW_HAPPLY) items(std::integral_constant<int, ROW_HAPPLY>{});
@@ -541,7 +579,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         if (p.fourier) wk = cx((T)1, (T)0);
       }
       item(std::integral_constant<int, -1>{}, lp(it.sa), lp(it.sb), (uint32_t)it.fa, (uint32_t)it.fb, it.zero,
-           !it.zero && it.fa == it.fb, wk, WN);
+           !it.zero && it.fa == it.fb, scale(wk, hc), WN);
     }
   }
   if (mode == ROW_RESID) {
@@ -557,6 +595,13 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
   }
   if (mode == ROW_FWD || mode == ROW_FWD_ALL) return;
   __syncthreads();
+  if constexpr (REGIO) {
+    ct_fft_to_regs<T, true, NT, LOGL2, 1, LOGE>(lds, tw, vr);
+    Cx<T>* __restrict__ rowp = rs_own ? rowb : rowa;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) rowp[(uint32_t)(j_own + NBR * r)] = cmulc(vr[r], twr.v[r]);
+    return;
+  }
   ct_fft<T, true, NT, LOGL2, 1, false, LOGE>(lds, tw);
   if (SPLIT) {
 #pragma unroll
@@ -567,7 +612,7 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
       const int r = rs ? rb : ra;
       Cx<T> twv;
       if constexpr (KEEP) twv = twk.v[q];
-      else twv = cmul(rs ? tb1 : tb0, row_tw<T>(p, (uint32_t)r, (uint32_t)(NT * qq)));
+      else twv = cmul(rs ? tb1 : tb0, row_tw_step<T, NT>(p, (uint32_t)r, (uint32_t)(NT * qq)));
       (rs ? rowb : rowa)[(uint32_t)n2] = cmulc(lds[lp(rs * L2 + n2)], twv);
     }
   } else {

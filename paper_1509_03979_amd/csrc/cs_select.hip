@@ -24,6 +24,7 @@
 #include "cs_device.h"
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdlib>
 #include <type_traits>
 
@@ -32,11 +33,13 @@ namespace csr {
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
 // ------------------------------------------------------------------ argmax outside a set
+// Each workgroup keeps its best two keys (part[2b], part[2b + 1]), so the
+// final also has the runner-up: the decision's margin.
 template <typename T>
 __global__ void k_argmax_partial(const T* __restrict__ dense, const uint32_t* __restrict__ excl, const Plan pl,
                                  ArgKey* __restrict__ part, SelState* sel) {
   const int64_t n = pl.n;
-  ArgKey best{0, 0, 0};
+  K2 t;
   bool bad = false;
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += st) {
@@ -44,20 +47,31 @@ __global__ void k_argmax_partial(const T* __restrict__ dense, const uint32_t* __
     const int64_t j = nat_of_key(p, pl);
     const T v = dense[p];
     bad |= !finite_v(v);
-    ArgKey k{mag_bits(v) + 1, 0xFFFFFFFFu - (uint32_t)j, 0};
-    if (key_gt(k, best)) best = k;
+    t.add(mag_bits(v) + 1, 0xFFFFFFFFu - (uint32_t)j);
   }
   if (bad) atomicOr(&sel->nonfinite, 1);
-  best = block_max_key(best);
-  if (threadIdx.x == 0) part[blockIdx.x] = best;
+  block_max_key2(t);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = t.best();
+    part[2 * blockIdx.x + 1] = t.second();
+  }
 }
 
-__global__ void k_argmax_final(const ArgKey* __restrict__ part, int np, int32_t* out_j) {
-  ArgKey best{0, 0, 0};
-  for (int i = threadIdx.x; i < np; i += blockDim.x)
-    if (key_gt(part[i], best)) best = part[i];
-  best = block_max_key(best);
-  if (threadIdx.x == 0) *out_j = best.hi ? (int32_t)(0xFFFFFFFFu - best.lo) : -1;
+template <typename T>
+__global__ void k_argmax_final(const ArgKey* __restrict__ part, int np, int32_t* out_j, SelState* sel) {
+  K2 t;
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const ArgKey a = part[2 * i], b = part[2 * i + 1];
+    t.add(a.hi, a.lo, b.hi, b.lo);
+  }
+  block_max_key2(t);
+  if (threadIdx.x == 0) {
+    *out_j = t.bh ? (int32_t)(0xFFFFFFFFu - t.bl) : -1;
+    if (t.bh && t.sh) {
+      const double vb = key_value<T>(t.bh);
+      note_margin(&sel->mmin, &sel->mrel, vb - key_value<T>(t.sh), vb);
+    }
+  }
 }
 
 template <typename T>
@@ -66,8 +80,30 @@ void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j
   const unsigned grid = (unsigned)std::min<int64_t>(kArgBlocks, nblk(n, 256));
   hipLaunchKernelGGL(k_argmax_partial<T>, dim3(grid), dim3(256), 0, c.stream, dense, excl, c.plan, c.argpart, c.sel);
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(1024), 0, c.stream, c.argpart, (int)grid, out_j);
+  hipLaunchKernelGGL(k_argmax_final<T>, dim3(1), dim3(1024), 0, c.stream, c.argpart, (int)grid, out_j, c.sel);
   CS_LAUNCH_CHECK();
+}
+
+__global__ void k_margins_reset(SelState* sel) {
+  if (threadIdx.x == 0) {
+    sel->mmin = __builtin_huge_val();
+    sel->mrel = __builtin_huge_val();
+  }
+}
+
+template <typename T>
+void margins_reset(Ctx<T>& c) {
+  hipLaunchKernelGGL(k_margins_reset, dim3(1), dim3(64), 0, c.stream, c.sel);
+  CS_LAUNCH_CHECK();
+}
+
+template <typename T>
+void margins_read(Ctx<T>& c, double* mmin, double* mrel) {
+  double h[2];
+  static_assert(offsetof(SelState, mrel) == offsetof(SelState, mmin) + sizeof(double), "layout");
+  dev_read(c.stream, &c.sel->mmin, h, sizeof(h));
+  *mmin = h[0];
+  *mrel = h[1];
 }
 
 // ------------------------------------------------------------------ top-K
@@ -450,6 +486,7 @@ __global__ __launch_bounds__(1024) void k_sel_pass(const T* __restrict__ vals, c
     o.pending = active ? 1 : 0;
     sel->head[(p + 1) & 1] = o;
     if (init == 2) sel->nonfinite = 0;
+    if (init) sel->below = 0;   // read by the final pass, a later launch
   }
   if (!active) return;
   const int mode = hd.mode;
@@ -521,6 +558,12 @@ __global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, 
   const int64_t st = (int64_t)gridDim.x * blockDim.x;
   const uint32_t* excl = (const uint32_t*)aux;
   const int32_t* list = (const int32_t*)aux;
+  // the largest admissible key below tau this thread sees (the first rejected
+  // candidate, for the margin; not needed under a tie, whose margin is 0)
+  uint64_t below = 0;
+  auto seen = [&](uint64_t key) {
+    if (key != 0 && key < tau && key > below) below = key;
+  };
   // --- keys above tau (and equal to it without a tie)
   if (mode == SEL_DENSE) {
     if (tie && blockIdx.x != 0) return;   // workgroup 0 owns every word when it also resolves the tie
@@ -532,6 +575,7 @@ __global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, 
         const int64_t q = w * 32 + e;
         if (q < count) {
           const uint64_t key = dense_key(vals, excl, q);
+          seen(key);
           if (key != 0 && (key > tau || (key == tau && !tie))) word |= 1u << e;
         }
       }
@@ -543,6 +587,7 @@ __global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, 
       const int64_t o = (int64_t)sg * cap;
       for (int i = lane; i < c; i += 64) {
         const uint64_t key = (uint64_t)rkey[o + i];
+        seen(key);
         if (key > tau || (key == tau && !tie)) {
           const uint32_t q = rpos[o + i];
           atomicOr(&bits[q >> 5], 1u << (q & 31));
@@ -552,11 +597,19 @@ __global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, 
   } else {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += st) {
       const uint64_t key = mag_bits(vals[i]) + 1;
+      seen(key);
       if (key > tau || (key == tau && !tie)) {
         const uint32_t q = (uint32_t)list[i];
         atomicOr(&bits[q >> 5], 1u << (q & 31));
       }
     }
+  }
+  if (!tie) {
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint64_t o = __shfl_down((unsigned long long)below, off, 64);
+      below = o > below ? o : below;
+    }
+    if (lane == 0 && below) atomicMax((unsigned long long*)&sel->below, (unsigned long long)below);
   }
   if (!tie || blockIdx.x != 0 || tau == 0) return;   // key 0 (excluded) is never marked
   // --- tie: the need lowest natural indices among the keys equal to tau
@@ -650,6 +703,28 @@ static inline int index_bits(int64_t n) {
   return std::max(b, 1);
 }
 
+// The selection's margin: the K-th key minus the first rejected one (0 under a
+// tie).  When the final pass saw no key below the threshold, a dense split's
+// rejected keys all lie below the band, so tau minus the band's lower bound is
+// a lower bound of the margin; a list or dense source had no rejected key.
+template <typename T>
+__global__ void k_sel_margin(SelState* sel, int p) {
+  if (threadIdx.x != 0) return;
+  const SelHead hd = sel->head[p & 1];
+  if (hd.mode == SEL_NONE || sel->tau == 0) return;
+  const double vt = key_value<T>(sel->tau);
+  if (sel->tie_out) {
+    note_margin(&sel->mmin, &sel->mrel, 0.0, vt);
+    return;
+  }
+  uint64_t b = sel->below;
+  if (b == 0) {
+    if (hd.mode != SEL_SEG) return;
+    b = sel->t_lo;
+  }
+  note_margin(&sel->mmin, &sel->mrel, vt - key_value<T>(b), vt);
+}
+
 template <typename T>
 static void sel_run(Ctx<T>& c, const T* vals, const void* aux, int64_t count, int init, int64_t k, int nseg,
                     int cap, unsigned grid, uint32_t* out_bits) {
@@ -663,6 +738,8 @@ static void sel_run(Ctx<T>& c, const T* vals, const void* aux, int64_t count, in
   }
   hipLaunchKernelGGL((k_sel_final<T>), dim3(grid), dim3(1024), 0, s, vals, aux, count, c.plan.words, c.plan, c.sel,
                      (const RecKey<T>*)c.rkey, c.rpos, c.rcnt, nseg, cap, c.hrows, passes, index_bits(c.plan.n), out_bits);
+  CS_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_sel_margin<T>), dim3(1), dim3(64), 0, s, c.sel, passes);
   CS_LAUNCH_CHECK();
 }
 
@@ -757,6 +834,8 @@ int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uin
 
 #define CS_INST(T)                                                                        \
   template void argmax_excl<T>(Ctx<T>&, const T*, const uint32_t*, int32_t*);           \
+  template void margins_reset<T>(Ctx<T>&);                                              \
+  template void margins_read<T>(Ctx<T>&, double*, double*);                             \
   template void topk_dense<T>(Ctx<T>&, const T*, const uint32_t*, int, uint32_t*);      \
   template void topk_compact<T>(Ctx<T>&, const T*, const int32_t*, int, int, uint32_t*); \
   template int bits_to_list<T>(Ctx<T>&, const uint32_t*, int32_t*, int, uint32_t*);

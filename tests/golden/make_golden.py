@@ -4,6 +4,7 @@
     python tests/golden/make_golden.py sp_n2p24           # SP, N = 2^24 (noiseless)
     python tests/golden/make_golden.py sp_ompr_n2p20:3:sp # signal 3, SP only
     python tests/golden/make_golden.py ompr_batched_256 6 # batched OMPR, 256 signals, 6 processes
+    python tests/golden/make_golden.py sp_adjoint_n2p16_all 2  # SP on the 64 signals of N = 2^16
 
 Each file holds the measurements the GPU consumes (float32 y, from the
 oracle's FP64 y = A s + noise; only up to N = 2^20, larger workloads recompute
@@ -75,7 +76,18 @@ def run(name: str, sig: int = 0, store_y: bool = True, algos=None):
                       "transforms": int(counter[0]), "true_support_match": bool(np.array_equal(r.support, d.supp))}
         print(name, algo, meta[algo], flush=True)
     path = os.path.join(OUT, f"{name}_sig{sig}.npz")
-    np.savez_compressed(path, meta=json.dumps(meta), **out)
+    if os.path.exists(path):
+        # keep the other algorithms' results already stored for this signal
+        old = np.load(path, allow_pickle=False)
+        old_meta = json.loads(str(old["meta"]))
+        for key in old.files:
+            if key != "meta" and key not in out:
+                out[key] = old[key]
+        for key, val in old_meta.items():
+            meta.setdefault(key, val)
+    tmp = path + ".tmp.npz"
+    np.savez_compressed(tmp, meta=json.dumps(meta), **out)
+    os.replace(tmp, path)
     print("wrote", path)
 
 
@@ -148,15 +160,47 @@ def run_batched(count: int = 256, cfg: int = 4, procs: int = 6, part_dir: str | 
     print("wrote", path)
 
 
+def _adjoint_one(sig):
+    """Oracle SP on signal `sig` of the 64-signal differentiated workload."""
+    w, d, op, y32 = measurements("sp_adjoint_n2p16", sig)
+    y = y32.astype(np.float64)
+    t = time.perf_counter()
+    r = oracle.sp(op, y, d.k)
+    meta = {"sig": sig, "stop": r.stop, "iters": int(r.iters), "seconds": time.perf_counter() - t,
+            "y_norm": float(np.linalg.norm(y)), "true_support_match": bool(np.array_equal(r.support, d.supp))}
+    print("adjoint sig", sig, meta, flush=True)
+    return r.support.astype(np.int32), r.s[r.support], meta
+
+
+def run_adjoint_all(procs: int = 2):
+    """SP on all 64 signals of the differentiated workload (N = 2^16, M = 2^14,
+    K = 300, 30 dB): supports and values, concatenated, with per-signal meta."""
+    import multiprocessing as mp
+    count = synth.WORKLOADS["sp_adjoint_n2p16"]["batch"]
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_adjoint_one, range(count))
+    offs = np.cumsum([0] + [r[0].size for r in res]).astype(np.int64)
+    path = os.path.join(OUT, "sp_adjoint_n2p16_all.npz")
+    np.savez_compressed(path, meta=json.dumps({"workload": "sp_adjoint_n2p16", "count": count,
+                                               "signals": [r[2] for r in res]}),
+                        offsets=offs, support=np.concatenate([r[0] for r in res]),
+                        values=np.concatenate([r[1] for r in res]))
+    print("wrote", path)
+
+
 if __name__ == "__main__":
+    if sys.argv[1:2] == ["sp_adjoint_n2p16_all"]:
+        run_adjoint_all(int(sys.argv[2]) if len(sys.argv) > 2 else 2)
+        sys.exit(0)
     if sys.argv[1:2] == ["ompr_batched_256"]:
         run_batched(256, 4, int(sys.argv[2]) if len(sys.argv) > 2 else 6)
         sys.exit(0)
-    # y is stored for workloads small enough to keep in the repository (N <= 2^20);
-    # larger ones recompute it with the oracle (measurements()).  NAME[:SIG[:ALGO]]
+    # y is stored for signal 0 of workloads small enough to keep in the repository
+    # (N <= 2^20, the benchmark's input); other signals and larger workloads
+    # recompute it with the oracle (measurements()).  NAME[:SIG[:ALGO]]
     # picks a signal other than 0 and one of the workload's algorithms.
     for arg in sys.argv[1:]:
         parts = arg.split(":")
         nm = parts[0]
         sg = int(parts[1]) if len(parts) > 1 else 0
-        run(nm, sg, store_y=synth.WORKLOADS[nm]["n"] <= 2 ** 20, algos=parts[2:3] or None)
+        run(nm, sg, store_y=synth.WORKLOADS[nm]["n"] <= 2 ** 20 and sg == 0, algos=parts[2:3] or None)

@@ -201,7 +201,9 @@ def test_batched_validation():
     f = cs.lib.cs_recover_ompr_batched
     ok = cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_OMPR)
     assert ok > 2 * cs.cs_workspace_size(cs.CS_F32, 1024, 256, 10, cs.CS_ALGO_OMPR)
-    assert cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_SP) == 0
+    sp = cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_SP)
+    assert sp >= 2 * cs.cs_workspace_size(cs.CS_F32, 1024, 256, 10, cs.CS_ALGO_SP)
+    assert cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_OMP) == 0
     assert cs.lib.cs_workspace_size_batched(cs.CS_F32, 0, items, cs.CS_ALGO_OMPR) == 0
     ws = ctypes.c_void_p(FAKE)
     assert f(cs.CS_F32, 0, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_INVALID
@@ -237,3 +239,26 @@ def test_static_workspace_entry_validates_on_the_host():
     assert "static workspace" in cs.cs_last_error()
     for dt, n in ((cs.CS_F32, 2 ** 21), (cs.CS_F64, 2 ** 20)):   # the largest sizes the header promises
         assert cs.cs_workspace_size(dt, n, n // 4, n // 256, cs.CS_ALGO_SP) <= cs.CS_STATIC_WS_BYTES
+
+
+def test_sp_batched_validation():
+    """cs_recover_sp_batched checks every item on the host first."""
+    items = (cs.cs_batch_item * 2)()
+    for i in range(2):
+        items[i].op = cs.cs_op(1024, 256, FAKE, FAKE)
+        items[i].y = items[i].s = items[i].support = FAKE
+        items[i].k = 10
+    f = cs.lib.cs_recover_sp_batched
+    ok = cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_SP)
+    ws = ctypes.c_void_p(FAKE)
+    assert f(cs.CS_F32, 0, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_INVALID
+    assert f(cs.CS_F32, 2, items, float("nan"), None, ws, ok, None, None) == cs.CS_E_INVALID
+    assert f(cs.CS_F32, 2, items, 1e-6, None, None, ok, None, None) == cs.CS_E_WORKSPACE
+    items[1].k = 129                                      # SP: 2K > M
+    assert f(cs.CS_F32, 2, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_SHAPE
+    assert cs.lib.cs_workspace_size_batched(cs.CS_F32, 2, items, cs.CS_ALGO_SP) == 0
+    items[1].k = 10
+    items[0].support = None
+    assert f(cs.CS_F32, 2, items, 1e-6, None, ws, ok, None, None) == cs.CS_E_INVALID
+    items[0].support = FAKE
+    assert f(cs.CS_F32, 2, items, 1e-6, None, ws, 100, None, None) == cs.CS_E_WORKSPACE

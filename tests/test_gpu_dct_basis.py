@@ -115,7 +115,7 @@ def test_recover_with_dct_basis(case):
     print(name, info, "oracle iters", ref.iters, ref.stop, flush=True)
     assert np.array_equal(supp, ref.support), (np.setdiff1d(supp, ref.support), np.setdiff1d(ref.support, supp))
     assert rel(s, ref.s) <= 1e-5
-    assert info["flags"] & ~cs.CS_F_CG_MAXITER == 0
+    assert info["flags"] & ~cs.CS_F_NEAR_TIE == 0, info
 
 
 @pytest.mark.parametrize("dt,tol,bar", [("f64", 1e-12, 1e-8), ("f32", 1e-6, 1e-3)])
@@ -134,7 +134,7 @@ def test_adjoint_ls_with_dct_basis(dt, tol, bar):
     announce("adjoint_ls psi", dt)
     gy, info = cs.cs_adjoint_ls(to_dev(gs, tdt), dop, to_dev(d.supp, torch.int32), tol)
     assert rel(gy.cpu().numpy(), g_ref) <= bar
-    assert info["flags"] == 0
+    assert info["flags"] & ~cs.CS_F_NEAR_TIE == 0
 
 
 # ------------------------------------------------------------------ separable 2-D DCT basis (psi = 2)
@@ -228,7 +228,7 @@ def test_recover_with_2d_dct_basis(case):
     print(name, info, "oracle iters", ref.iters, ref.stop, flush=True)
     assert np.array_equal(supp, ref.support), (np.setdiff1d(supp, ref.support), np.setdiff1d(ref.support, supp))
     assert rel(s, ref.s) <= 1e-5
-    assert info["flags"] & ~cs.CS_F_CG_MAXITER == 0
+    assert info["flags"] & ~cs.CS_F_NEAR_TIE == 0, info
 
 
 @pytest.mark.parametrize("dt,tol,bar", [("f64", 1e-12, 1e-8), ("f32", 1e-6, 1e-3)])
@@ -246,4 +246,4 @@ def test_adjoint_ls_with_2d_dct_basis(dt, tol, bar):
     announce("adjoint_ls psi2", dt)
     gy, info = cs.cs_adjoint_ls(to_dev(gs, tdt), dop, to_dev(d.supp, torch.int32), tol)
     assert rel(gy.cpu().numpy(), g_ref) <= bar
-    assert info["flags"] == 0
+    assert info["flags"] & ~cs.CS_F_NEAR_TIE == 0

@@ -104,7 +104,7 @@ def test_recover_with_real_fourier(case):
     print(name, info, "oracle iters", ref.iters, ref.stop, flush=True)
     assert np.array_equal(supp, ref.support), (np.setdiff1d(supp, ref.support), np.setdiff1d(ref.support, supp))
     assert rel(s, ref.s) <= 1e-5
-    assert info["flags"] & ~cs.CS_F_CG_MAXITER == 0
+    assert info["flags"] & ~cs.CS_F_NEAR_TIE == 0, info
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
@@ -152,7 +152,7 @@ def test_adjoint_ls_with_real_fourier(dt, tol, bar):
     announce("adjoint_ls fourier", dt)
     gy, info = cs.cs_adjoint_ls(to_dev(gs, tdt), dop, to_dev(d.supp, torch.int32), tol)
     assert rel(gy.cpu().numpy(), g_ref) <= bar
-    assert info["flags"] == 0
+    assert info["flags"] & ~cs.CS_F_NEAR_TIE == 0
 
 
 def test_batched_ompr_with_real_fourier():

@@ -25,6 +25,18 @@ def _tol(dt):
     return 1e-13 if dt == "f64" else 3e-6
 
 
+def _elementwise_ok(got, ref, n, dt):
+    """Every element within 32 u log2(N) rms(ref) (u the unit roundoff):
+    rounding spreads evenly over the outputs of an orthonormal transform, so
+    this is far above what rounding gives (about u sqrt(log2 N) rms per
+    element) yet far below what one wrong output would show, which the
+    relative L2 bound alone does not catch at large N."""
+    u = 2.0 ** -53 if dt == "f64" else 2.0 ** -24
+    rms = float(np.linalg.norm(ref) / np.sqrt(ref.size))
+    err = float(np.max(np.abs(np.asarray(got, np.float64) - ref)))
+    return err <= 32 * u * np.log2(n) * rms, err
+
+
 def _case(n, m, seed):
     rng = synth.rng_for(70, seed, 0)
     rows, signs = synth.draw_operator(rng, n, m)
@@ -49,10 +61,16 @@ def test_apply_A_and_At(n, m, dt):
     u = rng.standard_normal(m).astype(ndt)
     announce("apply_A", n, m, dt)
     ax = cs.cs_apply_A(to_dev(x, tdt), dop).cpu().numpy()
-    assert rel(ax, op.apply(x.astype(np.float64))) <= _tol(dt)
+    ref = op.apply(x.astype(np.float64))
+    assert rel(ax, ref) <= _tol(dt)
+    ok, err = _elementwise_ok(ax, ref, n, dt)
+    assert ok, ("A x element", err)
     announce("apply_At", n, m, dt)
     atu = cs.cs_apply_At(to_dev(u, tdt), dop).cpu().numpy()
-    assert rel(atu, op.adjoint(u.astype(np.float64))) <= _tol(dt)
+    ref = op.adjoint(u.astype(np.float64))
+    assert rel(atu, ref) <= _tol(dt)
+    ok, err = _elementwise_ok(atu, ref, n, dt)
+    assert ok, ("A^T u element", err)
     # A A^T = I_M (rows of an orthonormal matrix)
     announce("A At", n, m, dt)
     aatu = cs.cs_apply_A(to_dev(atu, tdt), dop).cpu().numpy()
