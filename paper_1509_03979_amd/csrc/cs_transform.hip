@@ -144,6 +144,73 @@ __global__ void k_mask_from_rows(const int32_t* __restrict__ rows, int64_t m, co
   atomicOr(&mask[b >> 5], 1u << (b & 31));
 }
 
+// The mask in two passes for shapes with L1 a multiple of 32 and L2 of 64.
+// First the natural-order bitmap of the rows (cleared beforehand): thread i
+// checks row i (in range, above row i-1) and the rows of a wave, ascending,
+// OR their bits per word with a segmented shuffle scan, so each word takes one
+// atomic per wave.
+__global__ void k_rows_bitmap(const int32_t* __restrict__ rows, int64_t m, int64_t n, uint32_t* __restrict__ nb,
+                              int32_t* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  uint32_t w = 0xFFFFFFFFu, v = 0u;
+  if (i < m) {
+    const int64_t q = rows[i];
+    if ((q >= 0 && q < n) && (i == 0 || rows[i - 1] < q)) {
+      w = (uint32_t)(q >> 5);
+      v = 1u << (q & 31);
+    } else {
+      atomicOr(bad, 1);
+    }
+  }
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t w2 = __shfl_up(w, off, 64), v2 = __shfl_up(v, off, 64);
+    if (lane >= off && w2 == w) v |= v2;
+  }
+  const uint32_t wn = __shfl_down(w, 1, 64);
+  if (w != 0xFFFFFFFFu && (lane == 63 || wn != w)) atomicOr(&nb[w], v);
+}
+
+__device__ __forceinline__ uint32_t spread16(uint32_t x) {   // bit i -> bit 2i
+  x &= 0xFFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+// Then the transpose into the freq layout: slot f = a L2 + b holds row
+// k = b L1 + a (half 0) and row N - k (half 1; row L for k = 0).  One wave per
+// tile of 32 a-values by 64 b-values: lane b holds the word of rows b L1 + a0 ..
+// + 31 and the two words around N - b L1 - a0; one ballot per a and half gives
+// 64 slots, interleaved into four mask words.
+__global__ __launch_bounds__(64) void k_mask_transpose(const uint32_t* __restrict__ nb, const Plan p,
+                                                       uint32_t* __restrict__ mask) {
+  const int lane = threadIdx.x;
+  const int64_t a0 = (int64_t)blockIdx.x * 32, b0 = (int64_t)blockIdx.y * 64, b = b0 + lane;
+  const int64_t L1 = p.L1, L2 = p.L2, n = p.n;
+  const uint32_t w0 = nb[(b * L1 + a0) >> 5];
+  const int64_t hi = n - b * L1 - a0;               // the row of half 1 at a = a0 (n: the k = 0 case)
+  const int64_t lo = hi - 31;
+  const uint32_t wlo = nb[lo >> 5];
+  const uint32_t whi = nb[(hi < n ? hi : n - 1) >> 5];
+  const bool k0 = (b == 0 && a0 == 0);
+  const uint32_t rowL = (nb[p.L >> 5] >> (p.L & 31)) & 1u;
+  for (int a = 0; a < 32; ++a) {
+    const bool h0 = (w0 >> a) & 1u;
+    const int64_t r1 = hi - a;
+    bool h1;
+    if (k0 && a == 0) h1 = rowL != 0;
+    else h1 = ((((r1 >> 5) == (lo >> 5)) ? wlo : whi) >> (r1 & 31)) & 1u;
+    const uint64_t m0 = __ballot(h0), m1 = __ballot(h1);
+    if (lane < 4) {
+      const uint32_t x0 = (uint32_t)(m0 >> (16 * lane)), x1 = (uint32_t)(m1 >> (16 * lane));
+      mask[(((a0 + a) * L2 + b0) >> 4) + lane] = spread16(x0) | (spread16(x1) << 1);
+    }
+  }
+}
+
 // Inverse of the randomizer's permutation; flags an entry out of range or a
 // repeated one (pinv starts at -1).
 __global__ void k_perm_inverse(const int32_t* __restrict__ perm, int64_t n, int32_t* __restrict__ pinv, int32_t* bad) {
@@ -219,10 +286,20 @@ void setup_operator(Ctx<T>& c) {
   hipLaunchKernelGGL(k_twiddle<T>, dim3(1), dim3(kTwStepHalf), 0, s, c.tw_step + kTwStepHalf, (int64_t)kTwStepHalf,
                      n4, 4 * st);
   CS_LAUNCH_CHECK();
-  fill_u32(c.mask, p.words, 0u, s);
   fill<int32_t>(c.ibuf, 1, 0, s);
-  hipLaunchKernelGGL(k_mask_from_rows, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, p, c.mask, c.ibuf);
-  CS_LAUNCH_CHECK();
+  if (p.L1 % 32 == 0 && p.L2 % 64 == 0) {
+    // natural row bitmap in nbits (free until the output), then the transpose
+    fill_u32(c.nbits, p.words, 0u, s);
+    hipLaunchKernelGGL(k_rows_bitmap, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, p.n, c.nbits, c.ibuf);
+    CS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_mask_transpose, dim3((unsigned)(p.L1 / 32), (unsigned)(p.L2 / 64)), dim3(64), 0, s,
+                       (const uint32_t*)c.nbits, p, c.mask);
+    CS_LAUNCH_CHECK();
+  } else {
+    fill_u32(c.mask, p.words, 0u, s);
+    hipLaunchKernelGGL(k_mask_from_rows, dim3(nblk(p.m, 256)), dim3(256), 0, s, c.rows, p.m, p, c.mask, c.ibuf);
+    CS_LAUNCH_CHECK();
+  }
   if (((uintptr_t)c.rsigns & 15u) == 0)
     hipLaunchKernelGGL(k_check_signs, dim3(nblk((p.n + 15) / 16, 256)), dim3(256), 0, s, c.rsigns, p.n, c.ibuf);
   else hipLaunchKernelGGL(k_check_signs1, dim3(nblk(p.n, 256)), dim3(256), 0, s, c.rsigns, p.n, c.ibuf);

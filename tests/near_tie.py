@@ -188,3 +188,142 @@ def certify_ompr(op, y, k, tol, eta, oracle_moves, gpu_moves, gpu_support, gpu_s
     if s_err > s_tol:
         return Verdict(False, t0, kind, gap0, eps_at, replayed, s_err, why="s differs from the LS on its support")
     return Verdict(True, t0, kind, gap0, eps_at, replayed, s_err)
+
+
+# ------------------------------------------------------------------ Subspace Pursuit
+#
+# An SP round from a support T (SP as Dai and Milenkovic define it, one of the
+# greedy methods of Sec. IV) takes D = the top-K of |A^T r| outside T,
+# solves least squares on U = T u D, keeps the top-K of |x~| over U and moves
+# there unless the residual grew.  The certificate takes the GPU's supports
+# after each round (G_0 the initial top-K of |A^T y|, G_1 .. G_R) and checks
+# every round in the oracle's FP64 quantities, with witnesses for what the
+# GPU does not report:
+#   * the expansion D_g: the oracle's D with the lowest-key members that the
+#     GPU did not keep traded for the GPU's entering indices outside it; D_g
+#     must be a top-K of |c| up to 2 eps (eps as for OMPR, on |T| = K);
+#   * the prune: G_t must be a top-K of |x~| over T u D_g up to 2 eps_U
+#     (eps on |U| = 2K, with ||x~||);
+#   * the move: ||r(G_t)|| <= ||r(G_{t-1})|| + 2 eps (a residual of an FP32
+#     least-squares fit carries the same bound as the correlations).
+# The final support G_R must be an SP fixed point up to the same bounds: the
+# oracle's next round keeps G_R, or keeping G_R is a top-K of |x~| up to
+# 2 eps_U, or the oracle's next support has a residual not below ||r(G_R)||
+# by more than 2 eps.  G_0 must be a top-K of |A^T y| up to 2 eps_0
+# (eps_0 = c_T u log2 N ||y||).
+
+
+@dataclasses.dataclass
+class SPVerdict:
+    ok: bool
+    round: int                # the round that failed (or -1)
+    kind: str                 # "init", "expand", "prune", "move", "final"
+    gaps: list                # (round, kind, gap, bound) for every check made
+    s_err: float = float("nan")
+    why: str = ""
+
+
+def _topk_gap(keys, idx, chosen):
+    """max key among idx outside `chosen` minus min key among `chosen`
+    (<= 0 when `chosen` is an exact top-|chosen| of keys over idx)."""
+    inside = np.isin(idx, chosen)
+    if inside.all() or not inside.any():
+        return float("-inf")
+    return float(keys[~inside].max() - keys[inside].min())
+
+
+def _sp_round(st: OracleState, T, k, tol):
+    """Oracle quantities for one SP round from T: x, c, eps, r norm, the
+    oracle's D (ascending) and the list of indices outside T."""
+    op = st.op
+    x, c = st.at(T)
+    eps = eps_keys(op.n, op.m, len(T), float(np.linalg.norm(x)), tol)
+    rn = float(np.linalg.norm(st.y - op.apply_sparse(T, x)))
+    excl = np.zeros(op.n, dtype=bool)
+    excl[T] = True
+    D, _ = oracle.greedy.topk_excluding(c, excl, k)
+    return x, c, eps, rn, D, np.flatnonzero(~excl)
+
+
+def _ls_on(st: OracleState, U):
+    op = st.op
+    x, _ = oracle.ls_cg(op, U, st.y, tol=1e-13, aty=st.aty)
+    return x
+
+
+def certify_sp(op, y, k, tol, gpu_supports, gpu_s, s_tol: float = 1e-5) -> SPVerdict:
+    """gpu_supports: [G_0, G_1, ..., G_R] (index arrays), G_R the returned
+    support; consecutive equal supports are allowed only at the end (a
+    round that kept the support).  gpu_s: the GPU's dense s."""
+    y = np.asarray(y, dtype=np.float64)
+    st = OracleState(op, y, 0.0)
+    gs = [np.sort(np.asarray(g, dtype=np.int64)) for g in gpu_supports]
+    while len(gs) > 1 and np.array_equal(gs[-1], gs[-2]):
+        gs.pop()
+    gaps = []
+    # G_0: a top-K of |A^T y| up to 2 eps_0
+    key0 = np.abs(st.aty)
+    eps0 = C_T * U32 * np.log2(op.n) * float(np.linalg.norm(y))
+    g = _topk_gap(key0, np.arange(op.n), gs[0])
+    gaps.append((0, "init", g, 2 * eps0))
+    if g > 2 * eps0:
+        return SPVerdict(False, 0, "init", gaps, why="G_0 is not a top-K of |A^T y| up to 2 eps")
+    for t in range(1, len(gs) + 1):
+        T = gs[t - 1]
+        x, c, eps, rn, D, outside = _sp_round(st, T, k, tol)
+        ac = np.abs(c)
+        final = t == len(gs)
+        if final:
+            # the next round: the oracle's own, from G_R
+            U = np.union1d(T, D)
+            xt = _ls_on(st, U)
+            epsu = eps_keys(op.n, op.m, len(U), float(np.linalg.norm(xt)), tol)
+            g = _topk_gap(np.abs(xt), U, T)
+            gaps.append((t, "final-keep", g, 2 * epsu))
+            if g <= 2 * epsu:
+                break
+            Tn = np.sort(U[oracle.greedy.topk_order(np.abs(xt), U, k)])
+            xn = _ls_on(st, Tn)
+            rnn = float(np.linalg.norm(y - op.apply_sparse(Tn, xn)))
+            gaps.append((t, "final-resid", rn - rnn, 2 * eps))
+            if rn - rnn <= 2 * eps:
+                break
+            return SPVerdict(False, t, "final", gaps,
+                             why="the final support is not an SP fixed point up to 2 eps")
+        G = gs[t]
+        E = np.setdiff1d(G, T)
+        extra = np.setdiff1d(E, D)
+        if extra.size:
+            spare = np.setdiff1d(D, G)
+            if spare.size < extra.size:
+                return SPVerdict(False, t, "expand", gaps, why="more entering indices than D can hold")
+            spare = spare[np.argsort(ac[spare], kind="stable")][: extra.size]
+            Dg = np.union1d(np.setdiff1d(D, spare), extra)
+        else:
+            Dg = D
+        g = _topk_gap(ac[outside], outside, Dg)
+        gaps.append((t, "expand", g, 2 * eps))
+        if g > 2 * eps:
+            return SPVerdict(False, t, "expand", gaps, why="no expansion within 2 eps explains G_t")
+        U = np.union1d(T, Dg)
+        if not np.isin(G, U).all():
+            return SPVerdict(False, t, "prune", gaps, why="G_t leaves T u D")
+        xt = _ls_on(st, U)
+        epsu = eps_keys(op.n, op.m, len(U), float(np.linalg.norm(xt)), tol)
+        g = _topk_gap(np.abs(xt), U, G)
+        gaps.append((t, "prune", g, 2 * epsu))
+        if g > 2 * epsu:
+            return SPVerdict(False, t, "prune", gaps, why="G_t is not a top-K of |x~| up to 2 eps")
+        xg = _ls_on(st, G)
+        rng_ = float(np.linalg.norm(y - op.apply_sparse(G, xg)))
+        gaps.append((t, "move", rng_ - rn, 2 * eps))
+        if rng_ - rn > 2 * eps:
+            return SPVerdict(False, t, "move", gaps, why="the residual grew by more than 2 eps")
+    fin = gs[-1]
+    xf = _ls_on(st, fin)
+    ref = np.zeros(op.n)
+    ref[fin] = xf
+    s_err = float(np.linalg.norm(np.asarray(gpu_s, dtype=np.float64) - ref) / np.linalg.norm(ref))
+    if s_err > s_tol:
+        return SPVerdict(False, len(gs), "s", gaps, s_err, why="s differs from the LS on its support")
+    return SPVerdict(True, -1, "", gaps, s_err)
