@@ -72,7 +72,7 @@ static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0)
   c.rkey = cv.take<T>((int64_t)sl.blocks * sl.cap);
   c.rpos = cv.take<uint32_t>((int64_t)sl.blocks * sl.cap);
   c.rcnt = cv.take<int32_t>(2 * (int64_t)sl.blocks);
-  c.hrows = cv.take<uint32_t>(2 * (int64_t)kPassBlocks * 2048);
+  c.hrows = cv.take<uint32_t>(3 * (int64_t)kSelBins);
   if (psi) {
     c.P1 = cv.take<T>(n);
     c.P2 = cv.take<T>(n);
@@ -219,7 +219,7 @@ static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, d
   Ctx<T> c{};
   ctx_init<T>(c, op, kmax_for(algo, k), ws, ws_bytes, stream);
   setup_operator<T>(c);
-  margins_reset<T>(c);
+  sel_reset<T>(c);
   load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
   c.tol_abs = prm.tol_abs != 0;

@@ -378,7 +378,7 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
     ctx_init<T>(c, &it.op, it.k, base + offs[i], ws_bytes - offs[i], stream);
     setup_operator<T>(c);
     load_measurements<T>(c, (const T*)it.y);
-    margins_reset<T>(c);
+    sel_reset<T>(c);
     topk_dense<T>(c, c.C0, nullptr, it.k, c.bits[0]);
     bits_to_list<T>(c, c.bits[0], c.list[0], it.k, c.wpre[0]);
     BSig<T>& h = hs[i];

@@ -270,7 +270,9 @@ inline SplitLayout split_layout(int64_t n) {
   g = (n + eb - 1) / eb;
   return SplitLayout{(int)g, eb, (int)(eb / 8 + 64)};
 }
-constexpr int kPassBlocks = 32;   // workgroups of a radix pass (one histogram row each)
+constexpr int kPassBlocks = 128;  // workgroups of a radix pass
+constexpr int kSelDigit = 13;     // radix digit width of the top-K passes
+constexpr int kSelBins = 1 << kSelDigit;
 
 struct ArgKey {            // argmax key: (magnitude bits + 1, ~index)
   uint64_t hi;
@@ -327,7 +329,8 @@ struct Ctx {
   void* rkey;              // dense top-K candidates: keys (width of T), positions and
   uint32_t* rpos;          //   per-block (count, selected count) pairs
   int32_t* rcnt;
-  uint32_t* hrows;         // radix histogram rows (2 x kPassBlocks x 2048)
+  uint32_t* hrows;         // radix histograms: three rows of kSelBins counts (pass p adds into
+                           //   row p mod 3, picks from row p-1 mod 3, clears row p+1 mod 3)
   int32_t* ibuf;           // small int scratch (>= 64)
   uint32_t* blockcnt;      // bitmap compaction block counts
   CgScalars* cg;
@@ -507,7 +510,7 @@ inline bool near_tie(double mrel, double tol_rel, bool f32, int logn) {
 }
 // Decision margins: cleared per call; read back as (smallest margin, smallest
 // margin relative to its key).
-template <typename T> void margins_reset(Ctx<T>& c);
+template <typename T> void sel_reset(Ctx<T>& c);
 template <typename T> void margins_read(Ctx<T>& c, double* mmin, double* mrel);
 template <typename T> void topk_dense(Ctx<T>& c, const T* dense, const uint32_t* excl, int k, uint32_t* out_bits);
 template <typename T> void topk_compact(Ctx<T>& c, const T* vals, const int32_t* list, int count, int k, uint32_t* out_bits);

@@ -66,6 +66,13 @@ __device__ __forceinline__ double wg_sum(double v, double* red, int nwaves) {
   return s;
 }
 
+// An empty register constraint: the value is taken as changed here, so no
+// computation on it moves above this point (no instruction is emitted).
+template <typename V>
+__device__ __forceinline__ void opaque(V& v) {
+  asm volatile("" : "+v"(v));
+}
+
 // First compact slot at or after key `key`: the support keys below it.
 template <typename T>
 __device__ __forceinline__ uint32_t slot_at(const ColIO<T>& io, size_t key, int64_t words) {
@@ -128,24 +135,37 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
   T v_x = (T)0, v_r = (T)0, v_d = (T)0, v_q = (T)0, v_b = (T)0;
   const bool dir = io.mode == COL_DIR, first = io.it == 0;
   const bool upd = dir && io.fused && !first;
-  if (has0) {
-    key0 = (uint32_t)io.list[sl0];
-    if (!INV) {
+  // Unconditional loads (a lane without a slot reads slot 0 and ignores it):
+  // a load under a condition would be waited for where the branches join,
+  // before the strip's dense loads issue.
+  const uint32_t slc = has0 ? sl0 : 0u;
+  // inverse passes: one load per role from a pointer picked by the (uniform)
+  // mode, the roles assigned after the FFT; the dense modes read the first
+  // entry of the (read-only) twiddle table instead, never used
+  uint32_t l_key = 0;
+  T l_a = (T)0, l_r = (T)0;
+  if constexpr (INV) {
+    const bool qm = io.mode == COL_Q;
+    const int32_t* pl = compact ? io.list : (const int32_t*)tw;
+    const T* pa = compact ? (qm ? io.d : io.b) : (const T*)tw;
+    const T* pr = (compact && qm && io.fused) ? io.r : pa;
+    l_key = (uint32_t)pl[slc];
+    l_a = pa[slc];
+    l_r = pr[slc];
+  }
+  if (!INV && compact) {
+    key0 = (uint32_t)io.list[slc];
+    {
       if (dir) {
-        v_r = io.r[sl0];
-        if (!first) v_d = io.d[sl0];
+        v_r = io.r[slc];
+        if (!first) v_d = io.d[slc];
         if (upd) {
-          v_x = io.x[sl0];
-          v_q = io.q[sl0];
+          v_x = io.x[slc];
+          v_q = io.q[slc];
         }
       } else {
-        v_x = io.x[sl0];
+        v_x = io.x[slc];
       }
-    } else if (io.mode == COL_Q) {
-      v_d = io.d[sl0];
-      if (io.fused) v_r = io.r[sl0];
-    } else {
-      v_b = io.b[sl0];
     }
   }
   // thread tid handles e = tid + q NT: row n1 = e >> LOGB, column b = e & (B-1),
@@ -196,6 +216,18 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
   }
   __syncthreads();
   ct_fft<T, INV, NT, LOGL1, LOGB, true, LOGE>(buf, tw);
+  if (INV && compact) {
+    // the first slot's values are used from here on only: pin them here so
+    // that no use (and no wait for their loads) moves up front
+    opaque(l_key);
+    opaque(l_a);
+    opaque(l_r);
+    const bool qm = io.mode == COL_Q;
+    key0 = l_key;
+    v_d = qm ? l_a : (T)0;
+    v_b = qm ? (T)0 : l_a;
+    v_r = (qm && io.fused) ? l_r : (T)0;
+  }
   if (INV && compact && io.mode == COL_Q && io.fused) {
     // q = H d on the strip's slots with the partials of the four inner
     // products of the CG step (r is the current residual, already updated by
@@ -349,10 +381,6 @@ __device__ __forceinline__ RowItem row_item(int t, int w, int ra, int rb, int L1
   return it;
 }
 
-__device__ __forceinline__ uint32_t mask2(const uint32_t* __restrict__ mask, int64_t f) {
-  return (mask[(2 * f) >> 5] >> ((2 * f) & 31)) & 3u;
-}
-
 // W_L^{r n2} = W_4N^{8 ((r n2) mod L)}
 template <typename T>
 __device__ __forceinline__ Cx<T> row_tw(const Plan& p, uint32_t r, uint32_t n2) {
@@ -474,8 +502,29 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
   // wkc = (c/2) W_4N^k: the DCT scale c and the halves of E and O folded into
   // the rotation (c/2 alone for the real Fourier basis); the partner's is
   // wmc = (c/2) e^{-i pi/4} conj(W_4N^k).
+  // An item's global inputs (the mask words of its two bins; y or the adjoint
+  // input at them), loaded ahead of the item so their latency overlaps the
+  // previous item's arithmetic.
+  struct ItemIn {
+    uint32_t wa, wb;
+    T a0, a1, b0, b1;
+  };
+  auto item_in = [&](auto md_tag, uint32_t fa, uint32_t fb) {
+    constexpr int MD = decltype(md_tag)::value;
+    const int mode = MD >= 0 ? MD : mode_rt;
+    ItemIn r{0u, 0u, (T)0, (T)0, (T)0, (T)0};
+    if (mode != ROW_ADJ && mode != ROW_FWD_ALL) {
+      r.wa = p.mask[fa >> 4];   // bits 2f, 2f + 1 of slot f
+      r.wb = p.mask[fb >> 4];
+    }
+    if (mode == ROW_ADJ || mode == ROW_RESID) {
+      r.a0 = fin[2u * fa]; r.a1 = fin[2u * fa + 1u];
+      r.b0 = fin[2u * fb]; r.b1 = fin[2u * fb + 1u];
+    }
+    return r;
+  };
   auto item = [&](auto md_tag, int sa, int sb, uint32_t fa, uint32_t fb, bool zero, bool self, Cx<T> wkc,
-                  Cx<T> WN) {
+                  Cx<T> WN, const ItemIn& in) {
     constexpr int MD = decltype(md_tag)::value;   // the mode when fixed at compile time, else -1
     const int mode = MD >= 0 ? MD : mode_rt;
     T xa0, xa1, xb0, xb1;   // X_k, X_{N-k} (self slot) and X_{L-k}, X_{L+k} (partner slot)
@@ -497,18 +546,18 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         xb0 = b.re; xb1 = -b.im;
       }
     } else {
-      xa0 = fin[2u * fa]; xa1 = fin[2u * fa + 1u];
-      xb0 = fin[2u * fb]; xb1 = fin[2u * fb + 1u];
+      xa0 = in.a0; xa1 = in.a1;
+      xb0 = in.b0; xb1 = in.b1;
     }
     if (mode != ROW_ADJ) {
       const bool all = mode == ROW_FWD_ALL;
-      const uint32_t ma = all ? 3u : mask2(p.mask, fa);
-      const uint32_t mb = zero ? 0u : (all ? 3u : mask2(p.mask, fb));
+      const uint32_t ma = all ? 3u : (in.wa >> ((fa & 15u) * 2u)) & 3u;
+      const uint32_t mb = zero ? 0u : (all ? 3u : (in.wb >> ((fb & 15u) * 2u)) & 3u);
       if (mode == ROW_RESID) {
-        xa0 = fin[2u * fa] - xa0;
-        xa1 = fin[2u * fa + 1u] - xa1;
-        xb0 = zero ? (T)0 : fin[2u * fb] - xb0;
-        xb1 = zero ? (T)0 : fin[2u * fb + 1u] - xb1;
+        xa0 = in.a0 - xa0;
+        xa1 = in.a1 - xa1;
+        xb0 = zero ? (T)0 : in.b0 - xb0;
+        xb1 = zero ? (T)0 : in.b1 - xb1;
       }
       xa0 = (ma & 1u) ? xa0 : (T)0;
       xa1 = (ma & 2u) ? xa1 : (T)0;
@@ -553,8 +602,13 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
     const uint32_t fa0 = (uint32_t)ra * L2 + (uint32_t)tid;
     const uint32_t fb0 = (uint32_t)rb * L2 + (uint32_t)(L2 - 1 - tid);
     auto items = [&](auto md_tag) {
+      // software-pipelined by one item: the next item's inputs are loaded
+      // (unconditionally, the last item reloading its own) before this one runs
+      ItemIn cur = item_in(md_tag, fa0, fb0);
 #pragma unroll 1
       for (int qi = 0; qi < PER_ITEM; ++qi) {
+        const int qn = qi + 1 < PER_ITEM ? qi + 1 : qi;
+        const ItemIn nxt = item_in(md_tag, fa0 + (uint32_t)(NT * qn), fb0 - (uint32_t)(NT * qn));
         // the real Fourier basis has no Makhoul rotation: wkc stays c/2
         const Cx<T> wkc = (qi && !p.fourier) ? cmul(kb1c, step[qi]) : kb1c;
         const Cx<T> WN = qi ? cmul(kb4, step[kTwStepHalf + qi]) : kb4;
@@ -562,7 +616,8 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         // index is a per-thread base plus an immediate
         const int dq = NT * qi + ((NT * qi) >> 4);
         item(md_tag, lp(tid) + dq, lp(2 * L2 - 1 - tid) - dq, fa0 + (uint32_t)(NT * qi),
-             fb0 - (uint32_t)(NT * qi), false, false, wkc, WN);
+             fb0 - (uint32_t)(NT * qi), false, false, wkc, WN, cur);
+        cur = nxt;
       }
     };
     if (mode_rt == ROW_HAPPLY) items(std::integral_constant<int, ROW_HAPPLY>{});
@@ -578,8 +633,9 @@ __device__ __forceinline__ void row_body(Cx<T>* __restrict__ buf, const Plan& p,
         WN = tw4n<T>(p, (uint32_t)(4 * it.k));
         if (p.fourier) wk = cx((T)1, (T)0);
       }
-      item(std::integral_constant<int, -1>{}, lp(it.sa), lp(it.sb), (uint32_t)it.fa, (uint32_t)it.fb, it.zero,
-           !it.zero && it.fa == it.fb, scale(wk, hc), WN);
+      const auto md = std::integral_constant<int, -1>{};
+      item(md, lp(it.sa), lp(it.sb), (uint32_t)it.fa, (uint32_t)it.fb, it.zero, !it.zero && it.fa == it.fb,
+           scale(wk, hc), WN, item_in(md, (uint32_t)it.fa, (uint32_t)it.fb));
     }
   }
   if (mode == ROW_RESID) {

@@ -11,11 +11,13 @@
 //  * argmax: packed keys (bits + 1, ~index) reduced with wavefront shuffles.
 //  * top-K of a dense vector: a sorted sample brackets the K-th key in a band;
 //    one streaming pass writes the bitmap of the keys above the band and
-//    collects the keys inside it; an MSB-first radix select (11-bit digits)
-//    over those candidates finds the threshold (each pass writes one
-//    histogram row per workgroup, and the next pass sums the rows to fix the
-//    digit, so there are no global atomics and no extra launches); if the K-th
-//    key is shared by more candidates than are still needed, the ones with the
+//    collects the keys inside it; an MSB-first radix select (13-bit digits)
+//    over those candidates finds the threshold.  Each pass adds its
+//    workgroup histograms into one global row with atomics (only the bins a
+//    workgroup saw), and the next pass reads that row to fix the digit, so a
+//    digit costs one row read and no extra launch; three rows rotate so that
+//    each pass also clears the row two passes ahead.  If the K-th key is
+//    shared by more candidates than are still needed, the ones with the
 //    lowest natural indices are kept.  When the band misses (too many keys
 //    above it, too few in it, or a full segment) the same radix passes run
 //    over every key instead.  Top-K of a compact vector runs the radix passes
@@ -84,16 +86,19 @@ void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j
   CS_LAUNCH_CHECK();
 }
 
-__global__ void k_margins_reset(SelState* sel) {
-  if (threadIdx.x == 0) {
+// Start of a call: no margin yet, the radix rows cleared.
+__global__ void k_sel_reset(SelState* sel, uint32_t* __restrict__ hrows) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * kSelBins) hrows[i] = 0u;
+  if (i == 0) {
     sel->mmin = __builtin_huge_val();
     sel->mrel = __builtin_huge_val();
   }
 }
 
 template <typename T>
-void margins_reset(Ctx<T>& c) {
-  hipLaunchKernelGGL(k_margins_reset, dim3(1), dim3(64), 0, c.stream, c.sel);
+void sel_reset(Ctx<T>& c) {
+  hipLaunchKernelGGL(k_sel_reset, dim3(nblk(3 * kSelBins, 256)), dim3(256), 0, c.stream, c.sel, c.hrows);
   CS_LAUNCH_CHECK();
 }
 
@@ -116,8 +121,14 @@ enum : int32_t {
 };
 
 constexpr int kSample = 2048;     // keys sampled to bracket the K-th key
-constexpr int kDigit = 11;        // radix digit width of the passes
-constexpr int kBins = 1 << kDigit;
+constexpr int kDigit = kSelDigit;  // radix digit width of the passes
+constexpr int kBins = kSelBins;
+constexpr int kIdxDigit = 11;     // digit width of the radix select over tied indices
+constexpr int kIdxBins = 1 << kIdxDigit;
+static_assert(kBins % 1024 == 0, "bins per thread of the digit pick");
+// rows rotate mod 3: after a selection of P passes only row (P - 1) mod 3 is
+// left uncleared, and the next selection's first pass adds into row 0
+static_assert((32 + kDigit - 1) / kDigit % 3 != 1 && (64 + kDigit - 1) / kDigit % 3 != 1, "row rotation");
 constexpr int kTieCap = 4096;     // tied candidates sorted in LDS by the final pass
 
 // Magnitude key of candidate i of a dense vector: 0 if excluded.
@@ -260,12 +271,21 @@ __global__ __launch_bounds__(1024) void k_sel_sample(const T* __restrict__ vals,
     const uint64_t low = kshift ? (1ull << kshift) - 1 : 0ull;   // bits below the sorted ones
     uint64_t thi = max_key(keybits), tlo = 1;
     if (rh >= 1) thi = ((uint64_t)s[std::min<int64_t>(rh, S) - 1] << kshift) | low;
+    // no sample rank is safely above the K-th, but about N/S keys exceed the
+    // sample's largest: with r >= 2 that is at most K/2 on average, so the
+    // largest still bounds the band from above (the first pass checks it)
+    else if (r >= 2.0 && s[0] != 0u) thi = ((uint64_t)s[0] << kshift) | low;
     if (rl >= 1 && rl <= S) tlo = std::max<uint64_t>(1, (uint64_t)s[rl - 1] << kshift);
     sel->t_lo = tlo;
     sel->t_hi = thi;
     sel->k = k;
     sel->nonfinite = 0;
   }
+}
+
+// Set bits of a wave-wide mask below this lane.
+__device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // Dense split (kSplitThreads per workgroup).  Workgroup b reads keys
@@ -296,20 +316,64 @@ __global__ __launch_bounds__(kSplitThreads) void k_sel_split(const T* __restrict
   for (int64_t r0 = b0; r0 < end; r0 += U * R) {
     T v[U][4];
     uint32_t ex[U];
+    // every load issued before any is used (a lane past the end re-reads the
+    // last four keys and marks them excluded), so the rounds are in flight together
+    uint32_t xw[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t p = r0 + u * R + wave * 256 + lane * 4;
-      if (p < end) {
-        load4(vals + p, v[u]);
-        ex[u] = excl ? (excl[p >> 5] >> (p & 31)) & 0xFu : 0u;
-      } else {
-        v[u][0] = v[u][1] = v[u][2] = v[u][3] = (T)0;
-        ex[u] = 0xFu;
-      }
+      const int64_t pc = p < end ? p : end - 4;
+      load4(vals + pc, v[u]);
+      xw[u] = excl ? excl[pc >> 5] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t p = r0 + u * R + wave * 256 + lane * 4;
+      ex[u] = p < end ? (xw[u] >> (p & 31)) & 0xFu : 0xFu;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t p = r0 + u * R + wave * 256 + lane * 4;
+      if constexpr (sizeof(T) == 4) {
+        // FP32: the keys and the band fit 32 bits
+        const uint32_t lo32 = (uint32_t)t_lo, hi32 = (uint32_t)t_hi;
+        uint32_t key[4], hib = 0, midb = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t m = __float_as_uint(v[u][e]) & 0x7FFFFFFFu;
+          const bool x = (ex[u] >> e) & 1u;
+          bad |= !x && m >= 0x7F800000u;
+          key[e] = x ? 0u : m + 1u;
+          hib |= (uint32_t)(key[e] > hi32) << e;
+          midb |= (uint32_t)(key[e] >= lo32 && key[e] <= hi32) << e;
+        }
+        uint32_t w = hib << ((lane & 7) * 4);
+        w |= __shfl_xor(w, 1, 64);
+        w |= __shfl_xor(w, 2, 64);
+        w |= __shfl_xor(w, 4, 64);
+        if ((lane & 7) == 0 && p < end) out_bits[p >> 5] = w;
+        hcnt += __popc(hib);
+        // each lane's band keys (at most four) at its exclusive prefix in the wave
+        const uint32_t cnt = __popc(midb);
+        if (__ballot(cnt != 0)) {
+          const uint64_t c0 = __ballot(cnt & 1u), c1 = __ballot(cnt & 2u), c2 = __ballot(cnt & 4u);
+          const uint32_t tot = (uint32_t)(__popcll(c0) + 2 * __popcll(c1) + 4 * __popcll(c2));
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&s_mid, tot);
+          base = __shfl(base, 0, 64);
+          uint32_t o = base + lane_prefix(c0) + 2 * lane_prefix(c1) + 4 * lane_prefix(c2);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if ((midb >> e) & 1u) {
+              if (o < (uint32_t)cap) {
+                bk[o] = (RecKey<T>)key[e];
+                bp[o] = (uint32_t)(p + e);
+              }
+              ++o;
+            }
+        }
+        continue;
+      }
       uint64_t key[4];
       uint32_t hib = 0, midb = 0;
 #pragma unroll
@@ -406,43 +470,37 @@ __device__ __forceinline__ void sel_decide(const SelState* sel, const int32_t* _
   }
 }
 
-// Every workgroup (1024 threads, two bins each) sums the histogram rows of the
-// previous pass and fixes the digit (high to low) that holds the need-th
-// candidate; all workgroups reach the same state.
-__device__ __forceinline__ void sel_pick(SelHead& hd, const uint32_t* __restrict__ rows, int nrows, int64_t* sc) {
+// Every workgroup (1024 threads, kBins / 1024 bins each) reads the histogram
+// row of the previous pass and fixes the digit (high to low) that holds the
+// need-th candidate; all workgroups reach the same state.
+__device__ __forceinline__ void sel_pick(SelHead& hd, const uint32_t* __restrict__ row, int64_t* sc) {
+  constexpr int BPT = kBins / 1024;
   const int w = hd.bit < kDigit ? hd.bit : kDigit, shift = hd.bit - w;
   const int nb = 1 << w;
   const int t = threadIdx.x;
-  int64_t c[2] = {0, 0};
+  uint32_t c[BPT];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int q = 2 * t + u;
-    if (q < nb) {
-      const int d = nb - 1 - q;
-      uint32_t a[kPassBlocks];
-#pragma unroll
-      for (int r = 0; r < kPassBlocks; ++r) a[r] = r < nrows ? rows[r * kBins + d] : 0u;
-      int64_t sum = 0;
-#pragma unroll
-      for (int r = 0; r < kPassBlocks; ++r) sum += a[r];
-      c[u] = sum;
-    }
+  for (int u = 0; u < BPT; ++u) {
+    const int q = BPT * t + u;
+    c[u] = q < nb ? row[nb - 1 - q] : 0u;
   }
-  const int64_t loc = c[0] + c[1];
+  int64_t loc = 0;
+#pragma unroll
+  for (int u = 0; u < BPT; ++u) loc += c[u];
   const int64_t incl = block_incl_scan(loc, sc), need = hd.need;
   int64_t run = incl - loc;
   __syncthreads();   // every thread has read hd.need
   if (run < need && need <= incl) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < BPT; ++u) {
       if (run < need && need <= run + c[u]) {
-        const uint64_t d = (uint64_t)(nb - 1 - (2 * t + u));
+        const uint64_t d = (uint64_t)(nb - 1 - (BPT * t + u));
         const int64_t rest = need - run;
         hd.need = rest;
         hd.prefix |= d << shift;
         hd.pmask |= (uint64_t)(nb - 1) << shift;
         hd.bit = shift;
-        if (shift == 0) hd.tie = rest < c[u] ? 1 : 0;
+        if (shift == 0) hd.tie = rest < (int64_t)c[u] ? 1 : 0;
       }
       run += c[u];
     }
@@ -451,11 +509,17 @@ __device__ __forceinline__ void sel_pick(SelHead& hd, const uint32_t* __restrict
   __syncthreads();
 }
 
+// Clears row r of the rotation (spread over the grid).
+__device__ __forceinline__ void sel_clear_row(uint32_t* __restrict__ hrows, int r) {
+  uint32_t* row = hrows + (int64_t)r * kBins;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kBins; i += gridDim.x * blockDim.x) row[i] = 0u;
+}
+
 // One radix pass p (1024 threads per workgroup, at most kPassBlocks
 // workgroups).  Reads the state left by pass p-1, picks the digit its
-// histogram rows fix, and if key bits remain unresolved writes one histogram
-// row per workgroup of the next digit (up to kDigit bits) among the candidates
-// matching the prefix.  State and rows are double-buffered by pass parity.
+// histogram row fixes, and if key bits remain unresolved adds the histogram of
+// the next digit (up to kDigit bits) among the candidates matching the prefix
+// into row p mod 3.  State is double-buffered by pass parity.
 // init = 1 (first pass over a dense split) decides the source (init = 3: the
 // same, but always every key: the fallback, for tests); init = 2 starts a
 // selection over a list of k entries.  Segments are read one
@@ -479,7 +543,8 @@ __global__ __launch_bounds__(1024) void k_sel_pass(const T* __restrict__ vals, c
     }
   }
   __syncthreads();
-  if (hd.pending) sel_pick(hd, hrows + (int64_t)((p - 1) & 1) * kPassBlocks * kBins, (int)gridDim.x, sc);
+  if (hd.pending) sel_pick(hd, hrows + (int64_t)((p + 2) % 3) * kBins, sc);
+  sel_clear_row(hrows, (p + 1) % 3);
   const bool active = hd.mode != SEL_NONE && hd.bit > 0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     SelHead o = hd;
@@ -517,8 +582,11 @@ __global__ __launch_bounds__(1024) void k_sel_pass(const T* __restrict__ vals, c
     }
   }
   __syncthreads();
-  uint32_t* row = hrows + (int64_t)(p & 1) * kPassBlocks * kBins + (int64_t)blockIdx.x * kBins;
-  for (uint32_t i = threadIdx.x; i <= dm; i += blockDim.x) row[i] = h[i];
+  uint32_t* row = hrows + (int64_t)(p % 3) * kBins;
+  for (uint32_t i = threadIdx.x; i <= dm; i += blockDim.x) {
+    const uint32_t v = h[i];
+    if (v) atomicAdd(&row[i], v);
+  }
 }
 
 // Final pass: picks the last digit, then marks the selected candidates: every
@@ -534,17 +602,18 @@ __global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, 
                                                     const RecKey<T>* __restrict__ rkey,
                                                     const uint32_t* __restrict__ rpos,
                                                     const int32_t* __restrict__ rcnt, int nseg, int cap,
-                                                    const uint32_t* __restrict__ hrows, int p, int jbits,
+                                                    uint32_t* __restrict__ hrows, int p, int jbits,
                                                     uint32_t* __restrict__ bits) {
   __shared__ SelHead hd;
   __shared__ int64_t sc[16];
   __shared__ uint64_t tb[kTieCap];
-  __shared__ uint32_t th[kBins];
+  __shared__ uint32_t th[kIdxBins];
   __shared__ uint32_t s_cnt, s_digit;
   __shared__ int64_t s_rest;
   if (threadIdx.x == 0) hd = sel->head[p & 1];
   __syncthreads();
-  if (hd.pending) sel_pick(hd, hrows + (int64_t)((p - 1) & 1) * kPassBlocks * kBins, (int)gridDim.x, sc);
+  if (hd.pending) sel_pick(hd, hrows + (int64_t)((p + 2) % 3) * kBins, sc);
+  sel_clear_row(hrows, (p + 1) % 3);
   const int mode = hd.mode;
   if (mode == SEL_NONE) return;
   const uint64_t tau = hd.prefix;
@@ -609,7 +678,15 @@ __global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, 
       const uint64_t o = __shfl_down((unsigned long long)below, off, 64);
       below = o > below ? o : below;
     }
-    if (lane == 0 && below) atomicMax((unsigned long long*)&sel->below, (unsigned long long)below);
+    // one atomic per workgroup: all of them target the same word
+    __shared__ uint64_t s_below[16];
+    if (lane == 0) s_below[threadIdx.x >> 6] = below;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t bm = 0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) bm = s_below[i] > bm ? s_below[i] : bm;
+      if (bm) atomicMax((unsigned long long*)&sel->below, (unsigned long long)bm);
+    }
   }
   if (!tie || blockIdx.x != 0 || tau == 0) return;   // key 0 (excluded) is never marked
   // --- tie: the need lowest natural indices among the keys equal to tau
@@ -656,7 +733,7 @@ __global__ __launch_bounds__(1024) void k_sel_final(const T* __restrict__ vals, 
   uint32_t jprefix = 0u, jmask = 0u;
   int64_t rest = need;
   for (int bit = jbits; bit > 0;) {
-    const int w = bit < kDigit ? bit : kDigit, shift = bit - w;
+    const int w = bit < kIdxDigit ? bit : kIdxDigit, shift = bit - w;
     const uint32_t dm = (1u << w) - 1;
     for (uint32_t i = threadIdx.x; i <= dm; i += blockDim.x) th[i] = 0u;
     __syncthreads();
@@ -707,6 +784,8 @@ static inline int index_bits(int64_t n) {
 // tie).  When the final pass saw no key below the threshold, a dense split's
 // rejected keys all lie below the band, so tau minus the band's lower bound is
 // a lower bound of the margin; a list or dense source had no rejected key.
+// (A kernel of its own: a device-scope release in every workgroup of the final
+// pass, so that its last one could note the margin, costs more than a launch.)
 template <typename T>
 __global__ void k_sel_margin(SelState* sel, int p) {
   if (threadIdx.x != 0) return;
@@ -834,7 +913,7 @@ int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uin
 
 #define CS_INST(T)                                                                        \
   template void argmax_excl<T>(Ctx<T>&, const T*, const uint32_t*, int32_t*);           \
-  template void margins_reset<T>(Ctx<T>&);                                              \
+  template void sel_reset<T>(Ctx<T>&);                                                  \
   template void margins_read<T>(Ctx<T>&, double*, double*);                             \
   template void topk_dense<T>(Ctx<T>&, const T*, const uint32_t*, int, uint32_t*);      \
   template void topk_compact<T>(Ctx<T>&, const T*, const int32_t*, int, int, uint32_t*); \
