@@ -12,6 +12,9 @@ Compressive Sensing of Large-Scale Signals"):
 * ``operator``  - the sensing operator A = D F R of Eq. (7) (Sec. III-A) with
                   F the orthonormal DCT-II and R a +-1 sign flip; dense cosine
                   formula for small N as a second route.
+* ``cpf``       - partial complex Fourier sensing of a real signal,
+                  A = D FFT R (the D(FFT(x)) operator of Sec. II), with complex
+                  measurements and the real-inner-product adjoint.
 * ``gram``      - closed-form Gram matrix A_S^T A_S of that operator
                   (a Toeplitz-plus-Hankel form derived from the cosine
                   product-to-sum identity; derived here, not in the paper).
@@ -34,6 +37,7 @@ paper prints no values: those are "parity unpinned" beyond the invariants
 noiseless well-separated inputs, the M = N special case).
 """
 from .operator import SRM, dct2_matrix, rdft_matrix  # noqa: F401
+from .cpf import CPF  # noqa: F401
 from .gram import gram_generator, gram_matrix  # noqa: F401
 from .lsq import ls, ls_dense, ls_gram, ls_cg  # noqa: F401
 from .greedy import omp, sp, ompr, cosamp, topk_order, argmax_excluding  # noqa: F401

@@ -16,11 +16,24 @@ from .operator import SRM
 
 
 def adjoint_gradient(op: SRM, supp, y, t_dense) -> tuple[np.ndarray, np.ndarray]:
-    """Returns (dL/dy as an M-vector, s_hat_S)."""
+    """Returns (dL/dy as an M-vector, s_hat_S).  With complex measurements the
+    gradient is dL/d(Re y) + i dL/d(Im y), from the stacked real system
+    [Re A_S; Im A_S] (the coefficients are real)."""
     s = np.asarray(supp, dtype=np.int64)
     a = op.columns(s)
+    cplx = np.iscomplexobj(a)
+    if cplx:
+        yc = np.asarray(y, dtype=np.complex128)
+        a = np.vstack([a.real, a.imag])
+        yv = np.concatenate([yc.real, yc.imag])
+    else:
+        yv = np.asarray(y, dtype=np.float64)
     G = a.T @ a
     cf = sla.cho_factor(G, lower=True)
-    s_hat = sla.cho_solve(cf, a.T @ np.asarray(y, dtype=np.float64))
+    s_hat = sla.cho_solve(cf, a.T @ yv)
     g = sla.cho_solve(cf, s_hat - np.asarray(t_dense, dtype=np.float64)[s])
-    return 2.0 * (a @ g), s_hat
+    gy = 2.0 * (a @ g)
+    if cplx:
+        m = gy.size // 2
+        gy = gy[:m] + 1j * gy[m:]
+    return gy, s_hat

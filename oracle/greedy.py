@@ -45,6 +45,12 @@ from .operator import SRM
 from .lsq import LSContext
 
 
+def measurement_vector(op, y) -> np.ndarray:
+    """y in FP64: complex for an operator with complex measurements (the
+    partial complex Fourier operator), real otherwise."""
+    return np.asarray(y, dtype=np.complex128 if getattr(op, "complex_meas", False) else np.float64)
+
+
 def topk_order(keys: np.ndarray, idx: np.ndarray, k: int) -> np.ndarray:
     """Positions of the first k candidates under (key desc, index asc)."""
     order = np.lexsort((idx, -keys))
@@ -98,7 +104,7 @@ def _dense(n, supp, vals):
 
 
 def omp(op: SRM, y, K: int, ls_route: str = "auto") -> Result:
-    y = np.asarray(y, dtype=np.float64)
+    y = measurement_vector(op, y)
     ctx = LSContext(op, y, ls_route)
     r = y.copy()
     S: list[int] = []
@@ -119,7 +125,7 @@ def omp(op: SRM, y, K: int, ls_route: str = "auto") -> Result:
 
 
 def sp(op: SRM, y, K: int, max_iter: int = 100, ls_route: str = "auto") -> Result:
-    y = np.asarray(y, dtype=np.float64)
+    y = measurement_vector(op, y)
     ctx = LSContext(op, y, ls_route)
     trace = []
     T, m = topk_excluding(ctx.aty, None, K)
@@ -159,7 +165,7 @@ def sp(op: SRM, y, K: int, max_iter: int = 100, ls_route: str = "auto") -> Resul
 
 def ompr(op: SRM, y, K: int, eta: float | None = None, max_iter: int | None = None,
          ls_route: str = "auto", l: int = 1) -> Result:
-    y = np.asarray(y, dtype=np.float64)
+    y = measurement_vector(op, y)
     if eta is None:
         eta = op.n / op.m
     if max_iter is None:
@@ -217,7 +223,7 @@ def cosamp(op: SRM, y, K: int, max_iter: int = 100, ls_route: str = "auto") -> R
     x (no second solve) and updates r = y - A x.  From the second round on it
     stops with the new (T, x) when the support repeats, and with the previous
     one when ||r|| grows, as SP does; at most ``max_iter`` rounds."""
-    y = np.asarray(y, dtype=np.float64)
+    y = measurement_vector(op, y)
     ctx = LSContext(op, y, ls_route)
     trace = []
     T = np.zeros(0, dtype=np.int64)

@@ -31,6 +31,11 @@ GRAM_LIMIT = 16384       # |S| for the Cholesky route (2 GiB Gram)
 
 def ls_dense(op: SRM, supp, y) -> np.ndarray:
     a = op.columns(supp)
+    if np.iscomplexobj(a):
+        # real coefficients, complex measurements: the stacked real system
+        yc = np.asarray(y, dtype=np.complex128)
+        sol, *_ = np.linalg.lstsq(np.vstack([a.real, a.imag]), np.concatenate([yc.real, yc.imag]), rcond=None)
+        return sol
     sol, *_ = np.linalg.lstsq(a, np.asarray(y, dtype=np.float64), rcond=None)
     return sol
 
@@ -115,7 +120,7 @@ class LSContext:
 
     def __init__(self, op: SRM, y, route: str = "auto"):
         self.op = op
-        self.y = np.asarray(y, dtype=np.float64)
+        self.y = np.asarray(y, dtype=np.complex128 if getattr(op, "complex_meas", False) else np.float64)
         self.route = route
         self.aty = op.adjoint(self.y)
         self._g = None

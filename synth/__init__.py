@@ -178,3 +178,24 @@ def fd_coordinates(batch: int, m: int, count: int = 32, cfg: int = 5):
     sigs = r.integers(0, batch, count)
     coords = r.integers(0, m, count)
     return list(zip(sigs.tolist(), coords.tolist()))
+
+
+def draw_fourier_problem(cfg: int, sig: int, n: int, m: int, k: int, values: str = "normal",
+                         snr_db: float | None = None) -> Draw:
+    """A problem for partial complex Fourier sensing of a real signal: ``rows``
+    holds M distinct frequencies drawn uniformly from [1, N/2) (ascending), the
+    signs are a random +-1 flip, the noise (when ``snr_db`` is given) is
+    complex, each entry (a + i b) / sqrt(2) with a, b unit-variance Gaussians."""
+    if not (1 <= k <= 2 * m and 1 <= m <= n // 2 - 1):
+        raise ValueError("need 1 <= K <= 2M and 1 <= M <= N/2 - 1")
+    ro = rng_for(cfg, sig, STREAM_OPERATOR)
+    rows = np.sort(1 + ro.choice(n // 2 - 1, m, replace=False)).astype(np.int32)
+    signs = (ro.integers(0, 2, n) * 2 - 1).astype(np.int8)
+    rs = rng_for(cfg, sig, STREAM_SIGNAL)
+    supp = np.sort(rs.choice(n, k, replace=False)).astype(np.int32)
+    vals = draw_values(rs, k, values)
+    noise = None
+    if snr_db is not None:
+        g = rng_for(cfg, sig, STREAM_NOISE).standard_normal((2, m))
+        noise = (g[0] + 1j * g[1]) / np.sqrt(2.0)
+    return Draw(n, m, k, rows, signs, supp, vals, noise, snr_db)
