@@ -117,8 +117,30 @@ typedef struct {
   int32_t psi;            /* sparsifying basis: 0 identity, 1 the transform F,
                              2 separable 2-D DCT-II on an n x n image             */
   int32_t xform;          /* F: 0 orthonormal DCT-II; 1 orthonormal real Fourier
-                             basis (partial Fourier sensing, see above)           */
+                             basis (partial Fourier sensing, see above); 2 partial
+                             complex Fourier sensing of a real signal (below)     */
 } cs_op;
+
+/*
+ * Partial complex Fourier sensing (xform = 2): A x = D(FFT(x)), the randomly
+ * partial Fourier matrix of Sec. II, for a real signal x.  F is the unitary
+ * DFT ((F v)_k = N^(-1/2) sum_n v_n e^(-2 pi i k n / N)), R the sign flip (and
+ * permutation), and `rows` holds the M sampled frequencies, strictly ascending
+ * in [1, N/2) (a real signal's coefficients at 0 and N/2 are real and those at
+ * N - k conjugate to those at k, so each complex degree of freedom is sampled
+ * once; M <= N/2 - 1).  The measurements y, cs_apply_A's output, cs_apply_At's
+ * input and cs_adjoint_ls's grad_y are M complex values stored as (re, im)
+ * pairs of the dtype (2M reals); s stays real.  The least squares is over real
+ * coefficients with the complex norm, and the adjoint is that of the real inner
+ * product Re<u, v>: A* u = R^T Re(F^H D^T u).  K may reach 2M (SP: K <= M,
+ * CoSaMP: 3K <= 2M).  OMPR's default step is N/M with this M; cs_info.resid_norm
+ * is the complex ||y - A s||, and decision margins of correlation keys are those
+ * of 2 A* r (the call runs the real rows k and N - k of the real Fourier basis,
+ * on which the complex problem is the same problem with the data scaled by
+ * sqrt 2).  psi must be 0; size the workspace with cs_workspace_size_op; the
+ * batched calls reject it (CS_E_OP).  Frequencies outside [1, N/2) or not
+ * strictly ascending give CS_E_OP.
+ */
 
 /* Optional knobs; pass NULL for the defaults shown. */
 typedef struct {

@@ -187,11 +187,34 @@ def _torch():
 
 def _dtype_code(t) -> int:
     torch = _torch()
-    if t.dtype == torch.float32:
+    if t.dtype in (torch.float32, torch.complex64):
         return CS_F32
-    if t.dtype == torch.float64:
+    if t.dtype in (torch.float64, torch.complex128):
         return CS_F64
-    raise TypeError("y must be float32 or float64")
+    raise TypeError("y must be float32 or float64 (complex64 or complex128 for partial complex Fourier sensing)")
+
+
+def _meas(y, op, what="y"):
+    """(dtype code, contiguous tensor whose memory the library reads, real dtype)
+    for a measurement-side vector: M reals, or with partial complex Fourier
+    sensing (xform = 2) M complex values, passed as (re, im) pairs."""
+    torch = _torch()
+    y = y.contiguous()
+    cplx = getattr(op, "xform", 0) == 2
+    if cplx != y.is_complex():
+        raise TypeError(f"{what} must be complex exactly when the operator is partial complex Fourier (xform = 2)")
+    if y.numel() != op.m or not y.is_cuda:
+        raise ValueError(f"{what} must be a device vector of length M")
+    real_dtype = y.real.dtype if cplx else y.dtype
+    return _dtype_code(y), y, real_dtype
+
+
+def _meas_empty(op, dtype, device):
+    """An output on the measurement side (M reals or M complex values)."""
+    torch = _torch()
+    if getattr(op, "xform", 0) == 2:
+        return torch.empty(op.m, dtype=torch.complex64 if dtype == torch.float32 else torch.complex128, device=device)
+    return torch.empty(op.m, dtype=dtype, device=device)
 
 
 def _stream_ptr(stream):
@@ -213,7 +236,8 @@ class Operator:
     s the row-major image of coefficients), and the transform F (xform 0: the
     orthonormal DCT-II; 1: the orthonormal real Fourier basis, partial
     Fourier sensing, where rows k and N-k hold the real and imaginary parts
-    of Fourier coefficient k)."""
+    of Fourier coefficient k; 2: partial complex Fourier sensing of a real
+    signal, rows = the M sampled frequencies in [1, N/2), y complex)."""
 
     def __init__(self, n: int, rows, signs, perm=None, psi: int = 0, xform: int = 0):
         torch = _torch()
@@ -259,11 +283,8 @@ def workspace(dtype_code: int, op: Operator, k: int, algo: int, device=None):
 
 def _recover(fn, algo, y, op: Operator, k: int, tol: float, ws=None, stream=None, **kw):
     torch = _torch()
-    dt = _dtype_code(y)
-    y = y.contiguous()
-    if y.numel() != op.m or not y.is_cuda:
-        raise ValueError("y must be a device vector of length M")
-    s = torch.empty(op.n, dtype=y.dtype, device=y.device)
+    dt, y, rdt = _meas(y, op)
+    s = torch.empty(op.n, dtype=rdt, device=y.device)
     supp = torch.empty(k, dtype=torch.int32, device=y.device)
     if ws is None:
         ws = workspace(dt, op, k, algo, y.device)
@@ -291,16 +312,13 @@ def cs_recover_sp_static(y, op: Operator, k: int, tol: float, s=None, support=No
     and `support` [K] to reuse output tensors; sizes beyond CS_STATIC_WS_BYTES
     of workspace raise with status CS_E_WORKSPACE."""
     torch = _torch()
-    dt = _dtype_code(y)
-    y = y.contiguous()
-    if y.numel() != op.m or not y.is_cuda:
-        raise ValueError("y must be a device vector of length M")
+    dt, y, rdt = _meas(y, op)
     if s is None:
-        s = torch.empty(op.n, dtype=y.dtype, device=y.device)
+        s = torch.empty(op.n, dtype=rdt, device=y.device)
     if support is None:
         support = torch.empty(k, dtype=torch.int32, device=y.device)
-    if s.numel() != op.n or s.dtype != y.dtype or support.numel() != k or support.dtype != torch.int32:
-        raise ValueError("s must be [N] in y's dtype and support [K] int32")
+    if s.numel() != op.n or s.dtype != rdt or support.numel() != k or support.dtype != torch.int32:
+        raise ValueError("s must be [N] in y's (real) dtype and support [K] int32")
     info = cs_info()
     prm = _params(**kw)
     st = lib.cs_recover_sp_static(dt, _ptr(y), ctypes.byref(op.c), int(k), float(tol), _ptr(s), _ptr(support),
@@ -322,14 +340,14 @@ def cs_recover_cosamp(y, op: Operator, k: int, tol: float, ws=None, stream=None,
 def cs_ls_solve(y, op: Operator, support, tol: float, x0=None, ws=None, stream=None, **kw):
     """CG weighted least squares on `support` (the CG function of Algorithm 1) -> (theta [k], info)."""
     torch = _torch()
-    dt = _dtype_code(y)
+    dt, y, rdt = _meas(y, op)
     k = int(support.numel())
-    theta = torch.empty(k, dtype=y.dtype, device=y.device)
+    theta = torch.empty(k, dtype=rdt, device=y.device)
     if ws is None:
         ws = workspace(dt, op, k, CS_ALGO_LS, y.device)
     info = cs_info()
     prm = _params(**kw)
-    st = lib.cs_ls_solve(dt, _ptr(y.contiguous()), ctypes.byref(op.c), _ptr(support.contiguous()), k, float(tol),
+    st = lib.cs_ls_solve(dt, _ptr(y), ctypes.byref(op.c), _ptr(support.contiguous()), k, float(tol),
                          _ptr(x0.contiguous()) if x0 is not None else None, _ptr(theta), ctypes.byref(prm),
                          _ptr(ws), ws.numel(), ctypes.byref(info), _stream_ptr(stream))
     _check(st)
@@ -337,14 +355,15 @@ def cs_ls_solve(y, op: Operator, support, tol: float, x0=None, ws=None, stream=N
 
 
 def cs_adjoint_ls(grad_s, op: Operator, support, tol: float, ws=None, stream=None, **kw):
-    """dL/dy [M] from dL/ds [N] on the frozen support: A_S (A_S^T A_S)^-1 (dL/ds)_S -> (grad_y, info)."""
+    """dL/dy [M] from dL/ds [N] on the frozen support: A_S (A_S^T A_S)^-1 (dL/ds)_S -> (grad_y, info).
+    With partial complex Fourier sensing grad_y is complex: dL/dRe y + i dL/dIm y."""
     torch = _torch()
     dt = _dtype_code(grad_s)
     k = int(support.numel())
     grad_s = grad_s.contiguous()
     if grad_s.numel() != op.n or not grad_s.is_cuda:
         raise ValueError("grad_s must be a device vector of length N")
-    grad_y = torch.empty(op.m, dtype=grad_s.dtype, device=grad_s.device)
+    grad_y = _meas_empty(op, grad_s.dtype, grad_s.device)
     if ws is None:
         ws = workspace(dt, op, k, CS_ALGO_LS, grad_s.device)
     info = cs_info()
@@ -556,10 +575,10 @@ def cs_time_shape(dtype_code: int, op: Operator, shape, reps: int = 20, ws=None,
 
 
 def cs_apply_A(x, op: Operator, ws=None, stream=None):
-    """A x for a dense x [N] -> [M]."""
+    """A x for a dense x [N] -> [M] (complex with partial complex Fourier sensing)."""
     torch = _torch()
     dt = _dtype_code(x)
-    out = torch.empty(op.m, dtype=x.dtype, device=x.device)
+    out = _meas_empty(op, x.dtype, x.device)
     if ws is None:
         ws = workspace(dt, op, 1, CS_ALGO_OPERATOR, x.device)
     _check(lib.cs_apply_A(dt, ctypes.byref(op.c), _ptr(x.contiguous()), _ptr(out), _ptr(ws), ws.numel(),
@@ -568,12 +587,13 @@ def cs_apply_A(x, op: Operator, ws=None, stream=None):
 
 
 def cs_apply_At(u, op: Operator, ws=None, stream=None):
-    """A^T u for u [M] -> [N]."""
+    """A^T u for u [M] -> [N] (with partial complex Fourier sensing u is
+    complex and this is the real-inner-product adjoint R^T Re(F^H D^T u))."""
     torch = _torch()
-    dt = _dtype_code(u)
-    out = torch.empty(op.n, dtype=u.dtype, device=u.device)
+    dt, u, rdt = _meas(u, op, "u")
+    out = torch.empty(op.n, dtype=rdt, device=u.device)
     if ws is None:
         ws = workspace(dt, op, 1, CS_ALGO_OPERATOR, u.device)
-    _check(lib.cs_apply_At(dt, ctypes.byref(op.c), _ptr(u.contiguous()), _ptr(out), _ptr(ws), ws.numel(),
+    _check(lib.cs_apply_At(dt, ctypes.byref(op.c), _ptr(u), _ptr(out), _ptr(ws), ws.numel(),
                            _stream_ptr(stream)))
     return out

@@ -28,9 +28,13 @@ struct Carver {
 };
 
 template <typename T>
-static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0) {
+static size_t carve(Ctx<T>& c, const Plan& p, int kmax, char* base, int psi = 0, int cplx = 0) {
   Carver cv{base};
   const int64_t n = p.n;
+  if (cplx) {   // p.m counts the real rows (twice the complex measurements)
+    c.rows_x = cv.take<int32_t>(p.m);
+    c.ybuf = cv.take<T>(p.m);
+  }
   c.W = cv.take<Cx<T>>(p.L);
   c.Dd = cv.take<T>(n);
   c.Cc = c.Dd;   // the operator entry points and the drivers never need both
@@ -99,27 +103,29 @@ static int kmax_for(cs_algo algo, int32_t k) {
   }
 }
 
-size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo, int psi) {
+size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo, int psi, int cplx) {
   Plan p;
-  if (!choose_plan(dt, n, m, p)) return 0;
-  if (dt == CS_F32) { Ctx<float> c{}; return carve(c, p, kmax_for(algo, k), nullptr, psi); }
+  if (!choose_plan(dt, n, cplx ? 2 * m : m, p)) return 0;
+  if (dt == CS_F32) { Ctx<float> c{}; return carve(c, p, kmax_for(algo, k), nullptr, psi, cplx); }
   Ctx<double> c{};
-  return carve(c, p, kmax_for(algo, k), nullptr, psi);
+  return carve(c, p, kmax_for(algo, k), nullptr, psi, cplx);
 }
 
 template <typename T>
 void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s, const Shape* force) {
   Plan p;
   const cs_dtype dt = sizeof(T) == 4 ? CS_F32 : CS_F64;
-  if (!choose_plan(dt, op->n, op->m, p, force)) throw Error(CS_E_SHAPE, "unsupported N or shape");
+  if (op->xform < 0 || op->xform > 2) throw Error(CS_E_OP, "operator xform must be 0, 1 or 2");
+  const int cplx = op->xform == 2 ? 1 : 0;
+  if (!choose_plan(dt, op->n, cplx ? 2 * op->m : op->m, p, force)) throw Error(CS_E_SHAPE, "unsupported N or shape");
   if (op->psi < 0 || op->psi > 2) throw Error(CS_E_OP, "operator psi must be 0, 1 or 2");
-  if (op->xform != 0 && op->xform != 1) throw Error(CS_E_OP, "operator xform must be 0 or 1");
+  if (cplx && op->psi != 0) throw Error(CS_E_OP, "partial complex Fourier sensing takes psi = 0");
   const int psi = op->psi;
   const int dlog = psi == 2 ? dct2d_side_log(dt, op->n) : 0;
   if (dlog < 0) throw Error(CS_E_SHAPE, "the 2-D DCT basis needs N = n^2 with n a power of two in [8, 8192] (FP64: 4096)");
-  const size_t need = carve(c, p, kmax, nullptr, psi);
+  const size_t need = carve(c, p, kmax, nullptr, psi, cplx);
   if (ws_bytes < need) throw Error(CS_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
-  carve(c, p, kmax, (char*)ws, psi);
+  carve(c, p, kmax, (char*)ws, psi, cplx);
   p.tw_lo = c.tw_lo;
   p.tw_hi = c.tw_hi;
   p.tw_step = c.tw_step;
@@ -129,7 +135,7 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   p.perm = psi ? nullptr : op->perm;
   p.pinv = (!psi && op->perm) ? c.pinv : nullptr;
   p.keynat = psi == 2 ? 1 : 0;
-  p.fourier = op->xform;
+  p.fourier = op->xform != 0 ? 1 : 0;
   c.plan = p;
   c.stream = s;
   c.psi = psi;
@@ -138,7 +144,9 @@ void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, h
   c.rperm = op->perm;
   c.rpinv = op->perm ? c.pinv : nullptr;
   c.signs = psi ? nullptr : op->signs;
-  c.rows = op->rows;
+  c.rows = cplx ? c.rows_x : op->rows;
+  c.cplx = cplx;
+  c.freq = cplx ? op->rows : nullptr;
   c.kmax = kmax;
   prepare_kernels<T>();
 }
@@ -150,16 +158,21 @@ template void ctx_init<double>(Ctx<double>&, const cs_op*, int, void*, size_t, h
 static void check_shape(cs_dtype dt, const cs_op* op, int32_t k, cs_algo algo) {
   if (dt != CS_F32 && dt != CS_F64) throw Error(CS_E_INVALID, "dtype must be CS_F32 or CS_F64");
   if (!op || !op->rows || !op->signs) throw Error(CS_E_INVALID, "null operator descriptor");
-  const int64_t n = op->n, m = op->m;
+  const int64_t n = op->n;
   if (n < 16 || n > (int64_t(1) << 26) || (n & (n - 1))) throw Error(CS_E_SHAPE, "N must be a power of two in [16, 2^26]");
+  if (op->xform < 0 || op->xform > 2) throw Error(CS_E_OP, "operator xform must be 0, 1 or 2");
+  // the real rows: partial complex Fourier sensing has two per sampled frequency
+  const int64_t m = op->xform == 2 ? 2 * op->m : op->m;
+  if (op->xform == 2 && (op->m < 1 || op->m > n / 2 - 1))
+    throw Error(CS_E_SHAPE, "partial complex Fourier sensing needs 1 <= M <= N/2 - 1 frequencies");
   if (m < 1 || m > n) throw Error(CS_E_SHAPE, "M must satisfy 1 <= M <= N");
   if (op->psi < 0 || op->psi > 2) throw Error(CS_E_OP, "operator psi must be 0, 1 or 2");
-  if (op->xform != 0 && op->xform != 1) throw Error(CS_E_OP, "operator xform must be 0 or 1");
+  if (op->xform == 2 && op->psi != 0) throw Error(CS_E_OP, "partial complex Fourier sensing takes psi = 0");
   if (op->psi == 2 && dct2d_side_log(dt, n) < 0)
     throw Error(CS_E_SHAPE, "the 2-D DCT basis needs N = n^2 with n a power of two in [8, 8192] (FP64: 4096)");
   if (algo == CS_ALGO_OPERATOR) return;
   if (k < 1) throw Error(CS_E_INVALID, "K must be >= 1");
-  if (k > m) throw Error(CS_E_SHAPE, "K must not exceed M");
+  if (k > m) throw Error(CS_E_SHAPE, op->xform == 2 ? "K must not exceed 2M" : "K must not exceed M");
   if (algo == CS_ALGO_SP && (int64_t)2 * k > m) throw Error(CS_E_SHAPE, "SP needs 2K <= M");
   if (algo == CS_ALGO_COSAMP && (int64_t)3 * k > m) throw Error(CS_E_SHAPE, "CoSaMP needs 3K <= M");
 }
@@ -220,8 +233,18 @@ static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, d
   ctx_init<T>(c, op, kmax_for(algo, k), ws, ws_bytes, stream);
   setup_operator<T>(c);
   sel_reset<T>(c);
-  load_measurements<T>(c, (const T*)y);
-  const cs_params prm = defaults(params);
+  cs_params prm = defaults(params);
+  if (c.cplx) {
+    // the real equivalent: y^ = sqrt 2 (Re y, -Im y) on the rows (k, N - k);
+    // its normal equations are twice the complex ones (an absolute CG
+    // tolerance doubles) and its correlations twice A* r (OMPR's step halves)
+    cplx_in<T>(c, (const T*)y, std::sqrt(2.0), -std::sqrt(2.0));
+    load_measurements<T>(c, c.ybuf);
+    if (prm.tol_abs) tol *= 2.0;
+    if (prm.ompr_eta > 0.0) prm.ompr_eta *= 0.5;
+  } else {
+    load_measurements<T>(c, (const T*)y);
+  }
   c.tol_abs = prm.tol_abs != 0;
   cs_info loc{};
   cs_info* inf = info ? info : &loc;
@@ -231,6 +254,7 @@ static void recover_t(cs_algo algo, const void* y, const cs_op* op, int32_t k, d
   else if (algo == CS_ALGO_COSAMP) run_cosamp<T>(c, k, tol, prm, (T*)s, support, inf);
   else run_ompr<T>(c, k, tol, prm, (T*)s, support, inf);
   read_margins<T>(c, tol, inf);
+  if (c.cplx) inf->resid_norm *= std::sqrt(0.5);   // ||y^ - A^ s|| = sqrt 2 ||y - A s||
   CS_HIP(hipStreamSynchronize(stream));
   if (prof_on()) prof_flush();
   fill_info<T>(c, inf);
@@ -329,8 +353,14 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   setup_operator<T>(c);
   const unsigned gk = (unsigned)((k + 255) / 256);
   const Supp S = support_keys<T>(c, support, k);
-  load_measurements<T>(c, (const T*)y);
   const cs_params prm = defaults(params);
+  if (c.cplx) {   // the real equivalent (see recover_t)
+    cplx_in<T>(c, (const T*)y, std::sqrt(2.0), -std::sqrt(2.0));
+    load_measurements<T>(c, c.ybuf);
+    if (prm.tol_abs) tol *= 2.0;
+  } else {
+    load_measurements<T>(c, (const T*)y);
+  }
   c.tol_abs = prm.tol_abs != 0;
   if (x0)
     hipLaunchKernelGGL((k_reorder<T, true>), dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0],
@@ -347,7 +377,7 @@ static void ls_t(const void* y, const cs_op* op, const int32_t* support, int32_t
   if (prof_on()) prof_flush();
   if (info) {
     std::memset(info, 0, sizeof(cs_info));
-    info->resid_norm = rn;
+    info->resid_norm = c.cplx ? rn * std::sqrt(0.5) : rn;
     info->min_margin = -1.0;   // no selection
     fill_info<T>(c, info);
   }
@@ -378,13 +408,21 @@ static void adj_t(const cs_op* op, const int32_t* support, int32_t k, const void
   const Supp S = support_keys<T>(c, support, k);
   const cs_params prm = defaults(params);
   c.tol_abs = prm.tol_abs != 0;
+  if (c.cplx && prm.tol_abs) tol *= 2.0;   // the real equivalent's normal equations (see recover_t)
   hipLaunchKernelGGL(k_grad_rhs<T>, dim3(gk), dim3(256), 0, stream, support, k, c.plan, c.signs, c.bits[0], c.wpre[0],
                      (const T*)grad, c.cb);
   CS_LAUNCH_CHECK();
   const int cap = prm.cg_max_iter > 0 ? prm.cg_max_iter : 2 * k + 50;
   cg_solve<T>(c, S, c.cx, false, tol, cap, true);
   apply_support<T>(c, S, c.cx, c.Yf);
-  gather_freq<T>(c, c.Yf, (T*)grad_y);
+  if (c.cplx) {
+    // dL/dy^ on the rows (k, N - k), then dL/dRe y = sqrt 2 dL/dy^_k and
+    // dL/dIm y = -sqrt 2 dL/dy^_{N-k} (y^ = sqrt 2 (Re y, -Im y))
+    gather_freq<T>(c, c.Yf, c.ybuf);
+    cplx_out<T>(c, (T*)grad_y, std::sqrt(2.0), -std::sqrt(2.0));
+  } else {
+    gather_freq<T>(c, c.Yf, (T*)grad_y);
+  }
   CS_HIP(hipStreamSynchronize(stream));
   if (prof_on()) prof_flush();
   if (info) {
@@ -448,9 +486,19 @@ static void apply_t(bool adjoint, const cs_op* op, const void* in, void* out, vo
       rand_in<T>(c, c.Yf, c.P2, nullptr);
       transform_fwd<T>(c, c.P2, c.Yf);
     }
-    gather_freq<T>(c, c.Yf, (T*)out);
+    if (c.cplx) {   // y_k = (row k - i row N-k) / sqrt 2
+      gather_freq<T>(c, c.Yf, c.ybuf);
+      cplx_out<T>(c, (T*)out, std::sqrt(0.5), -std::sqrt(0.5));
+    } else {
+      gather_freq<T>(c, c.Yf, (T*)out);
+    }
   } else {
-    scatter_freq<T>(c, (const T*)in, c.Yf);
+    if (c.cplx) {   // A* u = A^T (Re u, -Im u) / sqrt 2 on the rows (k, N - k)
+      cplx_in<T>(c, (const T*)in, std::sqrt(0.5), -std::sqrt(0.5));
+      scatter_freq<T>(c, c.ybuf, c.Yf);
+    } else {
+      scatter_freq<T>(c, (const T*)in, c.Yf);
+    }
     if (c.psi) {
       transform_adj<T>(c, c.Yf, c.P2, false);
       rand_out<T>(c, c.P2, c.P1, nullptr);
@@ -506,10 +554,13 @@ size_t cs_workspace_size(cs_dtype dtype, int64_t n, int64_t m, int32_t k, cs_alg
 }
 
 size_t cs_workspace_size_op(cs_dtype dtype, const cs_op* op, int32_t k, cs_algo algo) {
-  if (!op || op->psi < 0 || op->psi > 2) return 0;
+  if (!op || op->psi < 0 || op->psi > 2 || op->xform < 0 || op->xform > 2) return 0;
   if (op->psi == 2 && dct2d_side_log(dtype, op->n) < 0) return 0;
-  if (cs_workspace_size(dtype, op->n, op->m, k, algo) == 0) return 0;
-  return workspace_bytes(dtype, op->n, op->m, k, algo, op->psi);
+  const int cplx = op->xform == 2 ? 1 : 0;
+  if (cplx && (op->psi != 0 || op->m < 1 || op->m > op->n / 2 - 1)) return 0;
+  // sizes of the real rows: two per sampled frequency with complex sensing
+  if (cs_workspace_size(dtype, op->n, cplx ? 2 * op->m : op->m, k, algo) == 0) return 0;
+  return workspace_bytes(dtype, op->n, op->m, k, algo, op->psi, cplx);
 }
 
 cs_status cs_recover_omp(cs_dtype dtype, const void* y, const cs_op* op, int32_t k, double tol, void* s,
@@ -530,7 +581,7 @@ cs_status cs_recover_sp_static(cs_dtype dtype, const void* y, const cs_op* op, i
     check_shape(dtype, op, k, CS_ALGO_SP);
     if (!y || !s || !support) throw Error(CS_E_INVALID, "null y, s or support");
     check_tol(tol);
-    const size_t need = workspace_bytes(dtype, op->n, op->m, k, CS_ALGO_SP, op->psi);
+    const size_t need = workspace_bytes(dtype, op->n, op->m, k, CS_ALGO_SP, op->psi, op->xform == 2 ? 1 : 0);
     if (need == 0) throw Error(CS_E_SHAPE, "unsupported N or shape");
     if (need > (size_t)CS_STATIC_WS_BYTES)
       throw Error(CS_E_WORKSPACE, "these sizes need " + std::to_string(need) +
@@ -610,6 +661,7 @@ size_t cs_workspace_size_batched(cs_dtype dtype, int32_t count, const cs_batch_i
   for (int i = 0; i < count; ++i) {
     const cs_op& o = items[i].op;
     if (algo == CS_ALGO_OMPR && o.psi != 0) return 0;
+    if (o.xform == 2) return 0;   // complex measurements: single-signal calls only
     if (algo == CS_ALGO_SP && (int64_t)2 * items[i].k > o.m) return 0;
     if (cs_workspace_size_op(dtype, &o, items[i].k, algo) == 0) return 0;
   }
@@ -624,6 +676,7 @@ cs_status cs_recover_sp_batched(cs_dtype dtype, int32_t count, const cs_batch_it
     if (count < 1 || !items) throw Error(CS_E_INVALID, "count must be >= 1 with a non-null item array");
     for (int i = 0; i < count; ++i) {
       check_shape(dtype, &items[i].op, items[i].k, CS_ALGO_SP);
+      if (items[i].op.xform == 2) throw Error(CS_E_OP, "the batched calls take real measurements (xform 0 or 1)");
       if (!items[i].y || !items[i].s || !items[i].support) throw Error(CS_E_INVALID, "null y, s or support in batch");
     }
     check_tol(tol);
@@ -648,6 +701,7 @@ cs_status cs_recover_ompr_batched(cs_dtype dtype, int32_t count, const cs_batch_
     for (int i = 0; i < count; ++i) {
       check_shape(dtype, &items[i].op, items[i].k, CS_ALGO_OMPR);
       if (items[i].op.psi != 0) throw Error(CS_E_INVALID, "the batched call takes operators with psi = 0");
+      if (items[i].op.xform == 2) throw Error(CS_E_OP, "the batched calls take real measurements (xform 0 or 1)");
       if (!items[i].y || !items[i].s || !items[i].support) throw Error(CS_E_INVALID, "null y, s or support in batch");
       if (items[i].moves_cap < 0 || (items[i].moves_cap > 0 && !items[i].moves))
         throw Error(CS_E_INVALID, "moves_cap must be >= 0, with a non-null moves array when positive");

@@ -301,6 +301,14 @@ struct Ctx {
   Cx<T>* tw_dct = nullptr; // stage twiddles of the n/2-point row FFTs
   int dct_log = 0;
   const int32_t* rows;
+  // Partial complex Fourier sensing (cs_op.xform = 2): the M sampled
+  // frequencies k in [1, N/2) become the 2M rows k and N - k of the real
+  // Fourier basis (rows_x, ascending), and complex data enter and leave
+  // through ybuf (2M reals) by the row pairing of cplx_in / cplx_out.
+  int cplx = 0;
+  const int32_t* freq = nullptr;   // caller's frequencies (device, M)
+  int32_t* rows_x = nullptr;       // expanded rows (workspace, 2M)
+  T* ybuf = nullptr;               // expanded real data (workspace, 2M)
   int kmax;                // largest support handled by the compact buffers
   // dense N-vectors (v-order unless noted)
   Cx<T>* W;                // transform work buffer (L complex)
@@ -426,7 +434,7 @@ bool choose_plan(cs_dtype dt, int64_t n, int64_t m, Plan& p, const Shape* force 
 int shape_candidates(cs_dtype dt, int l, Shape* out, int max);
 // Installs (s != nullptr) or clears the process-wide shape for L = 2^l.
 bool set_shape_override(cs_dtype dt, int l, const Shape* s);
-size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo, int psi = 0);
+size_t workspace_bytes(cs_dtype dt, int64_t n, int64_t m, int32_t k, cs_algo algo, int psi = 0, int cplx = 0);
 
 template <typename T>
 void ctx_init(Ctx<T>& c, const cs_op* op, int kmax, void* ws, size_t ws_bytes, hipStream_t s,
@@ -441,6 +449,11 @@ template <typename T> void scatter_freq(Ctx<T>& c, const T* u, T* outf); // u [M
 // y -> Yf (freq layout), ||y|| -> ynorm, F^T D^T y (key order) -> C0
 template <typename T> void load_measurements(Ctx<T>& c, const T* y);
 template <typename T> void gather_freq(Ctx<T>& c, const T* inf, T* out); // freq layout -> [M]
+// Partial complex Fourier: M complex values (re, im pairs) <-> the 2M real
+// rows k, N - k.  cplx_in writes ybuf[i] = a Re u_i and ybuf[2M-1-i] = b Im u_i;
+// cplx_out writes out_i = (a r_i) + i (b r_{2M-1-i}) from r = ybuf.
+template <typename T> void cplx_in(Ctx<T>& c, const T* u, double a, double b);
+template <typename T> void cplx_out(Ctx<T>& c, T* out, double a, double b);
 template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
 // Reads `bytes` (a multiple of 4, at most 4096) of device memory on the host:
 // a one-block kernel copies them into a pinned, device-mapped host buffer

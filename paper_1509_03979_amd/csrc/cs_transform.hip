@@ -263,10 +263,27 @@ void fill_u32(uint32_t* p, int64_t count, uint32_t v, hipStream_t s) { fill<uint
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)std::max<int64_t>(1, (n + t - 1) / t); }
 
+// Partial complex Fourier sensing (cs_op.xform = 2).  For a real signal the
+// unitary DFT coefficient k in (0, N/2) is (row k - i row N-k) / sqrt 2 of the
+// orthonormal real Fourier basis, so the complex operator is the real one on
+// the rows k and N - k with the data paired by cplx_in / cplx_out; the rows
+// are [k_0 .. k_{M-1}, N - k_{M-1} .. N - k_0] (ascending when the k are).
+__global__ void k_expand_rows(const int32_t* __restrict__ freq, int64_t m, int64_t n, int32_t* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t k = freq[i];
+  rows[i] = k;
+  rows[2 * m - 1 - i] = (int32_t)(n - k);
+}
+
 template <typename T>
 void setup_operator(Ctx<T>& c) {
   const Plan& p = c.plan;
   hipStream_t s = c.stream;
+  if (c.cplx) {   // the rows (validated with the mask below) from the sampled frequencies
+    hipLaunchKernelGGL(k_expand_rows, dim3(nblk(p.m / 2, 256)), dim3(256), 0, s, c.freq, p.m / 2, p.n, c.rows_x);
+    CS_LAUNCH_CHECK();
+  }
   hipLaunchKernelGGL(k_stage_twiddles<T>, dim3(nblk(tw_table_count(p.logL1, p.logE), 256)), dim3(256), 0, s,
                      c.tw_col, p.logL1, p.logE);
   CS_LAUNCH_CHECK();
@@ -312,7 +329,9 @@ void setup_operator(Ctx<T>& c) {
   }
   int32_t bad = 0;
   dev_read(s, c.ibuf, &bad, sizeof(int32_t));
-  if (bad & 1) throw Error(CS_E_OP, "operator rows must be strictly ascending in [0, N)");
+  if (bad & 1)
+    throw Error(CS_E_OP, c.cplx ? "operator frequencies must be strictly ascending in [1, N/2)"
+                                : "operator rows must be strictly ascending in [0, N)");
   if (bad & 2) throw Error(CS_E_OP, "operator signs must be +1 or -1");
   if (bad & 4) throw Error(CS_E_OP, "operator perm must be a permutation of [0, N)");
 }
@@ -461,6 +480,35 @@ __global__ void k_gather_freq(const T* __restrict__ inf, const int32_t* __restri
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
   out[i] = inf[fpos(rows[i], p)];
+}
+
+// ---- partial complex Fourier (cs_op.xform = 2): the data pairing of the
+// rows k and N - k (k_expand_rows above)
+template <typename T>
+__global__ void k_cplx_in(const T* __restrict__ u, int64_t m, T a, T b, T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  out[i] = a * u[2 * i];
+  out[2 * m - 1 - i] = b * u[2 * i + 1];
+}
+template <typename T>
+__global__ void k_cplx_out(const T* __restrict__ r, int64_t m, T a, T b, T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  out[2 * i] = a * r[i];
+  out[2 * i + 1] = b * r[2 * m - 1 - i];
+}
+template <typename T>
+void cplx_in(Ctx<T>& c, const T* u, double a, double b) {
+  const int64_t m = c.plan.m / 2;
+  hipLaunchKernelGGL(k_cplx_in<T>, dim3(nblk(m, 256)), dim3(256), 0, c.stream, u, m, (T)a, (T)b, c.ybuf);
+  CS_LAUNCH_CHECK();
+}
+template <typename T>
+void cplx_out(Ctx<T>& c, T* out, double a, double b) {
+  const int64_t m = c.plan.m / 2;
+  hipLaunchKernelGGL(k_cplx_out<T>, dim3(nblk(m, 256)), dim3(256), 0, c.stream, (const T*)c.ybuf, m, (T)a, (T)b, out);
+  CS_LAUNCH_CHECK();
 }
 
 template <typename T>
@@ -847,6 +895,8 @@ void prepare_kernels() {
   template double launch_row<T>(Ctx<T>&, int, const T*, T*, double*, const int*, int*);      \
   template void transform_fwd<T>(Ctx<T>&, const T*, T*, bool);                                \
   template void load_measurements<T>(Ctx<T>&, const T*);                                \
+  template void cplx_in<T>(Ctx<T>&, const T*, double, double);                          \
+  template void cplx_out<T>(Ctx<T>&, T*, double, double);                               \
   template void transform_adj<T>(Ctx<T>&, const T*, T*, bool);                              \
   template void perm_in<T>(Ctx<T>&, const T*, T*);                                      \
   template void perm_out<T>(Ctx<T>&, const T*, T*);                                     \

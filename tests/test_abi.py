@@ -72,6 +72,30 @@ def test_workspace_for_a_dct_basis():
         assert cs.lib.cs_workspace_size_batched(dt, 1, items, cs.CS_ALGO_OMPR) == 0
 
 
+def test_workspace_for_complex_fourier_sensing():
+    """Partial complex Fourier sensing (xform = 2) with M frequencies sizes like
+    the real operator with the 2M rows k, N - k, plus the expanded rows and
+    data (2M int32 and 2M reals); M above N/2 - 1, psi != 0 and the batched
+    calls have no size."""
+    for dt, esz in ((cs.CS_F32, 4), (cs.CS_F64, 8)):
+        n, m, k = 2 ** 16, 2 ** 13, 300
+        real = cs.cs_workspace_size(dt, n, 2 * m, k, cs.CS_ALGO_SP)
+        got = cs.cs_workspace_size_op(dt, cs.cs_op(n, m, None, None, None, 0, 2), k, cs.CS_ALGO_SP)
+        assert 2 * m * (4 + esz) <= got - real <= 2 * m * (4 + esz) + 512
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, n // 2 - 1, None, None, None, 0, 2), k, cs.CS_ALGO_SP) > 0
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, n // 2, None, None, None, 0, 2), k, cs.CS_ALGO_SP) == 0
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, m, None, None, None, 1, 2), k, cs.CS_ALGO_SP) == 0
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, m, None, None, None, 0, 3), k, cs.CS_ALGO_SP) == 0
+        # K up to 2M real rows; SP needs 2K <= 2M
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, 100, None, None, None, 0, 2), 150, cs.CS_ALGO_OMP) > 0
+        assert cs.cs_workspace_size_op(dt, cs.cs_op(n, 100, None, None, None, 0, 2), 201, cs.CS_ALGO_OMP) == 0
+        items = (cs.cs_batch_item * 1)()
+        items[0].op = cs.cs_op(n, m, None, None, None, 0, 2)
+        items[0].k = 10
+        for algo in (cs.CS_ALGO_OMPR, cs.CS_ALGO_SP):
+            assert cs.lib.cs_workspace_size_batched(dt, 1, items, algo) == 0
+
+
 FAKE = 4096          # a 256-aligned fake device address: never dereferenced on these paths
 
 

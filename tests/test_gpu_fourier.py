@@ -52,7 +52,7 @@ def test_bad_transform_is_rejected():
     d = synth.draw_problem(97, 1, 1024, 300, 5, "normal", None)
     dop = cs.Operator.from_numpy(1024, d.rows, d.signs, xform=1)
     ws = cs.workspace(cs.CS_F32, dop, 1, cs.CS_ALGO_OPERATOR)
-    dop.c.xform = 2
+    dop.c.xform = 3
     with pytest.raises(cs.CSError) as e:
         cs.cs_apply_A(to_dev(np.ones(1024), torch.float32), dop, ws=ws)
     assert e.value.status == cs.CS_E_OP
