@@ -31,7 +31,8 @@ namespace csr {
 
 constexpr int kBArgBlocks = 64;   // most argmax blocks per signal (fits the argpart buffer)
 
-// argmax blocks of a signal: one per 4096 candidates, 1 .. kBArgBlocks
+// argmax blocks of a signal: one per 4096 candidates (16 per thread of
+// k_b_arg), 1 .. kBArgBlocks
 __host__ __device__ __forceinline__ int arg_blocks(int64_t n) {
   const int64_t b = n >> 12;
   return (int)(b < 1 ? 1 : (b > kBArgBlocks ? kBArgBlocks : b));
@@ -60,36 +61,61 @@ __global__ void k_b_start(const BSig<T>* __restrict__ sigs) {
   }
 }
 
-// Per-signal scalar work after the transform passes of a step.  Block 0 of
-// each signal: the CG start (WARM), the CG update (ITER) or the residual norm
-// (RESID, then SELECT).  Every block of a signal whose correlation is fresh
-// (phase RESID, or SELECT once block 0 has moved it on) also computes its
-// share of the argmax of |c| outside the support.  ids[blockIdx.y] picks the
-// signal.
+// Argmax partials of a signal's fresh correlations (RESID phase): workgroup
+// (x, y) takes keys x, x + nab B, ... of signal y, keeps its best two
+// (the runner-up gives the decision's margin).  Small workgroups: most of
+// the grid exits at once (signals in other phases, small signals' extra x).
+constexpr int kBArgThreads = 256;
+template <typename T>
+__global__ __launch_bounds__(kBArgThreads) void k_b_arg(const BSig<T>* __restrict__ sigs,
+                                                        const int32_t* __restrict__ ids) {
+  const BSig<T>& s = sigs[ids[blockIdx.y]];
+  if (s.st->phase != BP_RESID) return;
+  const Plan& p = s.plan;
+  const int nab = arg_blocks(p.n);
+  if ((int)blockIdx.x >= nab) return;
+  K2 t;
+  const int64_t stp = (int64_t)nab * blockDim.x;
+  // rounds of U keys per thread with every load of a round issued first (a
+  // key at a time would wait for each load in turn)
+  constexpr int U = 8;
+  const uint32_t* __restrict__ bits = s.bits;
+  const T* __restrict__ cc = s.Cc;
+  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < p.n; q0 += U * stp) {
+    uint32_t w[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t q = min(q0 + u * stp, p.n - 1);
+      w[u] = bits[q >> 5];
+      v[u] = cc[q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t q = q0 + u * stp;
+      if (q < p.n && !((w[u] >> (q & 31)) & 1u))
+        t.add(mag_bits(v[u]) + 1, 0xFFFFFFFFu - (uint32_t)nat_of_key(q, p));
+    }
+  }
+  block_max_key2(t);
+  if (threadIdx.x == 0) {
+    s.argpart[2 * blockIdx.x] = t.best();
+    s.argpart[2 * blockIdx.x + 1] = t.second();
+  }
+}
+
+// Per-signal scalar work after the transform passes of a step (after k_b_arg,
+// which reads the RESID phase this kernel moves on): the CG start (WARM), the
+// CG update (ITER) or the residual norm (RESID, then SELECT).  One workgroup
+// per signal, ids[blockIdx.x].
 template <typename T>
 __global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __restrict__ ids) {
-  const BSig<T>& s = sigs[ids[blockIdx.y]];
+  const BSig<T>& s = sigs[ids[blockIdx.x]];
   BState* st = s.st;
   const int phase = st->phase;
   if (phase > BP_RESID) return;
   const Plan& p = s.plan;
   const int tid = threadIdx.x;
-  const int nab = arg_blocks(p.n);
-  if (phase == BP_RESID && (int)blockIdx.x < nab) {
-    K2 t;   // best and runner-up (the runner-up gives the decision's margin)
-    const int64_t stp = (int64_t)nab * blockDim.x;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + tid; q < p.n; q += stp) {
-      if (bit_of(s.bits, q)) continue;
-      const int64_t j = nat_of_key(q, p);
-      t.add(mag_bits(s.Cc[q]) + 1, 0xFFFFFFFFu - (uint32_t)j);
-    }
-    block_max_key2(t);
-    if (tid == 0) {
-      s.argpart[2 * blockIdx.x] = t.best();
-      s.argpart[2 * blockIdx.x + 1] = t.second();
-    }
-  }
-  if (blockIdx.x != 0) return;
   CgScalars* cg = s.cg;
   const int k = st->k;
   const double nb = (double)p.n * sizeof(T), kb = (double)k, esz = (double)sizeof(T);
@@ -140,12 +166,17 @@ __global__ void k_b_post(const BSig<T>* __restrict__ sigs, const int32_t* __rest
       return;
     }
     const T alpha = (T)(rr / dq);
-    T* x = s.cx[st->cur];
+    T* __restrict__ x = s.cx[st->cur];
+    T* __restrict__ r = s.cr;
+    const T* __restrict__ dv = s.cd;
+    const T* __restrict__ qv = s.cq;
     double acc = 0.0;
+    // distinct buffers: the loads of several slots go out together
+#pragma unroll 4
     for (int i = tid; i < k; i += blockDim.x) {
-      x[i] += alpha * s.cd[i];
-      const T rv = s.cr[i] - alpha * s.cq[i];
-      s.cr[i] = rv;
+      x[i] += alpha * dv[i];
+      const T rv = r[i] - alpha * qv[i];
+      r[i] = rv;
       acc += (double)rv * (double)rv;
     }
     const double rn = block_sum_any(acc);
@@ -234,11 +265,27 @@ __global__ void k_b_select(const BSig<T>* __restrict__ sigs, const int32_t* __re
   if (!go) return;
   const int32_t kj = (int32_t)key_of_nat(sj, s.plan), kd = (int32_t)key_of_nat(sd, s.plan);
   const int32_t* old = s.list[cur];
-  // pd: slot of kd in the old list; pj: old keys below kj (kj is not in it)
-  for (int i = tid; i < k; i += blockDim.x) {
-    const int32_t v = old[i];
-    if (v == kd) spd = i;
-    if (v < kj && (i + 1 == k || old[i + 1] > kj)) spj = i + 1;
+  // pd: slot of kd in the old list; pj: old keys below kj (kj is not in it);
+  // the loads of U slots go out before any comparison
+  {
+    constexpr int U = 4;
+    const int bd = blockDim.x;
+    for (int i0 = tid; i0 < k; i0 += U * bd) {
+      int32_t v[U], vn[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = min(i0 + u * bd, k - 1);
+        v[u] = old[i];
+        vn[u] = old[min(i + 1, k - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = i0 + u * bd;
+        if (i >= k) continue;
+        if (v[u] == kd) spd = i;
+        if (v[u] < kj && (i + 1 == k || vn[u] > kj)) spj = i + 1;
+      }
+    }
   }
   __syncthreads();
   const int pd = spd, pj = spj;
@@ -247,34 +294,60 @@ __global__ void k_b_select(const BSig<T>* __restrict__ sigs, const int32_t* __re
     return;
   }
   const int q = pj - (pd < pj ? 1 : 0);          // slot of kj in the new list
-  int32_t* nl = s.list[nxt];
-  const T* xo = s.cx[cur];
-  T* xn = s.cx[nxt];
+  int32_t* __restrict__ nl = s.list[nxt];
+  const T* __restrict__ xo = s.cx[cur];
+  T* __restrict__ xn = s.cx[nxt];
+  const T* __restrict__ c0 = s.C0;
   const bool warm = st->warm != 0;
   double acc = 0.0;
-  for (int i = tid; i < k; i += blockDim.x) {
-    int32_t key;
-    T xv = (T)0;
-    if (i == q) {
-      key = kj;
-    } else {
+  // in rounds of U slots per thread, every load of a round issued before its
+  // results are used (the loop is a chain of dependent reads otherwise)
+  constexpr int U = 4;
+  const int bd = blockDim.x;
+  for (int i0 = tid; i0 < k; i0 += U * bd) {
+    int32_t key[U];
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * bd;
       const int r = i - (i > q ? 1 : 0);         // slot in the old list without kd
-      const int o = r + (r >= pd ? 1 : 0);
-      key = old[o];
-      if (warm) xv = xo[o];
+      const int o = min(r + (r >= pd ? 1 : 0), k - 1);
+      key[u] = (i == q) ? kj : old[o];
+      xv[u] = (warm && i != q) ? xo[o] : (T)0;
     }
-    nl[i] = key;
-    xn[i] = xv;
-    const T bv = s.C0[key];
-    s.cb[i] = bv;
-    acc += (double)bv * (double)bv;
+    T bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) bv[u] = c0[i0 + u * bd < k ? key[u] : kj];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * bd;
+      if (i < k) {
+        nl[i] = key[u];
+        xn[i] = xv[u];
+        s.cb[i] = bv[u];
+        acc += (double)bv[u] * (double)bv[u];
+      }
+    }
   }
   // prefix counts: words after kj's word gain one, words after kd's lose one
   const int64_t words = s.plan.words;
   const int64_t wj = kj >> 5, wd = kd >> 5;
-  const uint32_t* wo = s.wpre[cur];
-  uint32_t* wn = s.wpre[nxt];
-  for (int64_t w = tid; w < words; w += blockDim.x) wn[w] = wo[w] + (w > wj ? 1u : 0u) - (w > wd ? 1u : 0u);
+  const uint32_t* __restrict__ wo = s.wpre[cur];
+  uint32_t* __restrict__ wn = s.wpre[nxt];
+  constexpr int UW = 8;
+  for (int64_t w0 = tid; w0 < words; w0 += (int64_t)UW * bd) {
+    uint32_t v[UW];
+#pragma unroll
+    for (int u = 0; u < UW; ++u) {
+      const int64_t w = w0 + (int64_t)u * bd;
+      v[u] = w < words ? wo[w] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < UW; ++u) {
+      const int64_t w = w0 + (int64_t)u * bd;
+      if (w < words) wn[w] = v[u] + (w > wj ? 1u : 0u) - (w > wd ? 1u : 0u);
+    }
+  }
   const double bb = block_sum_any(acc);
   if (tid == 0) {
     s.bits[kd >> 5] &= ~(1u << (kd & 31));
@@ -466,8 +539,9 @@ void run_ompr_batched(int count, const cs_batch_item* items, double tol, const c
           CS_LAUNCH_CHECK();
         }
       }
-      hipLaunchKernelGGL(k_b_post<T>, dim3((unsigned)nab, (unsigned)na), dim3(cg_threads), 0, cap, d_sigs,
+      hipLaunchKernelGGL(k_b_arg<T>, dim3((unsigned)nab, (unsigned)na), dim3(kBArgThreads), 0, cap, d_sigs,
                          (const int32_t*)d_ids);
+      hipLaunchKernelGGL(k_b_post<T>, dim3((unsigned)na), dim3(cg_threads), 0, cap, d_sigs, (const int32_t*)d_ids);
       hipLaunchKernelGGL(k_b_select<T>, dim3((unsigned)na), dim3(1024), 0, cap, d_sigs, (const int32_t*)d_ids);
       CS_LAUNCH_CHECK();
     }

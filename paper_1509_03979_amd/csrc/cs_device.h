@@ -150,19 +150,36 @@ __device__ __forceinline__ int32_t ompr_drop_body(const T* __restrict__ x, const
                                                   const T* __restrict__ cc, const Plan& pl, T eta, int32_t jn,
                                                   double* margin = nullptr, double* mkey = nullptr) {
   K2 t;   // best two of (~bits(|z|), index): the smallest |z|, then the next
-  for (int i = threadIdx.x; i <= k; i += blockDim.x) {
-    int64_t j, key;
-    if (i < k) {
-      key = list[i];
-      j = nat_of_key(key, pl);
-    } else {
-      j = jn;
-      if (j < 0) continue;
-      key = key_of_nat(j, pl);
+  // Rounds of U slots per thread: the list and x loads of a round, then its
+  // correlation loads, are all issued before any is used, and none sits under
+  // a per-lane branch (a slot past the end reads slot k - 1 or key 0 and is
+  // dropped afterwards), so the round waits on two load latencies, not 2U.
+  constexpr int U = 4;
+  const int bd = blockDim.x;
+  const int64_t kjn = jn >= 0 ? key_of_nat(jn, pl) : 0;
+  for (int i0 = threadIdx.x; i0 <= k; i0 += U * bd) {
+    int64_t key[U];
+    T xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * bd;
+      const int li = i < k ? i : k - 1;
+      const int64_t kl = list[li];
+      const T xl = x[li];
+      key[u] = i < k ? kl : kjn;
+      xv[u] = i < k ? xl : (T)0;
     }
-    const T cv = cc[key];   // sign_j (A^T r)_j
-    const T z = (i < k) ? x[i] + eta * cv : eta * cv;
-    t.add(~mag_bits(z), (uint32_t)j);
+    T cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cv[u] = cc[key[u]];   // sign_j (A^T r)_j
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * bd;
+      if (i < k || (i == k && jn >= 0)) {
+        const int64_t j = i < k ? nat_of_key(key[u], pl) : (int64_t)jn;
+        t.add(~mag_bits(xv[u] + eta * cv[u]), (uint32_t)j);
+      }
+    }
   }
   block_max_key2(t);
   __shared__ uint32_t s_drop;
