@@ -294,10 +294,10 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t m) {
 // go to the workgroup's candidate segment.  Per workgroup it records
 // (candidates found, keys above the band).
 template <typename T>
-__global__ __launch_bounds__(kSplitThreads) void k_sel_split(const T* __restrict__ vals, const uint32_t* __restrict__ excl,
-                                                   int64_t n, int64_t eb, int cap, SelState* sel,
-                                                   RecKey<T>* __restrict__ rkey, uint32_t* __restrict__ rpos,
-                                                   int32_t* __restrict__ rcnt, uint32_t* __restrict__ out_bits) {
+__device__ __forceinline__ void sel_split_body(const T* __restrict__ vals, const uint32_t* __restrict__ excl,
+                                               int64_t n, int64_t eb, int cap, SelState* sel,
+                                               RecKey<T>* __restrict__ rkey, uint32_t* __restrict__ rpos,
+                                               int32_t* __restrict__ rcnt, uint32_t* __restrict__ out_bits) {
   __shared__ uint32_t s_mid;
   __shared__ uint32_t s_hi[kSplitThreads / 64];
   if (threadIdx.x == 0) s_mid = 0u;
@@ -334,46 +334,6 @@ __global__ __launch_bounds__(kSplitThreads) void k_sel_split(const T* __restrict
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t p = r0 + u * R + wave * 256 + lane * 4;
-      if constexpr (sizeof(T) == 4) {
-        // FP32: the keys and the band fit 32 bits
-        const uint32_t lo32 = (uint32_t)t_lo, hi32 = (uint32_t)t_hi;
-        uint32_t key[4], hib = 0, midb = 0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t m = __float_as_uint(v[u][e]) & 0x7FFFFFFFu;
-          const bool x = (ex[u] >> e) & 1u;
-          bad |= !x && m >= 0x7F800000u;
-          key[e] = x ? 0u : m + 1u;
-          hib |= (uint32_t)(key[e] > hi32) << e;
-          midb |= (uint32_t)(key[e] >= lo32 && key[e] <= hi32) << e;
-        }
-        uint32_t w = hib << ((lane & 7) * 4);
-        w |= __shfl_xor(w, 1, 64);
-        w |= __shfl_xor(w, 2, 64);
-        w |= __shfl_xor(w, 4, 64);
-        if ((lane & 7) == 0 && p < end) out_bits[p >> 5] = w;
-        hcnt += __popc(hib);
-        // each lane's band keys (at most four) at its exclusive prefix in the wave
-        const uint32_t cnt = __popc(midb);
-        if (__ballot(cnt != 0)) {
-          const uint64_t c0 = __ballot(cnt & 1u), c1 = __ballot(cnt & 2u), c2 = __ballot(cnt & 4u);
-          const uint32_t tot = (uint32_t)(__popcll(c0) + 2 * __popcll(c1) + 4 * __popcll(c2));
-          uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(&s_mid, tot);
-          base = __shfl(base, 0, 64);
-          uint32_t o = base + lane_prefix(c0) + 2 * lane_prefix(c1) + 4 * lane_prefix(c2);
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if ((midb >> e) & 1u) {
-              if (o < (uint32_t)cap) {
-                bk[o] = (RecKey<T>)key[e];
-                bp[o] = (uint32_t)(p + e);
-              }
-              ++o;
-            }
-        }
-        continue;
-      }
       uint64_t key[4];
       uint32_t hib = 0, midb = 0;
 #pragma unroll
@@ -406,6 +366,110 @@ __global__ __launch_bounds__(kSplitThreads) void k_sel_split(const T* __restrict
           if (((midb >> e) & 1u) && o[e] < (uint32_t)cap) {
             bk[o[e]] = (RecKey<T>)key[e];
             bp[o[e]] = (uint32_t)(p + e);
+          }
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) hcnt += __shfl_xor(hcnt, off, 64);
+  if (lane == 0) s_hi[wave] = hcnt;
+  if (bad) atomicOr(&sel->nonfinite, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    rcnt[2 * blockIdx.x] = (int32_t)s_mid;
+    uint32_t hsum = 0;
+    for (int i = 0; i < kSplitThreads / 64; ++i) hsum += s_hi[i];
+    rcnt[2 * blockIdx.x + 1] = (int32_t)hsum;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSplitThreads) void k_sel_split(const T* __restrict__ vals, const uint32_t* __restrict__ excl,
+                                                             int64_t n, int64_t eb, int cap, SelState* sel,
+                                                             RecKey<T>* __restrict__ rkey, uint32_t* __restrict__ rpos,
+                                                             int32_t* __restrict__ rcnt, uint32_t* __restrict__ out_bits) {
+  sel_split_body<T>(vals, excl, n, eb, cap, sel, rkey, rpos, rcnt, out_bits);
+}
+// OR of a value over each aligned group of eight lanes, by cross-lane moves
+// within quads and the mirror within half-rows (no LDS round trip).
+__device__ __forceinline__ uint32_t or8(uint32_t w) {
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0xB1, 0xF, 0xF, false);    // quad lanes 1 0 3 2
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x4E, 0xF, 0xF, false);    // quad lanes 2 3 0 1
+  w |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)w, 0x141, 0xF, 0xF, false);   // half-row mirror
+  return w;
+}
+
+// The dense split for FP32 keys: the same work as sel_split_body with 32-bit
+// keys, band and offsets within the workgroup's block (so address arithmetic
+// stays 32-bit), the bitmap words assembled by cross-lane moves.
+__global__ __launch_bounds__(kSplitThreads) void k_sel_split_f32(
+    const float* __restrict__ vals, const uint32_t* __restrict__ excl, int64_t n, int64_t eb, int cap, SelState* sel,
+    uint32_t* __restrict__ rkey, uint32_t* __restrict__ rpos, int32_t* __restrict__ rcnt,
+    uint32_t* __restrict__ out_bits) {
+  __shared__ uint32_t s_mid;
+  __shared__ uint32_t s_hi[kSplitThreads / 64];
+  if (threadIdx.x == 0) s_mid = 0u;
+  __syncthreads();
+  const uint32_t lo32 = (uint32_t)sel->t_lo, hi32 = (uint32_t)sel->t_hi;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t b0 = (int64_t)blockIdx.x * eb;
+  const uint32_t len = (uint32_t)(std::min<int64_t>(n, b0 + eb) - b0);   // a multiple of 32
+  const float* __restrict__ vb = vals + b0;
+  const uint32_t* __restrict__ xb = excl ? excl + (b0 >> 5) : nullptr;
+  uint32_t* __restrict__ ob = out_bits + (b0 >> 5);
+  uint32_t* __restrict__ bk = rkey + (int64_t)blockIdx.x * cap;
+  uint32_t* __restrict__ bp = rpos + (int64_t)blockIdx.x * cap;
+  uint32_t hcnt = 0;
+  bool bad = false;
+  constexpr int U = 4;                           // rounds in flight per iteration
+  constexpr uint32_t R = kSplitThreads * 4;       // keys per round
+  const uint32_t lo = (uint32_t)(wave * 256 + lane * 4);
+  for (uint32_t r0 = 0; r0 < len; r0 += U * R) {
+    float4 v[U];
+    uint32_t xw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {     // a lane past the end re-reads the last four keys, marked excluded below
+      const uint32_t off = r0 + u * R + lo;
+      const uint32_t oc = off < len ? off : len - 4;
+      v[u] = *reinterpret_cast<const float4*>(vb + oc);
+      xw[u] = xb ? xb[oc >> 5] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t off = r0 + u * R + lo;
+      const uint32_t ex = off < len ? (xw[u] >> (off & 31)) & 0xFu : 0xFu;
+      const float vv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+      uint32_t key[4], hib = 0, midb = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t m = __float_as_uint(vv[e]) & 0x7FFFFFFFu;
+        const bool x = (ex >> e) & 1u;
+        bad |= !x && m >= 0x7F800000u;
+        key[e] = x ? 0u : m + 1u;
+        hib |= (uint32_t)(key[e] > hi32) << e;
+        midb |= (uint32_t)(key[e] >= lo32 && key[e] <= hi32) << e;
+      }
+      // eight lanes hold the 32 bits of one word
+      const uint32_t w = or8(hib << ((lane & 7) * 4));
+      if ((lane & 7) == 0 && off < len) ob[off >> 5] = w;
+      hcnt += __popc(hib);
+      // each lane's band keys (at most four) at its exclusive prefix in the wave
+      const uint32_t cnt = __popc(midb);
+      if (__ballot(cnt != 0)) {
+        const uint64_t c0 = __ballot(cnt & 1u), c1 = __ballot(cnt & 2u), c2 = __ballot(cnt & 4u);
+        const uint32_t tot = (uint32_t)(__popcll(c0) + 2 * __popcll(c1) + 4 * __popcll(c2));
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&s_mid, tot);
+        base = __shfl(base, 0, 64);
+        uint32_t o = base + lane_prefix(c0) + 2 * lane_prefix(c1) + 4 * lane_prefix(c2);
+        const uint32_t pos = (uint32_t)b0 + off;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if ((midb >> e) & 1u) {
+            if (o < (uint32_t)cap) {
+              bk[o] = key[e];
+              bp[o] = pos + (uint32_t)e;
+            }
+            ++o;
           }
       }
     }
@@ -830,8 +894,12 @@ void topk_dense(Ctx<T>& c, const T* dense, const uint32_t* excl, int k, uint32_t
   hipLaunchKernelGGL((k_sel_sample<T>), dim3(1), dim3(1024), 0, s, dense, excl, n, (int64_t)k, 8 * (int)sizeof(T),
                      c.sel);
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_sel_split<T>), dim3(sl.blocks), dim3(kSplitThreads), 0, s, dense, excl, n, sl.per_block, sl.cap, c.sel,
-                     (RecKey<T>*)c.rkey, c.rpos, c.rcnt, out_bits);
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL(k_sel_split_f32, dim3(sl.blocks), dim3(kSplitThreads), 0, s, (const float*)dense, excl, n,
+                       sl.per_block, sl.cap, c.sel, (uint32_t*)c.rkey, c.rpos, c.rcnt, out_bits);
+  else
+    hipLaunchKernelGGL((k_sel_split<T>), dim3(sl.blocks), dim3(kSplitThreads), 0, s, dense, excl, n, sl.per_block,
+                       sl.cap, c.sel, (RecKey<T>*)c.rkey, c.rpos, c.rcnt, out_bits);
   CS_LAUNCH_CHECK();
   const unsigned grid = (unsigned)std::min(kPassBlocks, sl.blocks);
   // CS_SELECT_DENSE set: take the every-key fallback regardless of the band
