@@ -140,19 +140,16 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
     // T u D contains T and Cc holds A^T r for (T, x): no transform for the warm residual
     cg_solve<T>(c, supp(iU, 2 * K), xU, warm, tol, cg_cap(prm, 2 * K), false, true);
     topk_compact<T>(c, xU, c.list[iU], 2 * K, K, c.bits[iN]);     // T': top-K of |x~| over T u D
-    bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
-    if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
-    cg_solve<T>(c, supp(iN, K), xN, warm, tol, cg_cap(prm, K));
-    bits_differ(c.bits[iN], c.bits[iT], words, &c.cg->differ, s);
-    const double rn2 = resid_corr<T>(c, supp(iN, K), xN);     // also reads the flag back
-    const bool same = c.last_differ == 0;
-    if (same) {
-      std::swap(iT, iN);
-      std::swap(xT, xN);
-      rn = rn2;
+    // T' = T: the round ends the recovery with (T, x), x already the least
+    // squares on T, so neither that solve nor the residual is repeated
+    if (bits_equal(c.bits[iN], c.bits[iT], words, c.ibuf + 8, s)) {
       stopped = true;
       break;
     }
+    bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
+    if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
+    cg_solve<T>(c, supp(iN, K), xN, warm, tol, cg_cap(prm, K));
+    const double rn2 = resid_corr<T>(c, supp(iN, K), xN);
     if (rn2 > rn) {   // keep the previous (T, x)
       stopped = true;
       break;

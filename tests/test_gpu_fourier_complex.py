@@ -143,7 +143,7 @@ def test_gradient_through_sp(dt, bound):
     dop = cs.Operator.from_numpy(d.n, d.rows, d.signs, xform=2)
     yt = cdev(y, dt).requires_grad_(True)
     announce("gradient complex fourier", dt)
-    s, supp = cs.SPRecover.apply(yt, dop, d.k, 1e-10 if dt == "f64" else 1e-6)
+    s, supp = cs.SPRecover.apply(yt, dop, d.k, 1e-12 if dt == "f64" else 1e-6)
     t = d.s_dense()
     loss = ((s - torch.as_tensor(t, dtype=s.dtype, device="cuda")) ** 2).sum()
     loss.backward()
