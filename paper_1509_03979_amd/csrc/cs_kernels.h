@@ -100,6 +100,14 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
   constexpr int NT = nt_for(E, LOGE);
   constexpr int EPT = (E + NT - 1) / NT;
   constexpr int NW = NT / 64;
+  // Inverse passes read a dense strip: each thread's loads are the inputs of
+  // its first-stage butterfly, so that stage runs from registers.  Forward
+  // passes write a dense strip: each thread's stores are the outputs of its
+  // last-stage butterflies, so that stage ends in registers.
+  constexpr int LR0 = stage_lr(LOGL1, 0, LOGE);
+  constexpr bool REG_IN = INV && (E >> LR0) == NT && EPT == (1 << LR0) && LOGL1 > 0;
+  using CL = CmLast<LOGL1, LOGB, LOGE, NT>;
+  constexpr bool REG_OUT = !INV && CL::ok && CL::MAXB * CL::R == EPT && E % NT == 0;
   __shared__ double red[NW];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<T>* buf = (Cx<T>*)smem_raw;
@@ -207,15 +215,29 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
       slot(sl, (uint32_t)io.list[sl], (!dir || upd) ? io.x[sl] : (T)0, dir ? io.r[sl] : (T)0,
            need_d ? io.d[sl] : (T)0, upd ? io.q[sl] : (T)0);
     }
-  } else {
+  } else if constexpr (!REG_IN) {
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
       if (E % NT == 0 || e < E) buf[lp(e)] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
     }
   }
-  __syncthreads();
-  ct_fft<T, INV, NT, LOGL1, LOGB, true, LOGE>(buf, tw);
+  Cx<T> vo[REG_OUT ? CL::MAXB : 1][REG_OUT ? CL::R : 1];
+  if constexpr (REG_IN) {
+    Cx<T> vi[1 << LR0];
+#pragma unroll
+    for (int q = 0; q < (1 << LR0); ++q) {
+      const int e = tid + q * NT;
+      vi[q] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
+    }
+    ct_fft_cm_from_regs<T, INV, NT, LOGL1, LOGB, LOGE>(buf, tw, vi);
+  } else if constexpr (REG_OUT) {
+    __syncthreads();
+    ct_fft_cm_to_regs<T, INV, NT, LOGL1, LOGB, LOGE, CL::MAXB, CL::R>(buf, tw, vo);
+  } else {
+    __syncthreads();
+    ct_fft<T, INV, NT, LOGL1, LOGB, true, LOGE>(buf, tw);
+  }
   if (INV && compact) {
     // the first slot's values are used from here on only: pin them here so
     // that no use (and no wait for their loads) moves up front
@@ -286,6 +308,13 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
       if (E % NT == 0 || e < E) out[kb + e] = buf[lp(e)];
+    }
+  } else if constexpr (REG_OUT) {
+    // store e = tid + q NT holds last-stage output (q mod MAXB, q / MAXB)
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = tid + q * NT;
+      out[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))] = vo[q % CL::MAXB][q / CL::MAXB];
     }
   } else {
 #pragma unroll
