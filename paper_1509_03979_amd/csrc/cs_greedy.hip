@@ -147,9 +147,19 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
       break;
     }
     bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
-    if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
-    cg_solve<T>(c, supp(iN, K), xN, warm, tol, cg_cap(prm, K));
-    const double rn2 = resid_corr<T>(c, supp(iN, K), xN);
+    double rn2;
+    if (warm) {
+      // the residual at the warm start (x~ on T') first: its correlation is the
+      // solve's initial residual, so the solve starts without an H-apply, and
+      // when the solve takes no step it is the round's residual as well
+      remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
+      rn2 = resid_corr<T>(c, supp(iN, K), xN);
+      if (cg_solve<T>(c, supp(iN, K), xN, true, tol, cg_cap(prm, K), false, true) > 0)
+        rn2 = resid_corr<T>(c, supp(iN, K), xN);
+    } else {
+      cg_solve<T>(c, supp(iN, K), xN, false, tol, cg_cap(prm, K));
+      rn2 = resid_corr<T>(c, supp(iN, K), xN);
+    }
     if (rn2 > rn) {   // keep the previous (T, x)
       stopped = true;
       break;
