@@ -287,57 +287,4 @@ __device__ __forceinline__ void ct_fft_cm_from_regs(Cx<T>* buf, const Cx<T>* __r
   ct_fft<T, INV, NT, LOGN, LOGCNT, true, LOGE, LR>(buf, tw);
 }
 
-// Start (log2 span) of the last stage of the radix sequence.
-__host__ __device__ constexpr int last_stage_ns(int logn, int loge) {
-  int ns = 0;
-  while (ns + stage_lr(logn, ns, loge) < logn) ns += stage_lr(logn, ns, loge);
-  return ns;
-}
-
-// Column-major sets, last stage into registers: thread tid owns the
-// last-stage butterflies w = tid + q NT (f = w mod CNT, j = w / CNT < N/R) and
-// returns element j + r N/R of FFT f in v[q][r].  That is element
-// tid / CNT + (q + MAXB r) NT / CNT, which a strided store
-// e = tid + (q + MAXB r) NT writes.  The LDS is not written after the last read.
-template <int LOGN, int LOGCNT, int LOGE, int NT>
-struct CmLast {
-  static constexpr int LAST = last_stage_ns(LOGN, LOGE);
-  static constexpr int R = 1 << (LOGN - LAST);
-  static constexpr int TOTAL = (1 << (LOGN + LOGCNT)) >> (LOGN - LAST);
-  static constexpr int MAXB = TOTAL / NT > 0 ? TOTAL / NT : 1;
-  static constexpr bool ok = LAST > 0 && TOTAL % NT == 0 && NT % (1 << LOGCNT) == 0;
-};
-
-template <typename T, bool INV, int NT, int LOGN, int LOGCNT, int LOGE, int MAXB, int R>
-__device__ __forceinline__ void ct_fft_cm_to_regs(Cx<T>* buf, const Cx<T>* __restrict__ tw, Cx<T> (&v)[MAXB][R]) {
-  using L = CmLast<LOGN, LOGCNT, LOGE, NT>;
-  static_assert(L::ok && L::MAXB == MAXB && L::R == R, "last-stage register layout");
-  constexpr int CNT = 1 << LOGCNT, NB = (1 << LOGN) / R, NS = 1 << L::LAST;
-  constexpr int TWOFF = tw_stage_offset(LOGN, L::LAST, LOGE);
-  constexpr bool RD_FAST = ((NB * CNT) % 16) == 0;
-  ct_fft<T, INV, NT, LOGN, LOGCNT, true, LOGE, 0, L::LAST>(buf, tw);
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < MAXB; ++q) {
-    const int w = tid + q * NT;
-    const int f = w & (CNT - 1), j = w >> LOGCNT;
-    const int base = j * CNT + f;
-    if (RD_FAST) {
-      const int pb = lp(base);
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[pb + r * NB * CNT + ((r * NB * CNT) >> 4)];
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[lp(base + r * NB * CNT)];
-    }
-    const Cx<T>* tp = tw + TWOFF + (j & (NS - 1)) * (R - 1);
-#pragma unroll
-    for (int r = 1; r < R; ++r) {
-      const Cx<T> t = tp[r - 1];
-      v[q][r] = INV ? cmulc(v[q][r], t) : cmul(v[q][r], t);
-    }
-    dft_r<T, R, INV>(v[q]);
-  }
-}
-
 }  // namespace csr

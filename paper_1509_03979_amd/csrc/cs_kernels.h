@@ -101,13 +101,11 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
   constexpr int EPT = (E + NT - 1) / NT;
   constexpr int NW = NT / 64;
   // Inverse passes read a dense strip: each thread's loads are the inputs of
-  // its first-stage butterfly, so that stage runs from registers.  Forward
-  // passes write a dense strip: each thread's stores are the outputs of its
-  // last-stage butterflies, so that stage ends in registers.
+  // its first-stage butterfly, so that stage runs from registers.  (The
+  // forward pass keeps its last stage in LDS: storing straight from that
+  // stage's registers took as long and wrote more partial lines back from L2.)
   constexpr int LR0 = stage_lr(LOGL1, 0, LOGE);
   constexpr bool REG_IN = INV && (E >> LR0) == NT && EPT == (1 << LR0) && LOGL1 > 0;
-  using CL = CmLast<LOGL1, LOGB, LOGE, NT>;
-  constexpr bool REG_OUT = !INV && CL::ok && CL::MAXB * CL::R == EPT && E % NT == 0;
   __shared__ double red[NW];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<T>* buf = (Cx<T>*)smem_raw;
@@ -222,7 +220,6 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
       if (E % NT == 0 || e < E) buf[lp(e)] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
     }
   }
-  Cx<T> vo[REG_OUT ? CL::MAXB : 1][REG_OUT ? CL::R : 1];
   if constexpr (REG_IN) {
     Cx<T> vi[1 << LR0];
 #pragma unroll
@@ -231,9 +228,6 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
       vi[q] = in[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))];
     }
     ct_fft_cm_from_regs<T, INV, NT, LOGL1, LOGB, LOGE>(buf, tw, vi);
-  } else if constexpr (REG_OUT) {
-    __syncthreads();
-    ct_fft_cm_to_regs<T, INV, NT, LOGL1, LOGB, LOGE, CL::MAXB, CL::R>(buf, tw, vo);
   } else {
     __syncthreads();
     ct_fft<T, INV, NT, LOGL1, LOGB, true, LOGE>(buf, tw);
@@ -308,13 +302,6 @@ __device__ __forceinline__ void col_body(const Cx<T>* in, Cx<T>* out, const Plan
     for (int q = 0; q < EPT; ++q) {
       const int e = tid + q * NT;
       if (E % NT == 0 || e < E) out[kb + e] = buf[lp(e)];
-    }
-  } else if constexpr (REG_OUT) {
-    // store e = tid + q NT holds last-stage output (q mod MAXB, q / MAXB)
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = tid + q * NT;
-      out[(size_t)(e >> LOGB) * L2 + c0 + (e & (B - 1))] = vo[q % CL::MAXB][q / CL::MAXB];
     }
   } else {
 #pragma unroll
