@@ -359,9 +359,9 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
 
   const int* done = &c.cg->done;
 
-  // Iterations are queued in chunks; the host reads the flags between chunks.
-  // After the first chunk the next is sized from the observed geometric rate
-  // of r^T r so that few early-exit launches are queued.
+  // Iterations are queued in chunks; the host reads the flags after each
+  // chunk.  After the first read the chunks are sized from the observed
+  // geometric rate of r^T r so that few early-exit launches are queued.
   int it = 0;
   // The first chunk: the iterations the last solve of this size and start
   // took, plus one (early-exiting kernels cost less than a host round trip);
@@ -370,13 +370,14 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   // warm starts converge in few iterations (or none), whatever the same-size
   // solve of an earlier round took, and queued iterations would all exit.
   int first = warm ? 2 : 4;
+  bool hinted = false;
   for (int h = 0; h < 4; ++h)
     if (c.hint[h].k == k && c.hint[h].warm == (int)warm) {
       first = std::max(1, c.hint[h].it + 1);
+      hinted = true;
       break;
     }
   if (warm && c.last_warm_it >= 0) first = std::min(first, c.last_warm_it + 2);
-  int chunk = std::min(first, std::max(max_iter, 1));
   CgScalars host{};
   double rr_prev = -1.0;
   int it_prev = 0;
@@ -388,8 +389,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
   std::vector<Queued> queued;
   const int per_it = c.psi ? 4 : 2;   // transforms per iteration
   if (c.psi == 2 && !(warm && !r0_corr)) fill<T>(c.P3, c.plan.n, (T)0, s);   // (cleared above otherwise)
-  while (it < max_iter) {
-    const int q = std::min(chunk, max_iter - it);
+  auto queue_chunk = [&](int q) {
     for (int u = 0; u < q; ++u, ++it) {
       dir.it = it;
       qio.it = it;
@@ -417,8 +417,10 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
       if (c.psi == 2) continue;
       c.transforms += 2;   // (psi_middle counts Phi's two)
     }
-    dev_read(s, c.cg, &host, sizeof(CgScalars));
-    if (host.done) break;
+  };
+  // Iterations still needed after the last read (host.iters), from the
+  // observed geometric rate of r^T r over the last read span.
+  auto predict = [&]() {
     const double rr_now = host.rr[host.iters & 1];
     const double target = host.tol2 * host.ref;
     const double rr_ref = (rr_prev > 0.0) ? rr_prev : host.rr[0];
@@ -429,9 +431,52 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
       const double need = std::log(target / rr_now) / rate;      // iterations still needed
       if (std::isfinite(need)) next = (int)std::ceil(need);
     }
-    chunk = std::max(1, std::min(next, 64));
     rr_prev = rr_now;
     it_prev = host.iters;
+    return std::max(1, std::min(next, 64));
+  };
+  // With the mailbox, each chunk's scalars are posted behind it and the next
+  // chunk is queued before they are read, so the device does not idle across
+  // the read: chunk i + 1 runs while the host reads chunk i.  The run-ahead
+  // chunk is sized from the rate seen so far; before the first read only a
+  // cold start without a hint runs ahead (warm starts often converge at once).
+  const bool ahead = !no_alloc_mode();
+  struct Posted { int slot; uint32_t seq; };
+  Posted pend[2] = {};
+  int npend = 0, slot_next = 1;
+  auto post = [&]() {
+    pend[npend++] = Posted{slot_next, dev_post(s, c.cg, sizeof(CgScalars), slot_next)};
+    slot_next = 3 - slot_next;   // slots 1 and 2 alternate: at most two posts wait
+  };
+  if (max_iter > 0) {
+    queue_chunk(std::min(first, max_iter));
+    if (ahead) post();
+  }
+  bool known = false;
+  int need = 0;   // iterations still needed after host.iters at the last read
+  while (max_iter > 0) {
+    if (ahead) {
+      if (npend < 2 && it < max_iter) {
+        const int more = known ? need - (it - host.iters) : ((!warm && !hinted) ? 2 : 0);
+        if (more > 0) {
+          queue_chunk(std::min(more, max_iter - it));
+          post();
+        }
+      }
+      dev_wait(s, pend[0].slot, pend[0].seq, &host, sizeof(CgScalars));
+      pend[0] = pend[1];
+      --npend;
+    } else {
+      dev_read(s, c.cg, &host, sizeof(CgScalars));
+    }
+    known = true;
+    if (host.done) break;
+    need = predict();
+    if (npend == 0) {   // nothing queued beyond the read: queue the predicted rest now
+      if (it >= max_iter) break;
+      queue_chunk(std::min(std::max(1, need - (it - host.iters)), max_iter - it));
+      if (ahead) post();
+    }
   }
   if (!host.done) dev_read(s, c.cg, &host, sizeof(CgScalars));
   if (host.iters > 0) {

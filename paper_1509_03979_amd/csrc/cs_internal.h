@@ -455,11 +455,20 @@ template <typename T> void gather_freq(Ctx<T>& c, const T* inf, T* out); // freq
 template <typename T> void cplx_in(Ctx<T>& c, const T* u, double a, double b);
 template <typename T> void cplx_out(Ctx<T>& c, T* out, double a, double b);
 template <typename T> void fill(T* p, int64_t count, T v, hipStream_t s);
-// Reads `bytes` (a multiple of 4, at most 4096) of device memory on the host:
+// Reads `bytes` (a multiple of 4, at most 1016) of device memory on the host:
 // a one-block kernel copies them into a pinned, device-mapped host buffer
-// (one per calling thread, kept for the life of the process), then the stream
-// is synchronised.  Cheaper than a pageable device-to-host copy.
+// (one per calling thread, kept for the life of the process) once the queued
+// work before it is done, and the host waits for that.  Cheaper than a
+// pageable device-to-host copy.
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes);
+// The same read split in two: dev_post queues the copy into mailbox slot
+// `slot` (1..3) and returns its sequence number without waiting, so more work
+// can be queued behind it; dev_wait(slot, seq) waits for that copy.  Posts to
+// one slot land in stream order and a wait matches only its own sequence
+// number, so a post that is never collected does no harm.  Not available
+// while a NoAllocScope lives (no mailbox then).
+uint32_t dev_post(hipStream_t s, const void* dev, size_t bytes, int slot);
+void dev_wait(hipStream_t s, int slot, uint32_t seq, void* host, size_t bytes);
 // While a NoAllocScope lives on the calling thread, host reads are
 // stream-ordered copies into the caller's host memory followed by a stream
 // wait (the pinned mailbox allocates on its first use), and kernel timing is

@@ -343,9 +343,13 @@ void setup_operator(Ctx<T>& c) {
 // on that word instead of waiting for the stream (a stream wait adds the
 // runtime's completion signalling to every read of the greedy and CG loops).
 // A read that does not arrive within a bound falls back to a stream wait,
-// which also reports any error of the queued work.
+// which also reports any error of the queued work.  The mailbox has slots of
+// kSlotWords: slot 0 for the reads that wait at once, the others for reads
+// posted ahead of more queued work and collected later (dev_post / dev_wait).
 constexpr int kBoxWords = 1024;
 constexpr int kBoxHead = 2;
+constexpr int kBoxSlots = 4;
+constexpr int kSlotWords = kBoxWords / kBoxSlots;
 
 __global__ void k_post(const uint32_t* __restrict__ src, uint32_t* __restrict__ box, int words, uint32_t seq) {
   for (int i = threadIdx.x; i < words; i += blockDim.x) box[kBoxHead + i] = src[i];
@@ -404,13 +408,14 @@ void box_init() {
   }
 }
 uint32_t box_next() { return ++g_box.seq == 0 ? ++g_box.seq : g_box.seq; }   // never 0 (the initial word)
-// spin until the sequence word shows `want` (bounded; then a stream wait, which
-// also reports any error of the queued work), and copy the payload out
-void box_wait(hipStream_t s, uint32_t want, void* host, size_t bytes) {
+// spin until the sequence word of `slot` shows `want` (bounded; then a stream
+// wait, which also reports any error of the queued work), and copy the payload out
+void box_wait(hipStream_t s, int slot, uint32_t want, void* host, size_t bytes) {
+  const uint32_t* w = g_box.h + slot * kSlotWords;
   bool arrived = false;
   const auto t0 = std::chrono::steady_clock::now();
   for (uint32_t spin = 0;; ++spin) {
-    if (__atomic_load_n(g_box.h, __ATOMIC_ACQUIRE) == want) {
+    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) == want) {
       arrived = true;
       break;
     }
@@ -418,9 +423,9 @@ void box_wait(hipStream_t s, uint32_t want, void* host, size_t bytes) {
   }
   if (!arrived) {
     CS_HIP(hipStreamSynchronize(s));
-    if (__atomic_load_n(g_box.h, __ATOMIC_ACQUIRE) != want) throw Error(CS_E_HIP, "device read did not arrive");
+    if (__atomic_load_n(w, __ATOMIC_ACQUIRE) != want) throw Error(CS_E_HIP, "device read did not arrive");
   }
-  std::memcpy(host, g_box.h + kBoxHead, bytes);
+  std::memcpy(host, w + kBoxHead, bytes);
 }
 }  // namespace
 
@@ -447,13 +452,13 @@ void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, co
   hipLaunchKernelGGL(k_post_resid, dim3(1), dim3(1024), 0, s, partial, np, r2, flag, g_box.d, want);
   CS_LAUNCH_CHECK();
   struct { double r2; int32_t flag, pad; } h{};
-  box_wait(s, want, &h, sizeof(h));
+  box_wait(s, 0, want, &h, sizeof(h));
   *r2_host = h.r2;
   *flag_host = h.flag;
 }
 
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
-  if (bytes % 4 || bytes > 4 * (kBoxWords - kBoxHead)) throw Error(CS_E_INVALID, "dev_read size");
+  if (bytes % 4 || bytes > 4 * (kSlotWords - kBoxHead)) throw Error(CS_E_INVALID, "dev_read size");
   if (no_alloc_mode()) {
     CS_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
     CS_HIP(hipStreamSynchronize(s));
@@ -463,7 +468,24 @@ void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
   const uint32_t want = box_next();
   hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, g_box.d, (int)(bytes / 4), want);
   CS_LAUNCH_CHECK();
-  box_wait(s, want, host, bytes);
+  box_wait(s, 0, want, host, bytes);
+}
+
+uint32_t dev_post(hipStream_t s, const void* dev, size_t bytes, int slot) {
+  if (bytes % 4 || bytes > 4 * (kSlotWords - kBoxHead) || slot < 1 || slot >= kBoxSlots || no_alloc_mode())
+    throw Error(CS_E_INVALID, "dev_post");
+  box_init();
+  const uint32_t want = box_next();
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(64), 0, s, (const uint32_t*)dev, g_box.d + slot * kSlotWords,
+                     (int)(bytes / 4), want);
+  CS_LAUNCH_CHECK();
+  return want;
+}
+
+void dev_wait(hipStream_t s, int slot, uint32_t seq, void* host, size_t bytes) {
+  if (bytes % 4 || bytes > 4 * (kSlotWords - kBoxHead) || slot < 1 || slot >= kBoxSlots)
+    throw Error(CS_E_INVALID, "dev_wait");
+  box_wait(s, slot, seq, host, bytes);
 }
 
 // ------------------------------------------------------------------ freq-layout scatter / gather
