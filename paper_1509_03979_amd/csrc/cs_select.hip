@@ -191,20 +191,17 @@ __device__ __forceinline__ int64_t block_incl_scan(int64_t v, int64_t* ws) {
   return v + pre;
 }
 
-// One workgroup of 1024 threads, two keys each: sorts kSample keys taken at
-// hashed offsets of equal strides (all keys when N <= kSample; padding keys
-// are 0) in descending order and sets the candidate band [t_lo, t_hi] so
-// that, with high probability, fewer than K keys lie above t_hi and at least
-// K lie at or above t_lo.  The band only steers the work: the first radix
-// pass checks both counts and falls back to every key when either fails.
-// The sort runs on the top 32 key bits (all of an FP32 key); for longer keys
-// the band is widened to the edges of its 32-bit buckets.  Bitonic network;
-// pairs closer than 128 keys are exchanged with wavefront shuffles, the rest
-// through LDS.
+// One workgroup of 1024 threads, two keys each: takes kSample keys at hashed
+// offsets of equal strides (all keys when N <= kSample; padding keys are 0),
+// finds two of their order statistics and sets the candidate band [t_lo,
+// t_hi] so that, with high probability, fewer than K keys lie above t_hi and
+// at least K lie at or above t_lo.  The band only steers the work: the first
+// radix pass checks both counts and falls back to every key when either
+// fails.  The ranking runs on the top 32 key bits (all of an FP32 key); for
+// longer keys the band is widened to the edges of its 32-bit buckets.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_sel_sample(const T* __restrict__ vals, const uint32_t* __restrict__ excl,
                                                      int64_t n, int64_t k, int keybits, SelState* sel) {
-  __shared__ uint32_t s[kSample];
   const int t = threadIdx.x;
   const int S = (int)std::min<int64_t>(kSample, n);   // both powers of two
   const int64_t stride = n / S;
@@ -229,53 +226,80 @@ __global__ __launch_bounds__(1024) void k_sel_sample(const T* __restrict__ vals,
     const bool in = 2 * t + h < S && !((xw[h] >> (pos[h] & 31)) & 1u) && finite_v(val[h]);
     v[h] = in ? (uint32_t)((mag_bits(val[h]) + 1) >> kshift) : 0u;
   }
-#pragma unroll
-  for (int size = 2; size <= kSample; size <<= 1) {
-    const bool desc = ((2 * t) & size) == 0;
-#pragma unroll
-    for (int str = size >> 1; str > 0; str >>= 1) {
-      if (str == 1) {
-        if ((v[0] < v[1]) == desc) {
-          const uint32_t a = v[0];
-          v[0] = v[1];
-          v[1] = a;
-        }
-        continue;
-      }
-      uint32_t p0, p1;
-      if (str <= 64) {
-        p0 = __shfl_xor(v[0], str >> 1, 64);
-        p1 = __shfl_xor(v[1], str >> 1, 64);
-      } else {
-        s[2 * t] = v[0];
-        s[2 * t + 1] = v[1];
-        __syncthreads();
-        p0 = s[(2 * t) ^ str];
-        p1 = s[(2 * t + 1) ^ str];
-        __syncthreads();
-      }
-      const bool keep_max = (((2 * t) & str) == 0) == desc;
-      v[0] = keep_max ? max(v[0], p0) : min(v[0], p0);
-      v[1] = keep_max ? max(v[1], p1) : min(v[1], p1);
-    }
+  // expected sample rank of the K-th key and a margin of four standard
+  // deviations of a binomial count (none when the sample is every key)
+  const double r = (double)k * (double)S / (double)n;
+  const double margin = (S == n) ? 0.0 : 4.0 * sqrt(r) + 4.0;
+  const int64_t rh = (int64_t)floor(r - margin), rl = (int64_t)ceil(r + margin);
+  // the two keys needed, by descending rank among the kSample sample slots
+  // (padding and excluded slots hold 0 and rank last): rank rh, or the
+  // largest when no rank is safely above the K-th, and rank rl
+  uint32_t want[2] = {(uint32_t)(rh >= 1 ? std::min<int64_t>(rh, S) : 1),
+                      (uint32_t)(rl >= 1 && rl <= S ? rl : 1)};
+  // MSB-first radix select of both ranks at once, 8-bit digits: per digit one
+  // LDS histogram per rank over the keys that match its prefix, and one wave
+  // per rank finds the digit whose descending cumulative count reaches it
+  __shared__ uint32_t hist[2][256];
+  __shared__ uint32_t sel_pref[2], sel_need[2];
+  if (t < 2) {
+    sel_pref[t] = 0u;
+    sel_need[t] = want[t];
   }
-  s[2 * t] = v[0];
-  s[2 * t + 1] = v[1];
-  __syncthreads();
+#pragma unroll
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    if (t < 512) hist[t >> 8][t & 255] = 0u;
+    __syncthreads();
+    const uint32_t hi = shift == 24 ? 0u : ~((1u << (shift + 8)) - 1u);   // the digits already fixed
+    const uint32_t p0 = sel_pref[0], p1 = sel_pref[1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t d = (v[h] >> shift) & 255u;
+      if ((v[h] & hi) == p0) atomicAdd(&hist[0][d], 1u);
+      if ((v[h] & hi) == p1) atomicAdd(&hist[1][d], 1u);
+    }
+    __syncthreads();
+    const int wv = t >> 6, lane = t & 63;
+    if (wv < 2) {
+      // lane l holds digits 255 - 4l .. 252 - 4l (descending)
+      uint32_t c[4], sum = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        c[q] = hist[wv][255 - 4 * lane - q];
+        sum += c[q];
+      }
+      uint32_t incl = sum;   // inclusive prefix over lanes, in descending digit order
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+      }
+      const uint32_t need = sel_need[wv];
+      const uint32_t excl = incl - sum;
+      if (excl < need && need <= incl) {   // exactly one lane
+        uint32_t above = excl;
+        int q = 0;
+#pragma unroll
+        for (int qq = 0; qq < 3; ++qq)
+          if (q == qq && above + c[qq] < need) {
+            above += c[qq];
+            q = qq + 1;
+          }
+        sel_pref[wv] |= (uint32_t)(255 - 4 * lane - q) << shift;
+        sel_need[wv] = need - above;
+      }
+    }
+    __syncthreads();
+  }
   if (t == 0) {
-    // expected sample rank of the K-th key and a margin of four standard
-    // deviations of a binomial count (none when the sample is every key)
-    const double r = (double)k * (double)S / (double)n;
-    const double margin = (S == n) ? 0.0 : 4.0 * sqrt(r) + 4.0;
-    const int64_t rh = (int64_t)floor(r - margin), rl = (int64_t)ceil(r + margin);
-    const uint64_t low = kshift ? (1ull << kshift) - 1 : 0ull;   // bits below the sorted ones
+    const uint32_t khi = sel_pref[0], klo = sel_pref[1];
+    const uint64_t low = kshift ? (1ull << kshift) - 1 : 0ull;   // bits below the ranked ones
     uint64_t thi = max_key(keybits), tlo = 1;
-    if (rh >= 1) thi = ((uint64_t)s[std::min<int64_t>(rh, S) - 1] << kshift) | low;
+    if (rh >= 1) thi = ((uint64_t)khi << kshift) | low;
     // no sample rank is safely above the K-th, but about N/S keys exceed the
     // sample's largest: with r >= 2 that is at most K/2 on average, so the
     // largest still bounds the band from above (the first pass checks it)
-    else if (r >= 2.0 && s[0] != 0u) thi = ((uint64_t)s[0] << kshift) | low;
-    if (rl >= 1 && rl <= S) tlo = std::max<uint64_t>(1, (uint64_t)s[rl - 1] << kshift);
+    else if (r >= 2.0 && khi != 0u) thi = ((uint64_t)khi << kshift) | low;
+    if (rl >= 1 && rl <= S) tlo = std::max<uint64_t>(1, (uint64_t)klo << kshift);
     sel->t_lo = tlo;
     sel->t_hi = thi;
     sel->k = k;
