@@ -448,13 +448,21 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
     pend[npend++] = Posted{slot_next, dev_post(s, c.cg, sizeof(CgScalars), slot_next)};
     slot_next = 3 - slot_next;   // slots 1 and 2 alternate: at most two posts wait
   };
-  if (max_iter > 0) {
+  // When the last warm solve took no step, this one likely starts converged:
+  // its start is read before any iteration is queued (one read instead of a
+  // chunk of launches that would all exit at once).
+  bool settled = false;
+  if (warm && c.last_warm_it == 0 && max_iter > 0) {
+    dev_read(s, c.cg, &host, sizeof(CgScalars));
+    settled = host.done != 0;
+  }
+  if (max_iter > 0 && !settled) {
     queue_chunk(std::min(first, max_iter));
     if (ahead) post();
   }
   bool known = false;
   int need = 0;   // iterations still needed after host.iters at the last read
-  while (max_iter > 0) {
+  while (max_iter > 0 && !settled) {
     if (ahead) {
       if (npend < 2 && it < max_iter) {
         const int more = known ? need - (it - host.iters) : ((!warm && !hinted) ? 2 : 0);

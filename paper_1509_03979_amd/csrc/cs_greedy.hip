@@ -141,18 +141,33 @@ void run_sp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32_
     cg_solve<T>(c, supp(iU, 2 * K), xU, warm, tol, cg_cap(prm, 2 * K), false, true);
     topk_compact<T>(c, xU, c.list[iU], 2 * K, K, c.bits[iN]);     // T': top-K of |x~| over T u D
     // T' = T: the round ends the recovery with (T, x), x already the least
-    // squares on T, so neither that solve nor the residual is repeated
-    if (bits_equal(c.bits[iN], c.bits[iT], words, c.ibuf + 8, s)) {
+    // squares on T, so neither that solve nor the residual is repeated.  The
+    // comparison is read after T''s list (and warm start) are queued behind
+    // it; they are left unused when the sets are equal.
+    bool same;
+    if (no_alloc_mode()) {
+      same = bits_equal(c.bits[iN], c.bits[iT], words, c.ibuf + 8, s) != 0;
+      if (!same) {
+        bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
+        if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
+      }
+    } else {
+      const uint32_t seq = bits_differ_post(c.bits[iN], c.bits[iT], words, c.ibuf + 8, 3, s);
+      bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
+      if (warm) remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
+      int32_t differ = 0;
+      dev_wait(s, 3, seq, &differ, sizeof(differ));
+      same = differ == 0;
+    }
+    if (same) {
       stopped = true;
       break;
     }
-    bits_to_list<T>(c, c.bits[iN], c.list[iN], K, c.wpre[iN]);
     double rn2;
     if (warm) {
       // the residual at the warm start (x~ on T') first: its correlation is the
       // solve's initial residual, so the solve starts without an H-apply, and
       // when the solve takes no step it is the round's residual as well
-      remap<T>(c, c.list[iU], xU, 2 * K, c.list[iN], xN, K);
       rn2 = resid_corr<T>(c, supp(iN, K), xN);
       if (cg_solve<T>(c, supp(iN, K), xN, true, tol, cg_cap(prm, K), false, true) > 0)
         rn2 = resid_corr<T>(c, supp(iN, K), xN);

@@ -539,6 +539,10 @@ template <typename T> void topk_compact(Ctx<T>& c, const T* vals, const int32_t*
 template <typename T> int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uint32_t* wpre);
 void bits_or(const uint32_t* a, const uint32_t* b, uint32_t* out, int64_t words, hipStream_t s);
 int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, hipStream_t s);
+// The same comparison posted to mailbox slot `slot` without waiting (see
+// dev_post): the flag (nonzero when the sets differ) is collected by dev_wait.
+uint32_t bits_differ_post(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, int slot,
+                          hipStream_t s);
 // *flag = 1 if the bitmaps differ, else 0 (no host read)
 void bits_differ(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* flag, hipStream_t s);
 

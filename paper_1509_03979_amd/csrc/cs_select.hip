@@ -974,6 +974,14 @@ void bits_differ(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* f
   CS_LAUNCH_CHECK();
 }
 
+uint32_t bits_differ_post(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, int slot,
+                          hipStream_t s) {
+  fill<int32_t>(scratch, 1, 0, s);
+  hipLaunchKernelGGL(k_bits_diff, dim3(nblk(words, 256)), dim3(256), 0, s, a, b, words, scratch);
+  CS_LAUNCH_CHECK();
+  return dev_post(s, scratch, sizeof(int32_t), slot);
+}
+
 int bits_equal(const uint32_t* a, const uint32_t* b, int64_t words, int32_t* scratch, hipStream_t s) {
   fill<int32_t>(scratch, 1, 0, s);
   hipLaunchKernelGGL(k_bits_diff, dim3(nblk(words, 256)), dim3(256), 0, s, a, b, words, scratch);
