@@ -512,7 +512,7 @@ int cg_solve(Ctx<T>& c, const Supp& S, T* x, bool warm, double tol, int max_iter
 }
 
 template <typename T>
-double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
+static void resid_corr_passes(Ctx<T>& c, const Supp& S, const T* x) {
   if (c.psi == 2) {
     fill<T>(c.P3, c.plan.n, (T)0, c.stream);
     s2_scatter<T>(c, S, x);
@@ -526,6 +526,17 @@ double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
   launch_col<T>(c, c.W, (Cx<T>*)c.Cc, true, col_io<T>(c, COL_KEY, nullptr));
   c.transforms += 2;
   }
+}
+
+template <typename T>
+void resid_corr_queue(Ctx<T>& c, const Supp& S, const T* x) {
+  resid_corr_passes<T>(c, S, x);
+  dev_sum_resid(c.stream, c.partial2, (int)(c.plan.L1 >> 1), &c.cg->resid2);
+}
+
+template <typename T>
+double resid_corr(Ctx<T>& c, const Supp& S, const T* x) {
+  resid_corr_passes<T>(c, S, x);
   // one launch sums ||r||^2 and posts it with the support-comparison flag queued before it
   double r2 = 0.0;
   int32_t differ = 0;
@@ -584,6 +595,7 @@ void remap(Ctx<T>& c, const int32_t* from, const T* x, int kfrom, const int32_t*
   template int cg_solve<T>(Ctx<T>&, const Supp&, T*, bool, double, int, bool, bool); \
   template void apply_support<T>(Ctx<T>&, const Supp&, const T*, T*);               \
   template double resid_corr<T>(Ctx<T>&, const Supp&, const T*);                    \
+  template void resid_corr_queue<T>(Ctx<T>&, const Supp&, const T*);                \
   template void remap<T>(Ctx<T>&, const int32_t*, const T*, int, const int32_t*, T*, int);
 CS_INST(float)
 CS_INST(double)

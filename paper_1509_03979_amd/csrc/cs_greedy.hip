@@ -29,6 +29,10 @@ template <typename T>
 __global__ void k_ompr_drop(const T* __restrict__ x, const int32_t* __restrict__ list, int k,
                             const T* __restrict__ cc, const Plan pl, T eta, const int32_t* __restrict__ jptr,
                             int32_t* __restrict__ out, SelState* sel) {
+  if (*jptr == -2) {   // the residual gate stopped the step: no drop, no margin
+    if (threadIdx.x == 0) out[0] = -2;
+    return;
+  }
   double m = -1.0, mk = 0.0;
   const int32_t d = ompr_drop_body<T>(x, list, k, cc, pl, eta, *jptr, &m, &mk);
   if (threadIdx.x == 0) {
@@ -37,9 +41,10 @@ __global__ void k_ompr_drop(const T* __restrict__ x, const int32_t* __restrict__
   }
 }
 
-// key bitmap update for a swap: jd[0] = index to add, jd[1] = index to drop (natural)
+// key bitmap update for a swap: jd[0] = index to add, jd[1] = index to drop
+// (natural); no change when the step stops (no index to add, or it is the one dropped)
 __global__ void k_swap_bits(uint32_t* bits, const int32_t* __restrict__ jd, const Plan pl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && jd[0] >= 0 && jd[1] >= 0 && jd[0] != jd[1]) {
     const uint32_t pj = (uint32_t)key_of_nat(jd[0], pl), pd = (uint32_t)key_of_nat(jd[1], pl);
     bits[pd >> 5] &= ~(1u << (pd & 31));
     bits[pj >> 5] |= 1u << (pj & 31);
@@ -241,8 +246,14 @@ void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int3
   bool stopped = false;
   int32_t jd[2];
   const int l = prm.ompr_l > 0 ? prm.ompr_l : 1;
+  // l = 1: the residual test runs on the device (the argmax is skipped, j = -2,
+  // once ||r|| <= 1e-12 ||y||), so the residual is not read back each step;
+  // and the step's (j, i) is read after the swap, T''s list and the warm
+  // start are queued behind it (they change nothing when the step stops)
+  const double thr = 1e-12 * c.ynorm;
+  const bool ahead = !no_alloc_mode();
   for (int t = 1; t <= max_outer; ++t) {
-    if (rn <= 1e-12 * c.ynorm) { stopped = true; break; }
+    if (l > 1 && rn <= thr) { stopped = true; break; }
     if (l > 1) {
       // general replacement size: the kept set goes to bits[2], then becomes the support
       if (!ompr_step_l<T>(c, K, l, (T)eta, c.list[cur], xI, bits, c.bits[1], c.bits[2])) { stopped = true; break; }
@@ -258,22 +269,37 @@ void run_ompr(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int3
       ++swaps;
       continue;
     }
-    argmax_excl<T>(c, (const T*)c.Cc, bits, c.ibuf);
+    argmax_excl<T>(c, (const T*)c.Cc, bits, c.ibuf, &c.cg->resid2, thr * thr);
     hipLaunchKernelGGL(k_ompr_drop<T>, dim3(1), dim3(1024), 0, s, xI, c.list[cur], K, (const T*)c.Cc, c.plan,
                        (T)eta, (const int32_t*)c.ibuf, c.ibuf + 1, c.sel);
     CS_LAUNCH_CHECK();
-    dev_read(s, c.ibuf, jd, 2 * sizeof(int32_t));
+    auto queue_swap = [&]() {
+      hipLaunchKernelGGL(k_swap_bits, dim3(1), dim3(64), 0, s, bits, (const int32_t*)c.ibuf, c.plan);
+      CS_LAUNCH_CHECK();
+      bits_to_list<T>(c, bits, c.list[nxt], K, c.wpre[nxt]);
+      if (warm) remap<T>(c, c.list[cur], xI, K, c.list[nxt], xN, K);
+    };
+    if (ahead) {
+      const uint32_t seq = dev_post(s, c.ibuf, 2 * sizeof(int32_t), 3);
+      queue_swap();
+      dev_wait(s, 3, seq, jd, 2 * sizeof(int32_t));
+    } else {
+      dev_read(s, c.ibuf, jd, 2 * sizeof(int32_t));
+    }
     if (jd[0] < 0 || jd[1] == jd[0]) { stopped = true; break; }
-    hipLaunchKernelGGL(k_swap_bits, dim3(1), dim3(64), 0, s, bits, (const int32_t*)c.ibuf, c.plan);
-    CS_LAUNCH_CHECK();
-    bits_to_list<T>(c, bits, c.list[nxt], K, c.wpre[nxt]);
+    if (!ahead) queue_swap();
     const Supp S{bits, c.wpre[nxt], c.list[nxt], K};
-    if (warm) remap<T>(c, c.list[cur], xI, K, c.list[nxt], xN, K);
     cg_solve<T>(c, S, xN, warm, tol, cg_cap(prm, K));
-    rn = resid_corr<T>(c, S, xN);
+    resid_corr_queue<T>(c, S, xN);   // ||r||^2 stays on the device for the next step's gate
+    rn = -1.0;
     std::swap(cur, nxt);
     std::swap(xI, xN);
     ++swaps;
+  }
+  if (rn < 0.0) {   // the last residual of the l = 1 steps is on the device
+    double r2 = 0.0;
+    dev_read(s, &c.cg->resid2, &r2, sizeof(double));
+    rn = std::sqrt(r2);
   }
   if (!stopped) c.flags |= CS_F_OUTER_MAXITER;
   write_output<T>(c, c.list[cur], xI, K, s_out, supp_out);

@@ -479,6 +479,8 @@ struct NoAllocScope {
   NoAllocScope();
   ~NoAllocScope();
 };
+// Sums the row pass's residual partials into *r2 on the device (no read).
+void dev_sum_resid(hipStream_t s, const double* partial, int np, double* r2);
 void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, const int32_t* flag, double* r2_host,
                     int32_t* flag_host);
 template <typename T> double norm2_host(Ctx<T>& c, const T* v, int64_t count);   // ||v||, synchronises
@@ -520,7 +522,12 @@ template <typename T> void psi2_adjoint(Ctx<T>& c, const T* inf, T* out);
 template <typename T> void prepare_kernels();                             // LDS limits, once per process
 
 // ------------------------------------------------------------------ selection
-template <typename T> void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j);
+// argmax of |dense| outside `excl` into *out_j (natural index; -1: none).  With
+// r2 non-null the selection is gated on the device by the residual: *r2 <=
+// thr2 gives *out_j = -2 and notes no margin.
+template <typename T>
+void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j, const double* r2 = nullptr,
+                 double thr2 = 0.0);
 // A decision is a near-tie when its margin is within the resolution its keys
 // are computed to: relative to the chosen key, kNearTie (tol + u log2 N), with
 // tol the CG tolerance relative to ||b|| and u the working precision's unit
@@ -564,9 +571,12 @@ template <typename T>
 void apply_support(Ctx<T>& c, const Supp& S, const T* x, T* outf);
 
 // r = y - A x and F^T D^T r (key order, in Cc) for the solution x on S;
-// returns ||r|| (synchronises).
+// returns ||r|| (synchronises).  resid_corr_queue queues the same work and
+// leaves ||r||^2 on the device (CgScalars::resid2) without waiting.
 template <typename T>
 double resid_corr(Ctx<T>& c, const Supp& S, const T* x);
+template <typename T>
+void resid_corr_queue(Ctx<T>& c, const Supp& S, const T* x);
 
 // out[i] = x[slot of to[i] in from] or 0 when absent (both ascending key lists).
 template <typename T>

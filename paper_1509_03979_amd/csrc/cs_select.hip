@@ -59,8 +59,15 @@ __global__ void k_argmax_partial(const T* __restrict__ dense, const uint32_t* __
   }
 }
 
+// A residual gate (r2 non-null): when *r2 <= thr2 the selection is not made,
+// out_j = -2 and no margin is noted (the caller stops on a zero residual).
 template <typename T>
-__global__ void k_argmax_final(const ArgKey* __restrict__ part, int np, int32_t* out_j, SelState* sel) {
+__global__ void k_argmax_final(const ArgKey* __restrict__ part, int np, int32_t* out_j, SelState* sel,
+                               const double* __restrict__ r2, double thr2) {
+  if (r2 && *r2 <= thr2) {
+    if (threadIdx.x == 0) *out_j = -2;
+    return;
+  }
   K2 t;
   for (int i = threadIdx.x; i < np; i += blockDim.x) {
     const ArgKey a = part[2 * i], b = part[2 * i + 1];
@@ -77,12 +84,13 @@ __global__ void k_argmax_final(const ArgKey* __restrict__ part, int np, int32_t*
 }
 
 template <typename T>
-void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j) {
+void argmax_excl(Ctx<T>& c, const T* dense, const uint32_t* excl, int32_t* out_j, const double* r2, double thr2) {
   const int64_t n = c.plan.n;
   const unsigned grid = (unsigned)std::min<int64_t>(kArgBlocks, nblk(n, 256));
   hipLaunchKernelGGL(k_argmax_partial<T>, dim3(grid), dim3(256), 0, c.stream, dense, excl, c.plan, c.argpart, c.sel);
   CS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_argmax_final<T>, dim3(1), dim3(1024), 0, c.stream, c.argpart, (int)grid, out_j, c.sel);
+  hipLaunchKernelGGL(k_argmax_final<T>, dim3(1), dim3(1024), 0, c.stream, c.argpart, (int)grid, out_j, c.sel, r2,
+                     thr2);
   CS_LAUNCH_CHECK();
 }
 
@@ -1012,7 +1020,7 @@ int bits_to_list(Ctx<T>& c, const uint32_t* bits, int32_t* list, int expect, uin
 }
 
 #define CS_INST(T)                                                                        \
-  template void argmax_excl<T>(Ctx<T>&, const T*, const uint32_t*, int32_t*);           \
+  template void argmax_excl<T>(Ctx<T>&, const T*, const uint32_t*, int32_t*, const double*, double); \
   template void sel_reset<T>(Ctx<T>&);                                                  \
   template void margins_read<T>(Ctx<T>&, double*, double*);                             \
   template void topk_dense<T>(Ctx<T>&, const T*, const uint32_t*, int, uint32_t*);      \

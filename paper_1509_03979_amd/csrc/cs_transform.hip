@@ -457,6 +457,11 @@ void dev_read_resid(hipStream_t s, const double* partial, int np, double* r2, co
   *flag_host = h.flag;
 }
 
+void dev_sum_resid(hipStream_t s, const double* partial, int np, double* r2) {
+  hipLaunchKernelGGL(k_post_resid, dim3(1), dim3(1024), 0, s, partial, np, r2, nullptr, nullptr, 0u);
+  CS_LAUNCH_CHECK();
+}
+
 void dev_read(hipStream_t s, const void* dev, void* host, size_t bytes) {
   if (bytes % 4 || bytes > 4 * (kSlotWords - kBoxHead)) throw Error(CS_E_INVALID, "dev_read size");
   if (no_alloc_mode()) {
