@@ -109,7 +109,10 @@ void run_omp(Ctx<T>& c, int K, double tol, const cs_params& prm, T* s_out, int32
     if (warm) remap<T>(c, c.list[cur], xc, i - 1, c.list[nxt], xn, i);
     // least squares on S; the support only grew, so the warm start's residual is the stored correlation
     cg_solve<T>(c, S, xn, warm, tol, cg_cap(prm, i), false, true);
-    rn = resid_corr<T>(c, S, xn);                           // residual update (+ the next iteration's A^T r)
+    // residual update (+ the next iteration's A^T r); OMP runs exactly K
+    // iterations, so only the last residual norm is read back
+    if (i == K) rn = resid_corr<T>(c, S, xn);
+    else resid_corr_queue<T>(c, S, xn);
     std::swap(cur, nxt);
     std::swap(xc, xn);
   }
