@@ -9,8 +9,8 @@
 // values for non-negative numbers; a key of 0 marks an excluded candidate and
 // every admissible key is bits(|v|) + 1.
 //  * argmax: packed keys (bits + 1, ~index) reduced with wavefront shuffles.
-//  * top-K of a dense vector: a sorted sample brackets the K-th key in a band;
-//    one streaming pass writes the bitmap of the keys above the band and
+//  * top-K of a dense vector: order statistics of a sample bracket the K-th
+//    key in a band; one streaming pass writes the bitmap of the keys above the band and
 //    collects the keys inside it; an MSB-first radix select (13-bit digits)
 //    over those candidates finds the threshold.  Each pass adds its
 //    workgroup histograms into one global row with atomics (only the bins a
